@@ -1,0 +1,255 @@
+"""Seeded synthetic workloads for the packet-transport path.
+
+This module builds INPUTS only: shell velocities, electron densities, line
+lists, Sobolev optical depths and downbranch emission tables, drawn with
+``numpy.random.default_rng(seed)`` in a fixed order.  It holds none of the
+transport arithmetic and is shared by the HIP path and the CPU oracle.
+
+The paper's own workloads use Kurucz/CHIANTI atomic data and explosion models
+that are not available; these generators stand in for them with the shapes of
+the paper's models: 1-D spherical shells in homologous expansion
+(Kerzendorf & Sim 2014, section 2.1), a W7-like rho ~ v^-7 density (section
+5.3), a frequency-sorted line list with per-shell Sobolev depths (section 2.5).
+
+Draw order of every generator is part of its definition; changing it changes
+every downstream value.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+# CGS constants needed to build inputs (CODATA 2018 / IAU nominal)
+C_LIGHT = 2.99792458e10  # cm/s
+M_PROTON = 1.67262192369e-24  # g
+ANGSTROM = 1.0e-8  # cm
+DAY = 86400.0  # s
+KM = 1.0e5  # cm
+L_SUN = 3.828e33  # erg/s
+
+SCATTER = 0
+DOWNBRANCH = 1
+
+# emergent spectrum grid: 1000 bins linear in frequency, 500-20000 Angstrom
+SPEC_NU_MIN = C_LIGHT / (20000.0 * ANGSTROM)
+SPEC_NU_MAX = C_LIGHT / (500.0 * ANGSTROM)
+SPEC_BINS = 1000
+
+# requested emergent luminosity: log L/Lsun = 9.44 at 13 days (section 5.3)
+L_REQUESTED = 10.0 ** 9.44 * L_SUN
+
+
+@dataclasses.dataclass
+class Model:
+    """Arrays in the layout both implementations consume."""
+
+    v_bounds: np.ndarray  # [S+1] cm/s, increasing
+    t_exp: float  # s
+    n_e: np.ndarray  # [S] cm^-3
+    line_nu: np.ndarray  # [L] Hz, non-increasing
+    tau_sobolev: np.ndarray  # [S, L] shell-major
+    line_mode: int = SCATTER
+    line_upper: Optional[np.ndarray] = None  # [L] int32
+    n_levels: int = 0
+    level_ptr: Optional[np.ndarray] = None  # [n_levels+1] int64
+    em_line: Optional[np.ndarray] = None  # [nnz] int32
+    em_cum: Optional[np.ndarray] = None  # [nnz] float64
+    nu_min: float = SPEC_NU_MIN
+    nu_max: float = SPEC_NU_MAX
+    n_bins: int = SPEC_BINS
+    seed: int = 0
+
+    @property
+    def n_shells(self) -> int:
+        return int(self.v_bounds.shape[0] - 1)
+
+    @property
+    def n_lines(self) -> int:
+        return int(self.line_nu.shape[0])
+
+    def nbytes(self) -> int:
+        n = self.v_bounds.nbytes + self.n_e.nbytes + self.line_nu.nbytes + self.tau_sobolev.nbytes
+        for a in (self.line_upper, self.level_ptr, self.em_line, self.em_cum):
+            if a is not None:
+                n += a.nbytes
+        return n
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    model: Model
+    T_inner: float
+    n_packets: int
+    n_iterations: int
+    L_requested: float = L_REQUESTED
+
+
+def _contig(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def shells(n_shells: int, v_inner_kms: float, v_outer_kms: float, t_exp_days: float,
+           rho_inner: float = 1.0e-13):
+    """Shells evenly spaced in velocity with rho ~ v^-7 at the shell centre,
+    normalised to rho_inner in the innermost shell; n_e = rho / (2 m_p)."""
+    v = np.linspace(v_inner_kms * KM, v_outer_kms * KM, n_shells + 1)
+    v_mid = 0.5 * (v[:-1] + v[1:])
+    rho = rho_inner * (v_mid / v_mid[0]) ** -7.0
+    n_e = rho / (2.0 * M_PROTON)
+    return _contig(v, np.float64), t_exp_days * DAY, _contig(n_e, np.float64)
+
+
+def log_uniform_lines(rng, n_lines: int, lam_lo_aa: float, lam_hi_aa: float):
+    """Wavelengths log-uniform in [lam_lo, lam_hi] Angstrom -> frequencies,
+    sorted non-increasing (stable)."""
+    lam = np.exp(rng.uniform(math.log(lam_lo_aa), math.log(lam_hi_aa), n_lines)) * ANGSTROM
+    nu = C_LIGHT / lam
+    order = np.argsort(-nu, kind="stable")
+    return _contig(nu[order], np.float64)
+
+
+def tau_log_uniform(rng, n_shells, n_lines, lo_dex=-3.0, hi_dex=3.0):
+    return _contig(10.0 ** rng.uniform(lo_dex, hi_dex, size=(n_shells, n_lines)), np.float64)
+
+
+def tau_log_normal(rng, n_shells, n_lines, mu=math.log(0.1), sigma=3.0, clip=1.0e6):
+    t = np.exp(rng.normal(mu, sigma, size=(n_shells, n_lines)))
+    return _contig(np.clip(t, 0.0, clip), np.float64)
+
+
+def config1(seed: int = 0, n_packets: int = 10_000) -> Workload:
+    """Scatter mode, 20 shells 11000-20000 km/s at 13 d, 2000 lines
+    log-uniform in 3000-10000 A, tau log-uniform in [1e-3, 1e3], T_i = 1e4 K."""
+    rng = np.random.default_rng(seed)
+    v, t, n_e = shells(20, 11000.0, 20000.0, 13.0)
+    nu = log_uniform_lines(rng, 2000, 3000.0, 10000.0)
+    tau = tau_log_uniform(rng, 20, 2000)
+    m = Model(v_bounds=v, t_exp=t, n_e=n_e, line_nu=nu, tau_sobolev=tau, seed=seed)
+    return Workload("scatter-20shell-2000line", m, T_inner=10000.0, n_packets=n_packets,
+                    n_iterations=1)
+
+
+def config2_model(rng, n_shells=20, n_lines=300_000, seed=0, v_lo=10000.0, v_hi=25000.0):
+    v, t, n_e = shells(n_shells, v_lo, v_hi, 13.0)
+    nu = log_uniform_lines(rng, n_lines, 500.0, 20000.0)
+    tau = tau_log_normal(rng, n_shells, n_lines)
+    return Model(v_bounds=v, t_exp=t, n_e=n_e, line_nu=nu, tau_sobolev=tau, seed=seed)
+
+
+def config2(seed: int = 0, n_lines: int = 300_000, n_packets: int = 1_000_000,
+            n_iterations: int = 10) -> Workload:
+    """Paper-scale scatter model: 20 shells 10000-25000 km/s, 3e5 lines
+    log-uniform in 500-20000 A, tau log-normal (ln 0.1, 3) clipped to 1e6,
+    T_i = 9000 K, 1e6 packets, 10 iterations with the T_i update."""
+    rng = np.random.default_rng(seed)
+    m = config2_model(rng, 20, n_lines, seed)
+    return Workload("scatter-20shell-300kline", m, T_inner=9000.0, n_packets=n_packets,
+                    n_iterations=n_iterations)
+
+
+def synthetic_atom(rng, n_ions=30, n_levels_per_ion=40, n_lines=20_000):
+    """Synthetic downbranch atom: per ion, level energies (in frequency units)
+    0 and sorted U(0, c/500A); n_lines distinct (ion, lower<upper) pairs drawn
+    without replacement; A_ul log-uniform in 1e5-1e9 s^-1.  Emission
+    probabilities of an upper level are proportional to A_ul * nu_ul over its
+    downward lines.  Returns lines sorted by non-increasing frequency."""
+    nl = n_levels_per_ion
+    e = np.zeros((n_ions, nl))
+    for i in range(n_ions):
+        e[i, 1:] = np.sort(rng.uniform(0.0, C_LIGHT / (500.0 * ANGSTROM), nl - 1))
+    pairs = [(i, lo, up) for i in range(n_ions) for up in range(nl) for lo in range(up)]
+    pick = rng.choice(len(pairs), size=n_lines, replace=False)
+    ion = np.array([pairs[p][0] for p in pick])
+    lower = np.array([pairs[p][1] for p in pick])
+    upper = np.array([pairs[p][2] for p in pick])
+    nu = e[ion, upper] - e[ion, lower]
+    a_ul = 10.0 ** rng.uniform(5.0, 9.0, n_lines)
+    order = np.argsort(-nu, kind="stable")
+    nu, ion, upper, a_ul = nu[order], ion[order], upper[order], a_ul[order]
+    up_global = (ion * nl + upper).astype(np.int32)
+    n_levels = n_ions * nl
+    # CSR rows over upper levels, entries in line-index order
+    counts = np.bincount(up_global, minlength=n_levels)
+    level_ptr = np.zeros(n_levels + 1, dtype=np.int64)
+    level_ptr[1:] = np.cumsum(counts)
+    em_line = np.argsort(up_global, kind="stable").astype(np.int32)
+    weight = a_ul[em_line] * nu[em_line]
+    em_cum = np.zeros(n_lines, dtype=np.float64)
+    for lev in range(n_levels):
+        a, b = level_ptr[lev], level_ptr[lev + 1]
+        if b > a:
+            c = np.cumsum(weight[a:b])
+            em_cum[a:b] = c / c[-1]
+            em_cum[b - 1] = 1.0
+    return dict(line_nu=_contig(nu, np.float64), line_upper=_contig(up_global, np.int32),
+                n_levels=int(n_levels), level_ptr=_contig(level_ptr, np.int64),
+                em_line=_contig(em_line, np.int32), em_cum=_contig(em_cum, np.float64))
+
+
+def config3(seed: int = 0, n_packets: int = 500_000, n_lines: int = 20_000,
+            n_shells: int = 30) -> Workload:
+    """Downbranch mode: 30 ions x 40 levels, 2e4 lines, 30 shells over
+    10000-25000 km/s at 13 d, tau log-normal as config 2, T_i = 9000 K."""
+    rng = np.random.default_rng(seed)
+    v, t, n_e = shells(n_shells, 10000.0, 25000.0, 13.0)
+    atom = synthetic_atom(rng, 30, 40, n_lines)
+    tau = tau_log_normal(rng, n_shells, n_lines)
+    m = Model(v_bounds=v, t_exp=t, n_e=n_e, tau_sobolev=tau, line_mode=DOWNBRANCH,
+              seed=seed, **atom)
+    return Workload("downbranch-30shell-20kline", m, T_inner=9000.0, n_packets=n_packets,
+                    n_iterations=1)
+
+
+def config4_model(i: int) -> Workload:
+    """Model i of the batched mix: S ~ U{10..100}, L log-uniform in 1e4-3e5,
+    N log-uniform in 1e5-1e6, otherwise as config 2; Philox seed i."""
+    rng = np.random.default_rng(i)
+    S = int(rng.integers(10, 101))
+    L = int(round(math.exp(rng.uniform(math.log(1e4), math.log(3e5)))))
+    N = int(round(math.exp(rng.uniform(math.log(1e5), math.log(1e6)))))
+    m = config2_model(rng, S, L, seed=i)
+    return Workload(f"batch-model-{i}", m, T_inner=9000.0, n_packets=N, n_iterations=1)
+
+
+def config5_requests(duration_s: float = 60.0, rate_hz: float = 20.0, seed: int = 5):
+    """Poisson arrivals; request j is a config-4 style model from seed 1000+j
+    with U{1..10} iterations.  Returns (arrival_time, seed, n_iterations)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    j = 0
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t >= duration_s:
+            break
+        out.append((t, 1000 + j, int(rng.integers(1, 11))))
+        j += 1
+    return out
+
+
+def small_model(seed: int = 0, n_shells: int = 5, n_lines: int = 300, v_lo=11000.0,
+                v_hi=20000.0, lam=(3000.0, 10000.0), tau="loguniform", rho_inner=1e-13,
+                t_exp_days=13.0) -> Model:
+    """Small scatter-mode model for tests: same recipe, any size."""
+    rng = np.random.default_rng(seed)
+    v, t, n_e = shells(n_shells, v_lo, v_hi, t_exp_days, rho_inner)
+    nu = log_uniform_lines(rng, n_lines, lam[0], lam[1])
+    if tau == "loguniform":
+        ts = tau_log_uniform(rng, n_shells, n_lines)
+    else:
+        ts = tau_log_normal(rng, n_shells, n_lines)
+    return Model(v_bounds=v, t_exp=t, n_e=n_e, line_nu=nu, tau_sobolev=ts, seed=seed)
+
+
+def small_downbranch_model(seed: int = 0, n_shells: int = 6, n_ions: int = 4,
+                           n_levels_per_ion: int = 12, n_lines: int = 200) -> Model:
+    rng = np.random.default_rng(seed)
+    v, t, n_e = shells(n_shells, 10000.0, 25000.0, 13.0)
+    atom = synthetic_atom(rng, n_ions, n_levels_per_ion, n_lines)
+    tau = tau_log_normal(rng, n_shells, n_lines)
+    return Model(v_bounds=v, t_exp=t, n_e=n_e, tau_sobolev=tau, line_mode=DOWNBRANCH,
+                 seed=seed, **atom)

@@ -1,0 +1,695 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: numpy's
+Philox (an independent implementation of the published generator), closed
+forms, quadrature, brute force on tiny inputs, invariants the paper states and
+special cases.  None of these tests needs a GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+from oracle import oracle as O
+from paper_1401_5469_amd import workloads as W
+
+C_LIGHT = 2.99792458e10
+H = 6.62607015e-27
+KB = 1.380649e-16
+SIGMA_SB = 5.670374419e-5
+SIGMA_T = 6.6524587321e-25
+
+
+def _model(v_kms, n_e, line_nu=None, tau=None, t_days=13.0, seed=1, **kw):
+    v = np.asarray(v_kms, dtype=np.float64) * 1e5
+    S = v.shape[0] - 1
+    if line_nu is None:
+        line_nu = np.zeros(0)
+        tau = np.zeros((S, 0))
+    return W.Model(v_bounds=v, t_exp=t_days * 86400.0, n_e=np.asarray(n_e, dtype=np.float64),
+                   line_nu=np.asarray(line_nu, dtype=np.float64),
+                   tau_sobolev=np.ascontiguousarray(tau, dtype=np.float64), seed=seed, **kw)
+
+
+# --------------------------------------------------------------------------
+# random numbers
+# --------------------------------------------------------------------------
+def _numpy_philox_block(ctr, key):
+    """numpy's Philox4x64-10 increments its 256-bit counter before each
+    block, so the block for counter c is its first output when started at
+    c - 1."""
+    c = sum(int(ctr[i]) << (64 * i) for i in range(4))
+    c = (c - 1) % (1 << 256)
+    cm1 = np.array([(c >> (64 * i)) & ((1 << 64) - 1) for i in range(4)], dtype=np.uint64)
+    bg = np.random.Philox(counter=cm1, key=np.array(key, dtype=np.uint64))
+    return bg.random_raw(4)
+
+
+def test_philox_matches_numpy():
+    rng = np.random.default_rng(123)
+    cases = [([0, 0, 0, 0], [0, 0]), ([2**64 - 1] * 4, [2**64 - 1] * 2), ([5, 7, 0, 0], [0, 0])]
+    for _ in range(40):
+        cases.append((rng.integers(0, 2**64, size=4, dtype=np.uint64).tolist(),
+                      rng.integers(0, 2**64, size=2, dtype=np.uint64).tolist()))
+    for ctr, key in cases:
+        mine = O.philox4x64_10(ctr, key)
+        ref = _numpy_philox_block(ctr, key)
+        assert [int(x) for x in mine] == [int(x) for x in ref], (ctr, key)
+
+
+def test_uniform_is_open_interval_and_exact():
+    assert O.uniform(0) == 2.0**-53
+    assert O.uniform(2**64 - 1) == 1.0 - 2.0**-53
+    w = 0x123456789ABCDEF0
+    assert O.uniform(w) == ((w >> 12) + 0.5) / 2.0**52
+
+
+# --------------------------------------------------------------------------
+# injection (section 2.4)
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def thin_injection():
+    m = _model([11000, 14000, 17000, 20000], [0.0, 0.0, 0.0])
+    N = 200_000
+    r = O.run(m, 10000.0, N, want_jblue=False)
+    return m, r
+
+
+def test_injection_direction_is_sqrt_uniform(thin_injection):
+    _, r = thin_injection
+    mu0 = r["packets"]["mu0"]
+    assert mu0.min() > 0.0 and mu0.max() < 1.0
+    # zero limb darkening: P(mu < m) = m^2
+    res = stats.kstest(mu0, lambda m: m * m)
+    assert res.pvalue > 1e-3
+
+
+def _planck_cdf_table():
+    xs = np.concatenate([np.linspace(0.0, 1.0, 101)[1:], np.linspace(1.0, 40.0, 1200)[1:]])
+    f = lambda t: t**3 / math.expm1(t) if t > 0 else 0.0
+    cdf = []
+    acc, prev = 0.0, 0.0
+    for x in xs:
+        acc += integrate.quad(f, prev, x, epsabs=0, epsrel=1e-12)[0]
+        cdf.append(acc)
+        prev = x
+    total = math.pi**4 / 15.0
+    return np.concatenate([[0.0], xs]), np.concatenate([[0.0], np.array(cdf) / total])
+
+
+def test_injection_frequency_is_planck(thin_injection):
+    _, r = thin_injection
+    x = H * r["packets"]["nu_cmf0"] / (KB * 10000.0)
+    # exact moments of the Planck distribution in x = h nu / k T
+    z4 = math.pi**4 / 90.0
+    z5 = 1.0369277551433699
+    z6 = math.pi**6 / 945.0
+    m1 = 4.0 * z5 / z4
+    m2 = 20.0 * z6 / z4
+    sd = math.sqrt(m2 - m1 * m1)
+    assert abs(x.mean() - m1) < 4.5 * sd / math.sqrt(x.size)
+    assert abs((x * x).mean() - m2) < 4.5 * math.sqrt(np.var(x * x) / x.size)
+    xs, cdf = _planck_cdf_table()
+    res = stats.kstest(x, lambda v: np.interp(v, xs, cdf))
+    assert res.pvalue > 1e-3
+
+
+def test_injection_frame_transform_and_energy(thin_injection):
+    m, r = thin_injection
+    p = r["packets"]
+    ct = C_LIGHT * m.t_exp
+    r_in = m.v_bounds[0] * m.t_exp
+    D0 = 1.0 - p["mu0"] * r_in / ct
+    # nothing interacts in a thin model, so the escaping lab frequency is the
+    # injected one: nu_lab = nu_cmf / D (inverse of the first-order transform)
+    np.testing.assert_allclose(p["nu"], p["nu_cmf0"] / D0, rtol=1e-15, atol=0)
+    # every packet is injected with comoving energy 1/N (lab energy is then
+    # constant along the free flight)
+    np.testing.assert_allclose(p["energy"] * D0, 1.0 / p.size, rtol=1e-15)
+
+
+def test_next_line_is_closest_redward_line():
+    m = W.small_model(seed=3, n_shells=3, n_lines=400)
+    for pid in range(50):
+        s = O.inject(m, 10000.0, 50, 0, pid)
+        below = np.nonzero(m.line_nu < s["nu_cmf"])[0]
+        expect = below[0] if below.size else m.n_lines
+        assert s["next_line"] == expect
+
+
+# --------------------------------------------------------------------------
+# geometry (section 2.6)
+# --------------------------------------------------------------------------
+def _brute_distance(r, mu, r_in, r_out):
+    """First s > 0 where |x(s)| leaves (r_in, r_out), by scanning then
+    bisection on the squared radius r^2 + s^2 + 2 r s mu."""
+    rad = lambda s: math.sqrt(r * r + s * s + 2.0 * r * s * mu)
+    outside = lambda s: rad(s) <= r_in or rad(s) >= r_out
+    smax = 2.5 * r_out
+    n = 200_000
+    prev = 0.0
+    for i in range(1, n + 1):
+        s = smax * i / n
+        if outside(s):
+            lo, hi = prev, s
+            for _ in range(200):
+                mid = 0.5 * (lo + hi)
+                if outside(mid):
+                    hi = mid
+                else:
+                    lo = mid
+            return 0.5 * (lo + hi)
+        prev = s
+    raise AssertionError("no exit found")
+
+
+def test_distance_to_shell_bruteforce():
+    rng = np.random.default_rng(7)
+    r_in, r_out = 1.0e15, 1.6e15
+    for _ in range(40):
+        r = rng.uniform(r_in * 1.0001, r_out * 0.9999)
+        mu = rng.uniform(-1.0, 1.0)
+        b = r * r * (1 - mu * mu)
+        if abs(b - r_in * r_in) < 1e-3 * r_in * r_in:
+            continue  # keep clear of grazing rays
+        d = O.distance_to_shell(r, mu, r_in, r_out)
+        assert d == pytest.approx(_brute_distance(r, mu, r_in, r_out), rel=1e-9, abs=0)
+
+
+# --------------------------------------------------------------------------
+# optically thin model (no electrons, tau_S = 0): closed-form chords
+# --------------------------------------------------------------------------
+def test_thin_model_chords_and_jblue():
+    rng = np.random.default_rng(11)
+    v = [11000, 12500, 15000, 17000, 20000]
+    S = 4
+    nu_lines = np.sort(C_LIGHT / (np.exp(rng.uniform(np.log(3000), np.log(9000), 60)) * 1e-8))[::-1]
+    m = _model(v, np.zeros(S), line_nu=nu_lines.copy(), tau=np.zeros((S, 60)))
+    N = 1500
+    r = O.run(m, 10000.0, N)
+    p = r["packets"]
+    assert r["counters"]["escaped"] == N
+    assert np.all(p["status"] == O.ESCAPED)
+    assert r["counters"]["line_events"] == 0 and r["counters"]["escatters"] == 0
+
+    ct = C_LIGHT * m.t_exp
+    radii = m.v_bounds * m.t_exp
+    r0 = radii[0]
+    J = np.zeros(S)
+    NB = np.zeros(S)
+    JB = np.zeros((S, 60))
+    n_pass = 0
+    for i in range(N):
+        mu0, nu_lab, e_lab = p["mu0"][i], p["nu"][i], p["energy"][i]
+        p2 = r0 * r0 * (1.0 - mu0 * mu0)
+        s = np.sqrt(radii**2 - p2) - r0 * mu0  # chord parameter of every sphere
+        s[0] = 0.0
+        for j in range(S):
+            D = 1.0 - (r0 * mu0 + s[j]) / ct  # r mu grows by the path length
+            e_cmf = e_lab * D
+            J[j] += e_cmf * (s[j + 1] - s[j]) * D
+            NB[j] += e_cmf * nu_lab * D * (s[j + 1] - s[j]) * D
+        # resonance with line k where nu_lab (1 - (r0 mu0 + s)/ct) = nu_k
+        sk = ct * (1.0 - nu_lines / nu_lab) - r0 * mu0
+        for k in np.nonzero((sk > 0) & (sk < s[S]))[0]:
+            j = np.searchsorted(s, sk[k], side="right") - 1
+            JB[j, k] += e_lab * nu_lines[k] / nu_lab**2
+            n_pass += 1
+    np.testing.assert_allclose(r["J_raw"], J, rtol=1e-10)
+    np.testing.assert_allclose(r["nubar_raw"], NB, rtol=1e-10)
+    np.testing.assert_allclose(r["jblue_raw"], JB, rtol=1e-9, atol=1e-14 * JB.max())
+    # with tau_S = 0 every line in the swept frequency range is passed once
+    assert r["counters"]["line_passes"] == n_pass
+
+
+# --------------------------------------------------------------------------
+# one shell, one line: P(interact) = 1 - exp(-tau_S)
+# --------------------------------------------------------------------------
+def test_single_line_interaction_probability():
+    tau = 0.7
+    nu_line = C_LIGHT / 5500e-8
+    m = _model([11000, 20000], [0.0], line_nu=[nu_line], tau=[[tau]])
+    N = 200_000
+    r = O.run(m, 10000.0, N)
+    p = r["packets"]
+    ct = C_LIGHT * m.t_exp
+    r0, r1 = m.v_bounds * m.t_exp
+    s_exit = np.sqrt(r1 * r1 - r0 * r0 * (1 - p["mu0"] ** 2)) - r0 * p["mu0"]
+    nu_cmf_exit = p["nu_cmf0"] / (1 - p["mu0"] * r0 / ct) * (1 - (r0 * p["mu0"] + s_exit) / ct)
+    crosses = (p["nu_cmf0"] > nu_line) & (nu_cmf_exit < nu_line)
+    hit = p["n_line"] >= 1
+    assert not np.any(hit & ~crosses)
+    assert np.all(p["n_line"] <= 1)
+    nc, ni = int(crosses.sum()), int(hit.sum())
+    prob = 1.0 - math.exp(-tau)
+    assert nc > 2000
+    assert abs(ni - nc * prob) < 4.5 * math.sqrt(nc * prob * (1 - prob))
+
+
+# --------------------------------------------------------------------------
+# pure Thomson: analytic probability of escaping without scattering
+# --------------------------------------------------------------------------
+def _p0_thomson(radii, n_e, beta_scale):
+    r0 = radii[0]
+
+    def integrand(mu):
+        p2 = r0 * r0 * (1 - mu * mu)
+        s = np.sqrt(radii**2 - p2) - r0 * mu
+        s[0] = 0.0
+        tau = 0.0
+        for j in range(len(n_e)):
+            D = 1.0 - (r0 * mu + s[j]) / beta_scale
+            tau += SIGMA_T * n_e[j] * D * (s[j + 1] - s[j])
+        return 2.0 * mu * math.exp(-tau)
+
+    return integrate.quad(integrand, 0.0, 1.0, epsabs=1e-14, epsrel=1e-13, limit=200)[0]
+
+
+@pytest.mark.parametrize("shells", [1, 3])
+def test_pure_thomson_zero_scatter_escape(shells):
+    t_exp = 13.0 * 86400.0
+    if shells == 1:
+        v = [11000.0, 12100.0]
+        r_in = v[0] * 1e5 * t_exp
+        n_e = [5.0 / (SIGMA_T * r_in)]  # kappa r_in = 5 at rest
+    else:
+        v = [11000.0, 11800.0, 13000.0, 15000.0]
+        r_in = v[0] * 1e5 * t_exp
+        n_e = [4.0 / (SIGMA_T * r_in), 2.0 / (SIGMA_T * r_in), 0.5 / (SIGMA_T * r_in)]
+    m = _model(v, n_e)
+    N = 100_000
+    r = O.run(m, 10000.0, N, want_jblue=False)
+    p = r["packets"]
+    direct = (p["status"] == O.ESCAPED) & (p["n_escatter"] == 0)
+    P0 = _p0_thomson(m.v_bounds * m.t_exp, n_e, C_LIGHT * m.t_exp)
+    assert 0.05 < P0 < 0.95
+    k = int(direct.sum())
+    assert abs(k - N * P0) < 4.5 * math.sqrt(N * P0 * (1 - P0))
+    assert r["counters"]["escaped"] + r["counters"]["reabsorbed"] == N
+
+
+# --------------------------------------------------------------------------
+# invariants along traced histories (sections 2.5, 2.6)
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def traced():
+    m = W.small_model(seed=5, n_shells=5, n_lines=300)
+    r = O.run(m, 10000.0, 400, trace_cap=400_000)
+    assert r["trace_len"] <= 400_000
+    return m, r
+
+
+def test_comoving_energy_conserved(traced):
+    m, r = traced
+    ct = C_LIGHT * m.t_exp
+    ev = r["trace"]
+    sel = (ev["kind"] == O.EV_ESCATTER) | (ev["kind"] == O.EV_LINE)
+    e = ev[sel]
+    assert e.size > 1000
+    ein = e["e_in"] * (1 - e["mu_in"] * e["r"] / ct)
+    eout = e["e_out"] * (1 - e["mu_out"] * e["r"] / ct)
+    np.testing.assert_allclose(eout, ein, rtol=1e-14)
+    # crossings change nothing in the lab frame
+    x = ev[(ev["kind"] == O.EV_SHELL_IN) | (ev["kind"] == O.EV_SHELL_OUT)]
+    assert np.all(x["e_in"] == x["e_out"]) and np.all(x["nu_in"] == x["nu_out"])
+
+
+def test_line_event_at_resonance_and_emission_frequency(traced):
+    m, r = traced
+    ct = C_LIGHT * m.t_exp
+    e = r["trace"][r["trace"]["kind"] == O.EV_LINE]
+    nu_cmf_in = e["nu_in"] * (1 - e["mu_in"] * e["r"] / ct)
+    np.testing.assert_allclose(nu_cmf_in, m.line_nu[e["line"]], rtol=1e-12)
+    nu_cmf_out = e["nu_out"] * (1 - e["mu_out"] * e["r"] / ct)
+    np.testing.assert_allclose(nu_cmf_out, m.line_nu[e["emit_line"]], rtol=1e-14)
+    assert np.all(e["line"] == e["emit_line"])  # scatter mode
+
+
+def test_scatter_mode_comoving_frequency_never_increases(traced):
+    m, r = traced
+    ct = C_LIGHT * m.t_exp
+    ev = r["trace"]
+    for pid in np.unique(ev["packet_id"])[:200]:
+        h = ev[ev["packet_id"] == pid]
+        seq = []
+        for e in h:
+            seq.append(e["nu_in"] * (1 - e["mu_in"] * e["r"] / ct))
+            seq.append(e["nu_out"] * (1 - e["mu_out"] * e["r"] / ct))
+        seq = np.array(seq[1:])  # skip the injection record's duplicate
+        assert np.all(np.diff(seq) <= 1e-12 * seq[:-1]), pid
+
+
+def test_histories_terminate_and_bookkeeping(traced):
+    m, r = traced
+    c = r["counters"]
+    assert c["escaped"] + c["reabsorbed"] + c["capped"] == 400
+    assert c["capped"] == 0
+    # every escaping packet lands in exactly one spectrum bin (incl. under/over)
+    assert r["spec_raw"].sum() == pytest.approx(r["L_raw"][0], rel=1e-13, abs=0)
+    p = r["packets"]
+    assert int(p["n_segments"].sum()) == c["segments"]
+    assert int(p["n_passes"].sum()) == c["line_passes"]
+    for a in ("J_raw", "nubar_raw", "jblue_raw", "spec_raw"):
+        assert np.all(r[a] >= 0.0)
+
+
+def test_event_cap_marks_packets_capped():
+    m = W.small_model(seed=5, n_shells=5, n_lines=300)
+    r = O.run(m, 10000.0, 300, max_segments=3)
+    p = r["packets"]
+    assert np.all(p["n_segments"] <= 3)
+    capped = p["status"] == O.CAPPED
+    assert capped.sum() == r["counters"]["capped"] > 0
+    assert r["L_raw"][2] > 0
+
+
+def test_unreached_lines_have_zero_jblue():
+    m = W.small_model(seed=2, n_shells=3, n_lines=100)
+    # prepend lines far bluer than any injected packet
+    blue = np.array([5e16, 4e16, 3e16])
+    m.line_nu = np.concatenate([blue, m.line_nu])
+    m.tau_sobolev = np.ascontiguousarray(np.concatenate([np.ones((3, 3)), m.tau_sobolev], axis=1))
+    r = O.run(m, 10000.0, 300)
+    assert np.all(r["jblue_raw"][:, :3] == 0.0)
+    assert r["jblue_raw"][:, 3:].sum() > 0.0
+
+
+def test_subsets_add_up_and_records_repeat():
+    m = W.small_model(seed=4, n_shells=4, n_lines=200)
+    full = O.run(m, 10000.0, 200, packet_ids=np.arange(200))
+    a = O.run(m, 10000.0, 200, packet_ids=np.arange(0, 200, 2))
+    b = O.run(m, 10000.0, 200, packet_ids=np.arange(1, 200, 2))
+    for k in ("J_raw", "nubar_raw", "jblue_raw", "spec_raw", "L_raw"):
+        np.testing.assert_allclose(a[k] + b[k], full[k], rtol=1e-13, atol=1e-300)
+    assert np.array_equal(full["packets"][::2], a["packets"])
+    assert np.array_equal(full["packets"][1::2], b["packets"])
+
+
+# --------------------------------------------------------------------------
+# downbranch (Table 1)
+# --------------------------------------------------------------------------
+def test_downbranch_single_channel_rows_equal_scatter():
+    m = W.small_model(seed=8, n_shells=4, n_lines=250)
+    L = m.n_lines
+    d = W.Model(**{**m.__dict__})
+    d.line_mode = W.DOWNBRANCH
+    d.line_upper = np.arange(L, dtype=np.int32)
+    d.n_levels = L
+    d.level_ptr = np.arange(L + 1, dtype=np.int64)
+    d.em_line = np.arange(L, dtype=np.int32)
+    d.em_cum = np.ones(L)
+    a = O.run(m, 10000.0, 300)
+    b = O.run(d, 10000.0, 300)
+    assert np.array_equal(a["packets"], b["packets"])
+    for k in ("J_raw", "nubar_raw", "jblue_raw", "spec_raw", "L_raw"):
+        assert np.array_equal(a[k], b[k])
+
+
+def _optical_downbranch_model(seed=9, n_lines=40, n_levels=5, tau=3.0):
+    """Lines in the optical (where the injected packets are), each tied to one
+    of a few upper levels whose emission rows carry random weights."""
+    rng = np.random.default_rng(seed)
+    nu = np.sort(np.exp(rng.uniform(np.log(4e14), np.log(9e14), n_lines)))[::-1].copy()
+    up = rng.integers(0, n_levels, n_lines).astype(np.int32)
+    em_line = np.argsort(up, kind="stable").astype(np.int32)
+    level_ptr = np.concatenate([[0], np.cumsum(np.bincount(up, minlength=n_levels))]).astype(np.int64)
+    w = rng.uniform(0.1, 1.0, n_lines)
+    em_cum = np.zeros(n_lines)
+    for lev in range(n_levels):
+        a, b = level_ptr[lev], level_ptr[lev + 1]
+        c = np.cumsum(w[a:b])
+        em_cum[a:b] = c / c[-1]
+        em_cum[b - 1] = 1.0
+    v, t, n_e = W.shells(6, 10000.0, 25000.0, 13.0)
+    return W.Model(v_bounds=v, t_exp=t, n_e=n_e, line_nu=nu,
+                   tau_sobolev=np.full((6, n_lines), tau), line_mode=W.DOWNBRANCH,
+                   line_upper=up, n_levels=n_levels, level_ptr=level_ptr, em_line=em_line,
+                   em_cum=em_cum, seed=seed)
+
+
+def test_downbranch_emission_follows_branching_probabilities():
+    m = _optical_downbranch_model()
+    r = O.run(m, 9000.0, 30_000, trace_cap=3_000_000)
+    assert r["trace_len"] <= 3_000_000
+    e = r["trace"][r["trace"]["kind"] == O.EV_LINE]
+    assert e.size > 20_000
+    up = m.line_upper[e["line"]]
+    tested = 0
+    for lev in np.unique(up):
+        a, b = m.level_ptr[lev], m.level_ptr[lev + 1]
+        row = m.em_line[a:b]
+        prob = np.diff(np.concatenate([[0.0], m.em_cum[a:b]]))
+        emitted = e["emit_line"][up == lev]
+        assert np.all(np.isin(emitted, row))
+        if b - a < 2 or emitted.size < 500:
+            continue
+        counts = np.array([(emitted == j).sum() for j in row])
+        exp = prob * emitted.size
+        keep = exp > 5
+        if keep.sum() < 2:
+            continue
+        obs, ex = counts[keep], exp[keep]
+        ex = ex * obs.sum() / ex.sum()
+        assert stats.chisquare(obs, ex).pvalue > 1e-4
+        tested += 1
+    assert tested >= 3
+
+
+# --------------------------------------------------------------------------
+# estimator normalisation and the radiation-field update (sections 2.7, 2.8)
+# --------------------------------------------------------------------------
+def _planck_moments(T):
+    f0 = integrate.quad(lambda x: x**3 / math.expm1(x), 0, 200, epsrel=1e-13)[0]
+    f1 = integrate.quad(lambda x: x**4 / math.expm1(x), 0, 200, epsrel=1e-13)[0]
+    mean_nu = (f1 / f0) * KB * T / H
+    integral_B = 2 * H / C_LIGHT**2 * (KB * T / H) ** 4 * f0  # int B_nu dnu
+    return mean_nu, integral_B
+
+
+def test_radiation_temperature_and_dilution_from_planck_field():
+    m = W.small_model(seed=1, n_shells=3, n_lines=10)
+    S = m.n_shells
+    raw = dict(J_raw=np.ones(S), nubar_raw=np.ones(S), jblue_raw=None,
+               spec_raw=np.zeros(m.n_bins + 2), L_raw=np.array([1.0, 0.0, 0.0]))
+    unit = O.finalise(m, raw, 10000.0)["J"]  # estimator per unit raw sum
+    T = 7300.0
+    mean_nu, intB = _planck_moments(T)
+    target_J = np.array([1.0, 0.5, 0.25]) * intB  # W B integrated: W = 1, 0.5, 0.25
+    raw["J_raw"] = target_J / unit
+    raw["nubar_raw"] = raw["J_raw"] * mean_nu
+    f = O.finalise(m, raw, 10000.0)
+    np.testing.assert_allclose(f["T_R"], T, rtol=1e-10)
+    np.testing.assert_allclose(f["W"], [1.0, 0.5, 0.25], rtol=1e-9)
+
+
+def test_empty_shell_keeps_previous_radiation_field():
+    m = W.small_model(seed=1, n_shells=3, n_lines=10)
+    raw = dict(J_raw=np.array([1.0, 0.0, 1.0]), nubar_raw=np.array([1e15, 0.0, 1e15]),
+               jblue_raw=None, spec_raw=np.zeros(m.n_bins + 2), L_raw=np.zeros(3))
+    f = O.finalise(m, raw, 10000.0, T_R_prev=[1.0, 2.0, 3.0], W_prev=[4.0, 5.0, 6.0])
+    assert f["T_R"][1] == 2.0 and f["W"][1] == 5.0
+
+
+def test_initial_radiation_field_is_geometric_dilution():
+    m = W.small_model(seed=1, n_shells=4, n_lines=10)
+    T_R, Wd = O.initial_radiation_field(m)
+    assert np.all(T_R == 10000.0)
+    r_c = 0.5 * (m.v_bounds[1:] + m.v_bounds[:-1]) * m.t_exp
+    r_i = m.v_bounds[0] * m.t_exp
+    # solid angle of the inner sphere seen from r_c, over 4 pi
+    theta = np.arcsin(r_i / r_c)
+    omega = 2 * math.pi * (1 - np.cos(theta))
+    np.testing.assert_allclose(Wd, omega / (4 * math.pi), rtol=1e-12)
+
+
+def test_inner_temperature_update_direction_and_fixed_point():
+    m = W.small_model(seed=1, n_shells=2, n_lines=10)
+    base = dict(J_raw=np.ones(2), nubar_raw=np.ones(2) * 1e15, jblue_raw=None,
+                spec_raw=np.zeros(m.n_bins + 2), L_raw=np.array([0.5, 0.5, 0.0]))
+    T = 10000.0
+    L_i = O.finalise(m, base, T)["L_inner"]
+    assert L_i == pytest.approx(4 * math.pi * (m.v_bounds[0] * m.t_exp) ** 2 * SIGMA_SB * T**4,
+                                rel=1e-14, abs=0)
+    L_emit = 0.5 * L_i
+    assert O.finalise(m, base, T, L_requested=L_emit)["T_inner_next"] == pytest.approx(T, rel=1e-15, abs=0)
+    assert O.finalise(m, base, T, L_requested=2 * L_emit)["T_inner_next"] > T
+    assert O.finalise(m, base, T, L_requested=0.5 * L_emit)["T_inner_next"] < T
+    # L_i ~ T^4: a 16x luminosity deficit is one doubling of T (undamped)
+    assert O.finalise(m, base, T, L_requested=16 * L_emit)["T_inner_next"] == pytest.approx(2 * T, rel=1e-14, abs=0)
+    assert O.finalise(m, base, T, L_requested=16 * L_emit, damping=0.5)["T_inner_next"] == \
+        pytest.approx(math.sqrt(2) * T, rel=1e-14, abs=0)
+
+
+# --------------------------------------------------------------------------
+# static limit: T_R -> T_inner and W -> volume-averaged geometric dilution
+# --------------------------------------------------------------------------
+def test_static_thin_limit_recovers_blackbody_dilution():
+    v = [10.0, 12.0, 15.0, 20.0, 30.0]  # km/s: v/c < 1e-4
+    m = _model(v, np.zeros(4), t_days=1000.0)
+    N = 200_000
+    T = 8000.0
+    r = O.run(m, T, N, want_jblue=False)
+    f = O.finalise(m, r, T)
+    np.testing.assert_allclose(f["T_R"], T, rtol=1e-2)
+    radii = m.v_bounds * m.t_exp
+    r_i = radii[0]
+    for j in range(4):
+        a, b = radii[j], radii[j + 1]
+        w = integrate.quad(lambda x: 0.5 * (1 - math.sqrt(1 - (r_i / x) ** 2)) * x * x, a, b)[0]
+        w /= (b**3 - a**3) / 3.0
+        assert f["W"][j] == pytest.approx(w, rel=1.5e-2, abs=0)
+
+
+# --------------------------------------------------------------------------
+# grid refinement (idea of section 4): splitting shells changes nothing but noise
+# --------------------------------------------------------------------------
+def test_grid_refinement_changes_only_noise():
+    m = W.small_model(seed=6, n_shells=4, n_lines=200, rho_inner=3e-14)
+    v2 = np.sort(np.concatenate([m.v_bounds, 0.5 * (m.v_bounds[1:] + m.v_bounds[:-1])]))
+    m2 = W.Model(v_bounds=v2, t_exp=m.t_exp, n_e=np.repeat(m.n_e, 2),
+                 line_nu=m.line_nu, tau_sobolev=np.ascontiguousarray(np.repeat(m.tau_sobolev, 2, axis=0)),
+                 seed=m.seed)
+    N = 4000
+    stats_a, stats_b = [], []
+    for batch in range(6):
+        ids = np.arange(batch * N, (batch + 1) * N)
+        ra = O.run(m, 10000.0, 6 * N, packet_ids=ids, want_jblue=False)
+        rb = O.run(m2, 10000.0, 6 * N, packet_ids=ids, iteration=1, want_jblue=False)
+        stats_a.append(np.concatenate([ra["J_raw"], [ra["L_raw"][0]]]))
+        jb = rb["J_raw"].reshape(4, 2).sum(axis=1)
+        stats_b.append(np.concatenate([jb, [rb["L_raw"][0]]]))
+    a, b = np.array(stats_a), np.array(stats_b)
+    diff = a.sum(0) - b.sum(0)
+    sigma = np.sqrt(6 * (a.var(0, ddof=1) + b.var(0, ddof=1)))
+    assert np.all(np.abs(diff) < 4.5 * sigma + 1e-300), (diff, sigma)
+
+
+# --------------------------------------------------------------------------
+# competition between Thomson and line opacity on the first flight (2.6)
+# --------------------------------------------------------------------------
+def test_line_versus_electron_on_first_flight():
+    """On the first flight the packet reaches the resonance at d_l if the
+    electron optical depth up to it is not used up, and then interacts with
+    probability 1 - exp(-tau_S): P(first event is the line) =
+    exp(-kappa d_l) (1 - exp(-tau_S)) with kappa = sigma_T n_e D."""
+    tau = 1.3
+    nu_line = C_LIGHT / 5200e-8
+    t_exp = 13.0 * 86400.0
+    r_in = 11000e5 * t_exp
+    n_e = 1.5 / (SIGMA_T * r_in)
+    m = _model([11000, 20000], [n_e], line_nu=[nu_line], tau=[[tau]])
+    N = 100_000
+    r = O.run(m, 10000.0, N, want_jblue=False, trace_cap=8 * N)
+    ev = r["trace"]
+    assert r["trace_len"] <= 8 * N
+    # first event after injection, per packet
+    first = {}
+    for i in np.nonzero(ev["kind"] != O.EV_INJECT)[0]:
+        pid = int(ev["packet_id"][i])
+        if pid not in first:
+            first[pid] = int(ev["kind"][i])
+    p = r["packets"]
+    ct = C_LIGHT * m.t_exp
+    r0, r1 = m.v_bounds * m.t_exp
+    D0 = 1 - p["mu0"] * r0 / ct
+    nu_lab = p["nu_cmf0"] / D0
+    d_l = (p["nu_cmf0"] - nu_line) * ct / nu_lab
+    d_s = np.sqrt(r1 * r1 - r0 * r0 * (1 - p["mu0"] ** 2)) - r0 * p["mu0"]
+    reach = (p["nu_cmf0"] > nu_line) & (d_l < d_s)
+    d_reach = np.where(reach, d_l, 0.0)
+    prob = np.where(reach, np.exp(-SIGMA_T * n_e * D0 * d_reach) * (1 - math.exp(-tau)), 0.0)
+    observed = np.array([first.get(i, -1) == O.EV_LINE for i in range(N)])
+    assert not np.any(observed & ~reach)
+    expect = prob.sum()
+    var = (prob * (1 - prob)).sum()
+    assert expect > 500
+    assert abs(observed.sum() - expect) < 4.5 * math.sqrt(var)
+
+
+def test_spectrum_bins_escaping_lab_frequency_and_energy(thin_injection):
+    m, r = thin_injection
+    p = r["packets"]
+    esc = p["status"] == O.ESCAPED
+    edges = np.linspace(m.nu_min, m.nu_max, m.n_bins + 1)
+    hist, _ = np.histogram(p["nu"][esc], bins=edges, weights=p["energy"][esc])
+    inside = (p["nu"] >= m.nu_min) & (p["nu"] < m.nu_max)
+    np.testing.assert_allclose(r["spec_raw"][: m.n_bins], hist, rtol=1e-9, atol=1e-18)
+    assert r["spec_raw"][m.n_bins] == pytest.approx(p["energy"][esc & (p["nu"] < m.nu_min)].sum(),
+                                                    rel=1e-12, abs=1e-300)
+    assert r["spec_raw"][m.n_bins + 1] == pytest.approx(
+        p["energy"][esc & (p["nu"] >= m.nu_max)].sum(), rel=1e-12, abs=1e-300)
+    assert r["L_raw"][0] == pytest.approx(p["energy"][esc].sum(), rel=1e-12, abs=0)
+    assert inside.sum() > 0.9 * esc.sum()
+
+
+def test_redirections_are_isotropic():
+    """Thomson and line scattering redraw mu = 2z - 1 (sections 2.5)."""
+    m = W.small_model(seed=12, n_shells=4, n_lines=200, rho_inner=3e-13)
+    r = O.run(m, 10000.0, 1500, trace_cap=2_000_000)
+    assert r["trace_len"] <= 2_000_000
+    ev = r["trace"]
+    for kind in (O.EV_ESCATTER, O.EV_LINE):
+        mu = ev["mu_out"][ev["kind"] == kind]
+        assert mu.size > 3000
+        assert stats.kstest(mu, "uniform", args=(-1.0, 2.0)).pvalue > 1e-3
+
+
+def test_first_interaction_along_a_line_forest():
+    """Optical depths of passed lines are used up one after another: on a
+    straight flight with no electrons the first interaction is with line j
+    with probability prod_{i<j} exp(-tau_i) (1 - exp(-tau_j))."""
+    rng = np.random.default_rng(21)
+    n = 12
+    nu = np.sort(np.exp(rng.uniform(np.log(5.48e14), np.log(5.52e14), n)))[::-1].copy()
+    tau = rng.uniform(0.05, 0.6, n)
+    m = _model([11000, 20000], [0.0], line_nu=nu, tau=tau[None, :])
+    N = 200_000
+    r = O.run(m, 10000.0, N, want_jblue=False, trace_cap=6 * N)
+    assert r["trace_len"] <= 6 * N
+    ev = r["trace"]
+    first_line = np.full(N, -1)
+    seen = np.zeros(N, dtype=bool)
+    for i in np.nonzero(ev["kind"] == O.EV_LINE)[0]:
+        pid = int(ev["packet_id"][i])
+        if not seen[pid]:
+            seen[pid] = True
+            first_line[pid] = int(ev["line"][i])
+    p = r["packets"]
+    ct = C_LIGHT * m.t_exp
+    r0, r1 = m.v_bounds * m.t_exp
+    D0 = 1 - p["mu0"] * r0 / ct
+    nu_lab = p["nu_cmf0"] / D0
+    d_s = np.sqrt(r1 * r1 - r0 * r0 * (1 - p["mu0"] ** 2)) - r0 * p["mu0"]
+    # packets injected bluer than every line whose first flight sweeps them all
+    sweeps_all = (p["nu_cmf0"] > nu[0]) & ((p["nu_cmf0"] - nu[-1]) * ct / nu_lab < d_s)
+    k = int(sweeps_all.sum())
+    assert k > 3000
+    surv = np.concatenate([[1.0], np.cumprod(np.exp(-tau))])
+    prob = np.concatenate([surv[:-1] * (1 - np.exp(-tau)), [surv[-1]]])
+    counts = np.bincount(np.where(first_line[sweeps_all] < 0, n, first_line[sweeps_all]),
+                         minlength=n + 1)
+    assert stats.chisquare(counts, prob * k).pvalue > 1e-4
+
+
+def test_jblue_counts_the_interacting_passage():
+    """READING: J_blue sums over every packet that comes into resonance with the
+    line, whether or not it then interacts.  One shell, one line, no
+    electrons: every crossing packet contributes E nu_line / nu^2 with its
+    injected lab quantities."""
+    nu_line = C_LIGHT / 5500e-8
+    m = _model([11000, 20000], [0.0], line_nu=[nu_line], tau=[[2.0]])
+    N = 50_000
+    r = O.run(m, 10000.0, N)
+    p = r["packets"]
+    ct = C_LIGHT * m.t_exp
+    r0, r1 = m.v_bounds * m.t_exp
+    D0 = 1 - p["mu0"] * r0 / ct
+    nu_lab = p["nu_cmf0"] / D0
+    e_lab = (1.0 / N) / D0
+    d_l = (p["nu_cmf0"] - nu_line) * ct / nu_lab
+    d_s = np.sqrt(r1 * r1 - r0 * r0 * (1 - p["mu0"] ** 2)) - r0 * p["mu0"]
+    crosses = (p["nu_cmf0"] > nu_line) & (d_l < d_s)
+    expect = (e_lab * nu_line / nu_lab**2)[crosses].sum()
+    assert (p["n_line"] > 0).sum() > 0.5 * crosses.sum()
+    assert r["jblue_raw"][0, 0] == pytest.approx(expect, rel=1e-12, abs=0)
