@@ -1,0 +1,174 @@
+/*
+ * smc.h -- C ABI of libsmc, Monte Carlo r-packet transport through
+ * homologously expanding spherical ejecta on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the indivisible energy-packet scheme of Kerzendorf & Sim
+ * (2014), "A spectral synthesis code for rapid modelling of supernovae":
+ * packets are injected at the inner boundary (section 2.4), propagate through
+ * shells with Thomson and Sobolev line opacity (sections 2.5, 2.6), and build
+ * the J, nu-bar and J_blue estimators (section 2.7) and the emergent spectrum
+ * (section 2.9); each iteration ends with the radiation-field and T_inner
+ * update (sections 2.7, 2.8).
+ *
+ * Conventions for every entry point
+ *   - Return value: SMC_OK (0) on success, a negative SMC_E* code otherwise;
+ *     smc_last_error() then describes the failure (thread-local string, valid
+ *     until the next call on the same thread).  On error nothing is written
+ *     to the caller's output buffers.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the context's GPU.  The caller owns every buffer it
+ *     passes; the library only borrows them for the duration of the call,
+ *     except the model workspace, which it borrows until smc_model_free().
+ *   - Streams are hipStream_t passed as void* (NULL = the null stream).
+ *     Launches are asynchronous on that stream; smc_read_* synchronise it.
+ *   - Units are CGS.  Packet energies are fractions of L_i * dt: each packet
+ *     carries comoving energy 1/N at injection.
+ *   - Calls on one model must not overlap; distinct models may run
+ *     concurrently on distinct streams.
+ */
+#ifndef SMC_H
+#define SMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SMC_OK 0
+#define SMC_EINVAL (-1)  /* invalid argument or model (ordering, sizes, signs, CSR) */
+#define SMC_ENOMEM (-2)  /* workspace too small, or over the admitted budget */
+#define SMC_EDEVICE (-3) /* HIP runtime error (text in smc_last_error) */
+#define SMC_EBUSY (-4)   /* the object is in use */
+
+#define SMC_SCATTER 0    /* resonance scattering (Table 1, "scatter") */
+#define SMC_DOWNBRANCH 1 /* macro atom without internal jumps (Table 1, "downbranch") */
+
+/* packet status */
+#define SMC_LIVE 0
+#define SMC_ESCAPED 1    /* left through the outer boundary (section 2.6) */
+#define SMC_REABSORBED 2 /* crossed the inner boundary (section 2.6) */
+#define SMC_CAPPED 3     /* reached max_segments flight segments */
+
+/* capability / iteration flags */
+#define SMC_F_JBLUE 1u   /* tally J_blue per line and shell ("detailed" rates, section 2.7) */
+#define SMC_F_PACKETS 2u /* write one smc_packet_out per packet (parity and debugging) */
+
+/* counters returned by smc_read_counters, in this order */
+#define SMC_C_SEGMENTS 0    /* flight segments (one per distance comparison) */
+#define SMC_C_LINE_PASSES 1 /* Sobolev resonances reached (J_blue contributions) */
+#define SMC_C_LINE_EVENTS 2 /* line interactions */
+#define SMC_C_ESCATTERS 3   /* Thomson scatterings */
+#define SMC_C_ESCAPED 4
+#define SMC_C_REABSORBED 5
+#define SMC_C_CAPPED 6
+#define SMC_C_CROSSINGS 7   /* shell-boundary crossings */
+#define SMC_N_COUNTERS 8
+
+typedef struct smc_ctx smc_ctx;
+typedef struct smc_model smc_model;
+
+/* Model description (section 2.1 shells, section 2.5 lines).  All arrays are
+ * host pointers read during smc_model_load only. */
+typedef struct {
+  int32_t n_shells;          /* S >= 1 */
+  const double* v_bounds;    /* [S+1] boundary velocities [cm/s], > 0, strictly increasing */
+  double t_exp;              /* time since explosion [s], > 0; radii are v * t_exp */
+  const double* n_e;         /* [S] free-electron density [cm^-3], >= 0 */
+  int64_t n_lines;           /* L >= 0 */
+  const double* line_nu;     /* [L] line frequencies [Hz], non-increasing */
+  const double* tau_sobolev; /* [S*L] Sobolev optical depth, shell-major (shell s at s*L), >= 0 */
+  int32_t line_mode;         /* SMC_SCATTER or SMC_DOWNBRANCH */
+  /* downbranch only (ignored for SMC_SCATTER): upper level of each line and,
+   * per level, the downward lines it may emit in with cumulative
+   * probabilities (CSR rows; the last entry of each used row is 1). */
+  const int32_t* line_upper; /* [L] in [0, n_levels) */
+  int32_t n_levels;
+  const int64_t* level_ptr;  /* [n_levels+1] row offsets into em_line / em_cum */
+  int64_t n_em;              /* level_ptr[n_levels] */
+  const int32_t* em_line;    /* [n_em] emitted line index in [0, L) */
+  const double* em_cum;      /* [n_em] cumulative probability, non-decreasing within a row */
+  /* emergent spectrum: n_bins bins linear in lab frequency over
+   * [nu_min, nu_max), plus underflow and overflow (section 2.9) */
+  double nu_min, nu_max;
+  int32_t n_bins;            /* 1 .. 8192 */
+  uint64_t seed;             /* key of the model's Philox4x64-10 streams */
+} smc_model_desc;
+
+/* One Monte Carlo iteration (section 2.8). */
+typedef struct {
+  uint64_t n_packets;        /* N: sets the packet energy 1/N and the id range [0, N) */
+  uint32_t iteration;        /* enters every packet's random-number counter */
+  uint32_t flags;            /* SMC_F_JBLUE | SMC_F_PACKETS, subset of the load flags */
+  double T_inner;            /* > 0: inner-boundary temperature [K]; <= 0: use the value
+                                the previous iteration's update left on the device */
+  double L_requested;        /* > 0: update T_inner toward this emergent luminosity [erg/s] */
+  double damping;            /* exponent scale of the T_inner update, in (0, 1] */
+  uint64_t max_segments;     /* flight segments before a packet is CAPPED (>= 1) */
+  const uint64_t* packet_ids;/* device [n_ids] subset of ids in [0, N), or NULL for all N */
+  uint64_t n_ids;
+} smc_iter_params;
+
+/* Per-packet record (SMC_F_PACKETS), in work-list order.  hash is a
+ * word-wise FNV-1a over (kind, shell, line, emitted line) of every event,
+ * with kind 1 = outward crossing, 2 = inward crossing, 3 = Thomson, 4 = line. */
+typedef struct {
+  uint64_t id;
+  int32_t status;            /* SMC_ESCAPED / SMC_REABSORBED / SMC_CAPPED */
+  int32_t shell;             /* S after escape, -1 after reabsorption */
+  double nu, energy, mu, r;  /* final lab-frame frequency, energy, direction, radius */
+  double mu0, nu_cmf0;       /* injection direction and comoving frequency */
+  uint64_t n_segments, n_escatter, n_line, n_passes;
+  uint64_t hash;
+  int64_t last_line;         /* last absorbing line, -1 if none */
+} smc_packet_out;
+
+/* Create a context on HIP device `hip_device`. */
+int smc_ctx_create(smc_ctx** out, int hip_device);
+int smc_ctx_destroy(smc_ctx* ctx);
+const char* smc_last_error(void);
+
+/* Device workspace a model needs for up to n_packets_max packets per
+ * iteration with the given capability flags.  Writes *bytes. */
+int smc_model_workspace_bytes(const smc_model_desc* desc, uint64_t n_packets_max,
+                              uint32_t flags, uint64_t* bytes);
+
+/* Validate the description, copy its arrays into the caller's device
+ * workspace (`ws_bytes` bytes at `d_workspace`, 256-byte aligned) and derive
+ * the shell geometry (radii r = v t_exp and volumes) on the device
+ * (section 2.1).  Synchronises `stream` before returning, so the host arrays
+ * may be released afterwards.  The radiation field starts at T_R = 10^4 K and
+ * geometric dilution at the shell centres (section 2.8). */
+int smc_model_load(smc_ctx* ctx, const smc_model_desc* desc, uint64_t n_packets_max,
+                   uint32_t flags, void* d_workspace, uint64_t ws_bytes, void* stream,
+                   smc_model** out);
+/* Release the handle; never frees the caller's workspace. */
+int smc_model_free(smc_model* model);
+
+/* Enqueue one iteration on `stream`: reset the tallies, inject and propagate
+ * every packet (sections 2.4-2.6, 2.9), normalise the estimators and update
+ * T_R, W and T_inner (sections 2.7, 2.8).  Asynchronous. */
+int smc_run_iteration(smc_model* model, const smc_iter_params* params, void* stream);
+
+/* Copy the normalised estimators of the last iteration to host buffers:
+ * J and nubar [S] (section 2.7), jblue [S*L] shell-major (NULL to skip;
+ * requires SMC_F_JBLUE), T_R and W [S].  Any pointer may be NULL. */
+int smc_read_estimators(smc_model* model, double* J, double* nubar, double* jblue,
+                        double* T_R, double* W, void* stream);
+
+/* Copy the spectrum L_nu [n_bins+2] in erg s^-1 Hz^-1 (bins, underflow,
+ * overflow) and six scalars: L_emitted, L_reabsorbed, L_capped, L_inner,
+ * T_inner used by the iteration and T_inner for the next one. */
+int smc_read_spectrum(smc_model* model, double* L_nu, double* scalars6, void* stream);
+
+/* Copy the SMC_N_COUNTERS event counters of the last iteration. */
+int smc_read_counters(smc_model* model, uint64_t* counters, void* stream);
+
+/* Copy the first n per-packet records of the last iteration
+ * (requires SMC_F_PACKETS in both the load and the iteration flags). */
+int smc_read_packets(smc_model* model, smc_packet_out* out, uint64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

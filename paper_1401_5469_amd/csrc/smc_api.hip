@@ -1,0 +1,423 @@
+// smc_api.hip -- host runtime behind the C ABI declared in include/smc.h:
+// validation, workspace layout, uploads, launch sequencing and read-back.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "../../include/smc.h"
+#include "smc_internal.h"
+
+struct smc_ctx {
+  int device;
+  int n_cu;
+  int max_blocks_per_cu;
+};
+
+struct smc_model {
+  smc_ctx* ctx;
+  smc::Layout lay;
+  smc::DevModel dev;
+  uint8_t* base;
+  uint64_t ws_bytes;
+  uint64_t n_packets_max;
+  uint32_t load_flags;
+  bool has_T;        // a previous iteration left a T_inner on the device
+  bool ran;          // at least one iteration ran
+  uint32_t last_flags;
+  uint64_t last_work;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return SMC_OK;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SMC_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                 \
+  do {                                      \
+    hipError_t e_ = (expr);                 \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr uint64_t kAlign = 256;
+constexpr int kMaxBins = 8192;
+constexpr int kMaxShells = 4096;
+
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int validate(const smc_model_desc* d) {
+  if (!d) return fail(SMC_EINVAL, "null model description");
+  if (d->n_shells < 1 || d->n_shells > kMaxShells)
+    return fail(SMC_EINVAL, "n_shells=%d outside [1, %d]", d->n_shells, kMaxShells);
+  if (d->n_lines < 0 || d->n_lines > INT32_MAX)
+    return fail(SMC_EINVAL, "n_lines=%lld outside [0, 2^31)", (long long)d->n_lines);
+  if (d->n_bins < 1 || d->n_bins > kMaxBins)
+    return fail(SMC_EINVAL, "n_bins=%d outside [1, %d]", d->n_bins, kMaxBins);
+  if (!d->v_bounds || !d->n_e) return fail(SMC_EINVAL, "null shell arrays");
+  if (d->n_lines > 0 && (!d->line_nu || !d->tau_sobolev)) return fail(SMC_EINVAL, "null line arrays");
+  if (!(d->t_exp > 0.0) || !isfinite(d->t_exp)) return fail(SMC_EINVAL, "t_exp must be > 0");
+  if (!(d->nu_max > d->nu_min) || !isfinite(d->nu_max) || !isfinite(d->nu_min))
+    return fail(SMC_EINVAL, "spectrum range must satisfy nu_min < nu_max");
+  for (int i = 0; i <= d->n_shells; ++i) {
+    if (!(d->v_bounds[i] > 0.0) || !isfinite(d->v_bounds[i]))
+      return fail(SMC_EINVAL, "v_bounds[%d] must be finite and > 0", i);
+    if (i > 0 && !(d->v_bounds[i] > d->v_bounds[i - 1]))
+      return fail(SMC_EINVAL, "v_bounds must be strictly increasing (index %d)", i);
+  }
+  if (!(d->v_bounds[d->n_shells] < 2.99792458e10))
+    return fail(SMC_EINVAL, "outer velocity must be below c");
+  for (int i = 0; i < d->n_shells; ++i)
+    if (!(d->n_e[i] >= 0.0) || !isfinite(d->n_e[i]))
+      return fail(SMC_EINVAL, "n_e[%d] must be finite and >= 0", i);
+  for (int64_t k = 0; k < d->n_lines; ++k) {
+    if (!(d->line_nu[k] > 0.0) || !isfinite(d->line_nu[k]))
+      return fail(SMC_EINVAL, "line_nu[%lld] must be finite and > 0", (long long)k);
+    if (k > 0 && !(d->line_nu[k] <= d->line_nu[k - 1]))
+      return fail(SMC_EINVAL, "line_nu must be non-increasing (index %lld)", (long long)k);
+  }
+  const int64_t n_tau = (int64_t)d->n_shells * d->n_lines;
+  for (int64_t i = 0; i < n_tau; ++i)
+    if (!(d->tau_sobolev[i] >= 0.0) || !isfinite(d->tau_sobolev[i]))
+      return fail(SMC_EINVAL, "tau_sobolev[%lld] must be finite and >= 0", (long long)i);
+  if (d->line_mode != SMC_SCATTER && d->line_mode != SMC_DOWNBRANCH)
+    return fail(SMC_EINVAL, "unknown line_mode %d", d->line_mode);
+  if (d->line_mode == SMC_DOWNBRANCH && d->n_lines > 0) {
+    if (!d->line_upper || !d->level_ptr || !d->em_line || !d->em_cum || d->n_levels < 1)
+      return fail(SMC_EINVAL, "downbranch mode needs line_upper, level_ptr, em_line, em_cum");
+    if (d->level_ptr[0] != 0 || d->level_ptr[d->n_levels] != d->n_em)
+      return fail(SMC_EINVAL, "level_ptr must run from 0 to n_em");
+    for (int32_t v = 0; v < d->n_levels; ++v)
+      if (d->level_ptr[v + 1] < d->level_ptr[v])
+        return fail(SMC_EINVAL, "level_ptr must be non-decreasing (level %d)", v);
+    for (int64_t j = 0; j < d->n_em; ++j) {
+      if (d->em_line[j] < 0 || d->em_line[j] >= d->n_lines)
+        return fail(SMC_EINVAL, "em_line[%lld] out of range", (long long)j);
+      if (!(d->em_cum[j] >= 0.0 && d->em_cum[j] <= 1.0))
+        return fail(SMC_EINVAL, "em_cum[%lld] must lie in [0, 1]", (long long)j);
+    }
+    for (int64_t k = 0; k < d->n_lines; ++k) {
+      const int32_t u = d->line_upper[k];
+      if (u < 0 || u >= d->n_levels)
+        return fail(SMC_EINVAL, "line_upper[%lld] out of range", (long long)k);
+      if (!(d->level_ptr[u + 1] > d->level_ptr[u]))
+        return fail(SMC_EINVAL, "upper level %d of line %lld has no emission row", u,
+                    (long long)k);
+    }
+  }
+  return SMC_OK;
+}
+
+smc::Layout layout_of(const smc_model_desc* d, uint64_t n_packets_max, uint32_t flags) {
+  smc::Layout l;
+  memset(&l, 0, sizeof l);
+  const uint64_t S = (uint64_t)d->n_shells, L = (uint64_t)d->n_lines;
+  const uint64_t NB = (uint64_t)d->n_bins + 2;
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t o = off;
+    off = align_up(off + (bytes ? bytes : 1));
+    return o;
+  };
+  l.r_bounds = take((S + 1) * 8);
+  l.v_bounds = take((S + 1) * 8);
+  l.n_e = take(S * 8);
+  l.volume = take(S * 8);
+  l.line_nu = take(L * 8);
+  l.tau = take(S * L * 8);
+  if (d->line_mode == SMC_DOWNBRANCH) {
+    l.line_upper = take(L * 4);
+    l.level_ptr = take(((uint64_t)d->n_levels + 1) * 8);
+    l.em_line = take((uint64_t)d->n_em * 4);
+    l.em_cum = take((uint64_t)d->n_em * 8);
+  }
+  l.raw = take((2 * S + NB) * 8);
+  l.lsum = take(4 * 8);
+  l.counters = take((SMC_N_COUNTERS + 1) * 8);
+  l.jblue = (flags & SMC_F_JBLUE) ? take(S * L * 8) : 0;
+  l.out_shell = take(6 * S * 8);
+  l.out_spec = take(NB * 8);
+  l.scalars = take(8 * 8);
+  l.packets = (flags & SMC_F_PACKETS) ? take(n_packets_max * sizeof(smc_packet_out)) : 0;
+  l.total = off;
+  return l;
+}
+
+int sync_copy_out(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (!dst || bytes == 0) return SMC_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  return SMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* smc_last_error(void) { return g_err.c_str(); }
+
+int smc_ctx_create(smc_ctx** out, int hip_device) {
+  if (!out) return fail(SMC_EINVAL, "null output pointer");
+  *out = nullptr;
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n), "hipGetDeviceCount");
+  if (hip_device < 0 || hip_device >= n)
+    return fail(SMC_EINVAL, "device %d outside [0, %d)", hip_device, n);
+  HIP_TRY(hipSetDevice(hip_device), "hipSetDevice");
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, hip_device), "hipGetDeviceProperties");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(SMC_EDEVICE, "libsmc is built for gfx950, device %d is %s", hip_device,
+                prop.gcnArchName);
+  smc_ctx* c = new (std::nothrow) smc_ctx;
+  if (!c) return fail(SMC_ENOMEM, "host allocation failed");
+  c->device = hip_device;
+  c->n_cu = prop.multiProcessorCount;
+  c->max_blocks_per_cu = 8;
+  *out = c;
+  return ok();
+}
+
+int smc_ctx_destroy(smc_ctx* ctx) {
+  delete ctx;
+  return ok();
+}
+
+int smc_model_workspace_bytes(const smc_model_desc* desc, uint64_t n_packets_max, uint32_t flags,
+                              uint64_t* bytes) {
+  if (!bytes) return fail(SMC_EINVAL, "null output pointer");
+  int rc = validate(desc);
+  if (rc) return rc;
+  *bytes = layout_of(desc, n_packets_max, flags).total;
+  return ok();
+}
+
+int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max, uint32_t flags,
+                   void* d_workspace, uint64_t ws_bytes, void* stream, smc_model** out) {
+  if (!ctx || !out) return fail(SMC_EINVAL, "null context or output pointer");
+  *out = nullptr;
+  if (flags & ~(SMC_F_JBLUE | SMC_F_PACKETS)) return fail(SMC_EINVAL, "unknown flags 0x%x", flags);
+  int rc = validate(d);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0)
+    return fail(SMC_EINVAL, "workspace must be a non-null, 256-byte aligned device pointer");
+  smc::Layout lay = layout_of(d, n_packets_max, flags);
+  if (ws_bytes < lay.total)
+    return fail(SMC_ENOMEM, "workspace of %llu bytes is smaller than the %llu needed",
+                (unsigned long long)ws_bytes, (unsigned long long)lay.total);
+  const size_t lds = sizeof(double) * (2 * (size_t)d->n_shells + (size_t)d->n_bins + 2);
+  if (lds > 64 * 1024)
+    return fail(SMC_EINVAL, "2*n_shells + n_bins + 2 = %zu tallies exceed the 64 KiB LDS budget",
+                lds / 8);
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* base = (uint8_t*)d_workspace;
+  const uint64_t S = (uint64_t)d->n_shells, L = (uint64_t)d->n_lines;
+
+  HIP_TRY(hipMemcpyAsync(base + lay.v_bounds, d->v_bounds, (S + 1) * 8, hipMemcpyHostToDevice, s),
+          "upload v_bounds");
+  HIP_TRY(hipMemcpyAsync(base + lay.n_e, d->n_e, S * 8, hipMemcpyHostToDevice, s), "upload n_e");
+  if (L > 0) {
+    HIP_TRY(hipMemcpyAsync(base + lay.line_nu, d->line_nu, L * 8, hipMemcpyHostToDevice, s),
+            "upload line_nu");
+    HIP_TRY(hipMemcpyAsync(base + lay.tau, d->tau_sobolev, S * L * 8, hipMemcpyHostToDevice, s),
+            "upload tau_sobolev");
+  }
+  if (d->line_mode == SMC_DOWNBRANCH && L > 0) {
+    HIP_TRY(hipMemcpyAsync(base + lay.line_upper, d->line_upper, L * 4, hipMemcpyHostToDevice, s),
+            "upload line_upper");
+    HIP_TRY(hipMemcpyAsync(base + lay.level_ptr, d->level_ptr, ((uint64_t)d->n_levels + 1) * 8,
+                           hipMemcpyHostToDevice, s),
+            "upload level_ptr");
+    HIP_TRY(hipMemcpyAsync(base + lay.em_line, d->em_line, (uint64_t)d->n_em * 4,
+                           hipMemcpyHostToDevice, s),
+            "upload em_line");
+    HIP_TRY(hipMemcpyAsync(base + lay.em_cum, d->em_cum, (uint64_t)d->n_em * 8,
+                           hipMemcpyHostToDevice, s),
+            "upload em_cum");
+  }
+
+  smc_model* m = new (std::nothrow) smc_model;
+  if (!m) return fail(SMC_ENOMEM, "host allocation failed");
+  memset(m, 0, sizeof *m);
+  m->ctx = ctx;
+  m->lay = lay;
+  m->base = base;
+  m->ws_bytes = ws_bytes;
+  m->n_packets_max = n_packets_max;
+  m->load_flags = flags;
+  smc::DevModel& dm = m->dev;
+  dm.S = d->n_shells;
+  dm.L = (int32_t)d->n_lines;
+  dm.n_bins = d->n_bins;
+  dm.mode = d->line_mode;
+  dm.t_exp = d->t_exp;
+  dm.ct = 2.99792458e10 * d->t_exp;
+  dm.nu_min = d->nu_min;
+  dm.nu_max = d->nu_max;
+  dm.seed = d->seed;
+  dm.r_bounds = (const double*)(base + lay.r_bounds);
+  dm.n_e = (const double*)(base + lay.n_e);
+  dm.volume = (const double*)(base + lay.volume);
+  dm.line_nu = (const double*)(base + lay.line_nu);
+  dm.tau = (const double*)(base + lay.tau);
+  if (d->line_mode == SMC_DOWNBRANCH) {
+    dm.line_upper = (const int32_t*)(base + lay.line_upper);
+    dm.level_ptr = (const int64_t*)(base + lay.level_ptr);
+    dm.em_line = (const int32_t*)(base + lay.em_line);
+    dm.em_cum = (const double*)(base + lay.em_cum);
+  }
+  dm.raw = (double*)(base + lay.raw);
+  dm.lsum = (double*)(base + lay.lsum);
+  dm.counters = (unsigned long long*)(base + lay.counters);
+  dm.jblue = (flags & SMC_F_JBLUE) ? (double*)(base + lay.jblue) : nullptr;
+  dm.out_shell = (double*)(base + lay.out_shell);
+  dm.out_spec = (double*)(base + lay.out_spec);
+  dm.scalars = (double*)(base + lay.scalars);
+  dm.packets = (flags & SMC_F_PACKETS) ? (void*)(base + lay.packets) : nullptr;
+
+  hipError_t e = smc::launch_geometry(dm, (const double*)(base + lay.v_bounds), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete m;
+    return hip_fail(e, "model set-up");
+  }
+  *out = m;
+  return ok();
+}
+
+int smc_model_free(smc_model* model) {
+  delete model;
+  return ok();
+}
+
+int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
+  if (!m || !p) return fail(SMC_EINVAL, "null model or parameters");
+  if (p->n_packets == 0) return fail(SMC_EINVAL, "n_packets must be >= 1");
+  if (p->flags & ~(SMC_F_JBLUE | SMC_F_PACKETS)) return fail(SMC_EINVAL, "unknown flags");
+  if ((p->flags & ~m->load_flags) != 0)
+    return fail(SMC_EINVAL, "iteration flags 0x%x exceed the model's load flags 0x%x", p->flags,
+                m->load_flags);
+  const uint64_t n_work = p->packet_ids ? p->n_ids : p->n_packets;
+  if (p->packet_ids == nullptr && p->n_ids != 0)
+    return fail(SMC_EINVAL, "n_ids given without packet_ids");
+  if ((p->flags & SMC_F_PACKETS) && n_work > m->n_packets_max)
+    return fail(SMC_ENOMEM, "%llu packet records exceed n_packets_max=%llu",
+                (unsigned long long)n_work, (unsigned long long)m->n_packets_max);
+  if (!(p->T_inner > 0.0) && !m->has_T)
+    return fail(SMC_EINVAL, "T_inner must be > 0 on the first iteration");
+  if (!isfinite(p->T_inner)) return fail(SMC_EINVAL, "T_inner must be finite");
+  if (p->L_requested > 0.0 && !(p->damping > 0.0 && p->damping <= 1.0))
+    return fail(SMC_EINVAL, "damping must lie in (0, 1]");
+  if (p->max_segments < 1) return fail(SMC_EINVAL, "max_segments must be >= 1");
+
+  HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  smc::DevIter it;
+  it.n_packets = p->n_packets;
+  it.n_work = n_work;
+  it.ids = p->packet_ids;
+  it.max_segments = p->max_segments;
+  it.iteration = p->iteration;
+  it.flags = p->flags;
+  it.T_param = p->T_inner;
+  it.L_requested = p->L_requested;
+  it.damping = p->damping;
+
+  HIP_TRY(smc::launch_reset(m->dev, it, s), "reset launch");
+  if (n_work > 0) {
+    const int block = smc::transport_block_threads();
+    uint64_t want = (n_work + block - 1) / block;
+    const uint64_t cap = (uint64_t)m->ctx->n_cu * (uint64_t)m->ctx->max_blocks_per_cu;
+    if (want > cap) want = cap;
+    HIP_TRY(smc::launch_transport(m->dev, it, (int)want, s), "transport launch");
+  }
+  HIP_TRY(smc::launch_finalise(m->dev, it, s), "finalise launch");
+  m->has_T = true;
+  m->ran = true;
+  m->last_flags = p->flags;
+  m->last_work = n_work;
+  return ok();
+}
+
+int smc_read_estimators(smc_model* m, double* J, double* nubar, double* jblue, double* T_R,
+                        double* W, void* stream) {
+  if (!m) return fail(SMC_EINVAL, "null model");
+  if (!m->ran) return fail(SMC_EINVAL, "no iteration has run");
+  if (jblue && !(m->last_flags & SMC_F_JBLUE))
+    return fail(SMC_EINVAL, "J_blue was not tallied in the last iteration");
+  HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t S = (size_t)m->dev.S, L = (size_t)m->dev.L;
+  int rc;
+  if ((rc = sync_copy_out(J, m->dev.out_shell, S * 8, s))) return rc;
+  if ((rc = sync_copy_out(nubar, m->dev.out_shell + S, S * 8, s))) return rc;
+  if ((rc = sync_copy_out(T_R, m->dev.out_shell + 2 * S, S * 8, s))) return rc;
+  if ((rc = sync_copy_out(W, m->dev.out_shell + 3 * S, S * 8, s))) return rc;
+  if ((rc = sync_copy_out(jblue, m->dev.jblue, S * L * 8, s))) return rc;
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return ok();
+}
+
+int smc_read_spectrum(smc_model* m, double* L_nu, double* scalars6, void* stream) {
+  if (!m) return fail(SMC_EINVAL, "null model");
+  if (!m->ran) return fail(SMC_EINVAL, "no iteration has run");
+  HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  if ((rc = sync_copy_out(L_nu, m->dev.out_spec, ((size_t)m->dev.n_bins + 2) * 8, s))) return rc;
+  if ((rc = sync_copy_out(scalars6, m->dev.scalars, 6 * 8, s))) return rc;
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return ok();
+}
+
+int smc_read_counters(smc_model* m, uint64_t* counters, void* stream) {
+  if (!m || !counters) return fail(SMC_EINVAL, "null model or output");
+  if (!m->ran) return fail(SMC_EINVAL, "no iteration has run");
+  HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = sync_copy_out(counters, m->dev.counters, SMC_N_COUNTERS * 8, s);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return ok();
+}
+
+int smc_read_packets(smc_model* m, smc_packet_out* out, uint64_t n, void* stream) {
+  if (!m || !out) return fail(SMC_EINVAL, "null model or output");
+  if (!m->ran) return fail(SMC_EINVAL, "no iteration has run");
+  if (!(m->last_flags & SMC_F_PACKETS))
+    return fail(SMC_EINVAL, "packet records were not written in the last iteration");
+  if (n > m->last_work)
+    return fail(SMC_EINVAL, "asked for %llu records, the last iteration ran %llu packets",
+                (unsigned long long)n, (unsigned long long)m->last_work);
+  HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = sync_copy_out(out, m->dev.packets, n * sizeof(smc_packet_out), s);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// smc_internal.h -- device-side model layout shared by the kernels and the
+// host runtime of libsmc (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smc {
+
+// Byte layout of one model inside the caller's workspace; every region is
+// 256-byte aligned.  Offsets are relative to the workspace base.
+struct Layout {
+  uint64_t r_bounds, n_e, volume, v_bounds;        // shells
+  uint64_t line_nu, tau;                            // lines
+  uint64_t line_upper, level_ptr, em_line, em_cum;  // downbranch tables
+  uint64_t raw;        // [2S + NB + 2] J_raw, nubar_raw, spectrum raw
+  uint64_t lsum;       // [4] escaped, reabsorbed, capped lab energy (+ pad)
+  uint64_t counters;   // [SMC_N_COUNTERS + 1] u64; the last one is the work queue
+  uint64_t jblue;      // [S*L] raw, normalised in place by the finaliser
+  uint64_t out_shell;  // [6S] J, nubar, T_R, W, jblue scale, pad
+  uint64_t out_spec;   // [NB + 2] L_nu
+  uint64_t scalars;    // [8] L_emitted, L_reabsorbed, L_capped, L_inner, T_used, T_next, ...
+  uint64_t packets;    // [n_packets_max] smc_packet_out
+  uint64_t total;
+};
+
+// Everything a kernel needs about one model and one iteration.
+struct DevModel {
+  int32_t S;
+  int32_t L;
+  int32_t n_bins;
+  int32_t mode;
+  double t_exp;
+  double ct;
+  double nu_min, nu_max;
+  uint64_t seed;
+  const double* r_bounds;  // [S+1] radii
+  const double* n_e;       // [S]
+  const double* volume;    // [S]
+  const double* line_nu;   // [L]
+  const double* tau;       // [S*L]
+  const int32_t* line_upper;
+  const int64_t* level_ptr;
+  const int32_t* em_line;
+  const double* em_cum;
+  double* raw;             // J_raw[S], nubar_raw[S], spec_raw[NB+2]
+  double* lsum;            // [4]
+  unsigned long long* counters;  // [SMC_N_COUNTERS], then the work-queue head
+  double* jblue;           // [S*L] or nullptr
+  double* out_shell;       // J, nubar, T_R, W, jblue scale, each [S]
+  double* out_spec;        // [NB+2]
+  double* scalars;         // [8]
+  void* packets;           // smc_packet_out records or nullptr
+};
+
+struct DevIter {
+  uint64_t n_packets;      // N (energy 1/N)
+  uint64_t n_work;         // packets in this launch
+  const uint64_t* ids;     // device ids or nullptr (= slot index)
+  uint64_t max_segments;
+  uint32_t iteration;
+  uint32_t flags;
+  double T_param;          // > 0 overrides the device-resident T_inner
+  double L_requested;
+  double damping;
+};
+
+// scalars[] slots
+enum { SC_L_EMITTED = 0, SC_L_REABSORBED = 1, SC_L_CAPPED = 2, SC_L_INNER = 3,
+       SC_T_USED = 4, SC_T_NEXT = 5 };
+
+// Host-side launchers implemented in smc_kernels.hip.
+hipError_t launch_geometry(const DevModel& m, const double* v_bounds, hipStream_t s);
+hipError_t launch_reset(const DevModel& m, const DevIter& it, hipStream_t s);
+hipError_t launch_transport(const DevModel& m, const DevIter& it, int grid, hipStream_t s);
+hipError_t launch_finalise(const DevModel& m, const DevIter& it, hipStream_t s);
+size_t transport_lds_bytes(const DevModel& m);
+int transport_block_threads();
+
+}  // namespace smc

@@ -1,0 +1,259 @@
+"""Python binding of libsmc (include/smc.h): argument marshalling only.
+
+Every step of the transport runs in the HIP library; this module allocates
+the device workspace as a torch uint8 tensor, passes torch's current HIP
+stream, and copies results into numpy arrays.  torch is imported before the
+library is loaded so that both share one HIP runtime.  There is no CPU
+fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsmc.so")
+
+SMC_OK, SMC_EINVAL, SMC_ENOMEM, SMC_EDEVICE, SMC_EBUSY = 0, -1, -2, -3, -4
+SCATTER, DOWNBRANCH = 0, 1
+LIVE, ESCAPED, REABSORBED, CAPPED = 0, 1, 2, 3
+F_JBLUE, F_PACKETS = 1, 2
+COUNTER_NAMES = ("segments", "line_passes", "line_events", "escatters", "escaped",
+                 "reabsorbed", "capped", "crossings")
+
+_dp = C.POINTER(C.c_double)
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+_u64p = C.POINTER(C.c_uint64)
+
+
+class smc_model_desc(C.Structure):
+    _fields_ = [("n_shells", C.c_int32), ("v_bounds", _dp), ("t_exp", C.c_double), ("n_e", _dp),
+                ("n_lines", C.c_int64), ("line_nu", _dp), ("tau_sobolev", _dp),
+                ("line_mode", C.c_int32), ("line_upper", _i32p), ("n_levels", C.c_int32),
+                ("level_ptr", _i64p), ("n_em", C.c_int64), ("em_line", _i32p), ("em_cum", _dp),
+                ("nu_min", C.c_double), ("nu_max", C.c_double), ("n_bins", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class smc_iter_params(C.Structure):
+    _fields_ = [("n_packets", C.c_uint64), ("iteration", C.c_uint32), ("flags", C.c_uint32),
+                ("T_inner", C.c_double), ("L_requested", C.c_double), ("damping", C.c_double),
+                ("max_segments", C.c_uint64), ("packet_ids", C.c_void_p), ("n_ids", C.c_uint64)]
+
+
+PACKET_DTYPE = np.dtype([("id", np.uint64), ("status", np.int32), ("shell", np.int32),
+                         ("nu", np.float64), ("energy", np.float64), ("mu", np.float64),
+                         ("r", np.float64), ("mu0", np.float64), ("nu_cmf0", np.float64),
+                         ("n_segments", np.uint64), ("n_escatter", np.uint64),
+                         ("n_line", np.uint64), ("n_passes", np.uint64), ("hash", np.uint64),
+                         ("last_line", np.int64)], align=True)
+
+EXPORTS = ("smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_model_workspace_bytes",
+           "smc_model_load", "smc_model_free", "smc_run_iteration", "smc_read_estimators",
+           "smc_read_spectrum", "smc_read_counters", "smc_read_packets")
+
+
+class SmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libsmc error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libsmc.so (after torch, so that both share torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the HIP runtime libsmc links against)
+
+    if not os.path.exists(path):
+        raise RuntimeError(f"libsmc.so is not built ({path}); run python -m paper_1401_5469_amd.build")
+    L = C.CDLL(path)
+    vp = C.c_void_p
+    L.smc_ctx_create.argtypes = [C.POINTER(vp), C.c_int]
+    L.smc_ctx_destroy.argtypes = [vp]
+    L.smc_last_error.restype = C.c_char_p
+    L.smc_model_workspace_bytes.argtypes = [C.POINTER(smc_model_desc), C.c_uint64, C.c_uint32,
+                                            C.POINTER(C.c_uint64)]
+    L.smc_model_load.argtypes = [vp, C.POINTER(smc_model_desc), C.c_uint64, C.c_uint32, vp,
+                                 C.c_uint64, vp, C.POINTER(vp)]
+    L.smc_model_free.argtypes = [vp]
+    L.smc_run_iteration.argtypes = [vp, C.POINTER(smc_iter_params), vp]
+    L.smc_read_estimators.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, vp]
+    L.smc_read_spectrum.argtypes = [vp, _dp, _dp, vp]
+    L.smc_read_counters.argtypes = [vp, _u64p, vp]
+    L.smc_read_packets.argtypes = [vp, vp, C.c_uint64, vp]
+    for name in EXPORTS:
+        if name != "smc_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != SMC_OK:
+        raise SmcError(rc, _lib.smc_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        lib = load_library()
+        h = C.c_void_p()
+        _check(lib.smc_ctx_create(C.byref(h), int(device)))
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if self.handle:
+            _lib.smc_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _desc(model, keep: list) -> smc_model_desc:
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a
+
+    d = smc_model_desc()
+    S, L = model.n_shells, model.n_lines
+    d.n_shells = S
+    d.v_bounds = _ptr(arr(model.v_bounds, np.float64), _dp)
+    d.t_exp = float(model.t_exp)
+    d.n_e = _ptr(arr(model.n_e, np.float64), _dp)
+    d.n_lines = L
+    d.line_nu = _ptr(arr(model.line_nu if L else np.zeros(1), np.float64), _dp)
+    d.tau_sobolev = _ptr(arr(model.tau_sobolev if L else np.zeros(1), np.float64), _dp)
+    d.line_mode = int(model.line_mode)
+    if model.line_mode == DOWNBRANCH:
+        d.line_upper = _ptr(arr(model.line_upper, np.int32), _i32p)
+        d.n_levels = int(model.n_levels)
+        d.level_ptr = _ptr(arr(model.level_ptr, np.int64), _i64p)
+        d.n_em = int(model.em_line.shape[0])
+        d.em_line = _ptr(arr(model.em_line, np.int32), _i32p)
+        d.em_cum = _ptr(arr(model.em_cum, np.float64), _dp)
+    d.nu_min = float(model.nu_min)
+    d.nu_max = float(model.nu_max)
+    d.n_bins = int(model.n_bins)
+    d.seed = int(model.seed)
+    return d
+
+
+def workspace_bytes(model, n_packets_max: int, flags: int) -> int:
+    lib = load_library()
+    keep = []
+    d = _desc(model, keep)
+    out = C.c_uint64()
+    _check(lib.smc_model_workspace_bytes(C.byref(d), int(n_packets_max), int(flags), C.byref(out)))
+    return int(out.value)
+
+
+class Model:
+    """A model resident in device memory (section 2.1 shells, 2.5 lines)."""
+
+    def __init__(self, ctx: Context, model, n_packets_max: int, flags: int = F_JBLUE,
+                 workspace=None, stream=None):
+        import torch
+        lib = load_library()
+        keep = []
+        d = _desc(model, keep)
+        need = workspace_bytes(model, n_packets_max, flags)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        self.workspace = workspace
+        h = C.c_void_p()
+        _check(lib.smc_model_load(ctx.handle, C.byref(d), int(n_packets_max), int(flags),
+                                  C.c_void_p(workspace.data_ptr()), int(workspace.numel()),
+                                  _stream_ptr(stream), C.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+        self.S, self.L, self.n_bins = model.n_shells, model.n_lines, model.n_bins
+        self.flags = flags
+        self.n_packets_max = n_packets_max
+        self._ids = None
+
+    def free(self):
+        if self.handle:
+            _lib.smc_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def run_iteration(self, n_packets: int, T_inner: float, iteration: int = 0,
+                      flags: Optional[int] = None, L_requested: float = 0.0,
+                      damping: float = 1.0, max_segments: int = 10**7, packet_ids=None,
+                      stream=None):
+        """Enqueue one iteration.  packet_ids: optional torch int64/uint64
+        CUDA tensor or numpy array of ids (copied to the device)."""
+        import torch
+        p = smc_iter_params()
+        p.n_packets = int(n_packets)
+        p.iteration = int(iteration)
+        p.flags = int(self.flags if flags is None else flags)
+        p.T_inner = float(T_inner)
+        p.L_requested = float(L_requested)
+        p.damping = float(damping)
+        p.max_segments = int(max_segments)
+        if packet_ids is not None:
+            if not isinstance(packet_ids, torch.Tensor):
+                packet_ids = torch.as_tensor(np.asarray(packet_ids, dtype=np.int64))
+            ids = packet_ids.to(device=self.workspace.device, dtype=torch.int64).contiguous()
+            self._ids = ids  # keep alive until the next iteration
+            p.packet_ids = ids.data_ptr()
+            p.n_ids = int(ids.numel())
+        _check(_lib.smc_run_iteration(self.handle, C.byref(p), _stream_ptr(stream)))
+
+    def read_estimators(self, jblue: bool = True, stream=None):
+        S, L = self.S, self.L
+        out = dict(J=np.zeros(S), nubar=np.zeros(S), T_R=np.zeros(S), W=np.zeros(S),
+                   jblue=np.zeros((S, L)) if jblue else None)
+        _check(_lib.smc_read_estimators(self.handle, _ptr(out["J"], _dp), _ptr(out["nubar"], _dp),
+                                        _ptr(out["jblue"], _dp), _ptr(out["T_R"], _dp),
+                                        _ptr(out["W"], _dp), _stream_ptr(stream)))
+        return out
+
+    def read_spectrum(self, stream=None):
+        L_nu = np.zeros(self.n_bins + 2)
+        sc = np.zeros(6)
+        _check(_lib.smc_read_spectrum(self.handle, _ptr(L_nu, _dp), _ptr(sc, _dp),
+                                      _stream_ptr(stream)))
+        return dict(L_nu=L_nu, L_emitted=sc[0], L_reabsorbed=sc[1], L_capped=sc[2],
+                    L_inner=sc[3], T_inner=sc[4], T_inner_next=sc[5])
+
+    def read_counters(self, stream=None):
+        c = np.zeros(8, dtype=np.uint64)
+        _check(_lib.smc_read_counters(self.handle, _ptr(c, _u64p), _stream_ptr(stream)))
+        return {k: int(v) for k, v in zip(COUNTER_NAMES, c)}
+
+    def read_packets(self, n: int, stream=None):
+        out = np.zeros(int(n), dtype=PACKET_DTYPE)
+        _check(_lib.smc_read_packets(self.handle, C.c_void_p(out.ctypes.data), int(n),
+                                     _stream_ptr(stream)))
+        return out

@@ -1,0 +1,85 @@
+"""Shared helpers of the GPU parity tests: run the HIP path and the oracle on
+the same seeded inputs and compare them."""
+import numpy as np
+
+from oracle import oracle as O
+from paper_1401_5469_amd import smc
+
+REL = 1e-9  # per-packet and estimator tolerance (relative)
+DIVERGE_FRACTION = 1e-4
+
+
+def gpu_run(ctx, model, n_packets, T_inner, iteration=0, packet_ids=None, flags=None,
+            L_requested=0.0, damping=1.0, max_segments=10**7, n_packets_max=None, jblue=True):
+    if flags is None:
+        flags = (smc.F_JBLUE if jblue else 0) | smc.F_PACKETS
+    n_work = len(packet_ids) if packet_ids is not None else n_packets
+    m = smc.Model(ctx, model, n_packets_max or max(n_work, 1), flags=flags)
+    m.run_iteration(n_packets, T_inner, iteration=iteration, flags=flags,
+                    L_requested=L_requested, damping=damping, max_segments=max_segments,
+                    packet_ids=packet_ids)
+    out = dict(est=m.read_estimators(jblue=bool(flags & smc.F_JBLUE)), spec=m.read_spectrum(),
+               counters=m.read_counters())
+    if flags & smc.F_PACKETS:
+        out["packets"] = m.read_packets(n_work)
+    out["model"] = m
+    return out
+
+
+def oracle_run(model, n_packets, T_inner, iteration=0, packet_ids=None, L_requested=0.0,
+               damping=1.0, max_segments=10**7, jblue=True, T_R_prev=None, W_prev=None):
+    raw = O.run(model, T_inner, n_packets, iteration=iteration, packet_ids=packet_ids,
+                max_segments=max_segments, want_jblue=jblue)
+    fin = O.finalise(model, raw, T_inner, L_requested, T_R_prev, W_prev, damping=damping)
+    return raw, fin
+
+
+def divergent(gpu_packets, oracle_packets):
+    """Indices whose event sequence differs (branch ties decided differently)."""
+    return np.nonzero((gpu_packets["hash"] != oracle_packets["hash"]) |
+                      (gpu_packets["status"] != oracle_packets["status"]))[0]
+
+
+def assert_packets_match(g, o, rel=REL, allow_fraction=DIVERGE_FRACTION):
+    assert g.shape == o.shape
+    assert np.array_equal(g["id"], o["id"])
+    bad = divergent(g, o)
+    assert bad.size <= max(1, int(allow_fraction * g.size)), f"{bad.size} divergent packets"
+    ok = np.ones(g.size, dtype=bool)
+    ok[bad] = False
+    a, b = g[ok], o[ok]
+    for f in ("n_segments", "n_escatter", "n_line", "n_passes", "last_line", "shell"):
+        assert np.array_equal(a[f], b[f]), f
+    for f in ("nu", "energy", "r", "nu_cmf0"):
+        np.testing.assert_allclose(a[f], b[f], rtol=rel, atol=0, err_msg=f)
+    for f in ("mu", "mu0"):
+        np.testing.assert_allclose(a[f], b[f], rtol=rel, atol=rel, err_msg=f)
+    return bad
+
+
+def assert_close_or_zero(gpu, ref, rel=REL, what=""):
+    gpu = np.asarray(gpu)
+    ref = np.asarray(ref)
+    zero = ref == 0.0
+    assert np.all(gpu[zero] == 0.0), f"{what}: nonzero where the oracle has zero"
+    np.testing.assert_allclose(gpu[~zero], ref[~zero], rtol=rel, atol=0, err_msg=what)
+
+
+def spectrum_chi2_pvalue(a, b):
+    """Two-sample chi-square on binned luminosities (treated as counts after
+    scaling to the total), for bins with enough weight."""
+    from scipy import stats
+    a = np.asarray(a, dtype=float)
+    b = np.asarray(b, dtype=float)
+    keep = (a + b) > 0
+    a, b = a[keep], b[keep]
+    if a.size < 2:
+        return 1.0
+    s = a.sum() + b.sum()
+    ea = (a + b) * a.sum() / s
+    eb = (a + b) * b.sum() / s
+    big = (ea > 5) & (eb > 5)
+    if big.sum() < 2:
+        return 1.0
+    chi2 = (((a - ea) ** 2 / ea) + ((b - eb) ** 2 / eb))[big].sum()
+    return float(stats.chi2.sf(chi2, big.sum() - 1))

@@ -1,0 +1,146 @@
+"""The C ABI without a GPU: the library loads, exports every entry point the
+header declares, the Python structs match the header's layout, and host-side
+validation rejects bad models before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1401_5469_amd import smc
+from paper_1401_5469_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "smc.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(smc_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(smc.LIB_PATH):
+        from paper_1401_5469_amd import build
+        build.build()
+    return smc.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 11
+    assert set(names) == set(smc.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _c_layout():
+    src = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "smc.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m))
+int main(void) {
+  printf("smc_model_desc %zu\n", sizeof(smc_model_desc));
+  printf("smc_iter_params %zu\n", sizeof(smc_iter_params));
+  printf("smc_packet_out %zu\n", sizeof(smc_packet_out));
+  F(smc_model_desc, seed); F(smc_model_desc, n_em); F(smc_model_desc, nu_min);
+  F(smc_iter_params, packet_ids); F(smc_iter_params, n_ids); F(smc_iter_params, damping);
+  F(smc_packet_out, hash); F(smc_packet_out, last_line); F(smc_packet_out, nu_cmf0);
+  return 0;
+}
+"""
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        exe = os.path.join(d, "l")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    return dict(line.split() for line in out.strip().splitlines())
+
+
+def test_python_structs_match_header_layout():
+    lay = {k: int(v) for k, v in _c_layout().items()}
+    assert lay["smc_model_desc"] == C.sizeof(smc.smc_model_desc)
+    assert lay["smc_iter_params"] == C.sizeof(smc.smc_iter_params)
+    assert lay["smc_packet_out"] == smc.PACKET_DTYPE.itemsize
+    assert lay["smc_model_desc.seed"] == smc.smc_model_desc.seed.offset
+    assert lay["smc_model_desc.n_em"] == smc.smc_model_desc.n_em.offset
+    assert lay["smc_model_desc.nu_min"] == smc.smc_model_desc.nu_min.offset
+    assert lay["smc_iter_params.packet_ids"] == smc.smc_iter_params.packet_ids.offset
+    assert lay["smc_iter_params.n_ids"] == smc.smc_iter_params.n_ids.offset
+    assert lay["smc_iter_params.damping"] == smc.smc_iter_params.damping.offset
+    assert lay["smc_packet_out.hash"] == smc.PACKET_DTYPE.fields["hash"][1]
+    assert lay["smc_packet_out.last_line"] == smc.PACKET_DTYPE.fields["last_line"][1]
+    assert lay["smc_packet_out.nu_cmf0"] == smc.PACKET_DTYPE.fields["nu_cmf0"][1]
+
+
+def test_workspace_size_grows_with_flags_and_packets(lib):
+    m = W.small_model(seed=1, n_shells=5, n_lines=1000)
+    base = smc.workspace_bytes(m, 1000, 0)
+    jb = smc.workspace_bytes(m, 1000, smc.F_JBLUE)
+    pk = smc.workspace_bytes(m, 1000, smc.F_JBLUE | smc.F_PACKETS)
+    assert base >= m.nbytes()
+    assert jb - base >= 5 * 1000 * 8
+    assert pk - jb >= 1000 * smc.PACKET_DTYPE.itemsize
+    assert smc.workspace_bytes(m, 2000, smc.F_PACKETS) > smc.workspace_bytes(m, 1000, smc.F_PACKETS)
+
+
+def _expect_invalid(model):
+    with pytest.raises(smc.SmcError) as ei:
+        smc.workspace_bytes(model, 10, 0)
+    assert ei.value.code == smc.SMC_EINVAL
+    return str(ei.value)
+
+
+def test_host_validation_rejects_bad_models(lib):
+    m = W.small_model(seed=2, n_shells=4, n_lines=100)
+    bad = W.Model(**{**m.__dict__})
+    bad.line_nu = m.line_nu[::-1].copy()
+    assert "non-increasing" in _expect_invalid(bad)
+    bad = W.Model(**{**m.__dict__})
+    bad.v_bounds = m.v_bounds[::-1].copy()
+    assert "increasing" in _expect_invalid(bad)
+    bad = W.Model(**{**m.__dict__})
+    bad.n_e = -m.n_e
+    assert "n_e" in _expect_invalid(bad)
+    bad = W.Model(**{**m.__dict__})
+    t = m.tau_sobolev.copy()
+    t[1, 7] = -1.0
+    bad.tau_sobolev = t
+    assert "tau_sobolev" in _expect_invalid(bad)
+    bad = W.Model(**{**m.__dict__})
+    bad.nu_min, bad.nu_max = m.nu_max, m.nu_min
+    assert "spectrum" in _expect_invalid(bad)
+    bad = W.Model(**{**m.__dict__})
+    bad.n_bins = 0
+    assert "n_bins" in _expect_invalid(bad)
+
+
+def test_host_validation_rejects_bad_downbranch_tables(lib):
+    m = W.small_downbranch_model(seed=3)
+    assert smc.workspace_bytes(m, 10, 0) > 0
+    bad = W.Model(**{**m.__dict__})
+    lu = m.line_upper.copy()
+    lu[0] = m.n_levels
+    bad.line_upper = lu
+    assert "line_upper" in _expect_invalid(bad)
+    bad = W.Model(**{**m.__dict__})
+    el = m.em_line.copy()
+    el[0] = m.n_lines
+    bad.em_line = el
+    assert "em_line" in _expect_invalid(bad)
+
+
+def test_no_gpu_means_a_loud_error_not_a_fallback(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(smc.SmcError) as ei:
+        smc.Context(0)
+    assert ei.value.code in (smc.SMC_EDEVICE, smc.SMC_EINVAL)
