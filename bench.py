@@ -1,0 +1,153 @@
+"""Benchmark of the packet-transport hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 1]
+
+One step is one Monte Carlo iteration of the paper-scale scatter model
+(20 shells 10000-25000 km/s at 13 d, 3e5 lines, 1e6 packets; Kerzendorf & Sim
+2014 sections 2.4-2.8): reset, injection + propagation of every packet,
+estimator normalisation and the T_R / W / T_inner update, all on the device,
+with T_inner carried from one iteration to the next on the device.  The K
+timed steps are iterations 0..K-1 starting from T_inner = 9000 K.
+
+Prints ONE JSON line.  The value is packet interactions (line events plus
+Thomson scatterings) per second over the timed iterations.  The roofline
+entry prices the transport kernel's algorithmic bytes (32 B per line
+resonance: nu_k and tau_S read, J_blue read-modify-write) against the HBM
+peak; the CPU baseline times the FP64 oracle on a bounded packet sample of
+the same workload on one host core.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LINE_PASS = 32.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--packets", type=int, default=1_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=100_000,
+                    help="packets of iteration 0 the oracle runs for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-jblue", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, n_sample):
+    from oracle import build as ob
+    from oracle import oracle as O
+    import numpy as np
+
+    if not os.path.exists(ob.LIB):
+        ob.build()
+    ids = np.arange(n_sample, dtype=np.uint64)
+    t0 = time.perf_counter()
+    r = O.run(w.model, w.T_inner, w.n_packets, iteration=0, packet_ids=ids, want_jblue=True,
+              want_packets=False)
+    dt = time.perf_counter() - t0
+    c = r["counters"]
+    inter = c["line_events"] + c["escatters"]
+    return {"value": inter / dt, "unit": "interactions/s", "cores": 1, "kind": "oracle",
+            "sample": f"packet ids 0..{n_sample - 1} of iteration 0 at T_inner = {w.T_inner:g} K "
+                      f"({inter} interactions, {c['segments']} segments, {dt:.2f} s, "
+                      f"single-threaded FP64 C oracle)",
+            "packets_per_s": n_sample / dt, "segments_per_s": c["segments"] / dt,
+            "line_passes_per_s": c["line_passes"] / dt, "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported in this build "
+              "(the transport shards by packet ids; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1401_5469_amd import smc
+    from paper_1401_5469_amd import workloads as W
+
+    w = W.config2(n_packets=args.packets)
+    N = w.n_packets
+    flags = (0 if args.no_jblue else smc.F_JBLUE)
+    ctx = smc.Context(0)
+    model = smc.Model(ctx, w.model, N, flags=flags)
+    torch.cuda.synchronize()
+
+    def run(k, record):
+        for i in range(k):
+            model.run_iteration(N, w.T_inner if i == 0 else 0.0, iteration=i,
+                                flags=flags | smc.F_TIMING, L_requested=w.L_requested,
+                                damping=w.damping)
+            c = model.read_counters()
+            ms = model.read_timing()
+            if record is not None:
+                s = model.read_spectrum()
+                record.append((c, ms, s["T_inner"], s["L_emitted"] / s["L_inner"]))
+            print(f"# iteration {i}: {ms:.2f} ms transport, "
+                  f"{c['line_events'] + c['escatters']} interactions", file=sys.stderr,
+                  flush=True)
+
+    run(args.warmup, None)
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    run(args.steps, rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    inter = sum(c["line_events"] + c["escatters"] for c, _, _, _ in rec)
+    segs = sum(c["segments"] for c, _, _, _ in rec)
+    passes = sum(c["line_passes"] for c, _, _, _ in rec)
+    kern_ms = [ms for _, ms, _, _ in rec]
+    mean_ms = float(np.mean(kern_ms))
+    bytes_per_launch = BYTES_PER_LINE_PASS * passes / len(rec)
+    achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "packet-interactions/sec",
+        "value": inter / wall,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "shells": w.model.n_shells, "lines": w.model.n_lines,
+                   "packets_per_iteration": N, "iterations": args.steps,
+                   "T_inner_start": w.T_inner, "line_mode": "scatter",
+                   "jblue": not args.no_jblue},
+        "packets_per_s": N * args.steps / wall,
+        "segments_per_s": segs / wall,
+        "line_passes_per_s": passes / wall,
+        "transport_ms": kern_ms,
+        "T_inner": [t for _, _, t, _ in rec],
+        "escape_fraction": [f for _, _, _, f in rec],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "transport_kernel",
+                     "bytes_per_launch": bytes_per_launch},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -53,6 +53,7 @@ extern "C" {
 /* capability / iteration flags */
 #define SMC_F_JBLUE 1u   /* tally J_blue per line and shell ("detailed" rates, section 2.7) */
 #define SMC_F_PACKETS 2u /* write one smc_packet_out per packet (parity and debugging) */
+#define SMC_F_TIMING 4u  /* time the transport kernel with HIP events (smc_read_timing) */
 
 /* counters returned by smc_read_counters, in this order */
 #define SMC_C_SEGMENTS 0    /* flight segments (one per distance comparison) */
@@ -99,7 +100,7 @@ typedef struct {
 typedef struct {
   uint64_t n_packets;        /* N: sets the packet energy 1/N and the id range [0, N) */
   uint32_t iteration;        /* enters every packet's random-number counter */
-  uint32_t flags;            /* SMC_F_JBLUE | SMC_F_PACKETS, subset of the load flags */
+  uint32_t flags;            /* SMC_F_* bits; JBLUE and PACKETS must also be load flags */
   double T_inner;            /* > 0: inner-boundary temperature [K]; <= 0: use the value
                                 the previous iteration's update left on the device */
   double L_requested;        /* > 0: update T_inner toward this emergent luminosity [erg/s] */
@@ -167,6 +168,11 @@ int smc_read_counters(smc_model* model, uint64_t* counters, void* stream);
 /* Copy the first n per-packet records of the last iteration
  * (requires SMC_F_PACKETS in both the load and the iteration flags). */
 int smc_read_packets(smc_model* model, smc_packet_out* out, uint64_t n, void* stream);
+
+/* Duration in milliseconds of the last iteration's transport kernel, from
+ * HIP events recorded around it on the iteration's stream (requires
+ * SMC_F_TIMING in that iteration's flags).  Waits for the kernel to end. */
+int smc_read_timing(smc_model* model, double* transport_ms);
 
 #ifdef __cplusplus
 }

@@ -31,6 +31,8 @@ struct smc_model {
   bool ran;          // at least one iteration ran
   uint32_t last_flags;
   uint64_t last_work;
+  hipEvent_t ev_start, ev_stop;  // created on the first timed iteration
+  bool timed;                    // the last iteration recorded ev_start/ev_stop
 };
 
 namespace {
@@ -309,6 +311,10 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
 }
 
 int smc_model_free(smc_model* model) {
+  if (model) {
+    if (model->ev_start) (void)hipEventDestroy(model->ev_start);
+    if (model->ev_stop) (void)hipEventDestroy(model->ev_stop);
+  }
   delete model;
   return ok();
 }
@@ -316,8 +322,9 @@ int smc_model_free(smc_model* model) {
 int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   if (!m || !p) return fail(SMC_EINVAL, "null model or parameters");
   if (p->n_packets == 0) return fail(SMC_EINVAL, "n_packets must be >= 1");
-  if (p->flags & ~(SMC_F_JBLUE | SMC_F_PACKETS)) return fail(SMC_EINVAL, "unknown flags");
-  if ((p->flags & ~m->load_flags) != 0)
+  if (p->flags & ~(SMC_F_JBLUE | SMC_F_PACKETS | SMC_F_TIMING))
+    return fail(SMC_EINVAL, "unknown flags");
+  if ((p->flags & ~m->load_flags & (SMC_F_JBLUE | SMC_F_PACKETS)) != 0)
     return fail(SMC_EINVAL, "iteration flags 0x%x exceed the model's load flags 0x%x", p->flags,
                 m->load_flags);
   const uint64_t n_work = p->packet_ids ? p->n_ids : p->n_packets;
@@ -335,6 +342,11 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
 
   HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
+  const bool timed = (p->flags & SMC_F_TIMING) != 0;
+  if (timed && !m->ev_start) {
+    HIP_TRY(hipEventCreate(&m->ev_start), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&m->ev_stop), "hipEventCreate");
+  }
   smc::DevIter it;
   it.n_packets = p->n_packets;
   it.n_work = n_work;
@@ -347,6 +359,7 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   it.damping = p->damping;
 
   HIP_TRY(smc::launch_reset(m->dev, it, s), "reset launch");
+  if (timed) HIP_TRY(hipEventRecord(m->ev_start, s), "hipEventRecord");
   if (n_work > 0) {
     const int block = smc::transport_block_threads();
     uint64_t want = (n_work + block - 1) / block;
@@ -354,6 +367,8 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
     if (want > cap) want = cap;
     HIP_TRY(smc::launch_transport(m->dev, it, (int)want, s), "transport launch");
   }
+  if (timed) HIP_TRY(hipEventRecord(m->ev_stop, s), "hipEventRecord");
+  m->timed = timed;
   HIP_TRY(smc::launch_finalise(m->dev, it, s), "finalise launch");
   m->has_T = true;
   m->ran = true;
@@ -417,6 +432,17 @@ int smc_read_packets(smc_model* m, smc_packet_out* out, uint64_t n, void* stream
   int rc = sync_copy_out(out, m->dev.packets, n * sizeof(smc_packet_out), s);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return ok();
+}
+
+int smc_read_timing(smc_model* m, double* transport_ms) {
+  if (!m || !transport_ms) return fail(SMC_EINVAL, "null model or output");
+  if (!m->ran || !m->timed) return fail(SMC_EINVAL, "the last iteration was not timed");
+  HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
+  HIP_TRY(hipEventSynchronize(m->ev_stop), "hipEventSynchronize");
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, m->ev_start, m->ev_stop), "hipEventElapsedTime");
+  *transport_ms = (double)ms;
   return ok();
 }
 

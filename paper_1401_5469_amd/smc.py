@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libsmc.so")
 SMC_OK, SMC_EINVAL, SMC_ENOMEM, SMC_EDEVICE, SMC_EBUSY = 0, -1, -2, -3, -4
 SCATTER, DOWNBRANCH = 0, 1
 LIVE, ESCAPED, REABSORBED, CAPPED = 0, 1, 2, 3
-F_JBLUE, F_PACKETS = 1, 2
+F_JBLUE, F_PACKETS, F_TIMING = 1, 2, 4
 COUNTER_NAMES = ("segments", "line_passes", "line_events", "escatters", "escaped",
                  "reabsorbed", "capped", "crossings")
 
@@ -54,7 +54,7 @@ PACKET_DTYPE = np.dtype([("id", np.uint64), ("status", np.int32), ("shell", np.i
 
 EXPORTS = ("smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_model_workspace_bytes",
            "smc_model_load", "smc_model_free", "smc_run_iteration", "smc_read_estimators",
-           "smc_read_spectrum", "smc_read_counters", "smc_read_packets")
+           "smc_read_spectrum", "smc_read_counters", "smc_read_packets", "smc_read_timing")
 
 
 class SmcError(RuntimeError):
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
     L.smc_read_spectrum.argtypes = [vp, _dp, _dp, vp]
     L.smc_read_counters.argtypes = [vp, _u64p, vp]
     L.smc_read_packets.argtypes = [vp, vp, C.c_uint64, vp]
+    L.smc_read_timing.argtypes = [vp, _dp]
     for name in EXPORTS:
         if name != "smc_last_error":
             getattr(L, name).restype = C.c_int
@@ -251,6 +252,12 @@ class Model:
         c = np.zeros(8, dtype=np.uint64)
         _check(_lib.smc_read_counters(self.handle, _ptr(c, _u64p), _stream_ptr(stream)))
         return {k: int(v) for k, v in zip(COUNTER_NAMES, c)}
+
+    def read_timing(self):
+        """Transport-kernel duration of the last (timed) iteration in ms."""
+        ms = C.c_double()
+        _check(_lib.smc_read_timing(self.handle, C.byref(ms)))
+        return float(ms.value)
 
     def read_packets(self, n: int, stream=None):
         out = np.zeros(int(n), dtype=PACKET_DTYPE)

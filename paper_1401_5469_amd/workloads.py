@@ -86,6 +86,7 @@ class Workload:
     n_packets: int
     n_iterations: int
     L_requested: float = L_REQUESTED
+    damping: float = 0.5  # exponent scale of the T_inner update
 
 
 def _contig(a, dtype):
