@@ -93,7 +93,7 @@ typedef struct {
    * [nu_min, nu_max), plus underflow and overflow (section 2.9) */
   double nu_min, nu_max;
   int32_t n_bins;            /* 1 .. 8192 */
-  uint64_t seed;             /* key of the model's Philox4x64-10 streams */
+  uint64_t seed;             /* key of the model's Philox4x32-10 streams (low, high word) */
 } smc_model_desc;
 
 /* One Monte Carlo iteration (section 2.8). */
@@ -105,7 +105,7 @@ typedef struct {
                                 the previous iteration's update left on the device */
   double L_requested;        /* > 0: update T_inner toward this emergent luminosity [erg/s] */
   double damping;            /* exponent scale of the T_inner update, in (0, 1] */
-  uint64_t max_segments;     /* flight segments before a packet is CAPPED (>= 1) */
+  uint64_t max_segments;     /* flight segments before a packet is CAPPED, 1 .. 2^30 */
   const uint64_t* packet_ids;/* device [n_ids] subset of ids in [0, N), or NULL for all N */
   uint64_t n_ids;
 } smc_iter_params;

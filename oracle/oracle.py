@@ -24,6 +24,7 @@ _dp = C.POINTER(C.c_double)
 _i32p = C.POINTER(C.c_int32)
 _i64p = C.POINTER(C.c_int64)
 _u64p = C.POINTER(C.c_uint64)
+_u32p = C.POINTER(C.c_uint32)
 
 
 class _Model(C.Structure):
@@ -83,7 +84,7 @@ def lib():
                                       C.POINTER(_Out), C.POINTER(_Final)]
         L.oracle_finalise.restype = C.c_int
         L.oracle_initial_radiation_field.argtypes = [C.POINTER(_Model), _dp, _dp]
-        L.oracle_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
+        L.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
         L.oracle_uniform.argtypes = [C.c_uint64]
         L.oracle_uniform.restype = C.c_double
         L.oracle_distance_to_shell.argtypes = [C.c_double] * 4
@@ -224,11 +225,11 @@ def finalise(model, raw, T_inner, L_requested=0.0, T_R_prev=None, W_prev=None, d
     return out
 
 
-def philox4x64_10(ctr, key):
-    c = np.ascontiguousarray(ctr, dtype=np.uint64)
-    k = np.ascontiguousarray(key, dtype=np.uint64)
-    o = np.zeros(4, dtype=np.uint64)
-    lib().oracle_philox4x64_10(_ptr(c, _u64p), _ptr(k, _u64p), _ptr(o, _u64p))
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().oracle_philox4x32_10(_ptr(c, _u32p), _ptr(k, _u32p), _ptr(o, _u32p))
     return o
 
 

@@ -14,7 +14,7 @@
  *   - the emergent spectrum from escaping packets       (section 2.9)
  *
  * Readings taken where the paper is silent or garbled are marked READING.
- * Random numbers come from Philox4x64-10 (Salmon et al. 2011), a
+ * Random numbers come from Philox4x32-10 (Salmon et al. 2011), a
  * counter-based generator, in place of the Mersenne Twister named in
  * section 2; the draw schedule is fixed so that a second implementation can
  * reproduce every history.
@@ -39,31 +39,26 @@ static const double ORC_PI = 3.14159265358979323846;
 static const double ORC_PI4_OVER_90 = 1.0823232337111381915; /* zeta(4) = sum of l^-4 */
 static const int ORC_PLANCK_LMAX = 1000;
 
-const char* oracle_version(void) { return "smc-oracle 1"; }
+const char* oracle_version(void) { return "smc-oracle 2"; }
 
 /* ------------------------------------------------------------------------ */
-/* Philox4x64-10 (Salmon, Moraes, Dror & Shaw 2011, "Parallel random numbers: */
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw 2011, "Parallel random numbers: */
 /* as easy as 1, 2, 3").  Multipliers and Weyl key increments as published.  */
 /* ------------------------------------------------------------------------ */
-static void mulhilo64(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo) {
-  unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
-  *lo = (uint64_t)p;
-  *hi = (uint64_t)(p >> 64);
-}
-
-void oracle_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
-  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
-  uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
-  uint64_t k0 = key[0], k1 = key[1];
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
   for (int round = 0; round < 10; ++round) {
-    uint64_t hi0, lo0, hi1, lo1;
-    mulhilo64(M0, x0, &hi0, &lo0);
-    mulhilo64(M1, x2, &hi1, &lo1);
-    uint64_t y0 = hi1 ^ x1 ^ k0;
-    uint64_t y1 = lo1;
-    uint64_t y2 = hi0 ^ x3 ^ k1;
-    uint64_t y3 = lo0;
+    uint64_t p0 = (uint64_t)M0 * (uint64_t)x0;
+    uint64_t p1 = (uint64_t)M1 * (uint64_t)x2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t y0 = hi1 ^ x1 ^ k0;
+    uint32_t y1 = lo1;
+    uint32_t y2 = hi0 ^ x3 ^ k1;
+    uint32_t y3 = lo0;
     x0 = y0; x1 = y1; x2 = y2; x3 = y3;
     k0 += W0;
     k1 += W1;
@@ -71,28 +66,40 @@ void oracle_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t
   out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-/* Uniform deviate in the open interval (0,1): the top 52 bits plus one half,
- * scaled by 2^-52.  Exact in FP64, never 0 or 1, so it serves both the (0,1]
- * and [0,1] draws of sections 2.4-2.6. */
+/* Uniform deviate in the open interval (0,1): the top 52 bits of a 64-bit
+ * word plus one half, scaled by 2^-52.  Exact in FP64, never 0 or 1, so it
+ * serves both the (0,1] and [0,1] draws of sections 2.4-2.6. */
 double oracle_uniform(uint64_t word) {
   return ((double)(word >> 12) + 0.5) * 0x1p-52;
 }
 
-/* Per-packet random stream.  Draw d of packet p in iteration i is word d%4 of
- * Philox(counter = {d/4, p, i, 0}, key = {seed, 0}). */
+/* Per-packet random stream.  Draw d of packet p in iteration i is the 64-bit
+ * word (x[2j+1] << 32) | x[2j], j = d%2, of the Philox4x32-10 block x with
+ * counter {d/2, p_lo, p_hi, i} and key {seed_lo, seed_hi}. */
 typedef struct {
-  uint64_t key[2];
-  uint64_t packet, iteration;
+  uint32_t key[2];
+  uint64_t packet;
+  uint32_t iteration;
   uint64_t draw;
 } orc_stream;
 
 static double orc_next_uniform(orc_stream* s) {
-  uint64_t ctr[4] = {s->draw / 4, s->packet, s->iteration, 0};
-  uint64_t out[4];
-  oracle_philox4x64_10(ctr, s->key, out);
-  uint64_t w = out[s->draw % 4];
+  uint32_t ctr[4] = {(uint32_t)(s->draw / 2), (uint32_t)s->packet,
+                     (uint32_t)(s->packet >> 32), s->iteration};
+  uint32_t out[4];
+  oracle_philox4x32_10(ctr, s->key, out);
+  int j = (int)(s->draw % 2);
+  uint64_t w = ((uint64_t)out[2 * j + 1] << 32) | (uint64_t)out[2 * j];
   s->draw += 1;
   return oracle_uniform(w);
+}
+
+static void orc_stream_init(orc_stream* s, uint64_t seed, uint64_t packet, uint32_t iteration) {
+  s->key[0] = (uint32_t)seed;
+  s->key[1] = (uint32_t)(seed >> 32);
+  s->packet = packet;
+  s->iteration = iteration;
+  s->draw = 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -216,11 +223,7 @@ void oracle_inject(const oracle_model* m, double T_inner, uint64_t n_packets, ui
                    uint64_t packet_id, double* mu, double* nu_cmf, double* nu_lab,
                    double* e_lab, int64_t* next_line) {
   orc_stream s;
-  s.key[0] = m->seed;
-  s.key[1] = 0;
-  s.packet = packet_id;
-  s.iteration = iteration;
-  s.draw = 0;
+  orc_stream_init(&s, m->seed, packet_id, iteration);
   inject(m, T_inner, n_packets, &s, mu, nu_cmf, nu_lab, e_lab, next_line);
 }
 
@@ -262,11 +265,7 @@ static void run_packet(const oracle_model* m, const oracle_iter* it, uint64_t pi
   const double ct = ORC_C * m->t_exp;
 
   orc_stream s;
-  s.key[0] = m->seed;
-  s.key[1] = 0;
-  s.packet = pid;
-  s.iteration = it->iteration;
-  s.draw = 0;
+  orc_stream_init(&s, m->seed, pid, it->iteration);
 
   double mu, nu_cmf0, nu, E;
   int64_t next_line;

@@ -64,12 +64,12 @@ typedef struct {
   /* emergent spectrum grid, linear in lab-frame frequency */
   double nu_min, nu_max;
   int32_t n_bins;
-  uint64_t seed;               /* Philox key word 0 */
+  uint64_t seed;               /* Philox key (low word, high word) */
 } oracle_model;
 
 typedef struct {
   uint64_t n_packets;          /* N of the iteration: energy unit 1/N, ids in [0,N) */
-  uint32_t iteration;          /* Philox counter word 2 */
+  uint32_t iteration;          /* Philox counter word 3 */
   double T_inner;              /* inner boundary temperature [K] */
   uint64_t max_segments;       /* flight segments before a packet is CAPPED */
   const uint64_t* packet_ids;  /* subset of ids to run, NULL = all of [0,N) */
@@ -136,7 +136,7 @@ int oracle_finalise(const oracle_model* m, double T_inner, double L_requested, d
 void oracle_initial_radiation_field(const oracle_model* m, double* T_R, double* W);
 
 /* Helpers exposed so that the pins can test each step on its own. */
-void oracle_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double oracle_uniform(uint64_t word);
 double oracle_distance_to_shell(double r, double mu, double r_in, double r_out);
 void oracle_inject(const oracle_model* m, double T_inner, uint64_t n_packets, uint32_t iteration,

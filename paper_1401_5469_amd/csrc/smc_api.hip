@@ -148,8 +148,9 @@ smc::Layout layout_of(const smc_model_desc* d, uint64_t n_packets_max, uint32_t 
   l.v_bounds = take((S + 1) * 8);
   l.n_e = take(S * 8);
   l.volume = take(S * 8);
-  l.line_nu = take(L * 8);
-  l.tau = take(S * L * 8);
+  const uint64_t Lp = (L + 3) / 4 * 4;  // rows padded for aligned 4-line loads
+  l.line_nu = take(Lp * 8);
+  l.tau = take(S * Lp * 8);
   if (d->line_mode == SMC_DOWNBRANCH) {
     l.line_upper = take(L * 4);
     l.level_ptr = take(((uint64_t)d->n_levels + 1) * 8);
@@ -229,9 +230,10 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
   if (ws_bytes < lay.total)
     return fail(SMC_ENOMEM, "workspace of %llu bytes is smaller than the %llu needed",
                 (unsigned long long)ws_bytes, (unsigned long long)lay.total);
-  const size_t lds = sizeof(double) * (2 * (size_t)d->n_shells + (size_t)d->n_bins + 2);
+  const size_t lds = sizeof(double) * (2 * (size_t)d->n_shells + (size_t)d->n_bins + 2 + 3 +
+                                       SMC_N_COUNTERS);
   if (lds > 64 * 1024)
-    return fail(SMC_EINVAL, "2*n_shells + n_bins + 2 = %zu tallies exceed the 64 KiB LDS budget",
+    return fail(SMC_EINVAL, "2*n_shells + n_bins = %zu tallies exceed the 64 KiB LDS budget",
                 lds / 8);
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
@@ -242,9 +244,13 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
           "upload v_bounds");
   HIP_TRY(hipMemcpyAsync(base + lay.n_e, d->n_e, S * 8, hipMemcpyHostToDevice, s), "upload n_e");
   if (L > 0) {
+    const uint64_t Lp = (L + 3) / 4 * 4;
+    HIP_TRY(hipMemsetAsync(base + lay.line_nu, 0, Lp * 8, s), "clear line_nu");
+    HIP_TRY(hipMemsetAsync(base + lay.tau, 0, S * Lp * 8, s), "clear tau_sobolev");
     HIP_TRY(hipMemcpyAsync(base + lay.line_nu, d->line_nu, L * 8, hipMemcpyHostToDevice, s),
             "upload line_nu");
-    HIP_TRY(hipMemcpyAsync(base + lay.tau, d->tau_sobolev, S * L * 8, hipMemcpyHostToDevice, s),
+    HIP_TRY(hipMemcpy2DAsync(base + lay.tau, Lp * 8, d->tau_sobolev, L * 8, L * 8, S,
+                             hipMemcpyHostToDevice, s),
             "upload tau_sobolev");
   }
   if (d->line_mode == SMC_DOWNBRANCH && L > 0) {
@@ -338,7 +344,8 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   if (!isfinite(p->T_inner)) return fail(SMC_EINVAL, "T_inner must be finite");
   if (p->L_requested > 0.0 && !(p->damping > 0.0 && p->damping <= 1.0))
     return fail(SMC_EINVAL, "damping must lie in (0, 1]");
-  if (p->max_segments < 1) return fail(SMC_EINVAL, "max_segments must be >= 1");
+  if (p->max_segments < 1 || p->max_segments > (1ull << 30))
+    return fail(SMC_EINVAL, "max_segments must lie in [1, 2^30]");
 
   HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;

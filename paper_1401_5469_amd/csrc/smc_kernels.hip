@@ -34,28 +34,24 @@ constexpr int kBlock = 256;
 constexpr int kWave = 64;
 
 // ---------------------------------------------------------------------------
-// Philox4x64-10 (Salmon et al. 2011).  Packet p of iteration i draws its d-th
-// number from word d%4 of the block with counter {d/4, p, i, 0} and key
-// {seed, 0}; the four words of the current block stay in registers.
+// Philox4x32-10 (Salmon et al. 2011).  Draw d of packet p in iteration i is
+// the 64-bit word (x[2j+1] << 32) | x[2j], j = d%2, of the block x with
+// counter {d/2, p_lo, p_hi, i} and key {seed_lo, seed_hi}.
 // ---------------------------------------------------------------------------
-struct Stream {
-  uint64_t seed, pid, iter;
-  uint64_t next;   // index of the next draw
-  uint64_t block;  // block held in w0..w3
-  uint64_t w0, w1, w2, w3;
+struct Block {
+  uint64_t a, b;  // the block's two 64-bit draws
 };
 
-__device__ __forceinline__ void philox_block(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                             uint64_t k0, uint64_t k1, uint64_t& o0,
-                                             uint64_t& o1, uint64_t& o2, uint64_t& o3) {
-  constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+__device__ __forceinline__ Block philox_block(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
-    const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
-    const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
-    const uint64_t n0 = hi1 ^ c1 ^ k0;
-    const uint64_t n2 = hi0 ^ c3 ^ k1;
+    const uint32_t hi0 = __umulhi(M0, c0), lo0 = M0 * c0;
+    const uint32_t hi1 = __umulhi(M1, c2), lo1 = M1 * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
     c1 = lo1;
     c2 = n2;
@@ -63,32 +59,10 @@ __device__ __forceinline__ void philox_block(uint64_t c0, uint64_t c1, uint64_t 
     k0 += W0;
     k1 += W1;
   }
-  o0 = c0;
-  o1 = c1;
-  o2 = c2;
-  o3 = c3;
-}
-
-__device__ __forceinline__ void stream_init(Stream& g, uint64_t seed, uint64_t pid,
-                                            uint64_t iter) {
-  g.seed = seed;
-  g.pid = pid;
-  g.iter = iter;
-  g.next = 0;
-  g.block = ~0ull;
-}
-
-// uniform in (0,1): 52 random bits plus one half, times 2^-52 (exact)
-__device__ __forceinline__ double draw(Stream& g) {
-  const uint64_t b = g.next >> 2;
-  if (b != g.block) {
-    philox_block(b, g.pid, g.iter, 0, g.seed, 0, g.w0, g.w1, g.w2, g.w3);
-    g.block = b;
-  }
-  const uint32_t sel = (uint32_t)(g.next & 3);
-  const uint64_t w = sel == 0 ? g.w0 : sel == 1 ? g.w1 : sel == 2 ? g.w2 : g.w3;
-  g.next += 1;
-  return ((double)(w >> 12) + 0.5) * 0x1p-52;
+  Block r;
+  r.a = ((uint64_t)c1 << 32) | (uint64_t)c0;
+  r.b = ((uint64_t)c3 << 32) | (uint64_t)c2;
+  return r;
 }
 
 __device__ __forceinline__ uint64_t fnv_word(uint64_t h, uint64_t w) {
@@ -107,25 +81,6 @@ __device__ __forceinline__ double doppler(double r, double mu, double ct) {
   return 1.0 - (mu * r) / ct;
 }
 
-// Planck sampling in x = h nu / k T: pick the mixture term l with weight
-// l^-4 / zeta(4), then x ~ Gamma(4, l) from four uniforms.
-__device__ __forceinline__ double planck_x(Stream& g) {
-  const double target = draw(g) * kZeta4;
-  double acc = 0.0;
-  int l = 1;
-  for (; l <= kPlanckTerms; ++l) {
-    const double dl = (double)l;
-    acc += 1.0 / (dl * dl * dl * dl);
-    if (acc >= target) break;
-  }
-  if (l > kPlanckTerms) l = kPlanckTerms;
-  const double u1 = draw(g);
-  const double u2 = draw(g);
-  const double u3 = draw(g);
-  const double u4 = draw(g);
-  return -log(((u1 * u2) * u3) * u4) / (double)l;
-}
-
 // closest redward line: first k with nu_k < nu_cmf in the non-increasing list
 __device__ __forceinline__ int32_t first_below(const double* __restrict__ nu, int32_t n,
                                                double nu_cmf) {
@@ -141,27 +96,6 @@ __device__ __forceinline__ int32_t first_below(const double* __restrict__ nu, in
 }
 
 enum { EV_SHELL_OUT = 1, EV_SHELL_IN = 2, EV_ESCATTER = 3, EV_LINE = 4 };
-
-struct Packet {
-  uint64_t slot, pid;
-  double r, mu, nu, E;
-  double mu0, nu_cmf0;
-  int32_t shell;
-  int32_t next_line;
-  uint64_t n_seg, n_esc, n_line, n_pass, hash;
-  int32_t last_line;
-};
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
 
 // ---------------------------------------------------------------------------
 // model set-up (section 2.1): radii r = v t_exp, shell volumes, and the
@@ -202,37 +136,137 @@ __global__ void reset_kernel(DevModel m, DevIter it) {
 
 // ---------------------------------------------------------------------------
 // the transport kernel (sections 2.4-2.7, 2.9)
+//
+// Per lane: one packet at a time.  The lane keeps a four-draw window of its
+// Philox stream (two blocks) and tops it up before every flight segment, so a
+// segment's draws (tau_event, then one or two for the event) never wait for a
+// block in the middle of the physics, and every lane of a wavefront refills
+// in the same instruction stream.  Lines are read four at a time (aligned
+// 32-byte loads of nu and tau_S) into registers that persist across segments:
+// a packet trapped in the line forest usually finds its next lines there.
+// Divisions become reciprocal multiplies where only the last bit changes.
 // ---------------------------------------------------------------------------
+struct RngWindow {
+  uint64_t w0, w1, w2, w3;  // draws 2*block .. 2*block+3
+  uint32_t block;           // block index of w0, w1
+  uint32_t pos;             // next draw relative to w0
+};
+
+struct StreamKey {
+  uint32_t k0, k1;          // seed words
+  uint32_t p0, p1;          // packet id words
+  uint32_t iter;
+};
+
+__device__ __forceinline__ Block stream_block(const StreamKey& s, uint32_t blk) {
+  return philox_block(blk, s.p0, s.p1, s.iter, s.k0, s.k1);
+}
+
+__device__ __forceinline__ double to_uniform(uint64_t w) {
+  return ((double)(w >> 12) + 0.5) * 0x1p-52;
+}
+
+__device__ __forceinline__ uint64_t rng_word(const RngWindow& g, uint32_t i) {
+  const uint64_t lo = (i & 1) ? g.w1 : g.w0;
+  const uint64_t hi = (i & 1) ? g.w3 : g.w2;
+  return (i & 2) ? hi : lo;
+}
+
+__device__ __forceinline__ double rng_next(RngWindow& g) {
+  const double u = to_uniform(rng_word(g, g.pos));
+  g.pos += 1;
+  return u;
+}
+
+// make at least `need` (<= 3) draws available
+__device__ __forceinline__ void rng_topup(RngWindow& g, uint32_t need, const StreamKey& s) {
+  if (g.pos + need > 4) {
+    g.w0 = g.w2;
+    g.w1 = g.w3;
+    g.block += 1;
+    g.pos -= 2;
+    const Block nb = stream_block(s, g.block + 1);
+    g.w2 = nb.a;
+    g.w3 = nb.b;
+    if (g.pos + need > 4) {
+      g.w0 = g.w2;
+      g.w1 = g.w3;
+      g.block += 1;
+      g.pos -= 2;
+      const Block nb2 = stream_block(s, g.block + 1);
+      g.w2 = nb2.a;
+      g.w3 = nb2.b;
+    }
+  }
+}
+
+// Planck sampling in x = h nu / k T from five uniforms (mixture term l, then
+// a Gamma(4, l) deviate)
+__device__ __forceinline__ double planck_from(double u_l, double u1, double u2, double u3,
+                                              double u4) {
+  const double target = u_l * kZeta4;
+  double acc = 0.0;
+  int l = 1;
+  for (; l <= kPlanckTerms; ++l) {
+    const double dl = (double)l;
+    acc += 1.0 / (dl * dl * dl * dl);
+    if (acc >= target) break;
+  }
+  if (l > kPlanckTerms) l = kPlanckTerms;
+  return -log(((u1 * u2) * u3) * u4) / (double)l;
+}
+
+// LDS layout of one workgroup: J[S], nubar[S], spectrum[NB+2], L sums[3],
+// then the event counters (u64)
+__host__ __device__ __forceinline__ size_t lds_doubles(int S, int n_bins) {
+  return 2 * (size_t)S + (size_t)n_bins + 2 + 3;
+}
+
 __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter it) {
-  extern __shared__ double lds[];  // J[S], nubar[S], spectrum[NB+2]
+  extern __shared__ double lds[];
   const int S = m.S;
   const int32_t L = m.L;
-  const int n_lds = 2 * S + m.n_bins + 2;
-  for (int i = threadIdx.x; i < n_lds; i += blockDim.x) lds[i] = 0.0;
+  const size_t n_dbl = lds_doubles(S, m.n_bins);
+  unsigned long long* lds_cnt = reinterpret_cast<unsigned long long*>(lds + n_dbl);
+  for (size_t i = threadIdx.x; i < n_dbl + SMC_N_COUNTERS; i += blockDim.x) lds[i] = 0.0;
   __syncthreads();
   double* lds_J = lds;
   double* lds_nb = lds + S;
   double* lds_spec = lds + 2 * S;
+  double* lds_L = lds + 2 * S + m.n_bins + 2;
 
   const int lane = threadIdx.x & (kWave - 1);
   const double ct = m.ct;
+  const double inv_ct = 1.0 / ct;
   const double T_inner = m.scalars[SC_T_USED];
   const double r_inner = m.r_bounds[0];
   const double e_packet = 1.0 / (double)it.n_packets;
   const double dnu_bin = (m.nu_max - m.nu_min) / (double)m.n_bins;
   const bool want_jblue = m.jblue != nullptr && (it.flags & SMC_F_JBLUE);
   const bool want_packets = m.packets != nullptr && (it.flags & SMC_F_PACKETS);
+  const bool downbranch = m.mode == SMC_DOWNBRANCH;
+  StreamKey sk;
+  sk.k0 = (uint32_t)m.seed;
+  sk.k1 = (uint32_t)(m.seed >> 32);
+  sk.iter = it.iteration;
+  sk.p0 = sk.p1 = 0;
+  const size_t Lp = (size_t)((L + 3) & ~3);  // padded tau row stride
   unsigned long long* queue = m.counters + SMC_N_COUNTERS;
 
-  // per-lane tallies
-  double l_esc = 0.0, l_reab = 0.0, l_cap = 0.0;
-  unsigned long long c_seg = 0, c_pass = 0, c_line = 0, c_escat = 0, c_out = 0, c_reab = 0,
-                     c_cap = 0, c_cross = 0;
+  // packet state
+  uint64_t slot = 0, pid = 0;
+  double r = 0.0, mu = 0.0, nu = 0.0, E = 0.0, mu0 = 0.0, nu_cmf0 = 0.0;
+  int32_t shell = 0, next_line = 0, last_line = -1;
+  uint64_t n_seg = 0, n_pass = 0, hash = 0;
+  uint32_t n_esc = 0, n_line = 0;
+  RngWindow g;
+  // line window: lines wbase..wbase+3 of shell wshell
+  int32_t wbase = -8, wshell = -1;
+  double wn0 = 0, wn1 = 0, wn2 = 0, wn3 = 0, wt0 = 0, wt1 = 0, wt2 = 0, wt3 = 0;
+  // shell tallies held in registers while the packet stays in one shell
   double acc_J = 0.0, acc_nb = 0.0;
   int acc_shell = -1;
 
-  Packet p;
-  Stream g;
   bool active = false, exhausted = false;
 
   for (;;) {
@@ -249,23 +283,37 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
         const uint64_t idx = base + (uint64_t)__popcll(below);
         if (idx < it.n_work) {
           // ---- injection at the inner boundary (section 2.4)
-          p.slot = idx;
-          p.pid = it.ids ? it.ids[idx] : idx;
-          stream_init(g, m.seed, p.pid, it.iteration);
-          p.mu = sqrt(draw(g));  // zero limb darkening
-          const double x = planck_x(g);
+          slot = idx;
+          pid = it.ids ? it.ids[idx] : idx;
+          sk.p0 = (uint32_t)pid;
+          sk.p1 = (uint32_t)(pid >> 32);
+          // draws 0..5: mu, the Planck mixture term, four Gamma(4) uniforms
+          const Block b0 = stream_block(sk, 0), b1 = stream_block(sk, 1);
+          const Block b2 = stream_block(sk, 2), b3 = stream_block(sk, 3);
+          g.w0 = b2.a;
+          g.w1 = b2.b;
+          g.w2 = b3.a;
+          g.w3 = b3.b;
+          g.block = 2;
+          g.pos = 2;
+          mu = sqrt(to_uniform(b0.a));  // zero limb darkening
+          const double u_l = to_uniform(b0.b);
+          const double u1 = to_uniform(b1.a), u2 = to_uniform(b1.b);
+          const double u3 = to_uniform(b2.a), u4 = to_uniform(b2.b);
+          const double x = planck_from(u_l, u1, u2, u3, u4);
           const double nu_cmf = x * kKB * T_inner / kH;
-          const double D0 = doppler(r_inner, p.mu, ct);
-          p.nu = nu_cmf / D0;
-          p.E = e_packet / D0;
-          p.r = r_inner;
-          p.mu0 = p.mu;
-          p.nu_cmf0 = nu_cmf;
-          p.shell = 0;
-          p.next_line = L > 0 ? first_below(m.line_nu, L, nu_cmf) : 0;
-          p.n_seg = p.n_esc = p.n_line = p.n_pass = 0;
-          p.hash = 0xcbf29ce484222325ull;
-          p.last_line = -1;
+          const double D0 = doppler(r_inner, mu, ct);
+          nu = nu_cmf / D0;
+          E = e_packet / D0;
+          r = r_inner;
+          mu0 = mu;
+          nu_cmf0 = nu_cmf;
+          shell = 0;
+          next_line = L > 0 ? first_below(m.line_nu, L, nu_cmf) : 0;
+          n_seg = n_pass = 0;
+          n_esc = n_line = 0;
+          hash = 0xcbf29ce484222325ull;
+          last_line = -1;
           active = true;
         } else {
           exhausted = true;
@@ -277,72 +325,87 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
 
     // ---- one flight segment (section 2.6)
     int status = SMC_LIVE;
-    if (p.n_seg >= it.max_segments) {
+    if (n_seg >= it.max_segments) {
       status = SMC_CAPPED;
     } else {
-      p.n_seg += 1;
-      c_seg += 1;
-      const int sh = p.shell;
+      n_seg += 1;
+      rng_topup(g, 3, sk);  // tau_event + at most two event draws
+      const double tau0 = -log(rng_next(g));
+      const int sh = shell;
       const double r_in = m.r_bounds[sh];
       const double r_out = m.r_bounds[sh + 1];
-      double tau_event = -log(draw(g));
-
-      const double r = p.r, mu = p.mu, nu = p.nu, E = p.E;
-      const double D = doppler(r, mu, ct);
+      const double rmu = r * mu;
+      const double D = 1.0 - rmu * inv_ct;
       const double nu_cmf = nu * D;
       const double e_cmf = E * D;
       // distance to the shell boundary met first (ray-sphere intersection)
       const double b = r * r * ((1.0 - mu) * (1.0 + mu));
       const bool inward = mu < 0.0 && b < r_in * r_in;
-      double d_shell;
-      if (inward) {
-        d_shell = -r * mu - sqrt(r_in * r_in - b);
-      } else {
-        double q = r_out * r_out - b;
-        q = q < 0.0 ? 0.0 : q;
-        d_shell = sqrt(q) - r * mu;
-      }
+      double q = inward ? r_in * r_in - b : r_out * r_out - b;
+      q = q < 0.0 ? 0.0 : q;
+      const double sq = sqrt(q);
+      double d_shell = inward ? -rmu - sq : sq - rmu;
       d_shell = d_shell < 0.0 ? 0.0 : d_shell;
       const double kappa = kSigmaT * m.n_e[sh] * D;  // Thomson opacity with D
-      double d_electron = kappa > 0.0 ? tau_event / kappa : INFINITY;
+      const double inv_nu = 1.0 / nu;
+      const double ct_over_nu = ct * inv_nu;
+      const double jb_w = E * inv_nu * inv_nu;  // J_blue weight per unit nu_k
 
-      // line march: pass redward lines while d_line is the shortest distance
-      const double* __restrict__ tau_row = m.tau + (size_t)sh * (size_t)L;
-      const double ct_over_nu = ct / nu;
-      int32_t k = p.next_line;
+      // line march: pass redward lines while d_line is the shortest distance;
+      // tau_rem is the optical depth left for electrons after the lines passed
+      double tau_rem = tau0;
+      int32_t k = next_line;
       bool line_hit = false;
       double d_line = 0.0;
-      while (k < L) {
-        const double nu_k = m.line_nu[k];
-        d_line = (nu_cmf - nu_k) * ct_over_nu;
-        d_line = d_line < 0.0 ? 0.0 : d_line;
-        if (!(d_line < d_electron && d_line < d_shell)) break;
-        p.n_pass += 1;
-        c_pass += 1;
-        if (want_jblue) unsafeAtomicAdd(&m.jblue[(size_t)sh * (size_t)L + k], E * nu_k / (nu * nu));
-        const double tau_line = tau_row[k];
-        if (tau_line + kappa * d_line > tau_event) {
-          line_hit = true;
-          break;
+      const double* __restrict__ tau_row = m.tau + (size_t)sh * Lp;
+      double* jb_row = want_jblue ? m.jblue + (size_t)sh * (size_t)L : nullptr;
+      bool stop = k >= L;
+      while (!stop) {
+        const int32_t base = k & ~3;
+        if (base != wbase || sh != wshell) {
+          const double2* pn = reinterpret_cast<const double2*>(m.line_nu + base);
+          const double2* pt = reinterpret_cast<const double2*>(tau_row + base);
+          const double2 n01 = pn[0], n23 = pn[1], t01 = pt[0], t23 = pt[1];
+          wn0 = n01.x; wn1 = n01.y; wn2 = n23.x; wn3 = n23.y;
+          wt0 = t01.x; wt1 = t01.y; wt2 = t23.x; wt3 = t23.y;
+          wbase = base;
+          wshell = sh;
         }
-        tau_event -= tau_line;
-        if (kappa > 0.0) d_electron = tau_event / kappa;
-        k += 1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const double nu_k = j == 0 ? wn0 : j == 1 ? wn1 : j == 2 ? wn2 : wn3;
+          const double tau_k = j == 0 ? wt0 : j == 1 ? wt1 : j == 2 ? wt2 : wt3;
+          if (!stop && base + j >= k) {
+            if (base + j >= L) {
+              stop = true;
+            } else {
+              double dl = (nu_cmf - nu_k) * ct_over_nu;
+              dl = dl < 0.0 ? 0.0 : dl;
+              if (!(kappa * dl < tau_rem && dl < d_shell)) {
+                stop = true;
+              } else {
+                n_pass += 1;
+                if (jb_row) unsafeAtomicAdd(&jb_row[base + j], jb_w * nu_k);
+                if (tau_k + kappa * dl > tau_rem) {
+                  line_hit = true;
+                  d_line = dl;
+                  stop = true;
+                } else {
+                  tau_rem -= tau_k;
+                  k = base + j + 1;
+                }
+              }
+            }
+          }
+        }
       }
-      p.next_line = k;
+      next_line = k;
 
-      int kind;
-      double d;
-      if (line_hit) {
-        kind = EV_LINE;
-        d = d_line;
-      } else if (d_electron < d_shell) {
-        kind = EV_ESCATTER;
-        d = d_electron;
-      } else {
-        kind = inward ? EV_SHELL_IN : EV_SHELL_OUT;
-        d = d_shell;
-      }
+      // event choice: line, else electron, else boundary
+      const double d_electron = kappa > 0.0 ? tau_rem / kappa : INFINITY;
+      const bool escat = !line_hit && d_electron < d_shell;
+      const bool cross = !line_hit && !escat;
+      const double d = line_hit ? d_line : (escat ? d_electron : d_shell);
 
       // J and nu-bar estimators (section 2.7), register-accumulated per shell
       if (acc_shell != sh) {
@@ -358,58 +421,54 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
       acc_J += jc;
       acc_nb += jc * nu_cmf;
 
-      // move
+      // move along the flight path
       const double r_new = sqrt(r * r + d * d + 2.0 * r * d * mu);
-      double mu_new = (r * mu + d) / r_new;
+      double mu_new = (rmu + d) / r_new;
       mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
 
-      if (kind == EV_SHELL_OUT || kind == EV_SHELL_IN) {
-        p.r = kind == EV_SHELL_OUT ? r_out : r_in;
-        p.mu = mu_new;
-        c_cross += 1;
-        p.hash = fnv_event(p.hash, kind, sh, -1, -1);
-        p.shell = sh + (kind == EV_SHELL_OUT ? 1 : -1);
-        if (p.shell >= S)
+      if (cross) {
+        const int kind = inward ? EV_SHELL_IN : EV_SHELL_OUT;
+        r = inward ? r_in : r_out;
+        mu = mu_new;
+        hash = fnv_event(hash, kind, sh, -1, -1);
+        shell = sh + (inward ? -1 : 1);
+        if (shell >= S)
           status = SMC_ESCAPED;
-        else if (p.shell < 0)
+        else if (shell < 0)
           status = SMC_REABSORBED;
       } else {
-        p.r = r_new;
-        const double D_old = doppler(r_new, mu_new, ct);
+        // Thomson (coherent, isotropic in the comoving frame) or line
+        // interaction (branch draw, then direction; section 2.5)
+        const double D_old = 1.0 - (mu_new * r_new) * inv_ct;
         const double e_cmf_ev = E * D_old;
-        if (kind == EV_ESCATTER) {
-          // coherent isotropic Thomson scattering in the comoving frame
-          const double nu_cmf_ev = nu * D_old;
-          const double mu_out = 2.0 * draw(g) - 1.0;
-          const double D_new = doppler(r_new, mu_out, ct);
-          p.mu = mu_out;
-          p.nu = nu_cmf_ev / D_new;
-          p.E = e_cmf_ev / D_new;
-          p.n_esc += 1;
-          c_escat += 1;
-          p.hash = fnv_event(p.hash, kind, sh, -1, -1);
-        } else {
-          // line interaction: branch draw (used by downbranch), then direction
-          const double u_branch = draw(g);
-          const double u_mu = draw(g);
-          int32_t emit = k;
-          if (m.mode == SMC_DOWNBRANCH) {
+        double nu_cmf_out = nu * D_old;
+        int32_t emit = k;
+        if (line_hit) {
+          const double u_branch = rng_next(g);
+          if (downbranch) {
             const int32_t up = m.line_upper[k];
             const int64_t a = m.level_ptr[up], e = m.level_ptr[up + 1];
             int64_t j = a;
             while (j < e - 1 && !(m.em_cum[j] > u_branch)) ++j;
             emit = m.em_line[j];
           }
-          const double mu_out = 2.0 * u_mu - 1.0;
-          const double D_new = doppler(r_new, mu_out, ct);
-          p.mu = mu_out;
-          p.nu = m.line_nu[emit] / D_new;
-          p.E = e_cmf_ev / D_new;
-          p.next_line = emit + 1;
-          p.n_line += 1;
-          p.last_line = k;
-          c_line += 1;
-          p.hash = fnv_event(p.hash, kind, sh, k, emit);
+          nu_cmf_out = m.line_nu[emit];
+        }
+        const double mu_out = 2.0 * rng_next(g) - 1.0;
+        const double D_new = 1.0 - (mu_out * r_new) * inv_ct;
+        const double inv_D = 1.0 / D_new;
+        r = r_new;
+        mu = mu_out;
+        nu = nu_cmf_out * inv_D;
+        E = e_cmf_ev * inv_D;
+        if (line_hit) {
+          next_line = emit + 1;
+          n_line += 1;
+          last_line = k;
+          hash = fnv_event(hash, EV_LINE, sh, k, emit);
+        } else {
+          n_esc += 1;
+          hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
         }
       }
     }
@@ -417,41 +476,48 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
     if (status != SMC_LIVE) {
       // end of the history: spectrum and luminosity tallies (section 2.9)
       if (status == SMC_ESCAPED) {
-        c_out += 1;
-        l_esc += p.E;
         int bin;
-        if (!(p.nu >= m.nu_min)) {
+        if (!(nu >= m.nu_min)) {
           bin = m.n_bins;  // underflow (a NaN would land here too, never out of range)
         } else {
-          const double f = floor((p.nu - m.nu_min) / dnu_bin);
+          const double f = floor((nu - m.nu_min) / dnu_bin);
           bin = f >= (double)m.n_bins ? m.n_bins + 1 : (int)f;
         }
-        atomicAdd(&lds_spec[bin], p.E);
+        atomicAdd(&lds_spec[bin], E);
+        atomicAdd(&lds_L[0], E);
+        atomicAdd(&lds_cnt[SMC_C_ESCAPED], 1ull);
       } else if (status == SMC_REABSORBED) {
-        c_reab += 1;
-        l_reab += p.E;
+        atomicAdd(&lds_L[1], E);
+        atomicAdd(&lds_cnt[SMC_C_REABSORBED], 1ull);
       } else {
-        c_cap += 1;
-        l_cap += p.E;
+        atomicAdd(&lds_L[2], E);
+        atomicAdd(&lds_cnt[SMC_C_CAPPED], 1ull);
       }
+      // crossings = segments - interactions, except the capped check that
+      // ends a history without a segment
+      atomicAdd(&lds_cnt[SMC_C_SEGMENTS], (unsigned long long)n_seg);
+      atomicAdd(&lds_cnt[SMC_C_LINE_PASSES], (unsigned long long)n_pass);
+      atomicAdd(&lds_cnt[SMC_C_LINE_EVENTS], (unsigned long long)n_line);
+      atomicAdd(&lds_cnt[SMC_C_ESCATTERS], (unsigned long long)n_esc);
+      atomicAdd(&lds_cnt[SMC_C_CROSSINGS], (unsigned long long)(n_seg - n_line - n_esc));
       if (want_packets) {
         smc_packet_out rec;
-        rec.id = p.pid;
+        rec.id = pid;
         rec.status = status;
-        rec.shell = p.shell;
-        rec.nu = p.nu;
-        rec.energy = p.E;
-        rec.mu = p.mu;
-        rec.r = p.r;
-        rec.mu0 = p.mu0;
-        rec.nu_cmf0 = p.nu_cmf0;
-        rec.n_segments = p.n_seg;
-        rec.n_escatter = p.n_esc;
-        rec.n_line = p.n_line;
-        rec.n_passes = p.n_pass;
-        rec.hash = p.hash;
-        rec.last_line = p.last_line;
-        static_cast<smc_packet_out*>(m.packets)[p.slot] = rec;
+        rec.shell = shell;
+        rec.nu = nu;
+        rec.energy = E;
+        rec.mu = mu;
+        rec.r = r;
+        rec.mu0 = mu0;
+        rec.nu_cmf0 = nu_cmf0;
+        rec.n_segments = n_seg;
+        rec.n_escatter = n_esc;
+        rec.n_line = n_line;
+        rec.n_passes = n_pass;
+        rec.hash = hash;
+        rec.last_line = last_line;
+        static_cast<smc_packet_out*>(m.packets)[slot] = rec;
       }
       active = false;
     }
@@ -461,36 +527,19 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
     atomicAdd(&lds_J[acc_shell], acc_J);
     atomicAdd(&lds_nb[acc_shell], acc_nb);
   }
-  // wave reductions of the scalar tallies, one global atomic per wave each
-  l_esc = wave_sum(l_esc);
-  l_reab = wave_sum(l_reab);
-  l_cap = wave_sum(l_cap);
-  c_seg = wave_sum_u64(c_seg);
-  c_pass = wave_sum_u64(c_pass);
-  c_line = wave_sum_u64(c_line);
-  c_escat = wave_sum_u64(c_escat);
-  c_out = wave_sum_u64(c_out);
-  c_reab = wave_sum_u64(c_reab);
-  c_cap = wave_sum_u64(c_cap);
-  c_cross = wave_sum_u64(c_cross);
-  if (lane == 0) {
-    if (l_esc != 0.0) unsafeAtomicAdd(&m.lsum[0], l_esc);
-    if (l_reab != 0.0) unsafeAtomicAdd(&m.lsum[1], l_reab);
-    if (l_cap != 0.0) unsafeAtomicAdd(&m.lsum[2], l_cap);
-    atomicAdd(&m.counters[SMC_C_SEGMENTS], c_seg);
-    atomicAdd(&m.counters[SMC_C_LINE_PASSES], c_pass);
-    atomicAdd(&m.counters[SMC_C_LINE_EVENTS], c_line);
-    atomicAdd(&m.counters[SMC_C_ESCATTERS], c_escat);
-    atomicAdd(&m.counters[SMC_C_ESCAPED], c_out);
-    atomicAdd(&m.counters[SMC_C_REABSORBED], c_reab);
-    atomicAdd(&m.counters[SMC_C_CAPPED], c_cap);
-    atomicAdd(&m.counters[SMC_C_CROSSINGS], c_cross);
-  }
   __syncthreads();
   // merge the workgroup's LDS tallies into HBM
-  for (int i = threadIdx.x; i < n_lds; i += blockDim.x) {
+  for (size_t i = threadIdx.x; i < n_dbl; i += blockDim.x) {
     const double v = lds[i];
-    if (v != 0.0) unsafeAtomicAdd(&m.raw[i], v);
+    if (v == 0.0) continue;
+    if (i < 2 * (size_t)S + (size_t)m.n_bins + 2)
+      unsafeAtomicAdd(&m.raw[i], v);
+    else
+      unsafeAtomicAdd(&m.lsum[i - (2 * (size_t)S + (size_t)m.n_bins + 2)], v);
+  }
+  if (threadIdx.x < SMC_N_COUNTERS) {
+    const unsigned long long v = lds_cnt[threadIdx.x];
+    if (v) atomicAdd(&m.counters[threadIdx.x], v);
   }
 }
 
@@ -547,7 +596,7 @@ __global__ void jblue_scale_kernel(DevModel m) {
 int transport_block_threads() { return kBlock; }
 
 size_t transport_lds_bytes(const DevModel& m) {
-  return sizeof(double) * (2 * (size_t)m.S + (size_t)m.n_bins + 2);
+  return sizeof(double) * (lds_doubles(m.S, m.n_bins) + SMC_N_COUNTERS);
 }
 
 hipError_t launch_geometry(const DevModel& m, const double* v_bounds, hipStream_t s) {
