@@ -124,6 +124,16 @@ typedef struct {
   int64_t last_line;         /* last absorbing line, -1 if none */
 } smc_packet_out;
 
+/* Launch tuning of one model (0 in a field = the library default). */
+typedef struct {
+  int32_t blocks_per_cu;     /* lane-per-packet kernel: workgroups of 256 resident per CU */
+  int32_t long_waves_per_cu; /* wave-per-packet kernel: wavefronts resident per CU */
+  uint32_t long_budget;      /* flight segments after which a history moves from the
+                                lane-per-packet to the wave-per-packet kernel;
+                                UINT32_MAX keeps every history in the first kernel */
+  uint32_t reserved;         /* must be 0 */
+} smc_tune;
+
 /* Create a context on HIP device `hip_device`. */
 int smc_ctx_create(smc_ctx** out, int hip_device);
 int smc_ctx_destroy(smc_ctx* ctx);
@@ -169,8 +179,14 @@ int smc_read_counters(smc_model* model, uint64_t* counters, void* stream);
  * (requires SMC_F_PACKETS in both the load and the iteration flags). */
 int smc_read_packets(smc_model* model, smc_packet_out* out, uint64_t n, void* stream);
 
-/* Duration in milliseconds of the last iteration's transport kernel, from
- * HIP events recorded around it on the iteration's stream (requires
+/* Set (NULL: reset to defaults) or read the launch tuning of a model.  Tuning
+ * changes launch shapes only: results are identical up to the summation
+ * order of the tallies. */
+int smc_model_set_tune(smc_model* model, const smc_tune* tune);
+int smc_model_get_tune(smc_model* model, smc_tune* tune);
+
+/* Duration in milliseconds of the last iteration's transport kernels, from
+ * HIP events recorded around them on the iteration's stream (requires
  * SMC_F_TIMING in that iteration's flags).  Waits for the kernel to end. */
 int smc_read_timing(smc_model* model, double* transport_ms);
 

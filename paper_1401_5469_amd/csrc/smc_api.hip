@@ -16,7 +16,8 @@
 struct smc_ctx {
   int device;
   int n_cu;
-  int max_blocks_per_cu;
+  int transport_blocks_per_cu;  // occupancy of the lane-per-packet kernel
+  int long_blocks_per_cu;       // occupancy of the wave-per-packet kernel
 };
 
 struct smc_model {
@@ -33,6 +34,7 @@ struct smc_model {
   uint64_t last_work;
   hipEvent_t ev_start, ev_stop;  // created on the first timed iteration
   bool timed;                    // the last iteration recorded ev_start/ev_stop
+  smc_tune tune;
 };
 
 namespace {
@@ -66,6 +68,7 @@ int hip_fail(hipError_t e, const char* what) {
   } while (0)
 
 constexpr uint64_t kAlign = 256;
+constexpr uint32_t kDefaultLongBudget = 1024;
 constexpr int kMaxBins = 8192;
 constexpr int kMaxShells = 4096;
 
@@ -159,7 +162,8 @@ smc::Layout layout_of(const smc_model_desc* d, uint64_t n_packets_max, uint32_t 
   }
   l.raw = take((2 * S + NB) * 8);
   l.lsum = take(4 * 8);
-  l.counters = take((SMC_N_COUNTERS + 1) * 8);
+  l.counters = take(smc::CTR_TOTAL * 8);
+  l.longs = take(n_packets_max * sizeof(smc::LongState));
   l.jblue = (flags & SMC_F_JBLUE) ? take(S * L * 8) : 0;
   l.out_shell = take(6 * S * 8);
   l.out_spec = take(NB * 8);
@@ -198,7 +202,11 @@ int smc_ctx_create(smc_ctx** out, int hip_device) {
   if (!c) return fail(SMC_ENOMEM, "host allocation failed");
   c->device = hip_device;
   c->n_cu = prop.multiProcessorCount;
-  c->max_blocks_per_cu = 8;
+  int occ = 0;
+  HIP_TRY(smc::transport_occupancy(&occ), "occupancy query");
+  c->transport_blocks_per_cu = occ > 0 ? occ : 1;
+  HIP_TRY(smc::long_occupancy(&occ), "occupancy query");
+  c->long_blocks_per_cu = occ > 0 ? occ : 1;
   *out = c;
   return ok();
 }
@@ -279,6 +287,7 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
   smc::DevModel& dm = m->dev;
   dm.S = d->n_shells;
   dm.L = (int32_t)d->n_lines;
+  dm.Lp = (int32_t)((d->n_lines + 3) / 4 * 4);
   dm.n_bins = d->n_bins;
   dm.mode = d->line_mode;
   dm.t_exp = d->t_exp;
@@ -305,6 +314,8 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
   dm.out_spec = (double*)(base + lay.out_spec);
   dm.scalars = (double*)(base + lay.scalars);
   dm.packets = (flags & SMC_F_PACKETS) ? (void*)(base + lay.packets) : nullptr;
+  dm.longs = (smc::LongState*)(base + lay.longs);
+  dm.long_cap = n_packets_max;
 
   hipError_t e = smc::launch_geometry(dm, (const double*)(base + lay.v_bounds), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -361,6 +372,8 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   it.max_segments = p->max_segments;
   it.iteration = p->iteration;
   it.flags = p->flags;
+  it.long_budget = m->tune.long_budget == 0 ? kDefaultLongBudget
+                   : (m->tune.long_budget == UINT32_MAX ? 0 : m->tune.long_budget);
   it.T_param = p->T_inner;
   it.L_requested = p->L_requested;
   it.damping = p->damping;
@@ -370,9 +383,20 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   if (n_work > 0) {
     const int block = smc::transport_block_threads();
     uint64_t want = (n_work + block - 1) / block;
-    const uint64_t cap = (uint64_t)m->ctx->n_cu * (uint64_t)m->ctx->max_blocks_per_cu;
+    const int per_cu = m->tune.blocks_per_cu > 0 ? m->tune.blocks_per_cu
+                                                 : m->ctx->transport_blocks_per_cu;
+    const uint64_t cap = (uint64_t)m->ctx->n_cu * (uint64_t)per_cu;
     if (want > cap) want = cap;
     HIP_TRY(smc::launch_transport(m->dev, it, (int)want, s), "transport launch");
+    if (it.long_budget > 0) {
+      // histories handed off by the lane-per-packet kernel; the grid drains
+      // the device-side queue, so no host round trip is needed
+      const int lper = m->tune.long_waves_per_cu > 0 ? m->tune.long_waves_per_cu
+                                                     : m->ctx->long_blocks_per_cu;
+      uint64_t lgrid = (uint64_t)m->ctx->n_cu * (uint64_t)lper;
+      if (lgrid > n_work) lgrid = n_work;
+      HIP_TRY(smc::launch_long(m->dev, it, (int)lgrid, s), "long-history launch");
+    }
   }
   if (timed) HIP_TRY(hipEventRecord(m->ev_stop, s), "hipEventRecord");
   m->timed = timed;
@@ -439,6 +463,28 @@ int smc_read_packets(smc_model* m, smc_packet_out* out, uint64_t n, void* stream
   int rc = sync_copy_out(out, m->dev.packets, n * sizeof(smc_packet_out), s);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return ok();
+}
+
+int smc_model_set_tune(smc_model* m, const smc_tune* t) {
+  if (!m) return fail(SMC_EINVAL, "null model");
+  if (!t) {
+    memset(&m->tune, 0, sizeof m->tune);
+    return ok();
+  }
+  if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64 || t->long_waves_per_cu < 0 ||
+      t->long_waves_per_cu > 64)
+    return fail(SMC_EINVAL, "blocks_per_cu and long_waves_per_cu must lie in [0, 64]");
+  m->tune = *t;
+  return ok();
+}
+
+int smc_model_get_tune(smc_model* m, smc_tune* t) {
+  if (!m || !t) return fail(SMC_EINVAL, "null model or output");
+  *t = m->tune;
+  if (t->blocks_per_cu == 0) t->blocks_per_cu = m->ctx->transport_blocks_per_cu;
+  if (t->long_waves_per_cu == 0) t->long_waves_per_cu = m->ctx->long_blocks_per_cu;
+  if (t->long_budget == 0) t->long_budget = kDefaultLongBudget;
   return ok();
 }
 

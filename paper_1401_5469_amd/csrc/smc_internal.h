@@ -15,7 +15,9 @@ struct Layout {
   uint64_t line_upper, level_ptr, em_line, em_cum;  // downbranch tables
   uint64_t raw;        // [2S + NB + 2] J_raw, nubar_raw, spectrum raw
   uint64_t lsum;       // [4] escaped, reabsorbed, capped lab energy (+ pad)
-  uint64_t counters;   // [SMC_N_COUNTERS + 1] u64; the last one is the work queue
+  uint64_t counters;   // [SMC_N_COUNTERS + 3] u64: counters, work-queue head,
+                       // long-packet count, long-packet queue head
+  uint64_t longs;      // [n_packets_max] LongState: histories handed to the wave kernel
   uint64_t jblue;      // [S*L] raw, normalised in place by the finaliser
   uint64_t out_shell;  // [6S] J, nubar, T_R, W, jblue scale, pad
   uint64_t out_spec;   // [NB + 2] L_nu
@@ -24,10 +26,25 @@ struct Layout {
   uint64_t total;
 };
 
+// State of a packet handed from the lane-per-packet kernel to the
+// wave-per-packet kernel after `long_budget` flight segments (128 bytes).
+struct LongState {
+  uint64_t slot, pid;
+  double r, mu, nu, E, mu0, nu_cmf0;
+  uint64_t n_seg, n_pass, hash, draw;
+  int32_t shell, next_line, last_line;
+  uint32_t n_esc, n_line, pad;
+};
+
+// counters[] slots after the SMC_N_COUNTERS event counters
+enum { CTR_QUEUE = SMC_N_COUNTERS, CTR_LONG_COUNT = SMC_N_COUNTERS + 1,
+       CTR_LONG_QUEUE = SMC_N_COUNTERS + 2, CTR_TOTAL = SMC_N_COUNTERS + 3 };
+
 // Everything a kernel needs about one model and one iteration.
 struct DevModel {
   int32_t S;
   int32_t L;
+  int32_t Lp;              // tau_S row stride (L rounded up to a multiple of 4)
   int32_t n_bins;
   int32_t mode;
   double t_exp;
@@ -51,6 +68,8 @@ struct DevModel {
   double* out_spec;        // [NB+2]
   double* scalars;         // [8]
   void* packets;           // smc_packet_out records or nullptr
+  LongState* longs;        // hand-off buffer
+  uint64_t long_cap;
 };
 
 struct DevIter {
@@ -60,6 +79,7 @@ struct DevIter {
   uint64_t max_segments;
   uint32_t iteration;
   uint32_t flags;
+  uint32_t long_budget;    // segments before a history moves to the wave kernel (0: never)
   double T_param;          // > 0 overrides the device-resident T_inner
   double L_requested;
   double damping;
@@ -73,8 +93,12 @@ enum { SC_L_EMITTED = 0, SC_L_REABSORBED = 1, SC_L_CAPPED = 2, SC_L_INNER = 3,
 hipError_t launch_geometry(const DevModel& m, const double* v_bounds, hipStream_t s);
 hipError_t launch_reset(const DevModel& m, const DevIter& it, hipStream_t s);
 hipError_t launch_transport(const DevModel& m, const DevIter& it, int grid, hipStream_t s);
+hipError_t launch_long(const DevModel& m, const DevIter& it, int grid, hipStream_t s);
+int long_block_threads();
 hipError_t launch_finalise(const DevModel& m, const DevIter& it, hipStream_t s);
 size_t transport_lds_bytes(const DevModel& m);
+hipError_t transport_occupancy(int* blocks_per_cu);
+hipError_t long_occupancy(int* blocks_per_cu);
 int transport_block_threads();
 
 }  // namespace smc

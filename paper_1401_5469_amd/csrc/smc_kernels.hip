@@ -124,7 +124,7 @@ __global__ void reset_kernel(DevModel m, DevIter it) {
   const size_t n_raw = 2 * (size_t)m.S + (size_t)m.n_bins + 2;
   for (size_t i = tid; i < n_raw; i += stride) m.raw[i] = 0.0;
   if (tid < 4) m.lsum[tid] = 0.0;
-  if (tid < SMC_N_COUNTERS + 1) m.counters[tid] = 0ull;
+  if (tid < CTR_TOTAL) m.counters[tid] = 0ull;
   if (m.jblue && (it.flags & SMC_F_JBLUE)) {
     const size_t n = (size_t)m.S * (size_t)m.L;
     for (size_t i = tid; i < n; i += stride) m.jblue[i] = 0.0;
@@ -135,26 +135,33 @@ __global__ void reset_kernel(DevModel m, DevIter it) {
 }
 
 // ---------------------------------------------------------------------------
-// the transport kernel (sections 2.4-2.7, 2.9)
+// The transport (sections 2.4-2.7, 2.9) runs in two kernels.
 //
-// Per lane: one packet at a time.  The lane keeps a four-draw window of its
-// Philox stream (two blocks) and tops it up before every flight segment, so a
-// segment's draws (tau_event, then one or two for the event) never wait for a
-// block in the middle of the physics, and every lane of a wavefront refills
-// in the same instruction stream.  Lines are read four at a time (aligned
-// 32-byte loads of nu and tau_S) into registers that persist across segments:
-// a packet trapped in the line forest usually finds its next lines there.
-// Divisions become reciprocal multiplies where only the last bit changes.
+// transport_kernel: one packet per lane.  A persistent grid pulls packets from
+// a work queue (one atomic per wavefront per refill), so a lane whose packet
+// ends picks up the next one while its neighbours are still marching.  A
+// history still alive after `long_budget` flight segments is saved to the
+// hand-off buffer and its lane moves on: the packet-count tail of a
+// line-forest model is a few per cent of the packets carrying about half of
+// the segments, and a lane-per-packet wavefront runs those latency-bound.
+//
+// long_kernel: one packet per wavefront, for the handed-off histories.  The
+// 64 lanes hold the next 128 draws of the packet's stream with their
+// logarithms precomputed, and the next 64 lines of its shell, so a segment's
+// dependent chain is only the geometry and frame arithmetic; J_blue updates
+// go out from the lanes that own the passed lines in parallel.
+//
+// Both follow the same arithmetic, in FP64, as the reference formulation;
+// divisions that only change the last bit are reciprocal multiplies.
 // ---------------------------------------------------------------------------
-struct RngWindow {
-  uint64_t w0, w1, w2, w3;  // draws 2*block .. 2*block+3
-  uint32_t block;           // block index of w0, w1
-  uint32_t pos;             // next draw relative to w0
-};
+
+__device__ __forceinline__ double to_uniform(uint64_t w) {
+  return ((double)(w >> 12) + 0.5) * 0x1p-52;
+}
 
 struct StreamKey {
-  uint32_t k0, k1;          // seed words
-  uint32_t p0, p1;          // packet id words
+  uint32_t k0, k1;  // seed words
+  uint32_t p0, p1;  // packet id words
   uint32_t iter;
 };
 
@@ -162,9 +169,12 @@ __device__ __forceinline__ Block stream_block(const StreamKey& s, uint32_t blk) 
   return philox_block(blk, s.p0, s.p1, s.iter, s.k0, s.k1);
 }
 
-__device__ __forceinline__ double to_uniform(uint64_t w) {
-  return ((double)(w >> 12) + 0.5) * 0x1p-52;
-}
+// four-draw window of one lane's stream (two blocks)
+struct RngWindow {
+  uint64_t w0, w1, w2, w3;  // draws 2*block .. 2*block+3
+  uint32_t block;           // block index of w0, w1
+  uint32_t pos;             // next draw relative to w0
+};
 
 __device__ __forceinline__ uint64_t rng_word(const RngWindow& g, uint32_t i) {
   const uint64_t lo = (i & 1) ? g.w1 : g.w0;
@@ -200,8 +210,8 @@ __device__ __forceinline__ void rng_topup(RngWindow& g, uint32_t need, const Str
   }
 }
 
-// Planck sampling in x = h nu / k T from five uniforms (mixture term l, then
-// a Gamma(4, l) deviate)
+// Planck sampling in x = h nu / k T from five uniforms (mixture term l with
+// weight l^-4 / zeta(4), then a Gamma(4, l) deviate)
 __device__ __forceinline__ double planck_from(double u_l, double u1, double u2, double u3,
                                               double u4) {
   const double target = u_l * kZeta4;
@@ -222,19 +232,119 @@ __host__ __device__ __forceinline__ size_t lds_doubles(int S, int n_bins) {
   return 2 * (size_t)S + (size_t)n_bins + 2 + 3;
 }
 
+struct LdsTally {
+  double *J, *nb, *spec, *L;
+  unsigned long long* cnt;
+  size_t n_dbl;
+};
+
+__device__ __forceinline__ LdsTally lds_tally_init(const DevModel& m, double* lds) {
+  LdsTally t;
+  t.n_dbl = lds_doubles(m.S, m.n_bins);
+  t.J = lds;
+  t.nb = lds + m.S;
+  t.spec = lds + 2 * m.S;
+  t.L = lds + 2 * m.S + m.n_bins + 2;
+  t.cnt = reinterpret_cast<unsigned long long*>(lds + t.n_dbl);
+  for (size_t i = threadIdx.x; i < t.n_dbl + SMC_N_COUNTERS; i += blockDim.x) lds[i] = 0.0;
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ void lds_tally_flush(const DevModel& m, const LdsTally& t,
+                                                const double* lds) {
+  __syncthreads();
+  const size_t n_raw = 2 * (size_t)m.S + (size_t)m.n_bins + 2;
+  for (size_t i = threadIdx.x; i < t.n_dbl; i += blockDim.x) {
+    const double v = lds[i];
+    if (v == 0.0) continue;
+    if (i < n_raw)
+      unsafeAtomicAdd(&m.raw[i], v);
+    else
+      unsafeAtomicAdd(&m.lsum[i - n_raw], v);
+  }
+  if (threadIdx.x < SMC_N_COUNTERS) {
+    const unsigned long long v = t.cnt[threadIdx.x];
+    if (v) atomicAdd(&m.counters[threadIdx.x], v);
+  }
+}
+
+// spectrum bin of an escaping lab frequency (section 2.9): n_bins is the
+// underflow slot (also taken by a NaN), n_bins+1 the overflow slot
+__device__ __forceinline__ int spectrum_bin(const DevModel& m, double nu, double dnu_bin) {
+  if (!(nu >= m.nu_min)) return m.n_bins;
+  const double f = floor((nu - m.nu_min) / dnu_bin);
+  return f >= (double)m.n_bins ? m.n_bins + 1 : (int)f;
+}
+
+// end of a history: luminosity, spectrum and event tallies into LDS
+__device__ __forceinline__ void tally_end(const DevModel& m, const LdsTally& t, int status,
+                                          double nu, double E, double dnu_bin, uint64_t n_seg,
+                                          uint64_t n_pass, uint32_t n_line, uint32_t n_esc) {
+  if (status == SMC_ESCAPED) {
+    atomicAdd(&t.spec[spectrum_bin(m, nu, dnu_bin)], E);
+    atomicAdd(&t.L[0], E);
+    atomicAdd(&t.cnt[SMC_C_ESCAPED], 1ull);
+  } else if (status == SMC_REABSORBED) {
+    atomicAdd(&t.L[1], E);
+    atomicAdd(&t.cnt[SMC_C_REABSORBED], 1ull);
+  } else {
+    atomicAdd(&t.L[2], E);
+    atomicAdd(&t.cnt[SMC_C_CAPPED], 1ull);
+  }
+  // every segment ends in exactly one of line event, Thomson or crossing
+  atomicAdd(&t.cnt[SMC_C_SEGMENTS], (unsigned long long)n_seg);
+  atomicAdd(&t.cnt[SMC_C_LINE_PASSES], (unsigned long long)n_pass);
+  atomicAdd(&t.cnt[SMC_C_LINE_EVENTS], (unsigned long long)n_line);
+  atomicAdd(&t.cnt[SMC_C_ESCATTERS], (unsigned long long)n_esc);
+  atomicAdd(&t.cnt[SMC_C_CROSSINGS], (unsigned long long)(n_seg - n_line - n_esc));
+}
+
+__device__ __forceinline__ void write_record(const DevModel& m, uint64_t slot, uint64_t pid,
+                                             int status, int shell, double nu, double E,
+                                             double mu, double r, double mu0, double nu_cmf0,
+                                             uint64_t n_seg, uint32_t n_esc, uint32_t n_line,
+                                             uint64_t n_pass, uint64_t hash, int32_t last_line) {
+  smc_packet_out rec;
+  rec.id = pid;
+  rec.status = status;
+  rec.shell = shell;
+  rec.nu = nu;
+  rec.energy = E;
+  rec.mu = mu;
+  rec.r = r;
+  rec.mu0 = mu0;
+  rec.nu_cmf0 = nu_cmf0;
+  rec.n_segments = n_seg;
+  rec.n_escatter = n_esc;
+  rec.n_line = n_line;
+  rec.n_passes = n_pass;
+  rec.hash = hash;
+  rec.last_line = last_line;
+  static_cast<smc_packet_out*>(m.packets)[slot] = rec;
+}
+
+// distance along (r, mu) to the boundary of shell [r_in, r_out] met first
+// (ray-sphere intersection; a tangent ray misses the inner sphere)
+__device__ __forceinline__ double shell_distance(double r, double mu, double rmu, double r_in,
+                                                 double r_out, bool& inward) {
+  const double b = r * r * ((1.0 - mu) * (1.0 + mu));
+  inward = mu < 0.0 && b < r_in * r_in;
+  double q = inward ? r_in * r_in - b : r_out * r_out - b;
+  q = q < 0.0 ? 0.0 : q;
+  const double sq = sqrt(q);
+  const double d = inward ? -rmu - sq : sq - rmu;
+  return d < 0.0 ? 0.0 : d;
+}
+
+// ---------------------------------------------------------------------------
+// lane-per-packet kernel
+// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter it) {
   extern __shared__ double lds[];
+  const LdsTally tl = lds_tally_init(m, lds);
   const int S = m.S;
   const int32_t L = m.L;
-  const size_t n_dbl = lds_doubles(S, m.n_bins);
-  unsigned long long* lds_cnt = reinterpret_cast<unsigned long long*>(lds + n_dbl);
-  for (size_t i = threadIdx.x; i < n_dbl + SMC_N_COUNTERS; i += blockDim.x) lds[i] = 0.0;
-  __syncthreads();
-  double* lds_J = lds;
-  double* lds_nb = lds + S;
-  double* lds_spec = lds + 2 * S;
-  double* lds_L = lds + 2 * S + m.n_bins + 2;
-
   const int lane = threadIdx.x & (kWave - 1);
   const double ct = m.ct;
   const double inv_ct = 1.0 / ct;
@@ -245,13 +355,14 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
   const bool want_jblue = m.jblue != nullptr && (it.flags & SMC_F_JBLUE);
   const bool want_packets = m.packets != nullptr && (it.flags & SMC_F_PACKETS);
   const bool downbranch = m.mode == SMC_DOWNBRANCH;
+  const uint64_t budget = (it.long_budget > 0 && m.longs) ? it.long_budget : ~0ull;
   StreamKey sk;
   sk.k0 = (uint32_t)m.seed;
   sk.k1 = (uint32_t)(m.seed >> 32);
   sk.iter = it.iteration;
   sk.p0 = sk.p1 = 0;
-  const size_t Lp = (size_t)((L + 3) & ~3);  // padded tau row stride
-  unsigned long long* queue = m.counters + SMC_N_COUNTERS;
+  const size_t Lp = (size_t)m.Lp;
+  unsigned long long* queue = m.counters + CTR_QUEUE;
 
   // packet state
   uint64_t slot = 0, pid = 0;
@@ -259,7 +370,11 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
   int32_t shell = 0, next_line = 0, last_line = -1;
   uint64_t n_seg = 0, n_pass = 0, hash = 0;
   uint32_t n_esc = 0, n_line = 0;
+  bool handoff_tried = false;
   RngWindow g;
+  // cached shell parameters
+  int32_t c_shell = -1;
+  double c_rin = 0.0, c_rout = 0.0, c_ne = 0.0;
   // line window: lines wbase..wbase+3 of shell wshell
   int32_t wbase = -8, wshell = -1;
   double wn0 = 0, wn1 = 0, wn2 = 0, wn3 = 0, wt0 = 0, wt1 = 0, wt2 = 0, wt3 = 0;
@@ -297,10 +412,8 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
           g.block = 2;
           g.pos = 2;
           mu = sqrt(to_uniform(b0.a));  // zero limb darkening
-          const double u_l = to_uniform(b0.b);
-          const double u1 = to_uniform(b1.a), u2 = to_uniform(b1.b);
-          const double u3 = to_uniform(b2.a), u4 = to_uniform(b2.b);
-          const double x = planck_from(u_l, u1, u2, u3, u4);
+          const double x = planck_from(to_uniform(b0.b), to_uniform(b1.a), to_uniform(b1.b),
+                                       to_uniform(b2.a), to_uniform(b2.b));
           const double nu_cmf = x * kKB * T_inner / kH;
           const double D0 = doppler(r_inner, mu, ct);
           nu = nu_cmf / D0;
@@ -314,6 +427,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
           n_esc = n_line = 0;
           hash = 0xcbf29ce484222325ull;
           last_line = -1;
+          handoff_tried = false;
           active = true;
         } else {
           exhausted = true;
@@ -323,30 +437,57 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
     if (__ballot(active) == 0ull) break;
     if (!active) continue;
 
-    // ---- one flight segment (section 2.6)
     int status = SMC_LIVE;
     if (n_seg >= it.max_segments) {
       status = SMC_CAPPED;
-    } else {
+    } else if (n_seg >= budget && !handoff_tried) {
+      // ---- hand the history to the wave-per-packet kernel
+      handoff_tried = true;
+      const unsigned long long h = atomicAdd(&m.counters[CTR_LONG_COUNT], 1ull);
+      if (h < m.long_cap) {
+        LongState st;
+        st.slot = slot;
+        st.pid = pid;
+        st.r = r;
+        st.mu = mu;
+        st.nu = nu;
+        st.E = E;
+        st.mu0 = mu0;
+        st.nu_cmf0 = nu_cmf0;
+        st.n_seg = n_seg;
+        st.n_pass = n_pass;
+        st.hash = hash;
+        st.draw = 2ull * g.block + g.pos;
+        st.shell = shell;
+        st.next_line = next_line;
+        st.last_line = last_line;
+        st.n_esc = n_esc;
+        st.n_line = n_line;
+        st.pad = 0;
+        m.longs[h] = st;
+        active = false;
+        continue;
+      }
+    }
+    if (status == SMC_LIVE) {
+      // ---- one flight segment (section 2.6)
       n_seg += 1;
       rng_topup(g, 3, sk);  // tau_event + at most two event draws
       const double tau0 = -log(rng_next(g));
       const int sh = shell;
-      const double r_in = m.r_bounds[sh];
-      const double r_out = m.r_bounds[sh + 1];
+      if (sh != c_shell) {
+        c_shell = sh;
+        c_rin = m.r_bounds[sh];
+        c_rout = m.r_bounds[sh + 1];
+        c_ne = m.n_e[sh];
+      }
       const double rmu = r * mu;
       const double D = 1.0 - rmu * inv_ct;
       const double nu_cmf = nu * D;
       const double e_cmf = E * D;
-      // distance to the shell boundary met first (ray-sphere intersection)
-      const double b = r * r * ((1.0 - mu) * (1.0 + mu));
-      const bool inward = mu < 0.0 && b < r_in * r_in;
-      double q = inward ? r_in * r_in - b : r_out * r_out - b;
-      q = q < 0.0 ? 0.0 : q;
-      const double sq = sqrt(q);
-      double d_shell = inward ? -rmu - sq : sq - rmu;
-      d_shell = d_shell < 0.0 ? 0.0 : d_shell;
-      const double kappa = kSigmaT * m.n_e[sh] * D;  // Thomson opacity with D
+      bool inward;
+      const double d_shell = shell_distance(r, mu, rmu, c_rin, c_rout, inward);
+      const double kappa = kSigmaT * c_ne * D;  // Thomson opacity with D
       const double inv_nu = 1.0 / nu;
       const double ct_over_nu = ct * inv_nu;
       const double jb_w = E * inv_nu * inv_nu;  // J_blue weight per unit nu_k
@@ -356,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
       double tau_rem = tau0;
       int32_t k = next_line;
       bool line_hit = false;
-      double d_line = 0.0;
+      double d_line = 0.0, nu_hit = 0.0;
       const double* __restrict__ tau_row = m.tau + (size_t)sh * Lp;
       double* jb_row = want_jblue ? m.jblue + (size_t)sh * (size_t)L : nullptr;
       bool stop = k >= L;
@@ -389,6 +530,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
                 if (tau_k + kappa * dl > tau_rem) {
                   line_hit = true;
                   d_line = dl;
+                  nu_hit = nu_k;
                   stop = true;
                 } else {
                   tau_rem -= tau_k;
@@ -410,8 +552,8 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
       // J and nu-bar estimators (section 2.7), register-accumulated per shell
       if (acc_shell != sh) {
         if (acc_shell >= 0) {
-          atomicAdd(&lds_J[acc_shell], acc_J);
-          atomicAdd(&lds_nb[acc_shell], acc_nb);
+          atomicAdd(&tl.J[acc_shell], acc_J);
+          atomicAdd(&tl.nb[acc_shell], acc_nb);
         }
         acc_shell = sh;
         acc_J = 0.0;
@@ -428,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
 
       if (cross) {
         const int kind = inward ? EV_SHELL_IN : EV_SHELL_OUT;
-        r = inward ? r_in : r_out;
+        r = inward ? c_rin : c_rout;
         mu = mu_new;
         hash = fnv_event(hash, kind, sh, -1, -1);
         shell = sh + (inward ? -1 : 1);
@@ -445,14 +587,15 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
         int32_t emit = k;
         if (line_hit) {
           const double u_branch = rng_next(g);
+          nu_cmf_out = nu_hit;
           if (downbranch) {
             const int32_t up = m.line_upper[k];
             const int64_t a = m.level_ptr[up], e = m.level_ptr[up + 1];
             int64_t j = a;
             while (j < e - 1 && !(m.em_cum[j] > u_branch)) ++j;
             emit = m.em_line[j];
+            nu_cmf_out = m.line_nu[emit];
           }
-          nu_cmf_out = m.line_nu[emit];
         }
         const double mu_out = 2.0 * rng_next(g) - 1.0;
         const double D_new = 1.0 - (mu_out * r_new) * inv_ct;
@@ -474,73 +617,253 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
     }
 
     if (status != SMC_LIVE) {
-      // end of the history: spectrum and luminosity tallies (section 2.9)
-      if (status == SMC_ESCAPED) {
-        int bin;
-        if (!(nu >= m.nu_min)) {
-          bin = m.n_bins;  // underflow (a NaN would land here too, never out of range)
-        } else {
-          const double f = floor((nu - m.nu_min) / dnu_bin);
-          bin = f >= (double)m.n_bins ? m.n_bins + 1 : (int)f;
-        }
-        atomicAdd(&lds_spec[bin], E);
-        atomicAdd(&lds_L[0], E);
-        atomicAdd(&lds_cnt[SMC_C_ESCAPED], 1ull);
-      } else if (status == SMC_REABSORBED) {
-        atomicAdd(&lds_L[1], E);
-        atomicAdd(&lds_cnt[SMC_C_REABSORBED], 1ull);
-      } else {
-        atomicAdd(&lds_L[2], E);
-        atomicAdd(&lds_cnt[SMC_C_CAPPED], 1ull);
-      }
-      // crossings = segments - interactions, except the capped check that
-      // ends a history without a segment
-      atomicAdd(&lds_cnt[SMC_C_SEGMENTS], (unsigned long long)n_seg);
-      atomicAdd(&lds_cnt[SMC_C_LINE_PASSES], (unsigned long long)n_pass);
-      atomicAdd(&lds_cnt[SMC_C_LINE_EVENTS], (unsigned long long)n_line);
-      atomicAdd(&lds_cnt[SMC_C_ESCATTERS], (unsigned long long)n_esc);
-      atomicAdd(&lds_cnt[SMC_C_CROSSINGS], (unsigned long long)(n_seg - n_line - n_esc));
-      if (want_packets) {
-        smc_packet_out rec;
-        rec.id = pid;
-        rec.status = status;
-        rec.shell = shell;
-        rec.nu = nu;
-        rec.energy = E;
-        rec.mu = mu;
-        rec.r = r;
-        rec.mu0 = mu0;
-        rec.nu_cmf0 = nu_cmf0;
-        rec.n_segments = n_seg;
-        rec.n_escatter = n_esc;
-        rec.n_line = n_line;
-        rec.n_passes = n_pass;
-        rec.hash = hash;
-        rec.last_line = last_line;
-        static_cast<smc_packet_out*>(m.packets)[slot] = rec;
-      }
+      tally_end(m, tl, status, nu, E, dnu_bin, n_seg, n_pass, n_line, n_esc);
+      if (want_packets)
+        write_record(m, slot, pid, status, shell, nu, E, mu, r, mu0, nu_cmf0, n_seg, n_esc,
+                     n_line, n_pass, hash, last_line);
       active = false;
     }
   }
 
   if (acc_shell >= 0) {
-    atomicAdd(&lds_J[acc_shell], acc_J);
-    atomicAdd(&lds_nb[acc_shell], acc_nb);
+    atomicAdd(&tl.J[acc_shell], acc_J);
+    atomicAdd(&tl.nb[acc_shell], acc_nb);
   }
-  __syncthreads();
-  // merge the workgroup's LDS tallies into HBM
-  for (size_t i = threadIdx.x; i < n_dbl; i += blockDim.x) {
-    const double v = lds[i];
-    if (v == 0.0) continue;
-    if (i < 2 * (size_t)S + (size_t)m.n_bins + 2)
-      unsafeAtomicAdd(&m.raw[i], v);
-    else
-      unsafeAtomicAdd(&m.lsum[i - (2 * (size_t)S + (size_t)m.n_bins + 2)], v);
+  lds_tally_flush(m, tl, lds);
+}
+
+// ---------------------------------------------------------------------------
+// wave-per-packet kernel for the handed-off histories
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+constexpr int kLongBlock = 64;
+
+__global__ __launch_bounds__(kLongBlock) void long_kernel(DevModel m, DevIter it) {
+  extern __shared__ double lds[];
+  const LdsTally tl = lds_tally_init(m, lds);
+  const int S = m.S;
+  const int32_t L = m.L;
+  const int lane = threadIdx.x;
+  const double ct = m.ct;
+  const double inv_ct = 1.0 / ct;
+  const double dnu_bin = (m.nu_max - m.nu_min) / (double)m.n_bins;
+  const bool want_jblue = m.jblue != nullptr && (it.flags & SMC_F_JBLUE);
+  const bool want_packets = m.packets != nullptr && (it.flags & SMC_F_PACKETS);
+  const bool downbranch = m.mode == SMC_DOWNBRANCH;
+  const size_t Lp = (size_t)m.Lp;
+  unsigned long long n_long = m.counters[CTR_LONG_COUNT];
+  if (n_long > m.long_cap) n_long = m.long_cap;
+  StreamKey sk;
+  sk.k0 = (uint32_t)m.seed;
+  sk.k1 = (uint32_t)(m.seed >> 32);
+  sk.iter = it.iteration;
+
+  double acc_J = 0.0, acc_nb = 0.0;
+  int acc_shell = -1;
+
+  for (;;) {
+    unsigned long long idx = 0;
+    if (lane == 0) idx = atomicAdd(&m.counters[CTR_LONG_QUEUE], 1ull);
+    idx = __shfl(idx, 0, kWave);
+    if (idx >= n_long) break;
+    const LongState st = m.longs[idx];
+    uint64_t n_seg = st.n_seg, n_pass = st.n_pass, hash = st.hash, draw = st.draw;
+    double r = st.r, mu = st.mu, nu = st.nu, E = st.E;
+    int32_t shell = st.shell, next_line = st.next_line, last_line = st.last_line;
+    uint32_t n_esc = st.n_esc, n_line = st.n_line;
+    sk.p0 = (uint32_t)st.pid;
+    sk.p1 = (uint32_t)(st.pid >> 32);
+
+    // 128 upcoming draws: lane i holds draws 2(rb + i) and 2(rb + i) + 1,
+    // with their negative logarithms for tau_event
+    uint32_t rb = (uint32_t)(draw >> 1);
+    Block blk = stream_block(sk, rb + lane);
+    double ua = to_uniform(blk.a), ub = to_uniform(blk.b);
+    double la = -log(ua), lb = -log(ub);
+    // 64 lines of one shell: lane i holds line wbase + i
+    int32_t wbase = -1, wshell = -1;
+    double wn = 0.0, wt = 0.0;
+    // cached shell parameters
+    int32_t c_shell = -1;
+    double c_rin = 0.0, c_rout = 0.0, c_ne = 0.0;
+
+    int status = SMC_LIVE;
+    for (;;) {
+      if (n_seg >= it.max_segments) {
+        status = SMC_CAPPED;
+        break;
+      }
+      n_seg += 1;
+      if (draw + 3 > 2ull * (rb + kWave)) {
+        rb = (uint32_t)(draw >> 1);
+        blk = stream_block(sk, rb + lane);
+        ua = to_uniform(blk.a);
+        ub = to_uniform(blk.b);
+        la = -log(ua);
+        lb = -log(ub);
+      }
+      const int src0 = uniform_i32((int)((draw >> 1) - rb));
+      const double tau0 = readlane_f64((draw & 1) ? lb : la, src0);
+      draw += 1;
+      const int sh = shell;
+      if (sh != c_shell) {
+        c_shell = sh;
+        c_rin = m.r_bounds[sh];
+        c_rout = m.r_bounds[sh + 1];
+        c_ne = m.n_e[sh];
+      }
+      const double rmu = r * mu;
+      const double D = 1.0 - rmu * inv_ct;
+      const double nu_cmf = nu * D;
+      const double e_cmf = E * D;
+      bool inward;
+      const double d_shell = shell_distance(r, mu, rmu, c_rin, c_rout, inward);
+      const double kappa = kSigmaT * c_ne * D;
+      const double inv_nu = 1.0 / nu;
+      const double ct_over_nu = ct * inv_nu;
+      const double jb_w = E * inv_nu * inv_nu;
+
+      // line march over the register window; passed lines get their J_blue
+      // update from the lane holding them
+      double tau_rem = tau0;
+      int32_t k = next_line;
+      int32_t k_first = k;  // first line of the march still to be tallied
+      bool line_hit = false;
+      double d_line = 0.0, nu_hit = 0.0;
+      double* jb_row = want_jblue ? m.jblue + (size_t)sh * (size_t)L : nullptr;
+      while (k < L) {
+        if (sh != wshell || k >= wbase + kWave || k < wbase) {
+          if (jb_row && k > k_first) {
+            const int32_t line = wbase + lane;
+            if (line >= k_first && line < k) unsafeAtomicAdd(&jb_row[line], jb_w * wn);
+          }
+          k_first = k;
+          wbase = k;
+          wshell = sh;
+          const int32_t line = k + lane;
+          wn = line < L ? m.line_nu[line] : 0.0;
+          wt = line < L ? m.tau[(size_t)sh * Lp + line] : 0.0;
+        }
+        const int src = uniform_i32(k - wbase);
+        const double nu_k = readlane_f64(wn, src);
+        double dl = (nu_cmf - nu_k) * ct_over_nu;
+        dl = dl < 0.0 ? 0.0 : dl;
+        if (!(kappa * dl < tau_rem && dl < d_shell)) break;
+        n_pass += 1;
+        const double tau_k = readlane_f64(wt, src);
+        if (tau_k + kappa * dl > tau_rem) {
+          line_hit = true;
+          d_line = dl;
+          nu_hit = nu_k;
+          break;
+        }
+        tau_rem -= tau_k;
+        k += 1;
+      }
+      if (jb_row) {
+        const int32_t k_end = line_hit ? k + 1 : k;
+        const int32_t line = wbase + lane;
+        if (k_end > k_first && sh == wshell && line >= k_first && line < k_end)
+          unsafeAtomicAdd(&jb_row[line], jb_w * wn);
+      }
+      next_line = k;
+
+      const double d_electron = kappa > 0.0 ? tau_rem / kappa : INFINITY;
+      const bool escat = !line_hit && d_electron < d_shell;
+      const bool cross = !line_hit && !escat;
+      const double d = line_hit ? d_line : (escat ? d_electron : d_shell);
+
+      if (acc_shell != sh) {
+        if (acc_shell >= 0 && lane == 0) {
+          atomicAdd(&tl.J[acc_shell], acc_J);
+          atomicAdd(&tl.nb[acc_shell], acc_nb);
+        }
+        acc_shell = sh;
+        acc_J = 0.0;
+        acc_nb = 0.0;
+      }
+      const double jc = e_cmf * d * D;
+      acc_J += jc;
+      acc_nb += jc * nu_cmf;
+
+      const double r_new = sqrt(r * r + d * d + 2.0 * r * d * mu);
+      double mu_new = (rmu + d) / r_new;
+      mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
+
+      if (cross) {
+        const int kind = inward ? EV_SHELL_IN : EV_SHELL_OUT;
+        r = inward ? c_rin : c_rout;
+        mu = mu_new;
+        hash = fnv_event(hash, kind, sh, -1, -1);
+        shell = sh + (inward ? -1 : 1);
+        if (shell >= S) {
+          status = SMC_ESCAPED;
+          break;
+        }
+        if (shell < 0) {
+          status = SMC_REABSORBED;
+          break;
+        }
+      } else {
+        const double D_old = 1.0 - (mu_new * r_new) * inv_ct;
+        const double e_cmf_ev = E * D_old;
+        double nu_cmf_out = nu * D_old;
+        int32_t emit = k;
+        if (line_hit) {
+          const int sb = uniform_i32((int)((draw >> 1) - rb));
+          const double u_branch = readlane_f64((draw & 1) ? ub : ua, sb);
+          draw += 1;
+          nu_cmf_out = nu_hit;
+          if (downbranch) {
+            const int32_t up = m.line_upper[k];
+            const int64_t a = m.level_ptr[up], e = m.level_ptr[up + 1];
+            int64_t j = a;
+            while (j < e - 1 && !(m.em_cum[j] > u_branch)) ++j;
+            emit = m.em_line[j];
+            nu_cmf_out = m.line_nu[emit];
+          }
+        }
+        const int sm = uniform_i32((int)((draw >> 1) - rb));
+        const double mu_out = 2.0 * readlane_f64((draw & 1) ? ub : ua, sm) - 1.0;
+        draw += 1;
+        const double D_new = 1.0 - (mu_out * r_new) * inv_ct;
+        const double inv_D = 1.0 / D_new;
+        r = r_new;
+        mu = mu_out;
+        nu = nu_cmf_out * inv_D;
+        E = e_cmf_ev * inv_D;
+        if (line_hit) {
+          next_line = emit + 1;
+          n_line += 1;
+          last_line = k;
+          hash = fnv_event(hash, EV_LINE, sh, k, emit);
+        } else {
+          n_esc += 1;
+          hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
+        }
+      }
+    }
+
+    if (lane == 0) {
+      tally_end(m, tl, status, nu, E, dnu_bin, n_seg, n_pass, n_line, n_esc);
+      if (want_packets)
+        write_record(m, st.slot, st.pid, status, shell, nu, E, mu, r, st.mu0, st.nu_cmf0, n_seg,
+                     n_esc, n_line, n_pass, hash, last_line);
+    }
   }
-  if (threadIdx.x < SMC_N_COUNTERS) {
-    const unsigned long long v = lds_cnt[threadIdx.x];
-    if (v) atomicAdd(&m.counters[threadIdx.x], v);
+  if (acc_shell >= 0 && lane == 0) {
+    atomicAdd(&tl.J[acc_shell], acc_J);
+    atomicAdd(&tl.nb[acc_shell], acc_nb);
   }
+  lds_tally_flush(m, tl, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -594,6 +917,7 @@ __global__ void jblue_scale_kernel(DevModel m) {
 }  // namespace
 
 int transport_block_threads() { return kBlock; }
+int long_block_threads() { return kLongBlock; }
 
 size_t transport_lds_bytes(const DevModel& m) {
   return sizeof(double) * (lds_doubles(m.S, m.n_bins) + SMC_N_COUNTERS);
@@ -621,6 +945,22 @@ hipError_t launch_reset(const DevModel& m, const DevIter& it, hipStream_t s) {
 hipError_t launch_transport(const DevModel& m, const DevIter& it, int grid, hipStream_t s) {
   hipLaunchKernelGGL(transport_kernel, dim3(grid), dim3(kBlock), transport_lds_bytes(m), s, m,
                      it);
+  return hipGetLastError();
+}
+
+// resident workgroups per CU with the LDS of a typical model (S = 100,
+// 1000 spectrum bins); the LDS of one workgroup never limits these kernels
+hipError_t transport_occupancy(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel, kBlock,
+                                                      sizeof(double) * 1400);
+}
+hipError_t long_occupancy(int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, long_kernel, kLongBlock,
+                                                      sizeof(double) * 1400);
+}
+
+hipError_t launch_long(const DevModel& m, const DevIter& it, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(long_kernel, dim3(grid), dim3(kLongBlock), transport_lds_bytes(m), s, m, it);
   return hipGetLastError();
 }
 

@@ -39,6 +39,11 @@ class smc_model_desc(C.Structure):
                 ("seed", C.c_uint64)]
 
 
+class smc_tune(C.Structure):
+    _fields_ = [("blocks_per_cu", C.c_int32), ("long_waves_per_cu", C.c_int32),
+                ("long_budget", C.c_uint32), ("reserved", C.c_uint32)]
+
+
 class smc_iter_params(C.Structure):
     _fields_ = [("n_packets", C.c_uint64), ("iteration", C.c_uint32), ("flags", C.c_uint32),
                 ("T_inner", C.c_double), ("L_requested", C.c_double), ("damping", C.c_double),
@@ -54,7 +59,8 @@ PACKET_DTYPE = np.dtype([("id", np.uint64), ("status", np.int32), ("shell", np.i
 
 EXPORTS = ("smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_model_workspace_bytes",
            "smc_model_load", "smc_model_free", "smc_run_iteration", "smc_read_estimators",
-           "smc_read_spectrum", "smc_read_counters", "smc_read_packets", "smc_read_timing")
+           "smc_read_spectrum", "smc_read_counters", "smc_read_packets", "smc_read_timing",
+           "smc_model_set_tune", "smc_model_get_tune")
 
 
 class SmcError(RuntimeError):
@@ -91,6 +97,8 @@ def load_library(path: str = LIB_PATH):
     L.smc_read_counters.argtypes = [vp, _u64p, vp]
     L.smc_read_packets.argtypes = [vp, vp, C.c_uint64, vp]
     L.smc_read_timing.argtypes = [vp, _dp]
+    L.smc_model_set_tune.argtypes = [vp, C.POINTER(smc_tune)]
+    L.smc_model_get_tune.argtypes = [vp, C.POINTER(smc_tune)]
     for name in EXPORTS:
         if name != "smc_last_error":
             getattr(L, name).restype = C.c_int
@@ -252,6 +260,18 @@ class Model:
         c = np.zeros(8, dtype=np.uint64)
         _check(_lib.smc_read_counters(self.handle, _ptr(c, _u64p), _stream_ptr(stream)))
         return {k: int(v) for k, v in zip(COUNTER_NAMES, c)}
+
+    def set_tune(self, blocks_per_cu=0, long_waves_per_cu=0, long_budget=0):
+        """Launch tuning (0 = library default; long_budget=2**32-1 disables
+        the hand-off to the wave-per-packet kernel)."""
+        t = smc_tune(int(blocks_per_cu), int(long_waves_per_cu), int(long_budget), 0)
+        _check(_lib.smc_model_set_tune(self.handle, C.byref(t)))
+
+    def get_tune(self):
+        t = smc_tune()
+        _check(_lib.smc_model_get_tune(self.handle, C.byref(t)))
+        return dict(blocks_per_cu=t.blocks_per_cu, long_waves_per_cu=t.long_waves_per_cu,
+                    long_budget=t.long_budget)
 
     def read_timing(self):
         """Transport-kernel duration of the last (timed) iteration in ms."""

@@ -10,11 +10,14 @@ DIVERGE_FRACTION = 1e-4
 
 
 def gpu_run(ctx, model, n_packets, T_inner, iteration=0, packet_ids=None, flags=None,
-            L_requested=0.0, damping=1.0, max_segments=10**7, n_packets_max=None, jblue=True):
+            L_requested=0.0, damping=1.0, max_segments=10**7, n_packets_max=None, jblue=True,
+            tune=None):
     if flags is None:
         flags = (smc.F_JBLUE if jblue else 0) | smc.F_PACKETS
     n_work = len(packet_ids) if packet_ids is not None else n_packets
     m = smc.Model(ctx, model, n_packets_max or max(n_work, 1), flags=flags)
+    if tune:
+        m.set_tune(**tune)
     m.run_iteration(n_packets, T_inner, iteration=iteration, flags=flags,
                     L_requested=L_requested, damping=damping, max_segments=max_segments,
                     packet_ids=packet_ids)

@@ -25,9 +25,9 @@ def ctx():
 
 
 def _compare_iteration(ctx, model, N, T, iteration=0, ids=None, L_requested=0.0, damping=1.0,
-                       max_segments=10**7, jblue=True):
+                       max_segments=10**7, jblue=True, tune=None):
     g = gpu_run(ctx, model, N, T, iteration=iteration, packet_ids=ids, L_requested=L_requested,
-                damping=damping, max_segments=max_segments, jblue=jblue)
+                damping=damping, max_segments=max_segments, jblue=jblue, tune=tune)
     raw, fin = oracle_run(model, N, T, iteration=iteration, packet_ids=ids,
                           L_requested=L_requested, damping=damping,
                           max_segments=max_segments, jblue=jblue)
@@ -38,7 +38,7 @@ def _compare_iteration(ctx, model, N, T, iteration=0, ids=None, L_requested=0.0,
         keep = np.delete(all_ids, bad)
         g = gpu_run(ctx, model, N, T, iteration=iteration, packet_ids=keep,
                     L_requested=L_requested, damping=damping, max_segments=max_segments,
-                    jblue=jblue)
+                    jblue=jblue, tune=tune)
         raw, fin = oracle_run(model, N, T, iteration=iteration, packet_ids=keep,
                               L_requested=L_requested, damping=damping,
                               max_segments=max_segments, jblue=jblue)
@@ -78,6 +78,29 @@ def test_scatter_20shell_300kline_sample(ctx):
 def test_downbranch_30shell_20kline_sample(ctx):
     w = W.config3()
     _compare_iteration(ctx, w.model, 4000, w.T_inner)
+
+
+# histories moved to the wave-per-packet kernel after 1, 2 or 40 segments, or never
+HANDOFF = [dict(long_budget=1), dict(long_budget=2), dict(long_budget=40),
+           dict(long_budget=2**32 - 1)]
+
+
+@pytest.mark.parametrize("tune", HANDOFF, ids=lambda t: f"budget{t['long_budget']}")
+def test_handoff_scatter_300kline(ctx, tune):
+    w = W.config2()
+    _compare_iteration(ctx, w.model, 2000, w.T_inner, tune=tune)
+
+
+@pytest.mark.parametrize("tune", HANDOFF[:2], ids=lambda t: f"budget{t['long_budget']}")
+def test_handoff_downbranch(ctx, tune):
+    w = W.config3()
+    _compare_iteration(ctx, w.model, 2000, w.T_inner, tune=tune)
+
+
+def test_handoff_with_event_cap_and_small_grids(ctx):
+    m = W.small_model(seed=14, n_shells=6, n_lines=700)
+    _compare_iteration(ctx, m, 3000, 10000.0, max_segments=7,
+                       tune=dict(long_budget=3, blocks_per_cu=1, long_waves_per_cu=1))
 
 
 @pytest.mark.parametrize("n", [1, 63, 65, 257, 1000])
