@@ -134,7 +134,8 @@ typedef struct {
   uint32_t reserved;         /* must be 0 */
 } smc_tune;
 
-/* Create a context on HIP device `hip_device`. */
+/* Create a context on HIP device `hip_device`.  The context owns a few small
+ * device and pinned host buffers for multi-model launches (about 1.5 MB). */
 int smc_ctx_create(smc_ctx** out, int hip_device);
 int smc_ctx_destroy(smc_ctx* ctx);
 const char* smc_last_error(void);
@@ -178,6 +179,24 @@ int smc_read_counters(smc_model* model, uint64_t* counters, void* stream);
 /* Copy the first n per-packet records of the last iteration
  * (requires SMC_F_PACKETS in both the load and the iteration flags). */
 int smc_read_packets(smc_model* model, smc_packet_out* out, uint64_t n, void* stream);
+
+/* Enqueue one iteration of each of n_models models (1 .. 1024, distinct, all
+ * of this context) as ONE set of launches on `stream`: every kernel of the
+ * iteration covers all models, and the lane-per-packet kernel pulls packets
+ * of any model from one launch-wide queue, so models of uneven size and the
+ * long histories of one overlap the bulk of the others.  params[k] is model
+ * k's iteration (as for smc_run_iteration); `tune` (NULL: defaults) shapes
+ * the launches; flags may hold SMC_F_TIMING (smc_batch_read_timing).
+ * Results per model are those of smc_run_iteration up to the summation order
+ * of the tallies.  The context stages the model table in a ring of pinned
+ * and device buffers it owns, so calls may follow one another without
+ * waiting for the GPU.  Asynchronous. */
+int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
+                  int n_models, const smc_tune* tune, uint32_t flags, void* stream);
+
+/* Duration in milliseconds of the transport kernels of the last timed batch
+ * of this context.  Waits for them to end. */
+int smc_batch_read_timing(smc_ctx* ctx, double* transport_ms);
 
 /* Set (NULL: reset to defaults) or read the launch tuning of a model.  Tuning
  * changes launch shapes only: results are identical up to the summation

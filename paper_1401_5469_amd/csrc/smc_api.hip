@@ -13,11 +13,24 @@
 #include "../../include/smc.h"
 #include "smc_internal.h"
 
+// Multi-model launches stage their model table in pinned host memory and
+// copy it to a device table; kBatchSlots of each rotate so that a slot is
+// reused only after the launch that read it has finished (event per slot).
+constexpr int kBatchSlots = 4;
+
 struct smc_ctx {
   int device;
   int n_cu;
-  int transport_blocks_per_cu;  // occupancy of the lane-per-packet kernel
-  int long_blocks_per_cu;       // occupancy of the wave-per-packet kernel
+  int transport_blocks_per_cu[2];  // occupancy of the lane-per-packet kernel (single, multi)
+  int long_blocks_per_cu[2];       // occupancy of the wave-per-packet kernel
+  smc::BatchEntry* host_table[kBatchSlots];   // pinned
+  smc::BatchEntry* dev_table[kBatchSlots];
+  unsigned long long* dev_ctr[kBatchSlots];   // [3] launch-wide queues
+  hipEvent_t slot_done[kBatchSlots];
+  bool slot_used[kBatchSlots];
+  int next_slot;
+  hipEvent_t ev_start, ev_stop;               // timing of the last batch
+  bool batch_timed;
 };
 
 struct smc_model {
@@ -69,6 +82,84 @@ int hip_fail(hipError_t e, const char* what) {
 
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kDefaultLongBudget = 1024;
+
+void release_ctx(smc_ctx* c) {
+  if (!c) return;
+  for (int i = 0; i < kBatchSlots; ++i) {
+    if (c->slot_done[i]) (void)hipEventSynchronize(c->slot_done[i]);
+    if (c->host_table[i]) (void)hipHostFree(c->host_table[i]);
+    if (c->dev_table[i]) (void)hipFree(c->dev_table[i]);
+    if (c->dev_ctr[i]) (void)hipFree(c->dev_ctr[i]);
+    if (c->slot_done[i]) (void)hipEventDestroy(c->slot_done[i]);
+  }
+  if (c->ev_start) (void)hipEventDestroy(c->ev_start);
+  if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
+  delete c;
+}
+
+uint32_t budget_of(const smc_tune& t) {
+  return t.long_budget == 0 ? kDefaultLongBudget
+                            : (t.long_budget == UINT32_MAX ? 0u : t.long_budget);
+}
+
+// launch shape from the tuning (0 = occupancy default), capped by the work
+smc::Shape shape_of(const smc_ctx* c, const smc_tune& t, bool multi, uint64_t n_work,
+                    bool handoff) {
+  smc::Shape sh;
+  const int block = smc::transport_block_threads();
+  uint64_t want = (n_work + block - 1) / block;
+  const int per_cu = t.blocks_per_cu > 0 ? t.blocks_per_cu : c->transport_blocks_per_cu[multi];
+  const uint64_t cap = (uint64_t)c->n_cu * (uint64_t)per_cu;
+  sh.transport_grid = (int)(want > cap ? cap : want);
+  uint64_t lgrid = 0;
+  if (handoff && n_work > 0) {
+    const int lper = t.long_waves_per_cu > 0 ? t.long_waves_per_cu : c->long_blocks_per_cu[multi];
+    lgrid = (uint64_t)c->n_cu * (uint64_t)lper;
+    if (lgrid > n_work) lgrid = n_work;
+  }
+  sh.long_grid = (int)lgrid;
+  return sh;
+}
+
+// validate one iteration's parameters against its model; fill the device view
+int make_iter(const smc_model* m, const smc_iter_params* p, uint32_t budget, smc::DevIter* it) {
+  if (!p) return fail(SMC_EINVAL, "null parameters");
+  if (p->n_packets == 0) return fail(SMC_EINVAL, "n_packets must be >= 1");
+  if (p->flags & ~(SMC_F_JBLUE | SMC_F_PACKETS | SMC_F_TIMING))
+    return fail(SMC_EINVAL, "unknown flags");
+  if ((p->flags & ~m->load_flags & (SMC_F_JBLUE | SMC_F_PACKETS)) != 0)
+    return fail(SMC_EINVAL, "iteration flags 0x%x exceed the model's load flags 0x%x", p->flags,
+                m->load_flags);
+  if (p->packet_ids == nullptr && p->n_ids != 0)
+    return fail(SMC_EINVAL, "n_ids given without packet_ids");
+  const uint64_t n_work = p->packet_ids ? p->n_ids : p->n_packets;
+  if (n_work > m->n_packets_max)
+    return fail(SMC_ENOMEM, "%llu packets exceed the model's n_packets_max=%llu",
+                (unsigned long long)n_work, (unsigned long long)m->n_packets_max);
+  if (!(p->T_inner > 0.0) && !m->has_T)
+    return fail(SMC_EINVAL, "T_inner must be > 0 on the first iteration");
+  if (!isfinite(p->T_inner)) return fail(SMC_EINVAL, "T_inner must be finite");
+  if (p->L_requested > 0.0 && !(p->damping > 0.0 && p->damping <= 1.0))
+    return fail(SMC_EINVAL, "damping must lie in (0, 1]");
+  if (p->max_segments < 1 || p->max_segments > (1ull << 30))
+    return fail(SMC_EINVAL, "max_segments must lie in [1, 2^30]");
+  it->n_packets = p->n_packets;
+  it->n_work = n_work;
+  it->ids = p->packet_ids;
+  it->max_segments = p->max_segments;
+  it->iteration = p->iteration;
+  it->flags = p->flags;
+  it->long_budget = budget;
+  it->pad = 0;
+  it->T_param = p->T_inner;
+  it->L_requested = p->L_requested;
+  it->damping = p->damping;
+  return SMC_OK;
+}
+
+uint64_t jblue_entries(const smc_model* m, uint32_t flags) {
+  return (m->dev.jblue && (flags & SMC_F_JBLUE)) ? (uint64_t)m->dev.S * (uint64_t)m->dev.L : 0;
+}
 constexpr int kMaxBins = 8192;
 constexpr int kMaxShells = 4096;
 
@@ -200,19 +291,41 @@ int smc_ctx_create(smc_ctx** out, int hip_device) {
                 prop.gcnArchName);
   smc_ctx* c = new (std::nothrow) smc_ctx;
   if (!c) return fail(SMC_ENOMEM, "host allocation failed");
+  memset(c, 0, sizeof *c);
   c->device = hip_device;
   c->n_cu = prop.multiProcessorCount;
-  int occ = 0;
-  HIP_TRY(smc::transport_occupancy(&occ), "occupancy query");
-  c->transport_blocks_per_cu = occ > 0 ? occ : 1;
-  HIP_TRY(smc::long_occupancy(&occ), "occupancy query");
-  c->long_blocks_per_cu = occ > 0 ? occ : 1;
+  for (int multi = 0; multi < 2; ++multi) {
+    int occ = 0;
+    hipError_t e = smc::transport_occupancy(multi != 0, &occ);
+    if (e != hipSuccess) {
+      release_ctx(c);
+      return hip_fail(e, "occupancy query");
+    }
+    c->transport_blocks_per_cu[multi] = occ > 0 ? occ : 1;
+    e = smc::long_occupancy(multi != 0, &occ);
+    if (e != hipSuccess) {
+      release_ctx(c);
+      return hip_fail(e, "occupancy query");
+    }
+    c->long_blocks_per_cu[multi] = occ > 0 ? occ : 1;
+  }
+  for (int i = 0; i < kBatchSlots; ++i) {
+    const size_t tb = sizeof(smc::BatchEntry) * smc::kMaxBatchModels;
+    hipError_t e = hipHostMalloc((void**)&c->host_table[i], tb, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->dev_table[i], tb);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->dev_ctr[i], 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->slot_done[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      release_ctx(c);
+      return hip_fail(e, "batch table allocation");
+    }
+  }
   *out = c;
   return ok();
 }
 
 int smc_ctx_destroy(smc_ctx* ctx) {
-  delete ctx;
+  release_ctx(ctx);
   return ok();
 }
 
@@ -338,26 +451,10 @@ int smc_model_free(smc_model* model) {
 
 int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   if (!m || !p) return fail(SMC_EINVAL, "null model or parameters");
-  if (p->n_packets == 0) return fail(SMC_EINVAL, "n_packets must be >= 1");
-  if (p->flags & ~(SMC_F_JBLUE | SMC_F_PACKETS | SMC_F_TIMING))
-    return fail(SMC_EINVAL, "unknown flags");
-  if ((p->flags & ~m->load_flags & (SMC_F_JBLUE | SMC_F_PACKETS)) != 0)
-    return fail(SMC_EINVAL, "iteration flags 0x%x exceed the model's load flags 0x%x", p->flags,
-                m->load_flags);
-  const uint64_t n_work = p->packet_ids ? p->n_ids : p->n_packets;
-  if (p->packet_ids == nullptr && p->n_ids != 0)
-    return fail(SMC_EINVAL, "n_ids given without packet_ids");
-  if ((p->flags & SMC_F_PACKETS) && n_work > m->n_packets_max)
-    return fail(SMC_ENOMEM, "%llu packet records exceed n_packets_max=%llu",
-                (unsigned long long)n_work, (unsigned long long)m->n_packets_max);
-  if (!(p->T_inner > 0.0) && !m->has_T)
-    return fail(SMC_EINVAL, "T_inner must be > 0 on the first iteration");
-  if (!isfinite(p->T_inner)) return fail(SMC_EINVAL, "T_inner must be finite");
-  if (p->L_requested > 0.0 && !(p->damping > 0.0 && p->damping <= 1.0))
-    return fail(SMC_EINVAL, "damping must lie in (0, 1]");
-  if (p->max_segments < 1 || p->max_segments > (1ull << 30))
-    return fail(SMC_EINVAL, "max_segments must lie in [1, 2^30]");
-
+  smc::LaunchArgs a;
+  memset(&a, 0, sizeof a);
+  int rc = make_iter(m, p, budget_of(m->tune), &a.single.it);
+  if (rc) return rc;
   HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   const bool timed = (p->flags & SMC_F_TIMING) != 0;
@@ -365,46 +462,103 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
     HIP_TRY(hipEventCreate(&m->ev_start), "hipEventCreate");
     HIP_TRY(hipEventCreate(&m->ev_stop), "hipEventCreate");
   }
-  smc::DevIter it;
-  it.n_packets = p->n_packets;
-  it.n_work = n_work;
-  it.ids = p->packet_ids;
-  it.max_segments = p->max_segments;
-  it.iteration = p->iteration;
-  it.flags = p->flags;
-  it.long_budget = m->tune.long_budget == 0 ? kDefaultLongBudget
-                   : (m->tune.long_budget == UINT32_MAX ? 0 : m->tune.long_budget);
-  it.T_param = p->T_inner;
-  it.L_requested = p->L_requested;
-  it.damping = p->damping;
-
-  HIP_TRY(smc::launch_reset(m->dev, it, s), "reset launch");
-  if (timed) HIP_TRY(hipEventRecord(m->ev_start, s), "hipEventRecord");
-  if (n_work > 0) {
-    const int block = smc::transport_block_threads();
-    uint64_t want = (n_work + block - 1) / block;
-    const int per_cu = m->tune.blocks_per_cu > 0 ? m->tune.blocks_per_cu
-                                                 : m->ctx->transport_blocks_per_cu;
-    const uint64_t cap = (uint64_t)m->ctx->n_cu * (uint64_t)per_cu;
-    if (want > cap) want = cap;
-    HIP_TRY(smc::launch_transport(m->dev, it, (int)want, s), "transport launch");
-    if (it.long_budget > 0) {
-      // histories handed off by the lane-per-packet kernel; the grid drains
-      // the device-side queue, so no host round trip is needed
-      const int lper = m->tune.long_waves_per_cu > 0 ? m->tune.long_waves_per_cu
-                                                     : m->ctx->long_blocks_per_cu;
-      uint64_t lgrid = (uint64_t)m->ctx->n_cu * (uint64_t)lper;
-      if (lgrid > n_work) lgrid = n_work;
-      HIP_TRY(smc::launch_long(m->dev, it, (int)lgrid, s), "long-history launch");
-    }
-  }
-  if (timed) HIP_TRY(hipEventRecord(m->ev_stop, s), "hipEventRecord");
+  a.single.m = m->dev;
+  a.single.work_begin = 0;
+  a.single.long_begin = 0;
+  a.table = nullptr;
+  a.n_models = 1;
+  a.total_work = a.single.it.n_work;
+  a.ctr = m->dev.counters + smc::CTR_QUEUE;
+  const smc::Shape sh =
+      shape_of(m->ctx, m->tune, false, a.total_work, a.single.it.long_budget > 0);
+  HIP_TRY(smc::launch_iteration(a, false, sh, jblue_entries(m, p->flags),
+                                timed ? m->ev_start : nullptr, timed ? m->ev_stop : nullptr, s),
+          "iteration launch");
   m->timed = timed;
-  HIP_TRY(smc::launch_finalise(m->dev, it, s), "finalise launch");
   m->has_T = true;
   m->ran = true;
   m->last_flags = p->flags;
-  m->last_work = n_work;
+  m->last_work = a.single.it.n_work;
+  return ok();
+}
+
+int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
+                  int n_models, const smc_tune* tune, uint32_t flags, void* stream) {
+  if (!ctx || !models || !params) return fail(SMC_EINVAL, "null context, models or parameters");
+  if (n_models < 1 || n_models > smc::kMaxBatchModels)
+    return fail(SMC_EINVAL, "n_models=%d outside [1, %d]", n_models, smc::kMaxBatchModels);
+  if (flags & ~SMC_F_TIMING) return fail(SMC_EINVAL, "unknown batch flags 0x%x", flags);
+  smc_tune t;
+  memset(&t, 0, sizeof t);
+  if (tune) t = *tune;
+  const uint32_t budget = budget_of(t);
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  // take the next slot once the launch that last used it has finished
+  const int slot = ctx->next_slot;
+  if (ctx->slot_used[slot]) HIP_TRY(hipEventSynchronize(ctx->slot_done[slot]), "slot wait");
+  smc::BatchEntry* tab = ctx->host_table[slot];
+  uint64_t work = 0, max_jb = 0;
+  for (int k = 0; k < n_models; ++k) {
+    smc_model* m = models[k];
+    if (!m) return fail(SMC_EINVAL, "model %d is null", k);
+    if (m->ctx != ctx) return fail(SMC_EINVAL, "model %d belongs to another context", k);
+    for (int j = 0; j < k; ++j)
+      if (models[j] == m) return fail(SMC_EINVAL, "model %d appears twice in the batch", k);
+    int rc = make_iter(m, &params[k], budget, &tab[k].it);
+    if (rc) {
+      char msg[512];
+      snprintf(msg, sizeof msg, "model %d: %s", k, g_err.c_str());
+      return fail(rc, "%s", msg);
+    }
+    tab[k].m = m->dev;
+    tab[k].work_begin = work;
+    tab[k].long_begin = 0;
+    work += tab[k].it.n_work;
+    const uint64_t jb = jblue_entries(m, params[k].flags);
+    if (jb > max_jb) max_jb = jb;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipMemcpyAsync(ctx->dev_table[slot], tab, sizeof(smc::BatchEntry) * n_models,
+                         hipMemcpyHostToDevice, s),
+          "batch table upload");
+  const bool timed = (flags & SMC_F_TIMING) != 0;
+  if (timed && !ctx->ev_start) {
+    HIP_TRY(hipEventCreate(&ctx->ev_start), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&ctx->ev_stop), "hipEventCreate");
+  }
+  smc::LaunchArgs a;
+  memset(&a, 0, sizeof a);
+  a.table = ctx->dev_table[slot];
+  a.n_models = n_models;
+  a.total_work = work;
+  a.ctr = ctx->dev_ctr[slot];
+  const smc::Shape sh = shape_of(ctx, t, true, work, budget > 0);
+  HIP_TRY(smc::launch_iteration(a, true, sh, max_jb, timed ? ctx->ev_start : nullptr,
+                                timed ? ctx->ev_stop : nullptr, s),
+          "batch launch");
+  HIP_TRY(hipEventRecord(ctx->slot_done[slot], s), "hipEventRecord");
+  ctx->slot_used[slot] = true;
+  ctx->next_slot = (slot + 1) % kBatchSlots;
+  ctx->batch_timed = timed;
+  for (int k = 0; k < n_models; ++k) {
+    smc_model* m = models[k];
+    m->has_T = true;
+    m->ran = true;
+    m->timed = false;
+    m->last_flags = params[k].flags & ~SMC_F_TIMING;
+    m->last_work = tab[k].it.n_work;
+  }
+  return ok();
+}
+
+int smc_batch_read_timing(smc_ctx* ctx, double* transport_ms) {
+  if (!ctx || !transport_ms) return fail(SMC_EINVAL, "null context or output");
+  if (!ctx->batch_timed) return fail(SMC_EINVAL, "the last batch was not timed");
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  HIP_TRY(hipEventSynchronize(ctx->ev_stop), "hipEventSynchronize");
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_stop), "hipEventElapsedTime");
+  *transport_ms = (double)ms;
   return ok();
 }
 
@@ -482,8 +636,8 @@ int smc_model_set_tune(smc_model* m, const smc_tune* t) {
 int smc_model_get_tune(smc_model* m, smc_tune* t) {
   if (!m || !t) return fail(SMC_EINVAL, "null model or output");
   *t = m->tune;
-  if (t->blocks_per_cu == 0) t->blocks_per_cu = m->ctx->transport_blocks_per_cu;
-  if (t->long_waves_per_cu == 0) t->long_waves_per_cu = m->ctx->long_blocks_per_cu;
+  if (t->blocks_per_cu == 0) t->blocks_per_cu = m->ctx->transport_blocks_per_cu[0];
+  if (t->long_waves_per_cu == 0) t->long_waves_per_cu = m->ctx->long_blocks_per_cu[0];
   if (t->long_budget == 0) t->long_budget = kDefaultLongBudget;
   return ok();
 }

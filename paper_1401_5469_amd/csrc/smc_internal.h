@@ -11,12 +11,12 @@ namespace smc {
 // 256-byte aligned.  Offsets are relative to the workspace base.
 struct Layout {
   uint64_t r_bounds, n_e, volume, v_bounds;        // shells
-  uint64_t line_nu, tau;                            // lines
+  uint64_t line_nu, tau;                            // lines (rows padded to 4)
   uint64_t line_upper, level_ptr, em_line, em_cum;  // downbranch tables
   uint64_t raw;        // [2S + NB + 2] J_raw, nubar_raw, spectrum raw
   uint64_t lsum;       // [4] escaped, reabsorbed, capped lab energy (+ pad)
-  uint64_t counters;   // [SMC_N_COUNTERS + 3] u64: counters, work-queue head,
-                       // long-packet count, long-packet queue head
+  uint64_t counters;   // [CTR_TOTAL] u64: event counters, work-queue head,
+                       // hand-off count, hand-off queue head
   uint64_t longs;      // [n_packets_max] LongState: histories handed to the wave kernel
   uint64_t jblue;      // [S*L] raw, normalised in place by the finaliser
   uint64_t out_shell;  // [6S] J, nubar, T_R, W, jblue scale, pad
@@ -40,13 +40,14 @@ struct LongState {
 enum { CTR_QUEUE = SMC_N_COUNTERS, CTR_LONG_COUNT = SMC_N_COUNTERS + 1,
        CTR_LONG_QUEUE = SMC_N_COUNTERS + 2, CTR_TOTAL = SMC_N_COUNTERS + 3 };
 
-// Everything a kernel needs about one model and one iteration.
+// Everything a kernel needs about one model.
 struct DevModel {
   int32_t S;
   int32_t L;
   int32_t Lp;              // tau_S row stride (L rounded up to a multiple of 4)
   int32_t n_bins;
   int32_t mode;
+  int32_t pad;
   double t_exp;
   double ct;
   double nu_min, nu_max;
@@ -54,15 +55,15 @@ struct DevModel {
   const double* r_bounds;  // [S+1] radii
   const double* n_e;       // [S]
   const double* volume;    // [S]
-  const double* line_nu;   // [L]
-  const double* tau;       // [S*L]
+  const double* line_nu;   // [Lp]
+  const double* tau;       // [S*Lp]
   const int32_t* line_upper;
   const int64_t* level_ptr;
   const int32_t* em_line;
   const double* em_cum;
   double* raw;             // J_raw[S], nubar_raw[S], spec_raw[NB+2]
   double* lsum;            // [4]
-  unsigned long long* counters;  // [SMC_N_COUNTERS], then the work-queue head
+  unsigned long long* counters;  // [CTR_TOTAL]
   double* jblue;           // [S*L] or nullptr
   double* out_shell;       // J, nubar, T_R, W, jblue scale, each [S]
   double* out_spec;        // [NB+2]
@@ -72,6 +73,7 @@ struct DevModel {
   uint64_t long_cap;
 };
 
+// One iteration of one model.
 struct DevIter {
   uint64_t n_packets;      // N (energy 1/N)
   uint64_t n_work;         // packets in this launch
@@ -80,25 +82,52 @@ struct DevIter {
   uint32_t iteration;
   uint32_t flags;
   uint32_t long_budget;    // segments before a history moves to the wave kernel (0: never)
+  uint32_t pad;
   double T_param;          // > 0 overrides the device-resident T_inner
   double L_requested;
   double damping;
+};
+
+// One model of a launch: its arrays, its iteration, and its place in the
+// launch-wide packet and hand-off numbering.
+struct BatchEntry {
+  DevModel m;
+  DevIter it;
+  uint64_t work_begin;     // first launch-wide packet index of this model
+  uint64_t long_begin;     // first launch-wide hand-off index (set on the device)
+};
+
+// Arguments of every transport-path kernel.  A launch over one model passes
+// its entry by value (`single`); a launch over many passes a device table.
+struct LaunchArgs {
+  BatchEntry single;
+  const BatchEntry* table; // [n_models] (multi-model launches)
+  int32_t n_models;
+  int32_t pad;
+  uint64_t total_work;     // packets over all models
+  unsigned long long* ctr; // [3] work-queue head, hand-off total, hand-off queue head
 };
 
 // scalars[] slots
 enum { SC_L_EMITTED = 0, SC_L_REABSORBED = 1, SC_L_CAPPED = 2, SC_L_INNER = 3,
        SC_T_USED = 4, SC_T_NEXT = 5 };
 
-// Host-side launchers implemented in smc_kernels.hip.
+// Launch shape of one iteration (or one batch).
+struct Shape {
+  int transport_grid;
+  int long_grid;
+};
+
+// Host-side launchers implemented in smc_kernels.hip.  `multi` selects the
+// multi-model kernels (a.table valid) instead of the single-model ones.
 hipError_t launch_geometry(const DevModel& m, const double* v_bounds, hipStream_t s);
-hipError_t launch_reset(const DevModel& m, const DevIter& it, hipStream_t s);
-hipError_t launch_transport(const DevModel& m, const DevIter& it, int grid, hipStream_t s);
-hipError_t launch_long(const DevModel& m, const DevIter& it, int grid, hipStream_t s);
-int long_block_threads();
-hipError_t launch_finalise(const DevModel& m, const DevIter& it, hipStream_t s);
-size_t transport_lds_bytes(const DevModel& m);
-hipError_t transport_occupancy(int* blocks_per_cu);
-hipError_t long_occupancy(int* blocks_per_cu);
+hipError_t launch_iteration(const LaunchArgs& a, bool multi, const Shape& shape,
+                            uint64_t max_jblue, hipEvent_t ev_start, hipEvent_t ev_stop,
+                            hipStream_t s);
+hipError_t transport_occupancy(bool multi, int* blocks_per_cu);
+hipError_t long_occupancy(bool multi, int* blocks_per_cu);
 int transport_block_threads();
+int long_block_threads();
+constexpr int kMaxBatchModels = 1024;
 
 }  // namespace smc

@@ -1,14 +1,12 @@
 // smc_kernels.hip -- gfx950 kernels of the r-packet Monte Carlo transport
 // (Kerzendorf & Sim 2014, sections 2.1-2.9).
 //
-// One packet per lane.  A persistent grid pulls packets from a work queue
-// (one atomic per wavefront per refill), so a lane whose packet ends picks up
-// the next one while its neighbours are still marching through lines.  All
-// arithmetic on positions, directions, frequencies and energies is FP64.
-// Shell tallies (J, nu-bar) accumulate in registers while a packet stays in a
-// shell and are flushed to LDS copies private to the workgroup; the spectrum
-// is an LDS histogram; both are merged into HBM once per workgroup.  J_blue
-// (one entry per line and shell) is accumulated with hardware FP64 atomics.
+// Every kernel of the transport path comes in two instantiations: one for a
+// single model (its description travels as a kernel argument, so per-model
+// values are wave-uniform and live in scalar registers) and one for a launch
+// over many models of uneven size (a device table; each lane carries the
+// model of its current packet).  All arithmetic on positions, directions,
+// frequencies and energies is FP64.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -102,6 +100,7 @@ enum { EV_SHELL_OUT = 1, EV_SHELL_IN = 2, EV_ESCATTER = 3, EV_LINE = 4 };
 // initial radiation field of section 2.8 (T_R = 10^4 K, geometric dilution at
 // the shell centre)
 // ---------------------------------------------------------------------------
+
 __global__ void geometry_kernel(DevModel m, const double* __restrict__ v_bounds) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i <= m.S) const_cast<double*>(m.r_bounds)[i] = v_bounds[i] * m.t_exp;
@@ -117,8 +116,18 @@ __global__ void geometry_kernel(DevModel m, const double* __restrict__ v_bounds)
   if (i < 8) m.scalars[i] = 0.0;
 }
 
-// zero every tally of the iteration and fix T_inner (graph-safe: no memset)
-__global__ void reset_kernel(DevModel m, DevIter it) {
+// the model entry of a launch
+#define ENTRY(a, k) (kMulti ? (a).table[(k)] : (a).single)
+
+// ---------------------------------------------------------------------------
+// zero every tally of the iteration and fix T_inner (no memset: graph-safe);
+// blockIdx.y selects the model
+// ---------------------------------------------------------------------------
+template <bool kMulti>
+__global__ void reset_kernel(LaunchArgs a) {
+  const int k = kMulti ? (int)blockIdx.y : 0;
+  const DevModel& m = ENTRY(a, k).m;
+  const DevIter& it = ENTRY(a, k).it;
   const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   const size_t n_raw = 2 * (size_t)m.S + (size_t)m.n_bins + 2;
@@ -129,21 +138,21 @@ __global__ void reset_kernel(DevModel m, DevIter it) {
     const size_t n = (size_t)m.S * (size_t)m.L;
     for (size_t i = tid; i < n; i += stride) m.jblue[i] = 0.0;
   }
-  if (tid == 0) {
-    m.scalars[SC_T_USED] = it.T_param > 0.0 ? it.T_param : m.scalars[SC_T_NEXT];
-  }
+  if (tid == 0) m.scalars[SC_T_USED] = it.T_param > 0.0 ? it.T_param : m.scalars[SC_T_NEXT];
+  if (kMulti && k == 0 && tid < 3) a.ctr[tid] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
 // The transport (sections 2.4-2.7, 2.9) runs in two kernels.
 //
 // transport_kernel: one packet per lane.  A persistent grid pulls packets from
-// a work queue (one atomic per wavefront per refill), so a lane whose packet
-// ends picks up the next one while its neighbours are still marching.  A
-// history still alive after `long_budget` flight segments is saved to the
-// hand-off buffer and its lane moves on: the packet-count tail of a
-// line-forest model is a few per cent of the packets carrying about half of
-// the segments, and a lane-per-packet wavefront runs those latency-bound.
+// a launch-wide work queue (one atomic per wavefront per refill), so a lane
+// whose packet ends picks up the next one, from any model of the launch,
+// while its neighbours are still marching.  A history still alive after
+// `long_budget` flight segments is saved to its model's hand-off buffer and
+// its lane moves on: in a line-forest model a few per cent of the packets
+// carry about half of the segments, and a lane-per-packet wavefront runs
+// those latency-bound.
 //
 // long_kernel: one packet per wavefront, for the handed-off histories.  The
 // 64 lanes hold the next 128 draws of the packet's stream with their
@@ -151,8 +160,13 @@ __global__ void reset_kernel(DevModel m, DevIter it) {
 // dependent chain is only the geometry and frame arithmetic; J_blue updates
 // go out from the lanes that own the passed lines in parallel.
 //
-// Both follow the same arithmetic, in FP64, as the reference formulation;
+// Both follow the arithmetic of the FP64 reference formulation step by step;
 // divisions that only change the last bit are reciprocal multiplies.
+// Estimator tallies: J and nu-bar accumulate in registers while a packet
+// stays in one shell of one model, event counters and luminosity sums in a
+// private LDS slot per lane while the lane stays on one model; both reach
+// HBM with atomics only when that changes.  The spectrum takes one atomic
+// per escaping packet, J_blue one per passed resonance.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ double to_uniform(uint64_t w) {
@@ -226,78 +240,26 @@ __device__ __forceinline__ double planck_from(double u_l, double u1, double u2, 
   return -log(((u1 * u2) * u3) * u4) / (double)l;
 }
 
-// LDS layout of one workgroup: J[S], nubar[S], spectrum[NB+2], L sums[3],
-// then the event counters (u64)
-__host__ __device__ __forceinline__ size_t lds_doubles(int S, int n_bins) {
-  return 2 * (size_t)S + (size_t)n_bins + 2 + 3;
-}
-
-struct LdsTally {
-  double *J, *nb, *spec, *L;
-  unsigned long long* cnt;
-  size_t n_dbl;
-};
-
-__device__ __forceinline__ LdsTally lds_tally_init(const DevModel& m, double* lds) {
-  LdsTally t;
-  t.n_dbl = lds_doubles(m.S, m.n_bins);
-  t.J = lds;
-  t.nb = lds + m.S;
-  t.spec = lds + 2 * m.S;
-  t.L = lds + 2 * m.S + m.n_bins + 2;
-  t.cnt = reinterpret_cast<unsigned long long*>(lds + t.n_dbl);
-  for (size_t i = threadIdx.x; i < t.n_dbl + SMC_N_COUNTERS; i += blockDim.x) lds[i] = 0.0;
-  __syncthreads();
-  return t;
-}
-
-__device__ __forceinline__ void lds_tally_flush(const DevModel& m, const LdsTally& t,
-                                                const double* lds) {
-  __syncthreads();
-  const size_t n_raw = 2 * (size_t)m.S + (size_t)m.n_bins + 2;
-  for (size_t i = threadIdx.x; i < t.n_dbl; i += blockDim.x) {
-    const double v = lds[i];
-    if (v == 0.0) continue;
-    if (i < n_raw)
-      unsafeAtomicAdd(&m.raw[i], v);
-    else
-      unsafeAtomicAdd(&m.lsum[i - n_raw], v);
-  }
-  if (threadIdx.x < SMC_N_COUNTERS) {
-    const unsigned long long v = t.cnt[threadIdx.x];
-    if (v) atomicAdd(&m.counters[threadIdx.x], v);
-  }
+// distance along (r, mu) to the boundary of shell [r_in, r_out] met first
+// (ray-sphere intersection; a tangent ray misses the inner sphere)
+__device__ __forceinline__ double shell_distance(double r, double mu, double rmu, double r_in,
+                                                 double r_out, bool& inward) {
+  const double b = r * r * ((1.0 - mu) * (1.0 + mu));
+  inward = mu < 0.0 && b < r_in * r_in;
+  double q = inward ? r_in * r_in - b : r_out * r_out - b;
+  q = q < 0.0 ? 0.0 : q;
+  const double sq = sqrt(q);
+  const double d = inward ? -rmu - sq : sq - rmu;
+  return d < 0.0 ? 0.0 : d;
 }
 
 // spectrum bin of an escaping lab frequency (section 2.9): n_bins is the
 // underflow slot (also taken by a NaN), n_bins+1 the overflow slot
-__device__ __forceinline__ int spectrum_bin(const DevModel& m, double nu, double dnu_bin) {
+__device__ __forceinline__ int spectrum_bin(const DevModel& m, double nu) {
   if (!(nu >= m.nu_min)) return m.n_bins;
+  const double dnu_bin = (m.nu_max - m.nu_min) / (double)m.n_bins;
   const double f = floor((nu - m.nu_min) / dnu_bin);
   return f >= (double)m.n_bins ? m.n_bins + 1 : (int)f;
-}
-
-// end of a history: luminosity, spectrum and event tallies into LDS
-__device__ __forceinline__ void tally_end(const DevModel& m, const LdsTally& t, int status,
-                                          double nu, double E, double dnu_bin, uint64_t n_seg,
-                                          uint64_t n_pass, uint32_t n_line, uint32_t n_esc) {
-  if (status == SMC_ESCAPED) {
-    atomicAdd(&t.spec[spectrum_bin(m, nu, dnu_bin)], E);
-    atomicAdd(&t.L[0], E);
-    atomicAdd(&t.cnt[SMC_C_ESCAPED], 1ull);
-  } else if (status == SMC_REABSORBED) {
-    atomicAdd(&t.L[1], E);
-    atomicAdd(&t.cnt[SMC_C_REABSORBED], 1ull);
-  } else {
-    atomicAdd(&t.L[2], E);
-    atomicAdd(&t.cnt[SMC_C_CAPPED], 1ull);
-  }
-  // every segment ends in exactly one of line event, Thomson or crossing
-  atomicAdd(&t.cnt[SMC_C_SEGMENTS], (unsigned long long)n_seg);
-  atomicAdd(&t.cnt[SMC_C_LINE_PASSES], (unsigned long long)n_pass);
-  atomicAdd(&t.cnt[SMC_C_LINE_EVENTS], (unsigned long long)n_line);
-  atomicAdd(&t.cnt[SMC_C_ESCATTERS], (unsigned long long)n_esc);
-  atomicAdd(&t.cnt[SMC_C_CROSSINGS], (unsigned long long)(n_seg - n_line - n_esc));
 }
 
 __device__ __forceinline__ void write_record(const DevModel& m, uint64_t slot, uint64_t pid,
@@ -324,45 +286,113 @@ __device__ __forceinline__ void write_record(const DevModel& m, uint64_t slot, u
   static_cast<smc_packet_out*>(m.packets)[slot] = rec;
 }
 
-// distance along (r, mu) to the boundary of shell [r_in, r_out] met first
-// (ray-sphere intersection; a tangent ray misses the inner sphere)
-__device__ __forceinline__ double shell_distance(double r, double mu, double rmu, double r_in,
-                                                 double r_out, bool& inward) {
-  const double b = r * r * ((1.0 - mu) * (1.0 + mu));
-  inward = mu < 0.0 && b < r_in * r_in;
-  double q = inward ? r_in * r_in - b : r_out * r_out - b;
-  q = q < 0.0 ? 0.0 : q;
-  const double sq = sqrt(q);
-  const double d = inward ? -rmu - sq : sq - rmu;
-  return d < 0.0 ? 0.0 : d;
+// per-lane tally slot in LDS: luminosity sums and event counters of the
+// lane's current model
+struct LaneTally {
+  double L[3];
+  unsigned long long c[SMC_N_COUNTERS];
+};
+
+__device__ __forceinline__ void lane_tally_clear(LaneTally& t) {
+  t.L[0] = t.L[1] = t.L[2] = 0.0;
+#pragma unroll
+  for (int i = 0; i < SMC_N_COUNTERS; ++i) t.c[i] = 0ull;
+}
+
+__device__ __forceinline__ void lane_tally_flush(const DevModel& m, LaneTally& t) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (t.L[i] != 0.0) unsafeAtomicAdd(&m.lsum[i], t.L[i]);
+#pragma unroll
+  for (int i = 0; i < SMC_N_COUNTERS; ++i)
+    if (t.c[i]) atomicAdd(&m.counters[i], t.c[i]);
+  lane_tally_clear(t);
+}
+
+// end of a history: luminosity and event tallies (section 2.9 spectrum with
+// one global atomic)
+__device__ __forceinline__ void lane_tally_end(const DevModel& m, LaneTally& t, int status,
+                                               double nu, double E, uint64_t n_seg,
+                                               uint64_t n_pass, uint32_t n_line,
+                                               uint32_t n_esc) {
+  if (status == SMC_ESCAPED) {
+    unsafeAtomicAdd(&m.raw[2 * m.S + spectrum_bin(m, nu)], E);
+    t.L[0] += E;
+    t.c[SMC_C_ESCAPED] += 1;
+  } else if (status == SMC_REABSORBED) {
+    t.L[1] += E;
+    t.c[SMC_C_REABSORBED] += 1;
+  } else {
+    t.L[2] += E;
+    t.c[SMC_C_CAPPED] += 1;
+  }
+  // every segment ends in exactly one of line event, Thomson or crossing
+  t.c[SMC_C_SEGMENTS] += n_seg;
+  t.c[SMC_C_LINE_PASSES] += n_pass;
+  t.c[SMC_C_LINE_EVENTS] += n_line;
+  t.c[SMC_C_ESCATTERS] += n_esc;
+  t.c[SMC_C_CROSSINGS] += n_seg - n_line - n_esc;
+}
+
+// the per-model values the segment loop of a lane reads
+struct View {
+  const double* r_bounds;
+  const double* n_e;
+  const double* line_nu;
+  const double* tau;
+  double* jblue;          // nullptr when J_blue is not tallied
+  double ct, inv_ct;
+  uint64_t max_segments, budget;
+  int32_t S, L, Lp;
+  bool downbranch;
+  uint32_t k0, k1, iter;  // random-number key and counter word
+};
+
+__device__ __forceinline__ View make_view(const DevModel& m, const DevIter& it) {
+  View v;
+  v.r_bounds = m.r_bounds;
+  v.n_e = m.n_e;
+  v.line_nu = m.line_nu;
+  v.tau = m.tau;
+  v.jblue = (m.jblue != nullptr && (it.flags & SMC_F_JBLUE)) ? m.jblue : nullptr;
+  v.ct = m.ct;
+  v.inv_ct = 1.0 / m.ct;
+  v.max_segments = it.max_segments;
+  v.budget = (it.long_budget > 0 && m.longs) ? it.long_budget : ~0ull;
+  v.S = m.S;
+  v.L = m.L;
+  v.Lp = m.Lp;
+  v.downbranch = m.mode == SMC_DOWNBRANCH;
+  v.k0 = (uint32_t)m.seed;
+  v.k1 = (uint32_t)(m.seed >> 32);
+  v.iter = it.iteration;
+  return v;
 }
 
 // ---------------------------------------------------------------------------
 // lane-per-packet kernel
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter it) {
-  extern __shared__ double lds[];
-  const LdsTally tl = lds_tally_init(m, lds);
-  const int S = m.S;
-  const int32_t L = m.L;
+template <bool kMulti>
+__global__ __launch_bounds__(kBlock) void transport_kernel(LaunchArgs a) {
+  extern __shared__ unsigned char lds_raw[];
+  LaneTally* lane_tally = reinterpret_cast<LaneTally*>(lds_raw);
+  uint64_t* work_begin = reinterpret_cast<uint64_t*>(lds_raw + sizeof(LaneTally) * kBlock);
+  LaneTally& tly = lane_tally[threadIdx.x];
+  lane_tally_clear(tly);
+  if (kMulti) {
+    for (int i = threadIdx.x; i <= a.n_models; i += blockDim.x)
+      work_begin[i] = i < a.n_models ? a.table[i].work_begin : a.total_work;
+    __syncthreads();
+  }
   const int lane = threadIdx.x & (kWave - 1);
-  const double ct = m.ct;
-  const double inv_ct = 1.0 / ct;
-  const double T_inner = m.scalars[SC_T_USED];
-  const double r_inner = m.r_bounds[0];
-  const double e_packet = 1.0 / (double)it.n_packets;
-  const double dnu_bin = (m.nu_max - m.nu_min) / (double)m.n_bins;
-  const bool want_jblue = m.jblue != nullptr && (it.flags & SMC_F_JBLUE);
-  const bool want_packets = m.packets != nullptr && (it.flags & SMC_F_PACKETS);
-  const bool downbranch = m.mode == SMC_DOWNBRANCH;
-  const uint64_t budget = (it.long_budget > 0 && m.longs) ? it.long_budget : ~0ull;
-  StreamKey sk;
-  sk.k0 = (uint32_t)m.seed;
-  sk.k1 = (uint32_t)(m.seed >> 32);
-  sk.iter = it.iteration;
-  sk.p0 = sk.p1 = 0;
-  const size_t Lp = (size_t)m.Lp;
-  unsigned long long* queue = m.counters + CTR_QUEUE;
+  unsigned long long* queue = kMulti ? a.ctr : a.single.m.counters + CTR_QUEUE;
+  const uint64_t total_work = kMulti ? a.total_work : a.single.it.n_work;
+
+  // the lane's current model
+  int model = kMulti ? -1 : 0;
+  uint64_t model_end = 0;
+  View v = make_view(a.single.m, a.single.it);
+  int tally_model = kMulti ? -1 : 0;
 
   // packet state
   uint64_t slot = 0, pid = 0;
@@ -372,15 +402,20 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
   uint32_t n_esc = 0, n_line = 0;
   bool handoff_tried = false;
   RngWindow g;
+  StreamKey sk;
+  sk.k0 = v.k0;
+  sk.k1 = v.k1;
+  sk.iter = v.iter;
+  sk.p0 = sk.p1 = 0;
   // cached shell parameters
   int32_t c_shell = -1;
   double c_rin = 0.0, c_rout = 0.0, c_ne = 0.0;
-  // line window: lines wbase..wbase+3 of shell wshell
+  // line window: lines wbase..wbase+3 of shell wshell of the current model
   int32_t wbase = -8, wshell = -1;
   double wn0 = 0, wn1 = 0, wn2 = 0, wn3 = 0, wt0 = 0, wt1 = 0, wt2 = 0, wt3 = 0;
-  // shell tallies held in registers while the packet stays in one shell
+  // J and nu-bar of one shell of one model, held in registers
   double acc_J = 0.0, acc_nb = 0.0;
-  int acc_shell = -1;
+  int acc_shell = -1, acc_model = -1;
 
   bool active = false, exhausted = false;
 
@@ -395,11 +430,32 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
       base = __shfl(base, leader, kWave);
       if (need) {
         const unsigned long long below = need_mask & ((1ull << lane) - 1ull);
-        const uint64_t idx = base + (uint64_t)__popcll(below);
-        if (idx < it.n_work) {
+        const uint64_t gidx = base + (uint64_t)__popcll(below);
+        if (gidx < total_work) {
+          if (kMulti && (model < 0 || gidx >= model_end || gidx < work_begin[model])) {
+            // packet of another model: locate it, switch the lane's view
+            int lo = 0, hi = a.n_models - 1;
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (work_begin[mid] <= gidx)
+                lo = mid;
+              else
+                hi = mid - 1;
+            }
+            model = lo;
+            model_end = work_begin[lo + 1];
+            v = make_view(a.table[model].m, a.table[model].it);
+            sk.k0 = v.k0;
+            sk.k1 = v.k1;
+            sk.iter = v.iter;
+            c_shell = -1;
+            wshell = -1;
+          }
+          const DevModel& m = ENTRY(a, model).m;
+          const DevIter& it = ENTRY(a, model).it;
           // ---- injection at the inner boundary (section 2.4)
-          slot = idx;
-          pid = it.ids ? it.ids[idx] : idx;
+          slot = kMulti ? gidx - work_begin[model] : gidx;
+          pid = it.ids ? it.ids[slot] : slot;
           sk.p0 = (uint32_t)pid;
           sk.p1 = (uint32_t)(pid >> 32);
           // draws 0..5: mu, the Planck mixture term, four Gamma(4) uniforms
@@ -414,15 +470,17 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
           mu = sqrt(to_uniform(b0.a));  // zero limb darkening
           const double x = planck_from(to_uniform(b0.b), to_uniform(b1.a), to_uniform(b1.b),
                                        to_uniform(b2.a), to_uniform(b2.b));
+          const double T_inner = m.scalars[SC_T_USED];
+          const double r_inner = v.r_bounds[0];
           const double nu_cmf = x * kKB * T_inner / kH;
-          const double D0 = doppler(r_inner, mu, ct);
+          const double D0 = doppler(r_inner, mu, v.ct);
           nu = nu_cmf / D0;
-          E = e_packet / D0;
+          E = (1.0 / (double)it.n_packets) / D0;
           r = r_inner;
           mu0 = mu;
           nu_cmf0 = nu_cmf;
           shell = 0;
-          next_line = L > 0 ? first_below(m.line_nu, L, nu_cmf) : 0;
+          next_line = v.L > 0 ? first_below(v.line_nu, v.L, nu_cmf) : 0;
           n_seg = n_pass = 0;
           n_esc = n_line = 0;
           hash = 0xcbf29ce484222325ull;
@@ -436,13 +494,18 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
     }
     if (__ballot(active) == 0ull) break;
     if (!active) continue;
+    if (kMulti && tally_model != model) {
+      if (tally_model >= 0) lane_tally_flush(a.table[tally_model].m, tly);
+      tally_model = model;
+    }
 
     int status = SMC_LIVE;
-    if (n_seg >= it.max_segments) {
+    if (n_seg >= v.max_segments) {
       status = SMC_CAPPED;
-    } else if (n_seg >= budget && !handoff_tried) {
+    } else if (n_seg >= v.budget && !handoff_tried) {
       // ---- hand the history to the wave-per-packet kernel
       handoff_tried = true;
+      const DevModel& m = ENTRY(a, model).m;
       const unsigned long long h = atomicAdd(&m.counters[CTR_LONG_COUNT], 1ull);
       if (h < m.long_cap) {
         LongState st;
@@ -477,19 +540,19 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
       const int sh = shell;
       if (sh != c_shell) {
         c_shell = sh;
-        c_rin = m.r_bounds[sh];
-        c_rout = m.r_bounds[sh + 1];
-        c_ne = m.n_e[sh];
+        c_rin = v.r_bounds[sh];
+        c_rout = v.r_bounds[sh + 1];
+        c_ne = v.n_e[sh];
       }
       const double rmu = r * mu;
-      const double D = 1.0 - rmu * inv_ct;
+      const double D = 1.0 - rmu * v.inv_ct;
       const double nu_cmf = nu * D;
       const double e_cmf = E * D;
       bool inward;
       const double d_shell = shell_distance(r, mu, rmu, c_rin, c_rout, inward);
       const double kappa = kSigmaT * c_ne * D;  // Thomson opacity with D
       const double inv_nu = 1.0 / nu;
-      const double ct_over_nu = ct * inv_nu;
+      const double ct_over_nu = v.ct * inv_nu;
       const double jb_w = E * inv_nu * inv_nu;  // J_blue weight per unit nu_k
 
       // line march: pass redward lines while d_line is the shortest distance;
@@ -498,13 +561,13 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
       int32_t k = next_line;
       bool line_hit = false;
       double d_line = 0.0, nu_hit = 0.0;
-      const double* __restrict__ tau_row = m.tau + (size_t)sh * Lp;
-      double* jb_row = want_jblue ? m.jblue + (size_t)sh * (size_t)L : nullptr;
-      bool stop = k >= L;
+      const double* __restrict__ tau_row = v.tau + (size_t)sh * (size_t)v.Lp;
+      double* jb_row = v.jblue ? v.jblue + (size_t)sh * (size_t)v.L : nullptr;
+      bool stop = k >= v.L;
       while (!stop) {
         const int32_t base = k & ~3;
         if (base != wbase || sh != wshell) {
-          const double2* pn = reinterpret_cast<const double2*>(m.line_nu + base);
+          const double2* pn = reinterpret_cast<const double2*>(v.line_nu + base);
           const double2* pt = reinterpret_cast<const double2*>(tau_row + base);
           const double2 n01 = pn[0], n23 = pn[1], t01 = pt[0], t23 = pt[1];
           wn0 = n01.x; wn1 = n01.y; wn2 = n23.x; wn3 = n23.y;
@@ -517,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
           const double nu_k = j == 0 ? wn0 : j == 1 ? wn1 : j == 2 ? wn2 : wn3;
           const double tau_k = j == 0 ? wt0 : j == 1 ? wt1 : j == 2 ? wt2 : wt3;
           if (!stop && base + j >= k) {
-            if (base + j >= L) {
+            if (base + j >= v.L) {
               stop = true;
             } else {
               double dl = (nu_cmf - nu_k) * ct_over_nu;
@@ -550,12 +613,14 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
       const double d = line_hit ? d_line : (escat ? d_electron : d_shell);
 
       // J and nu-bar estimators (section 2.7), register-accumulated per shell
-      if (acc_shell != sh) {
+      if (acc_shell != sh || acc_model != model) {
         if (acc_shell >= 0) {
-          atomicAdd(&tl.J[acc_shell], acc_J);
-          atomicAdd(&tl.nb[acc_shell], acc_nb);
+          const DevModel& am = ENTRY(a, acc_model).m;
+          unsafeAtomicAdd(&am.raw[acc_shell], acc_J);
+          unsafeAtomicAdd(&am.raw[am.S + acc_shell], acc_nb);
         }
         acc_shell = sh;
+        acc_model = model;
         acc_J = 0.0;
         acc_nb = 0.0;
       }
@@ -574,31 +639,32 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
         mu = mu_new;
         hash = fnv_event(hash, kind, sh, -1, -1);
         shell = sh + (inward ? -1 : 1);
-        if (shell >= S)
+        if (shell >= v.S)
           status = SMC_ESCAPED;
         else if (shell < 0)
           status = SMC_REABSORBED;
       } else {
         // Thomson (coherent, isotropic in the comoving frame) or line
         // interaction (branch draw, then direction; section 2.5)
-        const double D_old = 1.0 - (mu_new * r_new) * inv_ct;
+        const double D_old = 1.0 - (mu_new * r_new) * v.inv_ct;
         const double e_cmf_ev = E * D_old;
         double nu_cmf_out = nu * D_old;
         int32_t emit = k;
         if (line_hit) {
           const double u_branch = rng_next(g);
           nu_cmf_out = nu_hit;
-          if (downbranch) {
+          if (v.downbranch) {
+            const DevModel& m = ENTRY(a, model).m;
             const int32_t up = m.line_upper[k];
-            const int64_t a = m.level_ptr[up], e = m.level_ptr[up + 1];
-            int64_t j = a;
-            while (j < e - 1 && !(m.em_cum[j] > u_branch)) ++j;
+            const int64_t lo = m.level_ptr[up], hi = m.level_ptr[up + 1];
+            int64_t j = lo;
+            while (j < hi - 1 && !(m.em_cum[j] > u_branch)) ++j;
             emit = m.em_line[j];
-            nu_cmf_out = m.line_nu[emit];
+            nu_cmf_out = v.line_nu[emit];
           }
         }
         const double mu_out = 2.0 * rng_next(g) - 1.0;
-        const double D_new = 1.0 - (mu_out * r_new) * inv_ct;
+        const double D_new = 1.0 - (mu_out * r_new) * v.inv_ct;
         const double inv_D = 1.0 / D_new;
         r = r_new;
         mu = mu_out;
@@ -617,8 +683,9 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
     }
 
     if (status != SMC_LIVE) {
-      tally_end(m, tl, status, nu, E, dnu_bin, n_seg, n_pass, n_line, n_esc);
-      if (want_packets)
+      const DevModel& m = ENTRY(a, model).m;
+      lane_tally_end(m, tly, status, nu, E, n_seg, n_pass, n_line, n_esc);
+      if (m.packets != nullptr && (ENTRY(a, model).it.flags & SMC_F_PACKETS))
         write_record(m, slot, pid, status, shell, nu, E, mu, r, mu0, nu_cmf0, n_seg, n_esc,
                      n_line, n_pass, hash, last_line);
       active = false;
@@ -626,59 +693,95 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(DevModel m, DevIter i
   }
 
   if (acc_shell >= 0) {
-    atomicAdd(&tl.J[acc_shell], acc_J);
-    atomicAdd(&tl.nb[acc_shell], acc_nb);
+    const DevModel& am = ENTRY(a, acc_model).m;
+    unsafeAtomicAdd(&am.raw[acc_shell], acc_J);
+    unsafeAtomicAdd(&am.raw[am.S + acc_shell], acc_nb);
   }
-  lds_tally_flush(m, tl, lds);
+  if (tally_model >= 0) lane_tally_flush(ENTRY(a, tally_model).m, tly);
+}
+
+// ---------------------------------------------------------------------------
+// hand-off numbering over the models of a multi-model launch
+// ---------------------------------------------------------------------------
+__global__ void long_prefix_kernel(LaunchArgs a, BatchEntry* table) {
+  if (threadIdx.x != 0) return;
+  unsigned long long total = 0;
+  for (int k = 0; k < a.n_models; ++k) {
+    table[k].long_begin = total;
+    unsigned long long n = table[k].m.counters[CTR_LONG_COUNT];
+    if (n > table[k].m.long_cap) n = table[k].m.long_cap;
+    total += n;
+  }
+  a.ctr[1] = total;
+  a.ctr[2] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
 // wave-per-packet kernel for the handed-off histories
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double readlane_f64(double v, int src) {
-  const uint64_t b = (uint64_t)__double_as_longlong(v);
+__device__ __forceinline__ double readlane_f64(double x, int src) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int uniform_i32(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 constexpr int kLongBlock = 64;
 
-__global__ __launch_bounds__(kLongBlock) void long_kernel(DevModel m, DevIter it) {
-  extern __shared__ double lds[];
-  const LdsTally tl = lds_tally_init(m, lds);
-  const int S = m.S;
-  const int32_t L = m.L;
+template <bool kMulti>
+__global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
+  __shared__ LaneTally tly;  // the wavefront's tallies, updated by lane 0
   const int lane = threadIdx.x;
-  const double ct = m.ct;
-  const double inv_ct = 1.0 / ct;
-  const double dnu_bin = (m.nu_max - m.nu_min) / (double)m.n_bins;
-  const bool want_jblue = m.jblue != nullptr && (it.flags & SMC_F_JBLUE);
-  const bool want_packets = m.packets != nullptr && (it.flags & SMC_F_PACKETS);
-  const bool downbranch = m.mode == SMC_DOWNBRANCH;
-  const size_t Lp = (size_t)m.Lp;
-  unsigned long long n_long = m.counters[CTR_LONG_COUNT];
-  if (n_long > m.long_cap) n_long = m.long_cap;
-  StreamKey sk;
-  sk.k0 = (uint32_t)m.seed;
-  sk.k1 = (uint32_t)(m.seed >> 32);
-  sk.iter = it.iteration;
-
+  unsigned long long n_long, *queue;
+  if (kMulti) {
+    n_long = a.ctr[1];
+    queue = a.ctr + 2;
+  } else {
+    n_long = a.single.m.counters[CTR_LONG_COUNT];
+    if (n_long > a.single.m.long_cap) n_long = a.single.m.long_cap;
+    queue = a.single.m.counters + CTR_LONG_QUEUE;
+  }
+  if (lane == 0) lane_tally_clear(tly);
+  int tally_model = kMulti ? -1 : 0;
   double acc_J = 0.0, acc_nb = 0.0;
-  int acc_shell = -1;
+  int acc_shell = -1, acc_model = -1;
 
   for (;;) {
-    unsigned long long idx = 0;
-    if (lane == 0) idx = atomicAdd(&m.counters[CTR_LONG_QUEUE], 1ull);
-    idx = __shfl(idx, 0, kWave);
-    if (idx >= n_long) break;
+    unsigned long long gidx = 0;
+    if (lane == 0) gidx = atomicAdd(queue, 1ull);
+    gidx = __shfl(gidx, 0, kWave);
+    if (gidx >= n_long) break;
+    int model = 0;
+    uint64_t idx = gidx;
+    if (kMulti) {
+      int lo = 0, hi = a.n_models - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.table[mid].long_begin <= gidx)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      model = uniform_i32(lo);
+      idx = gidx - a.table[model].long_begin;
+      if (tally_model != model) {
+        if (tally_model >= 0 && lane == 0) lane_tally_flush(a.table[tally_model].m, tly);
+        tally_model = model;
+      }
+    }
+    const DevModel& m = ENTRY(a, model).m;
+    const View v = make_view(m, ENTRY(a, model).it);
     const LongState st = m.longs[idx];
     uint64_t n_seg = st.n_seg, n_pass = st.n_pass, hash = st.hash, draw = st.draw;
     double r = st.r, mu = st.mu, nu = st.nu, E = st.E;
     int32_t shell = st.shell, next_line = st.next_line, last_line = st.last_line;
     uint32_t n_esc = st.n_esc, n_line = st.n_line;
+    StreamKey sk;
+    sk.k0 = v.k0;
+    sk.k1 = v.k1;
+    sk.iter = v.iter;
     sk.p0 = (uint32_t)st.pid;
     sk.p1 = (uint32_t)(st.pid >> 32);
 
@@ -691,13 +794,12 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(DevModel m, DevIter it
     // 64 lines of one shell: lane i holds line wbase + i
     int32_t wbase = -1, wshell = -1;
     double wn = 0.0, wt = 0.0;
-    // cached shell parameters
     int32_t c_shell = -1;
     double c_rin = 0.0, c_rout = 0.0, c_ne = 0.0;
 
     int status = SMC_LIVE;
     for (;;) {
-      if (n_seg >= it.max_segments) {
+      if (n_seg >= v.max_segments) {
         status = SMC_CAPPED;
         break;
       }
@@ -716,19 +818,19 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(DevModel m, DevIter it
       const int sh = shell;
       if (sh != c_shell) {
         c_shell = sh;
-        c_rin = m.r_bounds[sh];
-        c_rout = m.r_bounds[sh + 1];
-        c_ne = m.n_e[sh];
+        c_rin = v.r_bounds[sh];
+        c_rout = v.r_bounds[sh + 1];
+        c_ne = v.n_e[sh];
       }
       const double rmu = r * mu;
-      const double D = 1.0 - rmu * inv_ct;
+      const double D = 1.0 - rmu * v.inv_ct;
       const double nu_cmf = nu * D;
       const double e_cmf = E * D;
       bool inward;
       const double d_shell = shell_distance(r, mu, rmu, c_rin, c_rout, inward);
       const double kappa = kSigmaT * c_ne * D;
       const double inv_nu = 1.0 / nu;
-      const double ct_over_nu = ct * inv_nu;
+      const double ct_over_nu = v.ct * inv_nu;
       const double jb_w = E * inv_nu * inv_nu;
 
       // line march over the register window; passed lines get their J_blue
@@ -738,10 +840,10 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(DevModel m, DevIter it
       int32_t k_first = k;  // first line of the march still to be tallied
       bool line_hit = false;
       double d_line = 0.0, nu_hit = 0.0;
-      double* jb_row = want_jblue ? m.jblue + (size_t)sh * (size_t)L : nullptr;
-      while (k < L) {
+      double* jb_row = v.jblue ? v.jblue + (size_t)sh * (size_t)v.L : nullptr;
+      while (k < v.L) {
         if (sh != wshell || k >= wbase + kWave || k < wbase) {
-          if (jb_row && k > k_first) {
+          if (jb_row && k > k_first && wshell == sh) {
             const int32_t line = wbase + lane;
             if (line >= k_first && line < k) unsafeAtomicAdd(&jb_row[line], jb_w * wn);
           }
@@ -749,8 +851,8 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(DevModel m, DevIter it
           wbase = k;
           wshell = sh;
           const int32_t line = k + lane;
-          wn = line < L ? m.line_nu[line] : 0.0;
-          wt = line < L ? m.tau[(size_t)sh * Lp + line] : 0.0;
+          wn = line < v.L ? v.line_nu[line] : 0.0;
+          wt = line < v.L ? v.tau[(size_t)sh * (size_t)v.Lp + line] : 0.0;
         }
         const int src = uniform_i32(k - wbase);
         const double nu_k = readlane_f64(wn, src);
@@ -781,12 +883,14 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(DevModel m, DevIter it
       const bool cross = !line_hit && !escat;
       const double d = line_hit ? d_line : (escat ? d_electron : d_shell);
 
-      if (acc_shell != sh) {
+      if (acc_shell != sh || acc_model != model) {
         if (acc_shell >= 0 && lane == 0) {
-          atomicAdd(&tl.J[acc_shell], acc_J);
-          atomicAdd(&tl.nb[acc_shell], acc_nb);
+          const DevModel& am = ENTRY(a, acc_model).m;
+          unsafeAtomicAdd(&am.raw[acc_shell], acc_J);
+          unsafeAtomicAdd(&am.raw[am.S + acc_shell], acc_nb);
         }
         acc_shell = sh;
+        acc_model = model;
         acc_J = 0.0;
         acc_nb = 0.0;
       }
@@ -804,7 +908,7 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(DevModel m, DevIter it
         mu = mu_new;
         hash = fnv_event(hash, kind, sh, -1, -1);
         shell = sh + (inward ? -1 : 1);
-        if (shell >= S) {
+        if (shell >= v.S) {
           status = SMC_ESCAPED;
           break;
         }
@@ -813,7 +917,7 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(DevModel m, DevIter it
           break;
         }
       } else {
-        const double D_old = 1.0 - (mu_new * r_new) * inv_ct;
+        const double D_old = 1.0 - (mu_new * r_new) * v.inv_ct;
         const double e_cmf_ev = E * D_old;
         double nu_cmf_out = nu * D_old;
         int32_t emit = k;
@@ -822,19 +926,19 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(DevModel m, DevIter it
           const double u_branch = readlane_f64((draw & 1) ? ub : ua, sb);
           draw += 1;
           nu_cmf_out = nu_hit;
-          if (downbranch) {
+          if (v.downbranch) {
             const int32_t up = m.line_upper[k];
-            const int64_t a = m.level_ptr[up], e = m.level_ptr[up + 1];
-            int64_t j = a;
-            while (j < e - 1 && !(m.em_cum[j] > u_branch)) ++j;
+            const int64_t lo = m.level_ptr[up], hi = m.level_ptr[up + 1];
+            int64_t j = lo;
+            while (j < hi - 1 && !(m.em_cum[j] > u_branch)) ++j;
             emit = m.em_line[j];
-            nu_cmf_out = m.line_nu[emit];
+            nu_cmf_out = v.line_nu[emit];
           }
         }
         const int sm = uniform_i32((int)((draw >> 1) - rb));
         const double mu_out = 2.0 * readlane_f64((draw & 1) ? ub : ua, sm) - 1.0;
         draw += 1;
-        const double D_new = 1.0 - (mu_out * r_new) * inv_ct;
+        const double D_new = 1.0 - (mu_out * r_new) * v.inv_ct;
         const double inv_D = 1.0 / D_new;
         r = r_new;
         mu = mu_out;
@@ -853,23 +957,31 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(DevModel m, DevIter it
     }
 
     if (lane == 0) {
-      tally_end(m, tl, status, nu, E, dnu_bin, n_seg, n_pass, n_line, n_esc);
-      if (want_packets)
+      lane_tally_end(m, tly, status, nu, E, n_seg, n_pass, n_line, n_esc);
+      if (m.packets != nullptr && (ENTRY(a, model).it.flags & SMC_F_PACKETS))
         write_record(m, st.slot, st.pid, status, shell, nu, E, mu, r, st.mu0, st.nu_cmf0, n_seg,
                      n_esc, n_line, n_pass, hash, last_line);
     }
   }
-  if (acc_shell >= 0 && lane == 0) {
-    atomicAdd(&tl.J[acc_shell], acc_J);
-    atomicAdd(&tl.nb[acc_shell], acc_nb);
+  if (lane == 0) {
+    if (acc_shell >= 0) {
+      const DevModel& am = ENTRY(a, acc_model).m;
+      unsafeAtomicAdd(&am.raw[acc_shell], acc_J);
+      unsafeAtomicAdd(&am.raw[am.S + acc_shell], acc_nb);
+    }
+    if (tally_model >= 0) lane_tally_flush(ENTRY(a, tally_model).m, tly);
   }
-  lds_tally_flush(m, tl, lds);
 }
 
 // ---------------------------------------------------------------------------
-// estimator normalisation and radiation-field update (sections 2.7, 2.8)
+// estimator normalisation and radiation-field update (sections 2.7, 2.8);
+// blockIdx.x selects the model
 // ---------------------------------------------------------------------------
-__global__ void finalise_kernel(DevModel m, DevIter it) {
+template <bool kMulti>
+__global__ void finalise_kernel(LaunchArgs a) {
+  const int k = kMulti ? (int)blockIdx.x : 0;
+  const DevModel& m = ENTRY(a, k).m;
+  const DevIter& it = ENTRY(a, k).it;
   const int S = m.S;
   const double T = m.scalars[SC_T_USED];
   const double r_inner = m.r_bounds[0];
@@ -904,7 +1016,12 @@ __global__ void finalise_kernel(DevModel m, DevIter it) {
   }
 }
 
-__global__ void jblue_scale_kernel(DevModel m) {
+// J_blue normalisation: blockIdx.y selects the model
+template <bool kMulti>
+__global__ void jblue_scale_kernel(LaunchArgs a) {
+  const int k = kMulti ? (int)blockIdx.y : 0;
+  const DevModel& m = ENTRY(a, k).m;
+  if (!m.jblue || !(ENTRY(a, k).it.flags & SMC_F_JBLUE)) return;
   const size_t n = (size_t)m.S * (size_t)m.L;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   const double* scale = m.out_shell + 4 * m.S;
@@ -914,14 +1031,18 @@ __global__ void jblue_scale_kernel(DevModel m) {
   }
 }
 
+#undef ENTRY
+
+size_t transport_lds_bytes(bool multi, int n_models) {
+  size_t b = sizeof(LaneTally) * kBlock;
+  if (multi) b += sizeof(uint64_t) * ((size_t)n_models + 1);
+  return b;
+}
+
 }  // namespace
 
 int transport_block_threads() { return kBlock; }
 int long_block_threads() { return kLongBlock; }
-
-size_t transport_lds_bytes(const DevModel& m) {
-  return sizeof(double) * (lds_doubles(m.S, m.n_bins) + SMC_N_COUNTERS);
-}
 
 hipError_t launch_geometry(const DevModel& m, const double* v_bounds, hipStream_t s) {
   const int n = m.S + 1 > 8 ? m.S + 1 : 8;
@@ -929,53 +1050,75 @@ hipError_t launch_geometry(const DevModel& m, const double* v_bounds, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_reset(const DevModel& m, const DevIter& it, hipStream_t s) {
-  size_t n = 2 * (size_t)m.S + (size_t)m.n_bins + 2;
-  if (m.jblue && (it.flags & SMC_F_JBLUE)) {
-    const size_t nj = (size_t)m.S * (size_t)m.L;
-    if (nj > n) n = nj;
-  }
-  size_t blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m, it);
-  return hipGetLastError();
+hipError_t transport_occupancy(bool multi, int* blocks_per_cu) {
+  const size_t lds = transport_lds_bytes(multi, kMaxBatchModels);
+  return multi ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
+                                                              transport_kernel<true>, kBlock, lds)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
+                                                              transport_kernel<false>, kBlock,
+                                                              transport_lds_bytes(false, 1));
 }
 
-hipError_t launch_transport(const DevModel& m, const DevIter& it, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(transport_kernel, dim3(grid), dim3(kBlock), transport_lds_bytes(m), s, m,
-                     it);
-  return hipGetLastError();
+hipError_t long_occupancy(bool multi, int* blocks_per_cu) {
+  return multi ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, long_kernel<true>,
+                                                              kLongBlock, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, long_kernel<false>,
+                                                              kLongBlock, 0);
 }
 
-// resident workgroups per CU with the LDS of a typical model (S = 100,
-// 1000 spectrum bins); the LDS of one workgroup never limits these kernels
-hipError_t transport_occupancy(int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, transport_kernel, kBlock,
-                                                      sizeof(double) * 1400);
-}
-hipError_t long_occupancy(int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, long_kernel, kLongBlock,
-                                                      sizeof(double) * 1400);
-}
-
-hipError_t launch_long(const DevModel& m, const DevIter& it, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(long_kernel, dim3(grid), dim3(kLongBlock), transport_lds_bytes(m), s, m, it);
-  return hipGetLastError();
-}
-
-hipError_t launch_finalise(const DevModel& m, const DevIter& it, hipStream_t s) {
-  hipLaunchKernelGGL(finalise_kernel, dim3(1), dim3(256), 0, s, m, it);
+template <bool kMulti>
+static hipError_t launch_all(const LaunchArgs& a, const Shape& shape, uint64_t max_jblue,
+                             hipEvent_t ev_start, hipEvent_t ev_stop, hipStream_t s) {
+  const unsigned ny = kMulti ? (unsigned)a.n_models : 1u;
+  // reset: enough blocks to zero the largest J_blue array
+  uint64_t nz = max_jblue > 4096 ? max_jblue : 4096;
+  uint64_t bx = (nz + 255) / 256;
+  if (bx > 2048) bx = 2048;
+  if (kMulti && bx * ny > 65536) bx = (65536 + ny - 1) / ny;
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(reset_kernel<kMulti>, dim3((unsigned)bx, ny), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (m.jblue && (it.flags & SMC_F_JBLUE) && m.L > 0) {
-    const size_t n = (size_t)m.S * (size_t)m.L;
-    size_t blocks = (n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(jblue_scale_kernel, dim3((unsigned)blocks), dim3(256), 0, s, m);
+  if (ev_start) {
+    e = hipEventRecord(ev_start, s);
+    if (e != hipSuccess) return e;
+  }
+  if (shape.transport_grid > 0) {
+    hipLaunchKernelGGL(transport_kernel<kMulti>, dim3(shape.transport_grid), dim3(kBlock),
+                       transport_lds_bytes(kMulti, a.n_models), s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (shape.long_grid > 0) {
+      if (kMulti) {
+        hipLaunchKernelGGL(long_prefix_kernel, dim3(1), dim3(64), 0, s, a,
+                           const_cast<BatchEntry*>(a.table));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(long_kernel<kMulti>, dim3(shape.long_grid), dim3(kLongBlock), 0, s, a);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  if (ev_stop) {
+    e = hipEventRecord(ev_stop, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(finalise_kernel<kMulti>, dim3(ny), dim3(256), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (max_jblue > 0) {
+    uint64_t jx = (max_jblue + 255) / 256;
+    if (jx > 2048) jx = 2048;
+    if (kMulti && jx * ny > 65536) jx = (65536 + ny - 1) / ny;
+    if (jx < 1) jx = 1;
+    hipLaunchKernelGGL(jblue_scale_kernel<kMulti>, dim3((unsigned)jx, ny), dim3(256), 0, s, a);
     e = hipGetLastError();
   }
   return e;
+}
+
+hipError_t launch_iteration(const LaunchArgs& a, bool multi, const Shape& shape,
+                            uint64_t max_jblue, hipEvent_t ev_start, hipEvent_t ev_stop,
+                            hipStream_t s) {
+  return multi ? launch_all<true>(a, shape, max_jblue, ev_start, ev_stop, s)
+               : launch_all<false>(a, shape, max_jblue, ev_start, ev_stop, s);
 }
 
 }  // namespace smc

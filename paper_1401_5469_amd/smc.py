@@ -60,7 +60,7 @@ PACKET_DTYPE = np.dtype([("id", np.uint64), ("status", np.int32), ("shell", np.i
 EXPORTS = ("smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_model_workspace_bytes",
            "smc_model_load", "smc_model_free", "smc_run_iteration", "smc_read_estimators",
            "smc_read_spectrum", "smc_read_counters", "smc_read_packets", "smc_read_timing",
-           "smc_model_set_tune", "smc_model_get_tune")
+           "smc_model_set_tune", "smc_model_get_tune", "smc_batch_run", "smc_batch_read_timing")
 
 
 class SmcError(RuntimeError):
@@ -98,6 +98,9 @@ def load_library(path: str = LIB_PATH):
     L.smc_read_packets.argtypes = [vp, vp, C.c_uint64, vp]
     L.smc_read_timing.argtypes = [vp, _dp]
     L.smc_model_set_tune.argtypes = [vp, C.POINTER(smc_tune)]
+    L.smc_batch_run.argtypes = [vp, C.POINTER(vp), C.POINTER(smc_iter_params), C.c_int,
+                                C.POINTER(smc_tune), C.c_uint32, vp]
+    L.smc_batch_read_timing.argtypes = [vp, _dp]
     L.smc_model_get_tune.argtypes = [vp, C.POINTER(smc_tune)]
     for name in EXPORTS:
         if name != "smc_last_error":
@@ -128,6 +131,29 @@ class Context:
         _check(lib.smc_ctx_create(C.byref(h), int(device)))
         self.handle = h
         self.device = int(device)
+
+    def batch_run(self, models, params, tune=None, timing=False, stream=None):
+        """One iteration of every model in one set of launches.  params: one
+        dict per model with the keyword arguments of Model.run_iteration."""
+        n = len(models)
+        if len(params) != n:
+            raise ValueError("one parameter set per model")
+        arr = (smc_iter_params * n)()
+        handles = (C.c_void_p * n)()
+        for k, (m, p) in enumerate(zip(models, params)):
+            arr[k] = m._params(**p)
+            handles[k] = m.handle
+        t = None
+        if tune:
+            t = smc_tune(int(tune.get("blocks_per_cu", 0)), int(tune.get("long_waves_per_cu", 0)),
+                         int(tune.get("long_budget", 0)), 0)
+        _check(_lib.smc_batch_run(self.handle, handles, arr, n, C.byref(t) if t else None,
+                                  F_TIMING if timing else 0, _stream_ptr(stream)))
+
+    def batch_read_timing(self):
+        ms = C.c_double()
+        _check(_lib.smc_batch_read_timing(self.handle, C.byref(ms)))
+        return float(ms.value)
 
     def close(self):
         if self.handle:
@@ -215,12 +241,9 @@ class Model:
         except Exception:
             pass
 
-    def run_iteration(self, n_packets: int, T_inner: float, iteration: int = 0,
-                      flags: Optional[int] = None, L_requested: float = 0.0,
-                      damping: float = 1.0, max_segments: int = 10**7, packet_ids=None,
-                      stream=None):
-        """Enqueue one iteration.  packet_ids: optional torch int64/uint64
-        CUDA tensor or numpy array of ids (copied to the device)."""
+    def _params(self, n_packets: int, T_inner: float, iteration: int = 0,
+                flags: Optional[int] = None, L_requested: float = 0.0, damping: float = 1.0,
+                max_segments: int = 10**7, packet_ids=None):
         import torch
         p = smc_iter_params()
         p.n_packets = int(n_packets)
@@ -237,6 +260,16 @@ class Model:
             self._ids = ids  # keep alive until the next iteration
             p.packet_ids = ids.data_ptr()
             p.n_ids = int(ids.numel())
+        return p
+
+    def run_iteration(self, n_packets: int, T_inner: float, iteration: int = 0,
+                      flags: Optional[int] = None, L_requested: float = 0.0,
+                      damping: float = 1.0, max_segments: int = 10**7, packet_ids=None,
+                      stream=None):
+        """Enqueue one iteration.  packet_ids: optional torch int64/uint64
+        CUDA tensor or numpy array of ids (copied to the device)."""
+        p = self._params(n_packets, T_inner, iteration, flags, L_requested, damping,
+                         max_segments, packet_ids)
         _check(_lib.smc_run_iteration(self.handle, C.byref(p), _stream_ptr(stream)))
 
     def read_estimators(self, jblue: bool = True, stream=None):
