@@ -198,6 +198,33 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
  * of this context.  Waits for them to end. */
 int smc_batch_read_timing(smc_ctx* ctx, double* transport_ms);
 
+/* Pick launch tuning for this batch by running it: each candidate (NULL:
+ * the library's coordinate search over hand-off budget, waves per CU and
+ * workgroups per CU) runs one timed iteration of the whole batch and the
+ * fastest is written to *best (its time to *best_ms, may be NULL).  Every
+ * params[k].T_inner must be > 0 so that all trials see the same inputs; the
+ * models' tallies hold the last trial's results afterwards.  Synchronises
+ * `stream`. */
+int smc_batch_autotune(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
+                       int n_models, const smc_tune* candidates, int n_candidates,
+                       smc_tune* best, double* best_ms, void* stream);
+
+/* A captured sequence of iterations: n_iter iterations of the same
+ * n_models models (params[i*n_models + k] is iteration i of model k;
+ * T_inner <= 0 carries the device-side update between iterations), recorded
+ * once into a HIP graph and replayed by smc_graph_launch with no host work
+ * per iteration.  n_models = 1 records the single-model kernels.  The graph
+ * owns copies of the model tables; the models' workspaces and any
+ * packet_ids arrays must outlive it.  Recording uses a private stream (so
+ * `stream` may be the null stream) and enqueues nothing; launches must not
+ * overlap with other work on the same models. */
+typedef struct smc_graph smc_graph;
+int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
+                      int n_models, int n_iter, const smc_tune* tune, void* stream,
+                      smc_graph** out);
+int smc_graph_launch(smc_graph* graph, void* stream);
+int smc_graph_destroy(smc_graph* graph);
+
 /* Set (NULL: reset to defaults) or read the launch tuning of a model.  Tuning
  * changes launch shapes only: results are identical up to the summation
  * order of the tallies. */

@@ -9,6 +9,7 @@
 
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/smc.h"
 #include "smc_internal.h"
@@ -551,6 +552,66 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
   return ok();
 }
 
+int smc_batch_autotune(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
+                       int n_models, const smc_tune* candidates, int n_candidates,
+                       smc_tune* best, double* best_ms, void* stream) {
+  if (!ctx || !models || !params || !best) return fail(SMC_EINVAL, "null argument");
+  if (n_models < 1 || n_models > smc::kMaxBatchModels)
+    return fail(SMC_EINVAL, "n_models=%d outside [1, %d]", n_models, smc::kMaxBatchModels);
+  for (int k = 0; k < n_models; ++k)
+    if (!(params[k].T_inner > 0.0))
+      return fail(SMC_EINVAL, "autotuning needs T_inner > 0 for every model (model %d)", k);
+  auto trial = [&](const smc_tune& t, double* ms) -> int {
+    int rc = smc_batch_run(ctx, models, params, n_models, &t, SMC_F_TIMING, stream);
+    if (rc) return rc;
+    return smc_batch_read_timing(ctx, ms);
+  };
+  smc_tune cur;
+  memset(&cur, 0, sizeof cur);
+  double cur_ms = 0.0;
+  if (candidates && n_candidates > 0) {
+    double bms = INFINITY;
+    for (int i = 0; i < n_candidates; ++i) {
+      double ms;
+      int rc = trial(candidates[i], &ms);
+      if (rc) return rc;
+      if (ms < bms) {
+        bms = ms;
+        cur = candidates[i];
+      }
+    }
+    cur_ms = bms;
+  } else {
+    // coordinate search from the defaults: hand-off budget, then waves per
+    // CU of the wave-per-packet kernel, then workgroups per CU
+    int rc = trial(cur, &cur_ms);
+    if (rc) return rc;
+    const uint32_t budgets[] = {256, 1024, 4096, UINT32_MAX};
+    const int32_t waves[] = {4, 8, 16};
+    const int32_t blocks[] = {1, 2, 3};
+    for (int dim = 0; dim < 3; ++dim) {
+      const int n = dim == 0 ? 4 : 3;
+      for (int i = 0; i < n; ++i) {
+        smc_tune t = cur;
+        if (dim == 0) t.long_budget = budgets[i];
+        if (dim == 1) t.long_waves_per_cu = waves[i];
+        if (dim == 2) t.blocks_per_cu = blocks[i];
+        if (dim == 2 && blocks[i] > ctx->transport_blocks_per_cu[1]) continue;
+        double ms;
+        rc = trial(t, &ms);
+        if (rc) return rc;
+        if (ms < cur_ms) {
+          cur_ms = ms;
+          cur = t;
+        }
+      }
+    }
+  }
+  *best = cur;
+  if (best_ms) *best_ms = cur_ms;
+  return ok();
+}
+
 int smc_batch_read_timing(smc_ctx* ctx, double* transport_ms) {
   if (!ctx || !transport_ms) return fail(SMC_EINVAL, "null context or output");
   if (!ctx->batch_timed) return fail(SMC_EINVAL, "the last batch was not timed");
@@ -650,6 +711,159 @@ int smc_read_timing(smc_model* m, double* transport_ms) {
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, m->ev_start, m->ev_stop), "hipEventElapsedTime");
   *transport_ms = (double)ms;
+  return ok();
+}
+
+struct smc_graph {
+  smc_ctx* ctx;
+  std::vector<smc_model*> models;
+  std::vector<smc_iter_params> last;   // parameters of the last iteration, per model
+  smc::BatchEntry* host_tables;        // pinned, n_iter * n_models
+  smc::BatchEntry* dev_tables;
+  unsigned long long* dev_ctr;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+static void release_graph(smc_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->host_tables) (void)hipHostFree(g->host_tables);
+  if (g->dev_tables) (void)hipFree(g->dev_tables);
+  if (g->dev_ctr) (void)hipFree(g->dev_ctr);
+  delete g;
+}
+
+int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
+                      int n_models, int n_iter, const smc_tune* tune, void* stream,
+                      smc_graph** out) {
+  if (!ctx || !models || !params || !out) return fail(SMC_EINVAL, "null argument");
+  *out = nullptr;
+  if (n_models < 1 || n_models > smc::kMaxBatchModels || n_iter < 1 || n_iter > 1000)
+    return fail(SMC_EINVAL, "n_models must lie in [1, %d] and n_iter in [1, 1000]",
+                smc::kMaxBatchModels);
+  smc_tune t;
+  memset(&t, 0, sizeof t);
+  if (tune)
+    t = *tune;
+  else if (n_models == 1 && models[0])
+    t = models[0]->tune;
+  const uint32_t budget = budget_of(t);
+  for (int k = 0; k < n_models; ++k) {
+    if (!models[k] || models[k]->ctx != ctx)
+      return fail(SMC_EINVAL, "model %d is null or of another context", k);
+    for (int j = 0; j < k; ++j)
+      if (models[j] == models[k]) return fail(SMC_EINVAL, "model %d appears twice", k);
+    if (!(params[k].T_inner > 0.0) && !models[k]->has_T)
+      return fail(SMC_EINVAL, "model %d: the first captured iteration needs T_inner > 0", k);
+  }
+  HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  smc_graph* g = new (std::nothrow) smc_graph();
+  if (!g) return fail(SMC_ENOMEM, "host allocation failed");
+  g->ctx = ctx;
+  g->models.assign(models, models + n_models);
+  const size_t n_ent = (size_t)n_iter * (size_t)n_models;
+  hipError_t e = hipHostMalloc((void**)&g->host_tables, n_ent * sizeof(smc::BatchEntry),
+                               hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void**)&g->dev_tables, n_ent * sizeof(smc::BatchEntry));
+  if (e == hipSuccess) e = hipMalloc((void**)&g->dev_ctr, 4 * sizeof(unsigned long long));
+  if (e != hipSuccess) {
+    release_graph(g);
+    return hip_fail(e, "graph table allocation");
+  }
+  std::vector<uint64_t> work(n_iter, 0), max_jb(n_iter, 0);
+  for (int i = 0; i < n_iter; ++i) {
+    for (int k = 0; k < n_models; ++k) {
+      smc::BatchEntry& be = g->host_tables[(size_t)i * n_models + k];
+      smc_iter_params p = params[(size_t)i * n_models + k];
+      p.flags &= ~SMC_F_TIMING;
+      // later iterations may take T_inner from the device
+      smc_model tmp = *models[k];
+      tmp.has_T = true;
+      int rc = make_iter(&tmp, &p, budget, &be.it);
+      if (rc) {
+        release_graph(g);
+        return rc;
+      }
+      be.m = models[k]->dev;
+      be.work_begin = work[i];
+      be.long_begin = 0;
+      work[i] += be.it.n_work;
+      const uint64_t jb = jblue_entries(models[k], p.flags);
+      if (jb > max_jb[i]) max_jb[i] = jb;
+      if (i == n_iter - 1) g->last.push_back(p);
+    }
+  }
+  // the device tables are filled before capture; the graph only launches
+  e = hipMemcpy(g->dev_tables, g->host_tables, n_ent * sizeof(smc::BatchEntry),
+                hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    release_graph(g);
+    return hip_fail(e, "graph table upload");
+  }
+  // record on a private stream (the caller's may be the null stream, which
+  // cannot capture); the graph is launched later on the caller's stream
+  (void)stream;
+  hipStream_t s = nullptr;
+  e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    if (s) (void)hipStreamDestroy(s);
+    release_graph(g);
+    return hip_fail(e, "hipStreamBeginCapture");
+  }
+  hipError_t le = hipSuccess;
+  for (int i = 0; i < n_iter && le == hipSuccess; ++i) {
+    smc::LaunchArgs a;
+    memset(&a, 0, sizeof a);
+    const bool multi = n_models > 1;
+    if (multi) {
+      a.table = g->dev_tables + (size_t)i * n_models;
+      a.n_models = n_models;
+      a.total_work = work[i];
+      a.ctr = g->dev_ctr;
+    } else {
+      a.single = g->host_tables[i];
+      a.n_models = 1;
+      a.total_work = work[i];
+      a.ctr = models[0]->dev.counters + smc::CTR_QUEUE;
+    }
+    const smc::Shape sh = shape_of(ctx, t, multi, work[i], budget > 0);
+    le = smc::launch_iteration(a, multi, sh, max_jb[i], nullptr, nullptr, s);
+  }
+  e = hipStreamEndCapture(s, &g->graph);
+  (void)hipStreamDestroy(s);
+  if (le != hipSuccess || e != hipSuccess) {
+    release_graph(g);
+    return hip_fail(le != hipSuccess ? le : e, "graph capture");
+  }
+  e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    release_graph(g);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  *out = g;
+  return ok();
+}
+
+int smc_graph_launch(smc_graph* g, void* stream) {
+  if (!g) return fail(SMC_EINVAL, "null graph");
+  HIP_TRY(hipSetDevice(g->ctx->device), "hipSetDevice");
+  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream), "hipGraphLaunch");
+  for (size_t k = 0; k < g->models.size(); ++k) {
+    smc_model* m = g->models[k];
+    m->has_T = true;
+    m->ran = true;
+    m->timed = false;
+    m->last_flags = g->last[k].flags;
+    m->last_work = g->last[k].packet_ids ? g->last[k].n_ids : g->last[k].n_packets;
+  }
+  return ok();
+}
+
+int smc_graph_destroy(smc_graph* g) {
+  release_graph(g);
   return ok();
 }
 

@@ -60,7 +60,8 @@ PACKET_DTYPE = np.dtype([("id", np.uint64), ("status", np.int32), ("shell", np.i
 EXPORTS = ("smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_model_workspace_bytes",
            "smc_model_load", "smc_model_free", "smc_run_iteration", "smc_read_estimators",
            "smc_read_spectrum", "smc_read_counters", "smc_read_packets", "smc_read_timing",
-           "smc_model_set_tune", "smc_model_get_tune", "smc_batch_run", "smc_batch_read_timing")
+           "smc_model_set_tune", "smc_model_get_tune", "smc_batch_run", "smc_batch_read_timing",
+           "smc_batch_autotune", "smc_graph_capture", "smc_graph_launch", "smc_graph_destroy")
 
 
 class SmcError(RuntimeError):
@@ -101,6 +102,12 @@ def load_library(path: str = LIB_PATH):
     L.smc_batch_run.argtypes = [vp, C.POINTER(vp), C.POINTER(smc_iter_params), C.c_int,
                                 C.POINTER(smc_tune), C.c_uint32, vp]
     L.smc_batch_read_timing.argtypes = [vp, _dp]
+    L.smc_batch_autotune.argtypes = [vp, C.POINTER(vp), C.POINTER(smc_iter_params), C.c_int,
+                                     C.POINTER(smc_tune), C.c_int, C.POINTER(smc_tune), _dp, vp]
+    L.smc_graph_capture.argtypes = [vp, C.POINTER(vp), C.POINTER(smc_iter_params), C.c_int,
+                                    C.c_int, C.POINTER(smc_tune), vp, C.POINTER(vp)]
+    L.smc_graph_launch.argtypes = [vp, vp]
+    L.smc_graph_destroy.argtypes = [vp]
     L.smc_model_get_tune.argtypes = [vp, C.POINTER(smc_tune)]
     for name in EXPORTS:
         if name != "smc_last_error":
@@ -124,6 +131,34 @@ def _ptr(a, t):
     return a.ctypes.data_as(t) if a is not None else None
 
 
+def _tune(d):
+    return smc_tune(int(d.get("blocks_per_cu", 0)), int(d.get("long_waves_per_cu", 0)),
+                    int(d.get("long_budget", 0)), 0)
+
+
+class Graph:
+    """A captured sequence of iterations (smc_graph_*)."""
+
+    def __init__(self, handle, models, keep):
+        self.handle = handle
+        self.models = list(models)  # the workspaces must outlive the graph
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _check(_lib.smc_graph_launch(self.handle, _stream_ptr(stream)))
+
+    def destroy(self):
+        if self.handle:
+            _lib.smc_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 class Context:
     def __init__(self, device: int = 0):
         lib = load_library()
@@ -143,12 +178,50 @@ class Context:
         for k, (m, p) in enumerate(zip(models, params)):
             arr[k] = m._params(**p)
             handles[k] = m.handle
-        t = None
-        if tune:
-            t = smc_tune(int(tune.get("blocks_per_cu", 0)), int(tune.get("long_waves_per_cu", 0)),
-                         int(tune.get("long_budget", 0)), 0)
+        t = _tune(tune) if tune else None
         _check(_lib.smc_batch_run(self.handle, handles, arr, n, C.byref(t) if t else None,
                                   F_TIMING if timing else 0, _stream_ptr(stream)))
+
+    def batch_autotune(self, models, params, candidates=None, stream=None):
+        """Time the batch under each candidate tuning (default: the library's
+        coordinate search) and return (best tuning dict, its ms)."""
+        n = len(models)
+        arr = (smc_iter_params * n)()
+        handles = (C.c_void_p * n)()
+        for k, (m, p) in enumerate(zip(models, params)):
+            arr[k] = m._params(**p)
+            handles[k] = m.handle
+        cands, nc = None, 0
+        if candidates:
+            nc = len(candidates)
+            cands = (smc_tune * nc)()
+            for i, c in enumerate(candidates):
+                cands[i] = _tune(c)
+        best = smc_tune()
+        ms = C.c_double()
+        _check(_lib.smc_batch_autotune(self.handle, handles, arr, n, cands, nc, C.byref(best),
+                                       C.byref(ms), _stream_ptr(stream)))
+        return (dict(blocks_per_cu=best.blocks_per_cu, long_waves_per_cu=best.long_waves_per_cu,
+                     long_budget=best.long_budget), float(ms.value))
+
+    def capture(self, models, params_per_iter, tune=None, stream=None):
+        """Record iterations (a list, one list of per-model parameter dicts per
+        iteration) into a replayable HIP graph."""
+        n, n_iter = len(models), len(params_per_iter)
+        arr = (smc_iter_params * (n * n_iter))()
+        handles = (C.c_void_p * n)()
+        for k, m in enumerate(models):
+            handles[k] = m.handle
+        keep = []
+        for i, plist in enumerate(params_per_iter):
+            for k, (m, p) in enumerate(zip(models, plist)):
+                arr[i * n + k] = m._params(**p)
+                keep.append(m._ids)
+        h = C.c_void_p()
+        t = _tune(tune) if tune else None
+        _check(_lib.smc_graph_capture(self.handle, handles, arr, n, n_iter,
+                                      C.byref(t) if t else None, _stream_ptr(stream), C.byref(h)))
+        return Graph(h, models, keep)
 
     def batch_read_timing(self):
         ms = C.c_double()

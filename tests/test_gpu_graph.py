@@ -1,0 +1,94 @@
+"""Captured iteration sequences (HIP graphs) and the batch autotuner."""
+import numpy as np
+import pytest
+
+from paper_1401_5469_amd import smc
+from paper_1401_5469_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+F_ALL = smc.F_JBLUE | smc.F_PACKETS
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return smc.Context(0)
+
+
+def _iters(T0, n_iter, N, L_req):
+    # the first iteration fixes T_inner, later ones take the device-side update
+    return [dict(n_packets=N, T_inner=T0 if i == 0 else 0.0, iteration=i, flags=F_ALL,
+                 L_requested=L_req, damping=0.5) for i in range(n_iter)]
+
+
+def _state(m, N):
+    return dict(packets=m.read_packets(N), est=m.read_estimators(), spec=m.read_spectrum())
+
+
+def _same(a, b):
+    assert np.array_equal(a["packets"], b["packets"])
+    for k in ("J", "nubar", "T_R", "W"):
+        np.testing.assert_allclose(b["est"][k], a["est"][k], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(b["est"]["jblue"], a["est"]["jblue"], rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(b["spec"]["L_nu"], a["spec"]["L_nu"], rtol=1e-12, atol=1e-300)
+    assert b["spec"]["T_inner"] == pytest.approx(a["spec"]["T_inner"], rel=1e-12, abs=0)
+
+
+def test_graph_replays_match_eager_single_model(ctx):
+    import torch
+    w = W.config2(n_lines=20_000)
+    N = 3000
+    seq = _iters(w.T_inner, 3, N, w.L_requested)
+    eager = smc.Model(ctx, w.model, N, flags=F_ALL)
+    for p in seq:
+        eager.run_iteration(**p)
+    ref = _state(eager, N)
+    assert ref["spec"]["T_inner"] != w.T_inner  # the update was carried on the device
+
+    m = smc.Model(ctx, w.model, N, flags=F_ALL)
+    g = ctx.capture([m], [[p] for p in seq])
+    for replay in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        _same(ref, _state(m, N))
+        # eager work on the same stream between replays
+        scratch = torch.ones(1 << 20, device="cuda").sum().item()
+        assert scratch == float(1 << 20)
+    g.destroy()
+
+
+def test_graph_replays_match_eager_multi_model(ctx):
+    import torch
+    mix = [(W.small_model(seed=s, n_shells=S, n_lines=L), N)
+           for s, S, L, N in [(1, 4, 300, 500), (2, 9, 2000, 1300), (3, 2, 50, 70)]]
+    seqs = [_iters(9500.0, 2, N, 0.0) for _, N in mix]
+    eager = [smc.Model(ctx, mdl, N, flags=F_ALL) for mdl, N in mix]
+    for i in range(2):
+        ctx.batch_run(eager, [s[i] for s in seqs], tune=dict(long_budget=4))
+    refs = [_state(m, N) for m, (_, N) in zip(eager, mix)]
+    models = [smc.Model(ctx, mdl, N, flags=F_ALL) for mdl, N in mix]
+    g = ctx.capture(models, [[s[i] for s in seqs] for i in range(2)], tune=dict(long_budget=4))
+    for replay in range(2):
+        g.launch()
+        torch.cuda.synchronize()
+        for ref, m, (_, N) in zip(refs, models, mix):
+            _same(ref, _state(m, N))
+    g.destroy()
+
+
+def test_autotune_picks_a_valid_config(ctx):
+    mix = [(W.small_model(seed=s, n_shells=6, n_lines=3000, tau="lognormal"), 4000)
+           for s in range(3)]
+    models = [smc.Model(ctx, mdl, N, flags=smc.F_JBLUE) for mdl, N in mix]
+    params = [dict(n_packets=N, T_inner=9000.0) for _, N in mix]
+    best, ms = ctx.batch_autotune(models, params)
+    assert ms > 0.0
+    assert best["long_budget"] in (0, 256, 1024, 4096, 2**32 - 1)
+    cands = [dict(long_budget=8), dict(long_budget=2**32 - 1, blocks_per_cu=1)]
+    best2, ms2 = ctx.batch_autotune(models, params, candidates=cands)
+    assert best2 in [dict(blocks_per_cu=c.get("blocks_per_cu", 0), long_waves_per_cu=0,
+                          long_budget=c["long_budget"]) for c in cands]
+    with pytest.raises(smc.SmcError):
+        ctx.batch_autotune(models, [dict(n_packets=N, T_inner=0.0) for _, N in mix])
