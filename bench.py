@@ -1,6 +1,7 @@
 """Benchmark of the packet-transport hot path on one MI355X.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 1]
+    python bench.py --workload batched [--steps 3]
 
 One step is one Monte Carlo iteration of the paper-scale scatter model
 (20 shells 10000-25000 km/s at 13 d, 3e5 lines, 1e6 packets; Kerzendorf & Sim
@@ -40,6 +41,8 @@ def parse():
                     help="packets of iteration 0 the oracle runs for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-jblue", action="store_true")
+    ap.add_argument("--workload", default="paper-scale", choices=["paper-scale", "batched"])
+    ap.add_argument("--models", type=int, default=64, help="models in the batched mix")
     return ap.parse_args()
 
 
@@ -65,12 +68,105 @@ def cpu_baseline(w, n_sample):
             "line_passes_per_s": c["line_passes"] / dt, "seconds": dt}
 
 
+def batched(args):
+    """64 models of uneven size (shells U{10..100}, lines log-uniform 1e4-3e5,
+    packets log-uniform 1e5-1e6, otherwise as the paper-scale model; model i
+    from seed i), one iteration each: one autotuned multi-model launch per
+    step against 64 sequential single-model launches with the same packets."""
+    import numpy as np
+    import torch
+
+    from paper_1401_5469_amd import smc
+    from paper_1401_5469_amd import workloads as W
+
+    t0 = time.perf_counter()
+    mix = [W.config4_model(i) for i in range(args.models)]
+    gen_s = time.perf_counter() - t0
+    flags = 0 if args.no_jblue else smc.F_JBLUE
+    ctx = smc.Context(0)
+    models = [smc.Model(ctx, w.model, w.n_packets, flags=flags) for w in mix]
+    torch.cuda.synchronize()
+    print(f"# {len(mix)} models generated in {gen_s:.1f} s and loaded", file=sys.stderr, flush=True)
+    params = [dict(n_packets=w.n_packets, T_inner=w.T_inner, iteration=0, flags=flags)
+              for w in mix]
+
+    def counts(ms):
+        c = [m.read_counters() for m in ms]
+        return (sum(x["line_events"] + x["escatters"] for x in c), sum(x["segments"] for x in c))
+
+    # plain form: one single-model iteration after the other
+    for w, m, p in zip(mix[:2], models[:2], params[:2]):
+        m.run_iteration(**p)  # warm-up
+    torch.cuda.synchronize()
+    plain_walls = []
+    for step in range(args.steps):
+        t0 = time.perf_counter()
+        for m, p in zip(models, params):
+            m.run_iteration(**p)
+        torch.cuda.synchronize()
+        plain_walls.append(time.perf_counter() - t0)
+        print(f"# plain step {step}: {plain_walls[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    inter, segs = counts(models)
+
+    # batched form: the autotuned multi-model launch
+    t0 = time.perf_counter()
+    best, best_ms = ctx.batch_autotune(models, params)
+    tune_s = time.perf_counter() - t0
+    print(f"# autotune: {best} {best_ms:.1f} ms ({tune_s:.1f} s)", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ctx.batch_run(models, params, tune=best)
+    torch.cuda.synchronize()
+    walls, kern = [], []
+    for step in range(args.steps):
+        t0 = time.perf_counter()
+        ctx.batch_run(models, params, tune=best, timing=True)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        kern.append(ctx.batch_read_timing())
+        print(f"# batched step {step}: {walls[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    b_inter, b_segs = counts(models)
+    n = len(mix)
+    wall = float(np.mean(walls))
+    plain = float(np.mean(plain_walls))
+    out = {
+        "metric": "models/sec (batched)",
+        "value": n / wall,
+        "unit": "models/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched-{n}-models", "models": n,
+                   "packets_total": int(sum(w.n_packets for w in mix)),
+                   "shells_mean": float(np.mean([w.model.n_shells for w in mix])),
+                   "lines_mean": float(np.mean([w.model.n_lines for w in mix])),
+                   "jblue": not args.no_jblue},
+        "batched": {"models_per_s": n / wall, "interactions_per_s": b_inter / wall,
+                    "segments_per_s": b_segs / wall, "wall_ms": wall * 1e3,
+                    "transport_ms": kern, "tune": best, "autotune_s": tune_s},
+        "plain": {"models_per_s": n / plain, "interactions_per_s": inter / plain,
+                  "segments_per_s": segs / plain, "wall_ms": plain * 1e3},
+        "speedup_vs_plain": plain / wall,
+        "interactions_per_step": b_inter,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported in this build "
               "(the transport shards by packet ids; see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        if args.steps == 10:
+            args.steps = 3
+        return batched(args)
 
     import numpy as np
     import torch
