@@ -2,6 +2,7 @@
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 1]
     python bench.py --workload batched [--steps 3]
+    python bench.py --workload served [--duration 10]
 
 One step is one Monte Carlo iteration of the paper-scale scatter model
 (20 shells 10000-25000 km/s at 13 d, 3e5 lines, 1e6 packets; Kerzendorf & Sim
@@ -41,8 +42,13 @@ def parse():
                     help="packets of iteration 0 the oracle runs for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-jblue", action="store_true")
-    ap.add_argument("--workload", default="paper-scale", choices=["paper-scale", "batched"])
+    ap.add_argument("--workload", default="paper-scale",
+                    choices=["paper-scale", "batched", "served"])
     ap.add_argument("--models", type=int, default=64, help="models in the batched mix")
+    ap.add_argument("--duration", type=float, default=10.0,
+                    help="seconds of Poisson arrivals (20 per second) in the served mode")
+    ap.add_argument("--budget-gb", type=float, default=200.0,
+                    help="device-memory admission budget of the served mode")
     return ap.parse_args()
 
 
@@ -157,6 +163,90 @@ def batched(args):
     print(json.dumps(out), flush=True)
 
 
+def _gen_request(args):
+    t, seed, n_iter = args
+    from paper_1401_5469_amd import workloads as W
+    w = W.config4_model(seed)
+    return t, seed, n_iter, w
+
+
+def served(args):
+    """Poisson arrivals at 20 requests/s; request j is a model drawn as in the
+    batched mix from seed 1000+j with U{1..10} iterations.  The continuous-
+    batching server (admission by a device-memory budget, one multi-model
+    launch per step, state resident on the device) against the plain path
+    (one request at a time, one single-model launch per iteration), on the
+    same requests and packet counts."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    from paper_1401_5469_amd import serve
+    from paper_1401_5469_amd import workloads as W
+
+    arrivals = W.config5_requests(duration_s=args.duration)
+    t0 = time.perf_counter()
+    # generate the request models before the GPU is touched
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        gen = pool.map(_gen_request, arrivals)
+    print(f"# {len(gen)} requests generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+
+    def make():
+        return [serve.Request(model=w.model, n_iterations=n_iter, n_packets=w.n_packets,
+                              T_inner=w.T_inner, L_requested=w.L_requested, damping=w.damping,
+                              arrival=t) for t, seed, n_iter, w in gen]
+
+    budget = int(args.budget_gb * 2**30)
+    be = serve.GpuBackend()
+    reqs = make()
+    srv = serve.Server(be, memory_budget=budget)
+    for r in reqs:
+        srv.submit(r)
+    t0 = time.perf_counter()
+    last = 0
+    while srv.pending or srv.active:
+        if not srv.step():
+            nxt = srv.pending[0].arrival if srv.pending else None
+            if nxt is not None:
+                time.sleep(max(0.0, nxt - srv.now()))
+        done = sum(r.state == serve.DONE for r in reqs)
+        if done >= last + 50:
+            last = done
+            print(f"# served {done}/{len(reqs)} at {srv.now():.1f} s, active {len(srv.active)}",
+                  file=sys.stderr, flush=True)
+    served_wall = time.perf_counter() - t0
+    st = srv.stats()
+    packets = sum(r.n_packets * r.n_iterations for r in reqs)
+    print(f"# served: {st}", file=sys.stderr, flush=True)
+    plain_reqs = make()
+    t0 = time.perf_counter()
+    pst = serve.serve_plain(be, plain_reqs)
+    plain_wall = time.perf_counter() - t0
+    print(f"# plain: {pst}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "p99 synthesis latency (served)",
+        "value": st["p99_s"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": st["steps"],
+        "warmup": 0,
+        "ms_per_step": served_wall / max(st["steps"], 1) * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"served-poisson-20hz-{args.duration:g}s", "requests": len(reqs),
+                   "iterations_total": int(sum(r.n_iterations for r in reqs)),
+                   "packets_total": int(packets), "budget_gb": args.budget_gb},
+        "served": {**st, "wall_s": served_wall, "packets_per_s": packets / served_wall},
+        "plain": {**pst, "wall_s": plain_wall, "packets_per_s": packets / plain_wall},
+        "offered_packets_per_s": packets / args.duration,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -167,6 +257,8 @@ def main():
         if args.steps == 10:
             args.steps = 3
         return batched(args)
+    if args.workload == "served":
+        return served(args)
 
     import numpy as np
     import torch
