@@ -253,6 +253,13 @@ __device__ __forceinline__ double shell_distance(double r, double mu, double rmu
   return d < 0.0 ? 0.0 : d;
 }
 
+// 1/x from the hardware estimate and two Newton steps (last-bit accurate)
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // spectrum bin of an escaping lab frequency (section 2.9): n_bins is the
 // underflow slot (also taken by a NaN), n_bins+1 the overflow slot
 __device__ __forceinline__ int spectrum_bin(const DevModel& m, double nu) {
@@ -345,6 +352,7 @@ struct View {
   uint64_t max_segments, budget;
   int32_t S, L, Lp;
   bool downbranch;
+  bool records;           // per-packet records (and their event hash) are kept
   uint32_t k0, k1, iter;  // random-number key and counter word
 };
 
@@ -363,6 +371,7 @@ __device__ __forceinline__ View make_view(const DevModel& m, const DevIter& it) 
   v.L = m.L;
   v.Lp = m.Lp;
   v.downbranch = m.mode == SMC_DOWNBRANCH;
+  v.records = m.packets != nullptr && (it.flags & SMC_F_PACKETS);
   v.k0 = (uint32_t)m.seed;
   v.k1 = (uint32_t)(m.seed >> 32);
   v.iter = it.iteration;
@@ -607,7 +616,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(LaunchArgs a) {
       next_line = k;
 
       // event choice: line, else electron, else boundary
-      const double d_electron = kappa > 0.0 ? tau_rem / kappa : INFINITY;
+      const double d_electron = (!line_hit && kappa > 0.0) ? tau_rem * recip(kappa) : INFINITY;
       const bool escat = !line_hit && d_electron < d_shell;
       const bool cross = !line_hit && !escat;
       const double d = line_hit ? d_line : (escat ? d_electron : d_shell);
@@ -637,7 +646,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(LaunchArgs a) {
         const int kind = inward ? EV_SHELL_IN : EV_SHELL_OUT;
         r = inward ? c_rin : c_rout;
         mu = mu_new;
-        hash = fnv_event(hash, kind, sh, -1, -1);
+        if (v.records) hash = fnv_event(hash, kind, sh, -1, -1);
         shell = sh + (inward ? -1 : 1);
         if (shell >= v.S)
           status = SMC_ESCAPED;
@@ -665,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(LaunchArgs a) {
         }
         const double mu_out = 2.0 * rng_next(g) - 1.0;
         const double D_new = 1.0 - (mu_out * r_new) * v.inv_ct;
-        const double inv_D = 1.0 / D_new;
+        const double inv_D = recip(D_new);
         r = r_new;
         mu = mu_out;
         nu = nu_cmf_out * inv_D;
@@ -674,10 +683,10 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(LaunchArgs a) {
           next_line = emit + 1;
           n_line += 1;
           last_line = k;
-          hash = fnv_event(hash, EV_LINE, sh, k, emit);
+          if (v.records) hash = fnv_event(hash, EV_LINE, sh, k, emit);
         } else {
           n_esc += 1;
-          hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
+          if (v.records) hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
         }
       }
     }
@@ -728,6 +737,29 @@ __device__ __forceinline__ double readlane_f64(double x, int src) {
 
 __device__ __forceinline__ int uniform_i32(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// x moved by DPP (both 32-bit halves); lanes the control does not write keep 0
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, kCtrl, kRowMask,
+                                                            0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
+      0, (int)(uint32_t)(b >> 32), kCtrl, kRowMask, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// inclusive prefix sum over the 64 lanes (row shifts within rows of 16, then
+// the row broadcasts of lanes 15 and 31)
+__device__ __forceinline__ double wave_prefix_sum(double x) {
+  x += dpp_f64<0x111, 0xF>(x);  // row_shr:1
+  x += dpp_f64<0x112, 0xF>(x);  // row_shr:2
+  x += dpp_f64<0x114, 0xF>(x);  // row_shr:4
+  x += dpp_f64<0x118, 0xF>(x);  // row_shr:8
+  x += dpp_f64<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_f64<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 constexpr int kLongBlock = 64;
 
 template <bool kMulti>
@@ -773,9 +805,12 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
     }
     const DevModel& m = ENTRY(a, model).m;
     const View v = make_view(m, ENTRY(a, model).it);
+    const bool want_records = m.packets != nullptr && (ENTRY(a, model).it.flags & SMC_F_PACKETS);
     const LongState st = m.longs[idx];
-    uint64_t n_seg = st.n_seg, n_pass = st.n_pass, hash = st.hash, draw = st.draw;
+    uint64_t n_seg = st.n_seg, n_pass = st.n_pass, hash = st.hash;
+    uint32_t draw = (uint32_t)st.draw;
     double r = st.r, mu = st.mu, nu = st.nu, E = st.E;
+    double inv_nu = recip(nu);
     int32_t shell = st.shell, next_line = st.next_line, last_line = st.last_line;
     uint32_t n_esc = st.n_esc, n_line = st.n_line;
     StreamKey sk;
@@ -787,13 +822,14 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
 
     // 128 upcoming draws: lane i holds draws 2(rb + i) and 2(rb + i) + 1,
     // with their negative logarithms for tau_event
-    uint32_t rb = (uint32_t)(draw >> 1);
+    uint32_t rb = draw >> 1;
     Block blk = stream_block(sk, rb + lane);
     double ua = to_uniform(blk.a), ub = to_uniform(blk.b);
     double la = -log(ua), lb = -log(ub);
-    // 64 lines of one shell: lane i holds line wbase + i
+    // 64 lines of one shell: lane i holds line wbase + i, its frequency,
+    // reciprocal and Sobolev depth
     int32_t wbase = -1, wshell = -1;
-    double wn = 0.0, wt = 0.0;
+    double wn = 0.0, wt = 0.0, winv = 0.0;
     int32_t c_shell = -1;
     double c_rin = 0.0, c_rout = 0.0, c_ne = 0.0;
 
@@ -804,16 +840,15 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
         break;
       }
       n_seg += 1;
-      if (draw + 3 > 2ull * (rb + kWave)) {
-        rb = (uint32_t)(draw >> 1);
+      if (draw + 3 > 2u * (rb + kWave)) {
+        rb = draw >> 1;
         blk = stream_block(sk, rb + lane);
         ua = to_uniform(blk.a);
         ub = to_uniform(blk.b);
         la = -log(ua);
         lb = -log(ub);
       }
-      const int src0 = uniform_i32((int)((draw >> 1) - rb));
-      const double tau0 = readlane_f64((draw & 1) ? lb : la, src0);
+      const double tau0 = readlane_f64((draw & 1) ? lb : la, uniform_i32((int)((draw >> 1) - rb)));
       draw += 1;
       const int sh = shell;
       if (sh != c_shell) {
@@ -829,56 +864,66 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
       bool inward;
       const double d_shell = shell_distance(r, mu, rmu, c_rin, c_rout, inward);
       const double kappa = kSigmaT * c_ne * D;
-      const double inv_nu = 1.0 / nu;
       const double ct_over_nu = v.ct * inv_nu;
       const double jb_w = E * inv_nu * inv_nu;
-
-      // line march over the register window; passed lines get their J_blue
-      // update from the lane holding them
-      double tau_rem = tau0;
-      int32_t k = next_line;
-      int32_t k_first = k;  // first line of the march still to be tallied
-      bool line_hit = false;
-      double d_line = 0.0, nu_hit = 0.0;
       double* jb_row = v.jblue ? v.jblue + (size_t)sh * (size_t)v.L : nullptr;
+
+      // line march, all 64 window lines at once: lane j tests line wbase+j
+      // against the optical depth left after the lines before it (prefix
+      // sum over the lanes); the first lane that stops the march decides
+      double tau_ev = tau0;  // left after the windows already passed
+      int32_t k = next_line;
+      bool line_hit = false;
+      double d_line = 0.0, nu_hit = 0.0, inv_hit = 0.0, tau_rem = tau0;
       while (k < v.L) {
-        if (sh != wshell || k >= wbase + kWave || k < wbase) {
-          if (jb_row && k > k_first && wshell == sh) {
-            const int32_t line = wbase + lane;
-            if (line >= k_first && line < k) unsafeAtomicAdd(&jb_row[line], jb_w * wn);
-          }
-          k_first = k;
+        if (sh != wshell || k < wbase || k >= wbase + kWave) {
           wbase = k;
           wshell = sh;
           const int32_t line = k + lane;
-          wn = line < v.L ? v.line_nu[line] : 0.0;
+          wn = line < v.L ? v.line_nu[line] : 1.0;
           wt = line < v.L ? v.tau[(size_t)sh * (size_t)v.Lp + line] : 0.0;
+          winv = recip(wn);
         }
-        const int src = uniform_i32(k - wbase);
-        const double nu_k = readlane_f64(wn, src);
-        double dl = (nu_cmf - nu_k) * ct_over_nu;
+        const int32_t line = wbase + lane;
+        const bool live = line >= k && line < v.L;
+        const double t = live ? wt : 0.0;
+        const double before = wave_prefix_sum(t) - t;  // depth of the live lines below
+        double dl = (nu_cmf - wn) * ct_over_nu;
         dl = dl < 0.0 ? 0.0 : dl;
-        if (!(kappa * dl < tau_rem && dl < d_shell)) break;
-        n_pass += 1;
-        const double tau_k = readlane_f64(wt, src);
-        if (tau_k + kappa * dl > tau_rem) {
-          line_hit = true;
-          d_line = dl;
-          nu_hit = nu_k;
+        const double rem = tau_ev - before;
+        const bool reach = kappa * dl < rem && dl < d_shell;
+        const bool hit = reach && wt + kappa * dl > rem;
+        const unsigned long long stop = __ballot(live && (!reach || hit));
+        const unsigned long long hits = __ballot(live && hit);
+        const int first = stop ? (int)__builtin_ctzll(stop) : -1;
+        // J_blue: every line reached up to the stop, the interacting one included
+        const int end = first < 0 ? kWave : first + ((hits >> first) & 1ull ? 1 : 0);
+        if (jb_row && live && lane < end) unsafeAtomicAdd(&jb_row[line], jb_w * wn);
+        const int passed = end - (k - wbase) > 0 ? end - (k - wbase) : 0;
+        n_pass += (uint64_t)(first < 0 ? (int32_t)(v.L < wbase + kWave ? v.L - k : wbase + kWave - k)
+                                       : passed);
+        if (first >= 0) {
+          const int fl = uniform_i32(first);
+          k = wbase + fl;
+          if ((hits >> fl) & 1ull) {
+            line_hit = true;
+            d_line = readlane_f64(dl, fl);
+            nu_hit = readlane_f64(wn, fl);
+            inv_hit = readlane_f64(winv, fl);
+          } else {
+            tau_rem = readlane_f64(rem, fl);
+          }
           break;
         }
-        tau_rem -= tau_k;
-        k += 1;
-      }
-      if (jb_row) {
-        const int32_t k_end = line_hit ? k + 1 : k;
-        const int32_t line = wbase + lane;
-        if (k_end > k_first && sh == wshell && line >= k_first && line < k_end)
-          unsafeAtomicAdd(&jb_row[line], jb_w * wn);
+        // every live line of the window passed
+        const int top = uniform_i32(v.L < wbase + kWave ? v.L - wbase - 1 : kWave - 1);
+        tau_ev -= readlane_f64(before + t, top);
+        tau_rem = tau_ev;
+        k = wbase + top + 1;
       }
       next_line = k;
 
-      const double d_electron = kappa > 0.0 ? tau_rem / kappa : INFINITY;
+      const double d_electron = (!line_hit && kappa > 0.0) ? tau_rem * recip(kappa) : INFINITY;
       const bool escat = !line_hit && d_electron < d_shell;
       const bool cross = !line_hit && !escat;
       const double d = line_hit ? d_line : (escat ? d_electron : d_shell);
@@ -899,14 +944,13 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
       acc_nb += jc * nu_cmf;
 
       const double r_new = sqrt(r * r + d * d + 2.0 * r * d * mu);
-      double mu_new = (rmu + d) / r_new;
-      mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
-
       if (cross) {
         const int kind = inward ? EV_SHELL_IN : EV_SHELL_OUT;
+        double mu_new = (rmu + d) * recip(r_new);
+        mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
         r = inward ? c_rin : c_rout;
         mu = mu_new;
-        hash = fnv_event(hash, kind, sh, -1, -1);
+        if (want_records) hash = fnv_event(hash, kind, sh, -1, -1);
         shell = sh + (inward ? -1 : 1);
         if (shell >= v.S) {
           status = SMC_ESCAPED;
@@ -917,15 +961,17 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
           break;
         }
       } else {
-        const double D_old = 1.0 - (mu_new * r_new) * v.inv_ct;
+        // mu_new * r_new = r mu + d along the straight path
+        const double D_old = 1.0 - (rmu + d) * v.inv_ct;
         const double e_cmf_ev = E * D_old;
-        double nu_cmf_out = nu * D_old;
+        double nu_cmf_out, inv_cmf_out;
         int32_t emit = k;
         if (line_hit) {
-          const int sb = uniform_i32((int)((draw >> 1) - rb));
-          const double u_branch = readlane_f64((draw & 1) ? ub : ua, sb);
+          const double u_branch = readlane_f64((draw & 1) ? ub : ua,
+                                               uniform_i32((int)((draw >> 1) - rb)));
           draw += 1;
           nu_cmf_out = nu_hit;
+          inv_cmf_out = inv_hit;
           if (v.downbranch) {
             const int32_t up = m.line_upper[k];
             const int64_t lo = m.level_ptr[up], hi = m.level_ptr[up + 1];
@@ -933,32 +979,37 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
             while (j < hi - 1 && !(m.em_cum[j] > u_branch)) ++j;
             emit = m.em_line[j];
             nu_cmf_out = v.line_nu[emit];
+            inv_cmf_out = recip(nu_cmf_out);
           }
+        } else {
+          nu_cmf_out = nu * D_old;
+          inv_cmf_out = recip(nu_cmf_out);
         }
-        const int sm = uniform_i32((int)((draw >> 1) - rb));
-        const double mu_out = 2.0 * readlane_f64((draw & 1) ? ub : ua, sm) - 1.0;
+        const double mu_out =
+            2.0 * readlane_f64((draw & 1) ? ub : ua, uniform_i32((int)((draw >> 1) - rb))) - 1.0;
         draw += 1;
         const double D_new = 1.0 - (mu_out * r_new) * v.inv_ct;
-        const double inv_D = 1.0 / D_new;
+        const double inv_D = recip(D_new);
         r = r_new;
         mu = mu_out;
         nu = nu_cmf_out * inv_D;
         E = e_cmf_ev * inv_D;
+        inv_nu = D_new * inv_cmf_out;
         if (line_hit) {
           next_line = emit + 1;
           n_line += 1;
           last_line = k;
-          hash = fnv_event(hash, EV_LINE, sh, k, emit);
+          if (want_records) hash = fnv_event(hash, EV_LINE, sh, k, emit);
         } else {
           n_esc += 1;
-          hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
+          if (want_records) hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
         }
       }
     }
 
     if (lane == 0) {
       lane_tally_end(m, tly, status, nu, E, n_seg, n_pass, n_line, n_esc);
-      if (m.packets != nullptr && (ENTRY(a, model).it.flags & SMC_F_PACKETS))
+      if (want_records)
         write_record(m, st.slot, st.pid, status, shell, nu, E, mu, r, st.mu0, st.nu_cmf0, n_seg,
                      n_esc, n_line, n_pass, hash, last_line);
     }

@@ -61,7 +61,8 @@ def test_batch_equals_alone(ctx, tune):
     mix = _mix()
     together = _batch(ctx, mix, tune)
     for (mdl, N, T), b in zip(mix, together):
-        a = _alone(ctx, mdl, N, T)
+        # the same hand-off budget alone: each history takes the same kernels
+        a = _alone(ctx, mdl, N, T, tune=dict(long_budget=tune["long_budget"]) if tune else None)
         assert np.array_equal(a["packets"], b["packets"])
         for k in ("J", "nubar", "T_R", "W"):
             np.testing.assert_allclose(b["est"][k], a["est"][k], rtol=1e-12, atol=0)
