@@ -3,6 +3,8 @@
     python bench.py [--gpus 1] [--steps 10] [--warmup 1]
     python bench.py --workload batched [--steps 3]
     python bench.py --workload served [--duration 10]
+    python bench.py --workload copy      (plain 1 GiB device copies: the
+                                          reference for HBM byte counters)
 
 One step is one Monte Carlo iteration of the paper-scale scatter model
 (20 shells 10000-25000 km/s at 13 d, 3e5 lines, 1e6 packets; Kerzendorf & Sim
@@ -13,10 +15,14 @@ timed steps are iterations 0..K-1 starting from T_inner = 9000 K.
 
 Prints ONE JSON line.  The value is packet interactions (line events plus
 Thomson scatterings) per second over the timed iterations.  The roofline
-entry prices the transport kernel's algorithmic bytes (32 B per line
-resonance: nu_k and tau_S read, J_blue read-modify-write) against the HBM
-peak; the CPU baseline times the FP64 oracle on a bounded packet sample of
-the same workload on one host core.
+entry prices the transport pass (the lane-per-packet kernel and the
+group-per-packet kernel of the handed-off histories, timed together by the
+library's HIP events on the launch stream) at its algorithmic bytes (32 B
+per line resonance: nu_k and tau_S read, J_blue read-modify-write) against
+the HBM peak; `traffic` is the measured HBM bytes per transport pass from
+the committed hardware-counter summary when it was taken on the current
+kernel source (else null).  The CPU baseline times the FP64 oracle on a
+bounded packet sample of the same workload on one host core.
 """
 import argparse
 import json
@@ -30,6 +36,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LINE_PASS = 32.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1401_5469_amd", "csrc", "smc_kernels.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_scatter-20shell-300kline.json")
 
 
 def parse():
@@ -38,18 +46,54 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--packets", type=int, default=1_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=100_000,
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
                     help="packets of iteration 0 the oracle runs for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-jblue", action="store_true")
     ap.add_argument("--workload", default="paper-scale",
-                    choices=["paper-scale", "batched", "served"])
+                    choices=["paper-scale", "batched", "served", "copy"])
     ap.add_argument("--models", type=int, default=64, help="models in the batched mix")
     ap.add_argument("--duration", type=float, default=10.0,
                     help="seconds of Poisson arrivals (20 per second) in the served mode")
     ap.add_argument("--budget-gb", type=float, default=200.0,
                     help="device-memory admission budget of the served mode")
     return ap.parse_args()
+
+
+def measured_traffic():
+    """HBM bytes per transport pass from the hardware-counter summary, if it
+    was taken on the kernel source that is built now."""
+    import hashlib
+
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            summ = json.load(f)
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if summ.get("kernel_source_sha256") != sha:
+        return None
+    return summ.get("bytes_per_transport_pass")
+
+
+def copy_reference(args):
+    """Plain device copies of 1 GiB: what the HBM byte counters read for a
+    kernel that moves a known number of bytes."""
+    import torch
+
+    n = 1 << 30
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 5
+    print(json.dumps({"metric": "device copy bandwidth", "value": 2 * n / dt / 1e9,
+                      "unit": "GB/s", "bytes_read_per_copy": n, "bytes_written_per_copy": n,
+                      "copies": 5}), flush=True)
 
 
 def cpu_baseline(w, n_sample):
@@ -259,6 +303,8 @@ def main():
         return batched(args)
     if args.workload == "served":
         return served(args)
+    if args.workload == "copy":
+        return copy_reference(args)
 
     import numpy as np
     import torch
@@ -327,8 +373,9 @@ def main():
         "T_inner": [t for _, _, t, _ in rec],
         "escape_fraction": [f for _, _, _, f in rec],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "transport_kernel",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "traffic_unit": "HBM bytes per transport pass",
+                     "kernel": "transport pass: transport_kernel + long_kernel",
                      "bytes_per_launch": bytes_per_launch},
         "cpu_baseline": None,
     }

@@ -73,7 +73,8 @@ typedef struct smc_model smc_model;
  * host pointers read during smc_model_load only. */
 typedef struct {
   int32_t n_shells;          /* S >= 1 */
-  const double* v_bounds;    /* [S+1] boundary velocities [cm/s], > 0, strictly increasing */
+  const double* v_bounds;    /* [S+1] boundary velocities [cm/s], > 0, strictly increasing,
+                                below c/2 */
   double t_exp;              /* time since explosion [s], > 0; radii are v * t_exp */
   const double* n_e;         /* [S] free-electron density [cm^-3], >= 0 */
   int64_t n_lines;           /* L >= 0 */
@@ -127,11 +128,12 @@ typedef struct {
 /* Launch tuning of one model (0 in a field = the library default). */
 typedef struct {
   int32_t blocks_per_cu;     /* lane-per-packet kernel: workgroups of 256 resident per CU */
-  int32_t long_waves_per_cu; /* wave-per-packet kernel: wavefronts resident per CU */
+  int32_t long_waves_per_cu; /* group-per-packet kernel: wavefronts resident per CU */
   uint32_t long_budget;      /* flight segments after which a history moves from the
-                                lane-per-packet to the wave-per-packet kernel;
+                                lane-per-packet to the group-per-packet kernel;
                                 UINT32_MAX keeps every history in the first kernel */
-  uint32_t reserved;         /* must be 0 */
+  uint32_t long_lanes;       /* lanes that carry one handed-off history: 16, 32 or 64
+                                (a wavefront carries 64 / long_lanes of them) */
 } smc_tune;
 
 /* Create a context on HIP device `hip_device`.  The context owns a few small

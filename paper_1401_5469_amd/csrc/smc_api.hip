@@ -23,10 +23,10 @@ struct smc_ctx {
   int device;
   int n_cu;
   int transport_blocks_per_cu[2];  // occupancy of the lane-per-packet kernel (single, multi)
-  int long_blocks_per_cu[2];       // occupancy of the wave-per-packet kernel
+  int long_blocks_per_cu[2][3];    // occupancy of the group-per-packet kernel (16, 32, 64 lanes)
   smc::BatchEntry* host_table[kBatchSlots];   // pinned
   smc::BatchEntry* dev_table[kBatchSlots];
-  unsigned long long* dev_ctr[kBatchSlots];   // [3] launch-wide queues
+  unsigned long long* dev_ctr[kBatchSlots];   // launch-wide control blocks (kCtlBytes)
   hipEvent_t slot_done[kBatchSlots];
   bool slot_used[kBatchSlots];
   int next_slot;
@@ -39,6 +39,7 @@ struct smc_model {
   smc::Layout lay;
   smc::DevModel dev;
   uint8_t* base;
+  unsigned int* order_hist;  // this model's hand-off order histogram (single-model launches)
   uint64_t ws_bytes;
   uint64_t n_packets_max;
   uint32_t load_flags;
@@ -83,6 +84,13 @@ int hip_fail(hipError_t e, const char* what) {
 
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kDefaultLongBudget = 1024;
+constexpr int kDefaultLongLanes = 32;
+// wavefronts per CU of the group-per-packet kernel unless tuned (fewer when
+// its occupancy allows fewer)
+constexpr int kDefaultLongWaves = 8;
+// launch-wide control block of a multi-model launch: 4 queue counters, then
+// the hand-off order histogram and cursors
+constexpr size_t kCtlBytes = 4 * sizeof(unsigned long long) + 2 * smc::kOrderBuckets * 4;
 
 void release_ctx(smc_ctx* c) {
   if (!c) return;
@@ -97,6 +105,26 @@ void release_ctx(smc_ctx* c) {
   if (c->ev_stop) (void)hipEventDestroy(c->ev_stop);
   delete c;
 }
+
+int lanes_of(const smc_tune& t) { return t.long_lanes == 0 ? kDefaultLongLanes : (int)t.long_lanes; }
+int lanes_index(int lanes) { return lanes == 16 ? 0 : (lanes == 32 ? 1 : 2); }
+
+int default_long_waves(const smc_ctx* c, bool multi, const smc_tune& t) {
+  const int occ = c->long_blocks_per_cu[multi][lanes_index(lanes_of(t))];
+  return occ < kDefaultLongWaves ? occ : kDefaultLongWaves;
+}
+
+int check_tune(const smc_tune& t) {
+  if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64 || t.long_waves_per_cu < 0 ||
+      t.long_waves_per_cu > 64)
+    return fail(SMC_EINVAL, "blocks_per_cu and long_waves_per_cu must lie in [0, 64]");
+  if (t.long_lanes != 0 && t.long_lanes != 16 && t.long_lanes != 32 && t.long_lanes != 64)
+    return fail(SMC_EINVAL, "long_lanes must be 0, 16, 32 or 64 (got %u)", t.long_lanes);
+  return 0;
+}
+
+// hand-off positions run at the highest wave priority: two histories per SIMD
+uint32_t hot_of(const smc_ctx* c) { return 8u * (uint32_t)c->n_cu; }
 
 uint32_t budget_of(const smc_tune& t) {
   return t.long_budget == 0 ? kDefaultLongBudget
@@ -114,11 +142,12 @@ smc::Shape shape_of(const smc_ctx* c, const smc_tune& t, bool multi, uint64_t n_
   sh.transport_grid = (int)(want > cap ? cap : want);
   uint64_t lgrid = 0;
   if (handoff && n_work > 0) {
-    const int lper = t.long_waves_per_cu > 0 ? t.long_waves_per_cu : c->long_blocks_per_cu[multi];
+    const int lper = t.long_waves_per_cu > 0 ? t.long_waves_per_cu : default_long_waves(c, multi, t);
     lgrid = (uint64_t)c->n_cu * (uint64_t)lper;
     if (lgrid > n_work) lgrid = n_work;
   }
   sh.long_grid = (int)lgrid;
+  sh.long_lanes = lanes_of(t);
   return sh;
 }
 
@@ -185,8 +214,11 @@ int validate(const smc_model_desc* d) {
     if (i > 0 && !(d->v_bounds[i] > d->v_bounds[i - 1]))
       return fail(SMC_EINVAL, "v_bounds must be strictly increasing (index %d)", i);
   }
-  if (!(d->v_bounds[d->n_shells] < 2.99792458e10))
-    return fail(SMC_EINVAL, "outer velocity must be below c");
+  // first-order Doppler factors: D = 1 - mu v / c stays above 1/2, so lab
+  // energies stay below 2 packet units and their fixed-point sums cannot
+  // overflow
+  if (!(d->v_bounds[d->n_shells] < 0.5 * 2.99792458e10))
+    return fail(SMC_EINVAL, "outer velocity must be below c/2");
   for (int i = 0; i < d->n_shells; ++i)
     if (!(d->n_e[i] >= 0.0) || !isfinite(d->n_e[i]))
       return fail(SMC_EINVAL, "n_e[%d] must be finite and >= 0", i);
@@ -256,6 +288,8 @@ smc::Layout layout_of(const smc_model_desc* d, uint64_t n_packets_max, uint32_t 
   l.lsum = take(4 * 8);
   l.counters = take(smc::CTR_TOTAL * 8);
   l.longs = take(n_packets_max * sizeof(smc::LongState));
+  l.long_order = take(n_packets_max * 8);
+  l.long_hist = take(2 * smc::kOrderBuckets * 4);
   l.jblue = (flags & SMC_F_JBLUE) ? take(S * L * 8) : 0;
   l.out_shell = take(6 * S * 8);
   l.out_spec = take(NB * 8);
@@ -303,18 +337,20 @@ int smc_ctx_create(smc_ctx** out, int hip_device) {
       return hip_fail(e, "occupancy query");
     }
     c->transport_blocks_per_cu[multi] = occ > 0 ? occ : 1;
-    e = smc::long_occupancy(multi != 0, &occ);
-    if (e != hipSuccess) {
-      release_ctx(c);
-      return hip_fail(e, "occupancy query");
+    for (int li = 0; li < 3; ++li) {
+      e = smc::long_occupancy(multi != 0, 16 << li, &occ);
+      if (e != hipSuccess) {
+        release_ctx(c);
+        return hip_fail(e, "occupancy query");
+      }
+      c->long_blocks_per_cu[multi][li] = occ > 0 ? occ : 1;
     }
-    c->long_blocks_per_cu[multi] = occ > 0 ? occ : 1;
   }
   for (int i = 0; i < kBatchSlots; ++i) {
     const size_t tb = sizeof(smc::BatchEntry) * smc::kMaxBatchModels;
     hipError_t e = hipHostMalloc((void**)&c->host_table[i], tb, hipHostMallocDefault);
     if (e == hipSuccess) e = hipMalloc((void**)&c->dev_table[i], tb);
-    if (e == hipSuccess) e = hipMalloc((void**)&c->dev_ctr[i], 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->dev_ctr[i], kCtlBytes);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->slot_done[i], hipEventDisableTiming);
     if (e != hipSuccess) {
       release_ctx(c);
@@ -421,7 +457,7 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
     dm.em_cum = (const double*)(base + lay.em_cum);
   }
   dm.raw = (double*)(base + lay.raw);
-  dm.lsum = (double*)(base + lay.lsum);
+  dm.lsum = (unsigned long long*)(base + lay.lsum);
   dm.counters = (unsigned long long*)(base + lay.counters);
   dm.jblue = (flags & SMC_F_JBLUE) ? (double*)(base + lay.jblue) : nullptr;
   dm.out_shell = (double*)(base + lay.out_shell);
@@ -429,6 +465,8 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
   dm.scalars = (double*)(base + lay.scalars);
   dm.packets = (flags & SMC_F_PACKETS) ? (void*)(base + lay.packets) : nullptr;
   dm.longs = (smc::LongState*)(base + lay.longs);
+  dm.long_order = (uint64_t*)(base + lay.long_order);
+  m->order_hist = (unsigned int*)(base + lay.long_hist);
   dm.long_cap = n_packets_max;
 
   hipError_t e = smc::launch_geometry(dm, (const double*)(base + lay.v_bounds), s);
@@ -470,6 +508,9 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   a.n_models = 1;
   a.total_work = a.single.it.n_work;
   a.ctr = m->dev.counters + smc::CTR_QUEUE;
+  a.order_hist = m->order_hist;
+  a.max_lines = (uint32_t)m->dev.L;
+  a.hot = hot_of(m->ctx);
   const smc::Shape sh =
       shape_of(m->ctx, m->tune, false, a.total_work, a.single.it.long_budget > 0);
   HIP_TRY(smc::launch_iteration(a, false, sh, jblue_entries(m, p->flags),
@@ -492,6 +533,7 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
   smc_tune t;
   memset(&t, 0, sizeof t);
   if (tune) t = *tune;
+  if (int rc = check_tune(t)) return rc;
   const uint32_t budget = budget_of(t);
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   // take the next slot once the launch that last used it has finished
@@ -499,6 +541,7 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
   if (ctx->slot_used[slot]) HIP_TRY(hipEventSynchronize(ctx->slot_done[slot]), "slot wait");
   smc::BatchEntry* tab = ctx->host_table[slot];
   uint64_t work = 0, max_jb = 0;
+  uint32_t max_lines = 0;
   for (int k = 0; k < n_models; ++k) {
     smc_model* m = models[k];
     if (!m) return fail(SMC_EINVAL, "model %d is null", k);
@@ -515,6 +558,7 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
     tab[k].work_begin = work;
     tab[k].long_begin = 0;
     work += tab[k].it.n_work;
+    if ((uint32_t)m->dev.L > max_lines) max_lines = (uint32_t)m->dev.L;
     const uint64_t jb = jblue_entries(m, params[k].flags);
     if (jb > max_jb) max_jb = jb;
   }
@@ -533,6 +577,9 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
   a.n_models = n_models;
   a.total_work = work;
   a.ctr = ctx->dev_ctr[slot];
+  a.order_hist = (unsigned int*)(ctx->dev_ctr[slot] + 4);
+  a.max_lines = max_lines;
+  a.hot = hot_of(ctx);
   const smc::Shape sh = shape_of(ctx, t, true, work, budget > 0);
   HIP_TRY(smc::launch_iteration(a, true, sh, max_jb, timed ? ctx->ev_start : nullptr,
                                 timed ? ctx->ev_stop : nullptr, s),
@@ -582,21 +629,24 @@ int smc_batch_autotune(smc_ctx* ctx, smc_model* const* models, const smc_iter_pa
     }
     cur_ms = bms;
   } else {
-    // coordinate search from the defaults: hand-off budget, then waves per
-    // CU of the wave-per-packet kernel, then workgroups per CU
+    // coordinate search from the defaults: hand-off budget, lanes per
+    // handed-off history, wavefronts per CU of the group-per-packet kernel,
+    // then workgroups per CU
     int rc = trial(cur, &cur_ms);
     if (rc) return rc;
     const uint32_t budgets[] = {256, 1024, 4096, UINT32_MAX};
+    const uint32_t lanes[] = {16, 32, 64};
     const int32_t waves[] = {4, 8, 16};
     const int32_t blocks[] = {1, 2, 3};
-    for (int dim = 0; dim < 3; ++dim) {
+    for (int dim = 0; dim < 4; ++dim) {
       const int n = dim == 0 ? 4 : 3;
       for (int i = 0; i < n; ++i) {
         smc_tune t = cur;
         if (dim == 0) t.long_budget = budgets[i];
-        if (dim == 1) t.long_waves_per_cu = waves[i];
-        if (dim == 2) t.blocks_per_cu = blocks[i];
-        if (dim == 2 && blocks[i] > ctx->transport_blocks_per_cu[1]) continue;
+        if (dim == 1) t.long_lanes = lanes[i];
+        if (dim == 2) t.long_waves_per_cu = waves[i];
+        if (dim == 3) t.blocks_per_cu = blocks[i];
+        if (dim == 3 && blocks[i] > ctx->transport_blocks_per_cu[1]) continue;
         double ms;
         rc = trial(t, &ms);
         if (rc) return rc;
@@ -687,9 +737,7 @@ int smc_model_set_tune(smc_model* m, const smc_tune* t) {
     memset(&m->tune, 0, sizeof m->tune);
     return ok();
   }
-  if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64 || t->long_waves_per_cu < 0 ||
-      t->long_waves_per_cu > 64)
-    return fail(SMC_EINVAL, "blocks_per_cu and long_waves_per_cu must lie in [0, 64]");
+  if (int rc = check_tune(*t)) return rc;
   m->tune = *t;
   return ok();
 }
@@ -698,7 +746,8 @@ int smc_model_get_tune(smc_model* m, smc_tune* t) {
   if (!m || !t) return fail(SMC_EINVAL, "null model or output");
   *t = m->tune;
   if (t->blocks_per_cu == 0) t->blocks_per_cu = m->ctx->transport_blocks_per_cu[0];
-  if (t->long_waves_per_cu == 0) t->long_waves_per_cu = m->ctx->long_blocks_per_cu[0];
+  if (t->long_lanes == 0) t->long_lanes = kDefaultLongLanes;
+  if (t->long_waves_per_cu == 0) t->long_waves_per_cu = default_long_waves(m->ctx, false, *t);
   if (t->long_budget == 0) t->long_budget = kDefaultLongBudget;
   return ok();
 }
@@ -749,6 +798,7 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
     t = *tune;
   else if (n_models == 1 && models[0])
     t = models[0]->tune;
+  if (int rc = check_tune(t)) return rc;
   const uint32_t budget = budget_of(t);
   for (int k = 0; k < n_models; ++k) {
     if (!models[k] || models[k]->ctx != ctx)
@@ -767,12 +817,15 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
   hipError_t e = hipHostMalloc((void**)&g->host_tables, n_ent * sizeof(smc::BatchEntry),
                                hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc((void**)&g->dev_tables, n_ent * sizeof(smc::BatchEntry));
-  if (e == hipSuccess) e = hipMalloc((void**)&g->dev_ctr, 4 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc((void**)&g->dev_ctr, kCtlBytes);
   if (e != hipSuccess) {
     release_graph(g);
     return hip_fail(e, "graph table allocation");
   }
   std::vector<uint64_t> work(n_iter, 0), max_jb(n_iter, 0);
+  uint32_t max_lines = 0;
+  for (int k = 0; k < n_models; ++k)
+    if ((uint32_t)models[k]->dev.L > max_lines) max_lines = (uint32_t)models[k]->dev.L;
   for (int i = 0; i < n_iter; ++i) {
     for (int k = 0; k < n_models; ++k) {
       smc::BatchEntry& be = g->host_tables[(size_t)i * n_models + k];
@@ -823,12 +876,16 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
       a.n_models = n_models;
       a.total_work = work[i];
       a.ctr = g->dev_ctr;
+      a.order_hist = (unsigned int*)(g->dev_ctr + 4);
     } else {
       a.single = g->host_tables[i];
       a.n_models = 1;
       a.total_work = work[i];
       a.ctr = models[0]->dev.counters + smc::CTR_QUEUE;
+      a.order_hist = models[0]->order_hist;
     }
+    a.max_lines = max_lines;
+    a.hot = hot_of(ctx);
     const smc::Shape sh = shape_of(ctx, t, multi, work[i], budget > 0);
     le = smc::launch_iteration(a, multi, sh, max_jb[i], nullptr, nullptr, s);
   }

@@ -14,10 +14,12 @@ struct Layout {
   uint64_t line_nu, tau;                            // lines (rows padded to 4)
   uint64_t line_upper, level_ptr, em_line, em_cum;  // downbranch tables
   uint64_t raw;        // [2S + NB + 2] J_raw, nubar_raw, spectrum raw
-  uint64_t lsum;       // [4] escaped, reabsorbed, capped lab energy (+ pad)
+  uint64_t lsum;       // [4] u64 escaped, reabsorbed, capped lab energy in units of 2^-60 (+ pad)
   uint64_t counters;   // [CTR_TOTAL] u64: event counters, work-queue head,
                        // hand-off count, hand-off queue head
-  uint64_t longs;      // [n_packets_max] LongState: histories handed to the wave kernel
+  uint64_t longs;      // [n_packets_max] LongState: histories handed to the group kernel
+  uint64_t long_order; // [n_packets_max] u64: hand-off indices in processing order
+  uint64_t long_hist;  // [2 * kOrderBuckets] u32: bucket counts, then bucket cursors
   uint64_t jblue;      // [S*L] raw, normalised in place by the finaliser
   uint64_t out_shell;  // [6S] J, nubar, T_R, W, jblue scale, pad
   uint64_t out_spec;   // [NB + 2] L_nu
@@ -27,7 +29,7 @@ struct Layout {
 };
 
 // State of a packet handed from the lane-per-packet kernel to the
-// wave-per-packet kernel after `long_budget` flight segments (128 bytes).
+// group-per-packet kernel after `long_budget` flight segments (128 bytes).
 struct LongState {
   uint64_t slot, pid;
   double r, mu, nu, E, mu0, nu_cmf0;
@@ -35,6 +37,15 @@ struct LongState {
   int32_t shell, next_line, last_line;
   uint32_t n_esc, n_line, pad;
 };
+
+// Luminosity sums are kept in fixed point (energy x 2^60 rounded to an
+// integer), so that their totals, and the T_inner update that follows from
+// them, do not depend on the order in which packets end.
+constexpr double kLScale = 0x1p60;
+
+// The group kernel takes handed-off histories in order of the lines still
+// to their red (more first), sorted by counting into this many buckets.
+constexpr int kOrderBuckets = 1024;
 
 // counters[] slots after the SMC_N_COUNTERS event counters
 enum { CTR_QUEUE = SMC_N_COUNTERS, CTR_LONG_COUNT = SMC_N_COUNTERS + 1,
@@ -62,7 +73,7 @@ struct DevModel {
   const int32_t* em_line;
   const double* em_cum;
   double* raw;             // J_raw[S], nubar_raw[S], spec_raw[NB+2]
-  double* lsum;            // [4]
+  unsigned long long* lsum;  // [4] fixed-point energy sums (kLScale)
   unsigned long long* counters;  // [CTR_TOTAL]
   double* jblue;           // [S*L] or nullptr
   double* out_shell;       // J, nubar, T_R, W, jblue scale, each [S]
@@ -70,6 +81,7 @@ struct DevModel {
   double* scalars;         // [8]
   void* packets;           // smc_packet_out records or nullptr
   LongState* longs;        // hand-off buffer
+  uint64_t* long_order;    // [long_cap] this model's share of the launch-wide processing order
   uint64_t long_cap;
 };
 
@@ -81,7 +93,7 @@ struct DevIter {
   uint64_t max_segments;
   uint32_t iteration;
   uint32_t flags;
-  uint32_t long_budget;    // segments before a history moves to the wave kernel (0: never)
+  uint32_t long_budget;    // segments before a history moves to the group kernel (0: never)
   uint32_t pad;
   double T_param;          // > 0 overrides the device-resident T_inner
   double L_requested;
@@ -106,6 +118,10 @@ struct LaunchArgs {
   int32_t pad;
   uint64_t total_work;     // packets over all models
   unsigned long long* ctr; // [3] work-queue head, hand-off total, hand-off queue head
+  unsigned int* order_hist;  // [2 * kOrderBuckets] bucket counts, then cursors
+  uint32_t max_lines;      // largest line count of the launch's models
+  uint32_t hot;            // hand-off positions [0, hot) run at the highest wave priority,
+                           // [hot, 3 hot) and [3 hot, 7 hot) one and two steps lower
 };
 
 // scalars[] slots
@@ -115,7 +131,8 @@ enum { SC_L_EMITTED = 0, SC_L_REABSORBED = 1, SC_L_CAPPED = 2, SC_L_INNER = 3,
 // Launch shape of one iteration (or one batch).
 struct Shape {
   int transport_grid;
-  int long_grid;
+  int long_grid;   // wavefronts of the group-per-packet kernel
+  int long_lanes;  // lanes per handed-off history: 16, 32 or 64
 };
 
 // Host-side launchers implemented in smc_kernels.hip.  `multi` selects the
@@ -125,7 +142,7 @@ hipError_t launch_iteration(const LaunchArgs& a, bool multi, const Shape& shape,
                             uint64_t max_jblue, hipEvent_t ev_start, hipEvent_t ev_stop,
                             hipStream_t s);
 hipError_t transport_occupancy(bool multi, int* blocks_per_cu);
-hipError_t long_occupancy(bool multi, int* blocks_per_cu);
+hipError_t long_occupancy(bool multi, int lanes, int* blocks_per_cu);
 int transport_block_threads();
 int long_block_threads();
 constexpr int kMaxBatchModels = 1024;

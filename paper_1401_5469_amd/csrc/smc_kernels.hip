@@ -132,7 +132,7 @@ __global__ void reset_kernel(LaunchArgs a) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   const size_t n_raw = 2 * (size_t)m.S + (size_t)m.n_bins + 2;
   for (size_t i = tid; i < n_raw; i += stride) m.raw[i] = 0.0;
-  if (tid < 4) m.lsum[tid] = 0.0;
+  if (tid < 4) m.lsum[tid] = 0ull;
   if (tid < CTR_TOTAL) m.counters[tid] = 0ull;
   if (m.jblue && (it.flags & SMC_F_JBLUE)) {
     const size_t n = (size_t)m.S * (size_t)m.L;
@@ -140,6 +140,8 @@ __global__ void reset_kernel(LaunchArgs a) {
   }
   if (tid == 0) m.scalars[SC_T_USED] = it.T_param > 0.0 ? it.T_param : m.scalars[SC_T_NEXT];
   if (kMulti && k == 0 && tid < 3) a.ctr[tid] = 0ull;
+  if (k == 0)
+    for (size_t i = tid; i < (size_t)kOrderBuckets; i += stride) a.order_hist[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -154,17 +156,20 @@ __global__ void reset_kernel(LaunchArgs a) {
 // carry about half of the segments, and a lane-per-packet wavefront runs
 // those latency-bound.
 //
-// long_kernel: one packet per wavefront, for the handed-off histories.  The
-// 64 lanes hold the next 128 draws of the packet's stream with their
-// logarithms precomputed, and the next 64 lines of its shell, so a segment's
-// dependent chain is only the geometry and frame arithmetic; J_blue updates
-// go out from the lanes that own the passed lines in parallel.
+// long_kernel: one packet per group of G = 16, 32 or 64 lanes, for the
+// handed-off histories.  The G lanes hold the next 2G draws of the packet's
+// stream with their logarithms precomputed, and the next G lines of its
+// shell, so a segment's dependent chain is only the geometry and frame
+// arithmetic; J_blue updates go out from the lanes that own the passed lines
+// in parallel.  The uniform per-packet arithmetic is repeated in every lane
+// of a group, so narrower groups put more histories through each
+// instruction; wider ones march more lines per step.
 //
 // Both follow the arithmetic of the FP64 reference formulation step by step;
 // divisions that only change the last bit are reciprocal multiplies.
 // Estimator tallies: J and nu-bar accumulate in registers while a packet
 // stays in one shell of one model, event counters and luminosity sums in a
-// private LDS slot per lane while the lane stays on one model; both reach
+// private LDS slot per lane (per group) while it stays on one model; both reach
 // HBM with atomics only when that changes.  The spectrum takes one atomic
 // per escaping packet, J_blue one per passed resonance.
 // ---------------------------------------------------------------------------
@@ -296,12 +301,12 @@ __device__ __forceinline__ void write_record(const DevModel& m, uint64_t slot, u
 // per-lane tally slot in LDS: luminosity sums and event counters of the
 // lane's current model
 struct LaneTally {
-  double L[3];
+  unsigned long long L[3];  // fixed-point escaped, reabsorbed, capped energy
   unsigned long long c[SMC_N_COUNTERS];
 };
 
 __device__ __forceinline__ void lane_tally_clear(LaneTally& t) {
-  t.L[0] = t.L[1] = t.L[2] = 0.0;
+  t.L[0] = t.L[1] = t.L[2] = 0ull;
 #pragma unroll
   for (int i = 0; i < SMC_N_COUNTERS; ++i) t.c[i] = 0ull;
 }
@@ -309,7 +314,7 @@ __device__ __forceinline__ void lane_tally_clear(LaneTally& t) {
 __device__ __forceinline__ void lane_tally_flush(const DevModel& m, LaneTally& t) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
-    if (t.L[i] != 0.0) unsafeAtomicAdd(&m.lsum[i], t.L[i]);
+    if (t.L[i]) atomicAdd(&m.lsum[i], t.L[i]);
 #pragma unroll
   for (int i = 0; i < SMC_N_COUNTERS; ++i)
     if (t.c[i]) atomicAdd(&m.counters[i], t.c[i]);
@@ -322,15 +327,16 @@ __device__ __forceinline__ void lane_tally_end(const DevModel& m, LaneTally& t, 
                                                double nu, double E, uint64_t n_seg,
                                                uint64_t n_pass, uint32_t n_line,
                                                uint32_t n_esc) {
+  const unsigned long long q = (unsigned long long)__double2ll_rn(E * kLScale);
   if (status == SMC_ESCAPED) {
     unsafeAtomicAdd(&m.raw[2 * m.S + spectrum_bin(m, nu)], E);
-    t.L[0] += E;
+    t.L[0] += q;
     t.c[SMC_C_ESCAPED] += 1;
   } else if (status == SMC_REABSORBED) {
-    t.L[1] += E;
+    t.L[1] += q;
     t.c[SMC_C_REABSORBED] += 1;
   } else {
-    t.L[2] += E;
+    t.L[2] += q;
     t.c[SMC_C_CAPPED] += 1;
   }
   // every segment ends in exactly one of line event, Thomson or crossing
@@ -348,6 +354,10 @@ struct View {
   const double* line_nu;
   const double* tau;
   double* jblue;          // nullptr when J_blue is not tallied
+  const int32_t* line_upper;  // downbranch tables
+  const int64_t* level_ptr;
+  const int32_t* em_line;
+  const double* em_cum;
   double ct, inv_ct;
   uint64_t max_segments, budget;
   int32_t S, L, Lp;
@@ -363,6 +373,10 @@ __device__ __forceinline__ View make_view(const DevModel& m, const DevIter& it) 
   v.line_nu = m.line_nu;
   v.tau = m.tau;
   v.jblue = (m.jblue != nullptr && (it.flags & SMC_F_JBLUE)) ? m.jblue : nullptr;
+  v.line_upper = m.line_upper;
+  v.level_ptr = m.level_ptr;
+  v.em_line = m.em_line;
+  v.em_cum = m.em_cum;
   v.ct = m.ct;
   v.inv_ct = 1.0 / m.ct;
   v.max_segments = it.max_segments;
@@ -512,7 +526,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(LaunchArgs a) {
     if (n_seg >= v.max_segments) {
       status = SMC_CAPPED;
     } else if (n_seg >= v.budget && !handoff_tried) {
-      // ---- hand the history to the wave-per-packet kernel
+      // ---- hand the history to the group-per-packet kernel
       handoff_tried = true;
       const DevModel& m = ENTRY(a, model).m;
       const unsigned long long h = atomicAdd(&m.counters[CTR_LONG_COUNT], 1ull);
@@ -726,7 +740,85 @@ __global__ void long_prefix_kernel(LaunchArgs a, BatchEntry* table) {
 }
 
 // ---------------------------------------------------------------------------
-// wave-per-packet kernel for the handed-off histories
+// processing order of the handed-off histories: most lines still to the red
+// first (a counting sort into kOrderBuckets buckets).  Launch-wide position
+// q of the order lives in the long_order array of the model whose hand-off
+// range [long_begin, long_begin + count) holds q.
+// ---------------------------------------------------------------------------
+template <bool kMulti>
+__device__ __forceinline__ uint64_t long_total(const LaunchArgs& a) {
+  if (kMulti) return a.ctr[1];
+  const uint64_t n = a.single.m.counters[CTR_LONG_COUNT];
+  return n > a.single.m.long_cap ? a.single.m.long_cap : n;
+}
+
+// model whose hand-off range holds launch-wide index q
+template <bool kMulti>
+__device__ __forceinline__ int long_owner(const LaunchArgs& a, uint64_t q) {
+  if (!kMulti) return 0;
+  int lo = 0, hi = a.n_models - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.table[mid].long_begin <= q)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int order_bucket(int32_t L, int32_t next_line, uint32_t max_lines) {
+  const uint64_t rem = (uint64_t)(int64_t)(L - next_line);
+  const uint64_t b = rem * (uint64_t)kOrderBuckets / ((uint64_t)max_lines + 1ull);
+  return b >= (uint64_t)kOrderBuckets ? kOrderBuckets - 1 : (int)b;
+}
+
+template <bool kMulti>
+__device__ __forceinline__ int bucket_of_long(const LaunchArgs& a, uint64_t q) {
+  const int k = long_owner<kMulti>(a, q);
+  const DevModel& m = ENTRY(a, k).m;
+  return order_bucket(m.L, m.longs[q - ENTRY(a, k).long_begin].next_line, a.max_lines);
+}
+
+template <bool kMulti>
+__global__ void order_count_kernel(LaunchArgs a) {
+  const uint64_t n = long_total<kMulti>(a);
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (uint64_t)gridDim.x * blockDim.x)
+    atomicAdd(&a.order_hist[bucket_of_long<kMulti>(a, q)], 1u);
+}
+
+// cursor[b] = histories in buckets above b (one workgroup of kOrderBuckets)
+__global__ __launch_bounds__(kOrderBuckets) void order_scan_kernel(LaunchArgs a) {
+  __shared__ unsigned int buf[kOrderBuckets];
+  const int t = threadIdx.x;
+  const int b = kOrderBuckets - 1 - t;  // thread t takes bucket b, from the top down
+  const unsigned int c = a.order_hist[b];
+  buf[t] = c;
+  __syncthreads();
+  for (int off = 1; off < kOrderBuckets; off <<= 1) {
+    const unsigned int add = t >= off ? buf[t - off] : 0u;
+    __syncthreads();
+    buf[t] += add;
+    __syncthreads();
+  }
+  a.order_hist[kOrderBuckets + b] = buf[t] - c;
+}
+
+template <bool kMulti>
+__global__ void order_place_kernel(LaunchArgs a) {
+  const uint64_t n = long_total<kMulti>(a);
+  for (uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t pos =
+        atomicAdd(&a.order_hist[kOrderBuckets + bucket_of_long<kMulti>(a, q)], 1u);
+    const int j = long_owner<kMulti>(a, pos);
+    ENTRY(a, j).m.long_order[pos - ENTRY(a, j).long_begin] = q;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// group-per-packet kernel for the handed-off histories
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double readlane_f64(double x, int src) {
   const uint64_t b = (uint64_t)__double_as_longlong(x);
@@ -734,8 +826,6 @@ __device__ __forceinline__ double readlane_f64(double x, int src) {
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
-
-__device__ __forceinline__ int uniform_i32(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // x moved by DPP (both 32-bit halves); lanes the control does not write keep 0
 template <int kCtrl, int kRowMask>
@@ -748,107 +838,214 @@ __device__ __forceinline__ double dpp_f64(double x) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// inclusive prefix sum over the 64 lanes (row shifts within rows of 16, then
-// the row broadcasts of lanes 15 and 31)
-__device__ __forceinline__ double wave_prefix_sum(double x) {
-  x += dpp_f64<0x111, 0xF>(x);  // row_shr:1
-  x += dpp_f64<0x112, 0xF>(x);  // row_shr:2
-  x += dpp_f64<0x114, 0xF>(x);  // row_shr:4
-  x += dpp_f64<0x118, 0xF>(x);  // row_shr:8
-  x += dpp_f64<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
-  x += dpp_f64<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
-  return x;
+// Make the values available in registers at this point (the compiler
+// inserts the wait for any load that produced them here).
+__device__ __forceinline__ void settle() {}
+template <typename T, typename... R>
+__device__ __forceinline__ void settle(const T& x, const R&... rest) {
+  asm volatile("" ::"v"(x));
+  settle(rest...);
 }
+
+__device__ __forceinline__ double join_u32(uint32_t lo, uint32_t hi) {
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Copy one double per active lane from HBM to LDS without passing through
+// registers: the two words land at lo[lane] and hi[lane] (lane = wave lane).
+// The wavefront waits for the copy only where it reads the LDS words.
+__device__ __forceinline__ void copy_f64_to_lds(const double* src, uint32_t* lo, uint32_t* hi) {
+  typedef __attribute__((address_space(1))) void* global_ptr;
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(src);
+  __builtin_amdgcn_global_load_lds((global_ptr)(w), (lds_ptr)lo, 4, 0, 0);
+  __builtin_amdgcn_global_load_lds((global_ptr)(w + 1), (lds_ptr)hi, 4, 0, 0);
+}
+
+// Lane groups of G = 16, 32 or 64 lanes (aligned, one packet each).  Values
+// that are uniform over a group live in every lane of it; with G = 64 they
+// are wave-uniform and the compiler keeps the integer ones in scalar
+// registers.
+template <int G>
+struct Group {
+  static constexpr unsigned long long kMask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+  int lane, base;  // lane within the group, first wave lane of the group
+
+  // a group-uniform integer (scalar register when G = 64)
+  __device__ __forceinline__ int uni(int x) const {
+    if constexpr (G == 64) return __builtin_amdgcn_readfirstlane(x);
+    return x;
+  }
+  // lane `src` (group-uniform) of the group's copy of x
+  __device__ __forceinline__ double bcast(double x, int src) const {
+    if constexpr (G == 64) return readlane_f64(x, src);
+    return __shfl(x, base + src, kWave);
+  }
+  __device__ __forceinline__ unsigned long long bcast_u64(unsigned long long x, int src) const {
+    return __shfl(x, base + src, kWave);
+  }
+  // this group's bits of a wave ballot
+  __device__ __forceinline__ unsigned long long bits(unsigned long long w) const {
+    if constexpr (G == 64) return w;
+    return (w >> base) & kMask;
+  }
+  // inclusive prefix sum over the group (row shifts within rows of 16 lanes,
+  // then the row broadcasts of lanes 15 and 31)
+  __device__ __forceinline__ double prefix_sum(double x) const {
+    x += dpp_f64<0x111, 0xF>(x);  // row_shr:1
+    x += dpp_f64<0x112, 0xF>(x);  // row_shr:2
+    x += dpp_f64<0x114, 0xF>(x);  // row_shr:4
+    x += dpp_f64<0x118, 0xF>(x);  // row_shr:8
+    if constexpr (G >= 32) x += dpp_f64<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+    if constexpr (G == 64) x += dpp_f64<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+    return x;
+  }
+};
 
 constexpr int kLongBlock = 64;
 
-template <bool kMulti>
+// One handed-off history per group of G lanes, 64/G histories per wavefront.
+// The group holds the next 2G draws of its packet's stream with their
+// logarithms precomputed, and the next G lines of its shell; a segment tests
+// all G lines at once (each lane against the optical depth left after the
+// live lines below it), and J_blue updates leave from every reached lane
+// together.  A group whose packet ends takes the next one from the hand-off
+// queue while the other groups of its wavefront keep marching.
+template <bool kMulti, int G>
 __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
-  __shared__ LaneTally tly;  // the wavefront's tallies, updated by lane 0
-  const int lane = threadIdx.x;
-  unsigned long long n_long, *queue;
-  if (kMulti) {
-    n_long = a.ctr[1];
-    queue = a.ctr + 2;
-  } else {
-    n_long = a.single.m.counters[CTR_LONG_COUNT];
-    if (n_long > a.single.m.long_cap) n_long = a.single.m.long_cap;
-    queue = a.single.m.counters + CTR_LONG_QUEUE;
-  }
-  if (lane == 0) lane_tally_clear(tly);
+  constexpr int kGroups = kWave / G;
+  __shared__ LaneTally tly_all[kGroups];  // one tally slot per group, its lane 0 writes it
+  // next window of each group, copied ahead straight from HBM: low and high
+  // words of the line frequencies, then of the Sobolev depths, by wave lane
+  __shared__ uint32_t pf[4][kWave];
+  Group<G> grp;
+  grp.lane = threadIdx.x & (G - 1);
+  grp.base = threadIdx.x & ~(G - 1);
+  const bool leader = grp.lane == 0;
+  LaneTally& tly = tly_all[threadIdx.x / G];
+  const unsigned long long n_long = long_total<kMulti>(a);
+  unsigned long long* queue = kMulti ? a.ctr + 2 : a.single.m.counters + CTR_LONG_QUEUE;
+  if (leader) lane_tally_clear(tly);
   int tally_model = kMulti ? -1 : 0;
   double acc_J = 0.0, acc_nb = 0.0;
   int acc_shell = -1, acc_model = -1;
 
+  // the group's current history
+  bool have = false, drained = false;
+  int model = 0, tier = 0;
+  View v;
+  StreamKey sk;
+  uint64_t slot = 0, pid = 0, n_seg = 0, n_pass = 0, hash = 0;
+  double mu0 = 0.0, nu_cmf0 = 0.0;
+  uint32_t draw = 0, rb = 0, n_esc = 0, n_line = 0;
+  double r = 0.0, mu = 0.0, nu = 0.0, E = 0.0, inv_nu = 0.0;
+  int32_t shell = 0, next_line = 0, last_line = -1;
+  // draws 2(rb + i) and 2(rb + i) + 1 in group lane i, with -log of each
+  double ua = 0.0, ub = 0.0, la = 0.0, lb = 0.0;
+  // line wbase + i of shell wshell in group lane i: frequency, reciprocal,
+  // depth, and the J_blue the history has left on it since the window was
+  // installed (the following window of the same shell waits in pf)
+  int32_t wbase = -1, wshell = -1;
+  double wn = 0.0, wt = 0.0, winv = 0.0, jb_acc = 0.0;
+  int32_t c_shell = -1;
+  double c_rin = 0.0, c_rout = 0.0, c_ne = 0.0;
+
   for (;;) {
-    unsigned long long gidx = 0;
-    if (lane == 0) gidx = atomicAdd(queue, 1ull);
-    gidx = __shfl(gidx, 0, kWave);
-    if (gidx >= n_long) break;
-    int model = 0;
-    uint64_t idx = gidx;
-    if (kMulti) {
-      int lo = 0, hi = a.n_models - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a.table[mid].long_begin <= gidx)
-          lo = mid;
-        else
-          hi = mid - 1;
-      }
-      model = uniform_i32(lo);
-      idx = gidx - a.table[model].long_begin;
-      if (tally_model != model) {
-        if (tally_model >= 0 && lane == 0) lane_tally_flush(a.table[tally_model].m, tly);
-        tally_model = model;
+    bool fetched = false;
+    if (!have && !drained) {
+      unsigned long long pos = 0;
+      if (leader) pos = atomicAdd(queue, 1ull);
+      pos = grp.bcast_u64(pos, 0);
+      fetched = true;
+      if (pos >= n_long) {
+        drained = true;
+      } else {
+        // position -> hand-off index -> model and slot in its buffer
+        const int jo = grp.uni(long_owner<kMulti>(a, pos));
+        const uint64_t gidx = ENTRY(a, jo).m.long_order[pos - ENTRY(a, jo).long_begin];
+        model = grp.uni(long_owner<kMulti>(a, gidx));
+        const uint64_t idx = gidx - ENTRY(a, model).long_begin;
+        tier = pos < a.hot ? 3 : (pos < 3ull * a.hot ? 2 : (pos < 7ull * a.hot ? 1 : 0));
+        if (kMulti && tally_model != model) {
+          if (tally_model >= 0 && leader) lane_tally_flush(a.table[tally_model].m, tly);
+          tally_model = model;
+        }
+        v = make_view(ENTRY(a, model).m, ENTRY(a, model).it);
+        const LongState st = ENTRY(a, model).m.longs[idx];
+        slot = st.slot;
+        pid = st.pid;
+        mu0 = st.mu0;
+        nu_cmf0 = st.nu_cmf0;
+        n_seg = st.n_seg;
+        n_pass = st.n_pass;
+        hash = st.hash;
+        draw = (uint32_t)st.draw;
+        r = st.r;
+        mu = st.mu;
+        nu = st.nu;
+        E = st.E;
+        inv_nu = recip(nu);
+        shell = st.shell;
+        next_line = st.next_line;
+        last_line = st.last_line;
+        n_esc = st.n_esc;
+        n_line = st.n_line;
+        sk.k0 = v.k0;
+        sk.k1 = v.k1;
+        sk.iter = v.iter;
+        sk.p0 = (uint32_t)pid;
+        sk.p1 = (uint32_t)(pid >> 32);
+        rb = draw >> 1;
+        const Block blk = stream_block(sk, rb + grp.lane);
+        ua = to_uniform(blk.a);
+        ub = to_uniform(blk.b);
+        la = -log(ua);
+        lb = -log(ub);
+        wbase = -1;
+        wshell = -1;
+        c_shell = -1;
+        have = true;
+        // wait for the history's loads here, once per history, so that the
+        // segment loop never inherits a pending load (and with it a wait for
+        // the copies and atomics it issues itself)
+        settle(slot, pid, mu0, nu_cmf0, n_seg, n_pass, hash, draw, r, mu, nu, E, shell,
+               next_line, last_line, n_esc, n_line);
+        settle(v.r_bounds, v.n_e, v.line_nu, v.tau, v.jblue, v.line_upper, v.level_ptr,
+               v.em_line, v.em_cum, v.ct, v.inv_ct, v.max_segments, v.S, v.L, v.Lp,
+               (int)v.downbranch, (int)v.records, sk.k0, sk.k1, sk.iter);
       }
     }
-    const DevModel& m = ENTRY(a, model).m;
-    const View v = make_view(m, ENTRY(a, model).it);
-    const bool want_records = m.packets != nullptr && (ENTRY(a, model).it.flags & SMC_F_PACKETS);
-    const LongState st = m.longs[idx];
-    uint64_t n_seg = st.n_seg, n_pass = st.n_pass, hash = st.hash;
-    uint32_t draw = (uint32_t)st.draw;
-    double r = st.r, mu = st.mu, nu = st.nu, E = st.E;
-    double inv_nu = recip(nu);
-    int32_t shell = st.shell, next_line = st.next_line, last_line = st.last_line;
-    uint32_t n_esc = st.n_esc, n_line = st.n_line;
-    StreamKey sk;
-    sk.k0 = v.k0;
-    sk.k1 = v.k1;
-    sk.iter = v.iter;
-    sk.p0 = (uint32_t)st.pid;
-    sk.p1 = (uint32_t)(st.pid >> 32);
+    if (__ballot(have) == 0ull) break;  // every group drained
+    if (__ballot(fetched)) {
+      // the wavefront issues at the priority of its most urgent history
+      if (__ballot(have && tier == 3))
+        __builtin_amdgcn_s_setprio(3);
+      else if (__ballot(have && tier == 2))
+        __builtin_amdgcn_s_setprio(2);
+      else if (__ballot(have && tier == 1))
+        __builtin_amdgcn_s_setprio(1);
+      else
+        __builtin_amdgcn_s_setprio(0);
+    }
+    if (!have) continue;
 
-    // 128 upcoming draws: lane i holds draws 2(rb + i) and 2(rb + i) + 1,
-    // with their negative logarithms for tau_event
-    uint32_t rb = draw >> 1;
-    Block blk = stream_block(sk, rb + lane);
-    double ua = to_uniform(blk.a), ub = to_uniform(blk.b);
-    double la = -log(ua), lb = -log(ub);
-    // 64 lines of one shell: lane i holds line wbase + i, its frequency,
-    // reciprocal and Sobolev depth
-    int32_t wbase = -1, wshell = -1;
-    double wn = 0.0, wt = 0.0, winv = 0.0;
-    int32_t c_shell = -1;
-    double c_rin = 0.0, c_rout = 0.0, c_ne = 0.0;
-
+    // ---- one flight segment of the group's history
     int status = SMC_LIVE;
-    for (;;) {
+    do {
       if (n_seg >= v.max_segments) {
         status = SMC_CAPPED;
         break;
       }
       n_seg += 1;
-      if (draw + 3 > 2u * (rb + kWave)) {
+      if (draw + 3 > 2u * (rb + G)) {
         rb = draw >> 1;
-        blk = stream_block(sk, rb + lane);
+        const Block blk = stream_block(sk, rb + grp.lane);
         ua = to_uniform(blk.a);
         ub = to_uniform(blk.b);
         la = -log(ua);
         lb = -log(ub);
       }
-      const double tau0 = readlane_f64((draw & 1) ? lb : la, uniform_i32((int)((draw >> 1) - rb)));
+      const double tau0 = grp.bcast((draw & 1) ? lb : la, grp.uni((int)((draw >> 1) - rb)));
       draw += 1;
       const int sh = shell;
       if (sh != c_shell) {
@@ -856,6 +1053,9 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
         c_rin = v.r_bounds[sh];
         c_rout = v.r_bounds[sh + 1];
         c_ne = v.n_e[sh];
+        // wait for these loads here, on the rare shell change, so that the
+        // segment code after the branch has nothing in flight to wait for
+        asm volatile("" ::"v"(c_rin), "v"(c_rout), "v"(c_ne));
       }
       const double rmu = r * mu;
       const double D = 1.0 - rmu * v.inv_ct;
@@ -868,56 +1068,84 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
       const double jb_w = E * inv_nu * inv_nu;
       double* jb_row = v.jblue ? v.jblue + (size_t)sh * (size_t)v.L : nullptr;
 
-      // line march, all 64 window lines at once: lane j tests line wbase+j
-      // against the optical depth left after the lines before it (prefix
-      // sum over the lanes); the first lane that stops the march decides
+      // line march over the window: lane j tests line wbase+j against the
+      // optical depth left after the live lines before it; the first lane
+      // that stops the march decides
       double tau_ev = tau0;  // left after the windows already passed
       int32_t k = next_line;
       bool line_hit = false;
       double d_line = 0.0, nu_hit = 0.0, inv_hit = 0.0, tau_rem = tau0;
       while (k < v.L) {
-        if (sh != wshell || k < wbase || k >= wbase + kWave) {
+        if (sh != wshell || k < wbase || k >= wbase + G) {
+          // The following window of the same shell was copied ahead from
+          // HBM into LDS by the direct global-to-LDS load; anything else (a
+          // new shell, a jump after a downbranch emission) is loaded now.
+          // Nothing outside this block waits for those copies, and the old
+          // window's J_blue leaves in one atomic per lane.
+          const bool ahead = sh == wshell && k == wbase + G;
+          const int32_t line = k + grp.lane;
+          const bool in = line < v.L;
+          const size_t row = (size_t)sh * (size_t)v.Lp;
+          if (ahead) {
+            const double n_raw = join_u32(pf[0][threadIdx.x], pf[1][threadIdx.x]);
+            const double t_raw = join_u32(pf[2][threadIdx.x], pf[3][threadIdx.x]);
+            wn = in ? n_raw : 1.0;
+            wt = in ? t_raw : 0.0;
+          } else {
+            const int32_t lc = line < v.Lp ? line : v.Lp - 1;
+            const double n_raw = v.line_nu[lc];
+            const double t_raw = v.tau[row + lc];
+            wn = in ? n_raw : 1.0;
+            wt = in ? t_raw : 0.0;
+          }
+          // the window is in registers (and its LDS copy free for reuse)
+          // before the next copy and the atomic are issued
+          asm volatile("s_waitcnt lgkmcnt(0)" ::"v"(wn), "v"(wt) : "memory");
+          const int32_t next = k + G + grp.lane;
+          const int32_t nc = next < v.Lp ? next : v.Lp - 1;
+          copy_f64_to_lds(v.line_nu + nc, &pf[0][0], &pf[1][0]);
+          copy_f64_to_lds(v.tau + row + nc, &pf[2][0], &pf[3][0]);
+          if (v.jblue && wshell >= 0 && jb_acc != 0.0)
+            unsafeAtomicAdd(&v.jblue[(size_t)wshell * (size_t)v.L + wbase + grp.lane], jb_acc);
+          jb_acc = 0.0;
           wbase = k;
           wshell = sh;
-          const int32_t line = k + lane;
-          wn = line < v.L ? v.line_nu[line] : 1.0;
-          wt = line < v.L ? v.tau[(size_t)sh * (size_t)v.Lp + line] : 0.0;
           winv = recip(wn);
         }
-        const int32_t line = wbase + lane;
+        const int32_t line = wbase + grp.lane;
         const bool live = line >= k && line < v.L;
         const double t = live ? wt : 0.0;
-        const double before = wave_prefix_sum(t) - t;  // depth of the live lines below
+        const double before = grp.prefix_sum(t) - t;  // depth of the live lines below
         double dl = (nu_cmf - wn) * ct_over_nu;
         dl = dl < 0.0 ? 0.0 : dl;
         const double rem = tau_ev - before;
         const bool reach = kappa * dl < rem && dl < d_shell;
         const bool hit = reach && wt + kappa * dl > rem;
-        const unsigned long long stop = __ballot(live && (!reach || hit));
-        const unsigned long long hits = __ballot(live && hit);
+        const unsigned long long stop = grp.bits(__ballot(live && (!reach || hit)));
+        const unsigned long long hits = grp.bits(__ballot(live && hit));
         const int first = stop ? (int)__builtin_ctzll(stop) : -1;
         // J_blue: every line reached up to the stop, the interacting one included
-        const int end = first < 0 ? kWave : first + ((hits >> first) & 1ull ? 1 : 0);
-        if (jb_row && live && lane < end) unsafeAtomicAdd(&jb_row[line], jb_w * wn);
+        const int end = first < 0 ? G : first + ((hits >> first) & 1ull ? 1 : 0);
+        if (jb_row && live && grp.lane < end) jb_acc += jb_w * wn;
         const int passed = end - (k - wbase) > 0 ? end - (k - wbase) : 0;
-        n_pass += (uint64_t)(first < 0 ? (int32_t)(v.L < wbase + kWave ? v.L - k : wbase + kWave - k)
+        n_pass += (uint64_t)(first < 0 ? (int32_t)(v.L < wbase + G ? v.L - k : wbase + G - k)
                                        : passed);
         if (first >= 0) {
-          const int fl = uniform_i32(first);
+          const int fl = grp.uni(first);
           k = wbase + fl;
           if ((hits >> fl) & 1ull) {
             line_hit = true;
-            d_line = readlane_f64(dl, fl);
-            nu_hit = readlane_f64(wn, fl);
-            inv_hit = readlane_f64(winv, fl);
+            d_line = grp.bcast(dl, fl);
+            nu_hit = grp.bcast(wn, fl);
+            inv_hit = grp.bcast(winv, fl);
           } else {
-            tau_rem = readlane_f64(rem, fl);
+            tau_rem = grp.bcast(rem, fl);
           }
           break;
         }
         // every live line of the window passed
-        const int top = uniform_i32(v.L < wbase + kWave ? v.L - wbase - 1 : kWave - 1);
-        tau_ev -= readlane_f64(before + t, top);
+        const int top = grp.uni(v.L < wbase + G ? v.L - wbase - 1 : G - 1);
+        tau_ev -= grp.bcast(before + t, top);
         tau_rem = tau_ev;
         k = wbase + top + 1;
       }
@@ -929,7 +1157,7 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
       const double d = line_hit ? d_line : (escat ? d_electron : d_shell);
 
       if (acc_shell != sh || acc_model != model) {
-        if (acc_shell >= 0 && lane == 0) {
+        if (acc_shell >= 0 && leader) {
           const DevModel& am = ENTRY(a, acc_model).m;
           unsafeAtomicAdd(&am.raw[acc_shell], acc_J);
           unsafeAtomicAdd(&am.raw[am.S + acc_shell], acc_nb);
@@ -950,16 +1178,10 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
         mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
         r = inward ? c_rin : c_rout;
         mu = mu_new;
-        if (want_records) hash = fnv_event(hash, kind, sh, -1, -1);
+        if (v.records) hash = fnv_event(hash, kind, sh, -1, -1);
         shell = sh + (inward ? -1 : 1);
-        if (shell >= v.S) {
-          status = SMC_ESCAPED;
-          break;
-        }
-        if (shell < 0) {
-          status = SMC_REABSORBED;
-          break;
-        }
+        if (shell >= v.S) status = SMC_ESCAPED;
+        if (shell < 0) status = SMC_REABSORBED;
       } else {
         // mu_new * r_new = r mu + d along the straight path
         const double D_old = 1.0 - (rmu + d) * v.inv_ct;
@@ -967,17 +1189,17 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
         double nu_cmf_out, inv_cmf_out;
         int32_t emit = k;
         if (line_hit) {
-          const double u_branch = readlane_f64((draw & 1) ? ub : ua,
-                                               uniform_i32((int)((draw >> 1) - rb)));
+          const double u_branch =
+              grp.bcast((draw & 1) ? ub : ua, grp.uni((int)((draw >> 1) - rb)));
           draw += 1;
           nu_cmf_out = nu_hit;
           inv_cmf_out = inv_hit;
           if (v.downbranch) {
-            const int32_t up = m.line_upper[k];
-            const int64_t lo = m.level_ptr[up], hi = m.level_ptr[up + 1];
+            const int32_t up = v.line_upper[k];
+            const int64_t lo = v.level_ptr[up], hi = v.level_ptr[up + 1];
             int64_t j = lo;
-            while (j < hi - 1 && !(m.em_cum[j] > u_branch)) ++j;
-            emit = m.em_line[j];
+            while (j < hi - 1 && !(v.em_cum[j] > u_branch)) ++j;
+            emit = v.em_line[j];
             nu_cmf_out = v.line_nu[emit];
             inv_cmf_out = recip(nu_cmf_out);
           }
@@ -986,7 +1208,7 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
           inv_cmf_out = recip(nu_cmf_out);
         }
         const double mu_out =
-            2.0 * readlane_f64((draw & 1) ? ub : ua, uniform_i32((int)((draw >> 1) - rb))) - 1.0;
+            2.0 * grp.bcast((draw & 1) ? ub : ua, grp.uni((int)((draw >> 1) - rb))) - 1.0;
         draw += 1;
         const double D_new = 1.0 - (mu_out * r_new) * v.inv_ct;
         const double inv_D = recip(D_new);
@@ -999,22 +1221,30 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
           next_line = emit + 1;
           n_line += 1;
           last_line = k;
-          if (want_records) hash = fnv_event(hash, EV_LINE, sh, k, emit);
+          if (v.records) hash = fnv_event(hash, EV_LINE, sh, k, emit);
         } else {
           n_esc += 1;
-          if (want_records) hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
+          if (v.records) hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
         }
       }
-    }
+    } while (false);
 
-    if (lane == 0) {
-      lane_tally_end(m, tly, status, nu, E, n_seg, n_pass, n_line, n_esc);
-      if (want_records)
-        write_record(m, st.slot, st.pid, status, shell, nu, E, mu, r, st.mu0, st.nu_cmf0, n_seg,
-                     n_esc, n_line, n_pass, hash, last_line);
+    if (status != SMC_LIVE) {
+      if (v.jblue && wshell >= 0 && jb_acc != 0.0)
+        unsafeAtomicAdd(&v.jblue[(size_t)wshell * (size_t)v.L + wbase + grp.lane], jb_acc);
+      jb_acc = 0.0;
+      wshell = -1;
+      if (leader) {
+        const DevModel& m = ENTRY(a, model).m;
+        lane_tally_end(m, tly, status, nu, E, n_seg, n_pass, n_line, n_esc);
+        if (v.records)
+          write_record(m, slot, pid, status, shell, nu, E, mu, r, mu0, nu_cmf0, n_seg, n_esc,
+                       n_line, n_pass, hash, last_line);
+      }
+      have = false;
     }
   }
-  if (lane == 0) {
+  if (leader) {
     if (acc_shell >= 0) {
       const DevModel& am = ENTRY(a, acc_model).m;
       unsafeAtomicAdd(&am.raw[acc_shell], acc_J);
@@ -1055,10 +1285,10 @@ __global__ void finalise_kernel(LaunchArgs a) {
   for (int b = threadIdx.x; b < m.n_bins + 2; b += blockDim.x)
     m.out_spec[b] = L_inner * m.raw[2 * S + b] / dnu;
   if (threadIdx.x == 0) {
-    const double L_emit = L_inner * m.lsum[0];
+    const double L_emit = L_inner * ((double)m.lsum[0] / kLScale);
     m.scalars[SC_L_EMITTED] = L_emit;
-    m.scalars[SC_L_REABSORBED] = L_inner * m.lsum[1];
-    m.scalars[SC_L_CAPPED] = L_inner * m.lsum[2];
+    m.scalars[SC_L_REABSORBED] = L_inner * ((double)m.lsum[1] / kLScale);
+    m.scalars[SC_L_CAPPED] = L_inner * ((double)m.lsum[2] / kLScale);
     m.scalars[SC_L_INNER] = L_inner;
     // raise T_inner when the emergent luminosity is short of the request
     m.scalars[SC_T_NEXT] = (it.L_requested > 0.0 && L_emit > 0.0)
@@ -1110,11 +1340,25 @@ hipError_t transport_occupancy(bool multi, int* blocks_per_cu) {
                                                               transport_lds_bytes(false, 1));
 }
 
-hipError_t long_occupancy(bool multi, int* blocks_per_cu) {
-  return multi ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, long_kernel<true>,
-                                                              kLongBlock, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, long_kernel<false>,
-                                                              kLongBlock, 0);
+template <bool kMulti>
+static hipError_t long_occupancy_of(int lanes, int* blocks_per_cu) {
+  switch (lanes) {
+    case 16:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, long_kernel<kMulti, 16>,
+                                                          kLongBlock, 0);
+    case 32:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, long_kernel<kMulti, 32>,
+                                                          kLongBlock, 0);
+    case 64:
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, long_kernel<kMulti, 64>,
+                                                          kLongBlock, 0);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t long_occupancy(bool multi, int lanes, int* blocks_per_cu) {
+  return multi ? long_occupancy_of<true>(lanes, blocks_per_cu)
+               : long_occupancy_of<false>(lanes, blocks_per_cu);
 }
 
 template <bool kMulti>
@@ -1144,7 +1388,27 @@ static hipError_t launch_all(const LaunchArgs& a, const Shape& shape, uint64_t m
                            const_cast<BatchEntry*>(a.table));
         if ((e = hipGetLastError()) != hipSuccess) return e;
       }
-      hipLaunchKernelGGL(long_kernel<kMulti>, dim3(shape.long_grid), dim3(kLongBlock), 0, s, a);
+      const unsigned og = (unsigned)(shape.long_grid < 1024 ? shape.long_grid : 1024);
+      hipLaunchKernelGGL(order_count_kernel<kMulti>, dim3(og), dim3(256), 0, s, a);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(kOrderBuckets), 0, s, a);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(order_place_kernel<kMulti>, dim3(og), dim3(256), 0, s, a);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      const dim3 grid(shape.long_grid), block(kLongBlock);
+      switch (shape.long_lanes) {
+        case 16:
+          hipLaunchKernelGGL((long_kernel<kMulti, 16>), grid, block, 0, s, a);
+          break;
+        case 32:
+          hipLaunchKernelGGL((long_kernel<kMulti, 32>), grid, block, 0, s, a);
+          break;
+        case 64:
+          hipLaunchKernelGGL((long_kernel<kMulti, 64>), grid, block, 0, s, a);
+          break;
+        default:
+          return hipErrorInvalidValue;
+      }
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }

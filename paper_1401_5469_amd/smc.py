@@ -41,7 +41,7 @@ class smc_model_desc(C.Structure):
 
 class smc_tune(C.Structure):
     _fields_ = [("blocks_per_cu", C.c_int32), ("long_waves_per_cu", C.c_int32),
-                ("long_budget", C.c_uint32), ("reserved", C.c_uint32)]
+                ("long_budget", C.c_uint32), ("long_lanes", C.c_uint32)]
 
 
 class smc_iter_params(C.Structure):
@@ -133,7 +133,7 @@ def _ptr(a, t):
 
 def _tune(d):
     return smc_tune(int(d.get("blocks_per_cu", 0)), int(d.get("long_waves_per_cu", 0)),
-                    int(d.get("long_budget", 0)), 0)
+                    int(d.get("long_budget", 0)), int(d.get("long_lanes", 0)))
 
 
 class Graph:
@@ -202,7 +202,7 @@ class Context:
         _check(_lib.smc_batch_autotune(self.handle, handles, arr, n, cands, nc, C.byref(best),
                                        C.byref(ms), _stream_ptr(stream)))
         return (dict(blocks_per_cu=best.blocks_per_cu, long_waves_per_cu=best.long_waves_per_cu,
-                     long_budget=best.long_budget), float(ms.value))
+                     long_budget=best.long_budget, long_lanes=best.long_lanes), float(ms.value))
 
     def capture(self, models, params_per_iter, tune=None, stream=None):
         """Record iterations (a list, one list of per-model parameter dicts per
@@ -367,17 +367,19 @@ class Model:
         _check(_lib.smc_read_counters(self.handle, _ptr(c, _u64p), _stream_ptr(stream)))
         return {k: int(v) for k, v in zip(COUNTER_NAMES, c)}
 
-    def set_tune(self, blocks_per_cu=0, long_waves_per_cu=0, long_budget=0):
+    def set_tune(self, blocks_per_cu=0, long_waves_per_cu=0, long_budget=0, long_lanes=0):
         """Launch tuning (0 = library default; long_budget=2**32-1 disables
-        the hand-off to the wave-per-packet kernel)."""
-        t = smc_tune(int(blocks_per_cu), int(long_waves_per_cu), int(long_budget), 0)
+        the hand-off to the group-per-packet kernel; long_lanes = 16, 32 or
+        64 lanes per handed-off history)."""
+        t = smc_tune(int(blocks_per_cu), int(long_waves_per_cu), int(long_budget),
+                     int(long_lanes))
         _check(_lib.smc_model_set_tune(self.handle, C.byref(t)))
 
     def get_tune(self):
         t = smc_tune()
         _check(_lib.smc_model_get_tune(self.handle, C.byref(t)))
         return dict(blocks_per_cu=t.blocks_per_cu, long_waves_per_cu=t.long_waves_per_cu,
-                    long_budget=t.long_budget)
+                    long_budget=t.long_budget, long_lanes=t.long_lanes)
 
     def read_timing(self):
         """Transport-kernel duration of the last (timed) iteration in ms."""

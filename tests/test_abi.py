@@ -107,6 +107,9 @@ def test_host_validation_rejects_bad_models(lib):
     bad.v_bounds = m.v_bounds[::-1].copy()
     assert "increasing" in _expect_invalid(bad)
     bad = W.Model(**{**m.__dict__})
+    bad.v_bounds = m.v_bounds * (0.6 * 2.99792458e10 / m.v_bounds[-1])  # outer shell at 0.6 c
+    assert "c/2" in _expect_invalid(bad)
+    bad = W.Model(**{**m.__dict__})
     bad.n_e = -m.n_e
     assert "n_e" in _expect_invalid(bad)
     bad = W.Model(**{**m.__dict__})

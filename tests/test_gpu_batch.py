@@ -54,15 +54,19 @@ def _batch(ctx, mix, tune=None):
     return out
 
 
-@pytest.mark.parametrize("tune", [None, dict(long_budget=2), dict(long_budget=2**32 - 1),
-                                  dict(blocks_per_cu=1, long_waves_per_cu=1, long_budget=5)],
-                         ids=["default", "handoff2", "nohandoff", "narrow"])
+@pytest.mark.parametrize("tune", [None, dict(long_budget=2), dict(long_budget=2, long_lanes=64),
+                                  dict(long_budget=2**32 - 1),
+                                  dict(blocks_per_cu=1, long_waves_per_cu=1, long_budget=5,
+                                       long_lanes=32)],
+                         ids=["default", "handoff2", "handoff2-lanes64", "nohandoff", "narrow"])
 def test_batch_equals_alone(ctx, tune):
     mix = _mix()
     together = _batch(ctx, mix, tune)
     for (mdl, N, T), b in zip(mix, together):
-        # the same hand-off budget alone: each history takes the same kernels
-        a = _alone(ctx, mdl, N, T, tune=dict(long_budget=tune["long_budget"]) if tune else None)
+        # the same hand-off budget and group width alone: each history takes
+        # the same kernels with the same rounding
+        same = {k: v for k, v in (tune or {}).items() if k in ("long_budget", "long_lanes")}
+        a = _alone(ctx, mdl, N, T, tune=same or None)
         assert np.array_equal(a["packets"], b["packets"])
         for k in ("J", "nubar", "T_R", "W"):
             np.testing.assert_allclose(b["est"][k], a["est"][k], rtol=1e-12, atol=0)

@@ -86,9 +86,13 @@ def test_autotune_picks_a_valid_config(ctx):
     best, ms = ctx.batch_autotune(models, params)
     assert ms > 0.0
     assert best["long_budget"] in (0, 256, 1024, 4096, 2**32 - 1)
-    cands = [dict(long_budget=8), dict(long_budget=2**32 - 1, blocks_per_cu=1)]
+    assert best["long_lanes"] in (0, 16, 32, 64)
+    cands = [dict(long_budget=8, long_lanes=64), dict(long_budget=2**32 - 1, blocks_per_cu=1)]
     best2, ms2 = ctx.batch_autotune(models, params, candidates=cands)
     assert best2 in [dict(blocks_per_cu=c.get("blocks_per_cu", 0), long_waves_per_cu=0,
-                          long_budget=c["long_budget"]) for c in cands]
+                          long_budget=c["long_budget"], long_lanes=c.get("long_lanes", 0))
+                     for c in cands]
+    with pytest.raises(smc.SmcError):
+        ctx.batch_autotune(models, params, candidates=[dict(long_lanes=48)])
     with pytest.raises(smc.SmcError):
         ctx.batch_autotune(models, [dict(n_packets=N, T_inner=0.0) for _, N in mix])

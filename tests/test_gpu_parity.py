@@ -80,27 +80,47 @@ def test_downbranch_30shell_20kline_sample(ctx):
     _compare_iteration(ctx, w.model, 4000, w.T_inner)
 
 
-# histories moved to the wave-per-packet kernel after 1, 2 or 40 segments, or never
-HANDOFF = [dict(long_budget=1), dict(long_budget=2), dict(long_budget=40),
-           dict(long_budget=2**32 - 1)]
+# histories moved to the group-per-packet kernel (16, 32 or 64 lanes per
+# history) after 1, 2 or 40 segments, or never
+HANDOFF = [dict(long_budget=1, long_lanes=16), dict(long_budget=2, long_lanes=32),
+           dict(long_budget=2, long_lanes=64), dict(long_budget=40, long_lanes=16),
+           dict(long_budget=40, long_lanes=64), dict(long_budget=2**32 - 1)]
 
 
-@pytest.mark.parametrize("tune", HANDOFF, ids=lambda t: f"budget{t['long_budget']}")
+def _tid(t):
+    return f"budget{t['long_budget']}" + (f"-lanes{t['long_lanes']}" if "long_lanes" in t else "")
+
+
+@pytest.mark.parametrize("tune", HANDOFF, ids=_tid)
 def test_handoff_scatter_300kline(ctx, tune):
     w = W.config2()
     _compare_iteration(ctx, w.model, 2000, w.T_inner, tune=tune)
 
 
-@pytest.mark.parametrize("tune", HANDOFF[:2], ids=lambda t: f"budget{t['long_budget']}")
+@pytest.mark.parametrize("tune", HANDOFF[:3], ids=_tid)
 def test_handoff_downbranch(ctx, tune):
     w = W.config3()
     _compare_iteration(ctx, w.model, 2000, w.T_inner, tune=tune)
 
 
-def test_handoff_with_event_cap_and_small_grids(ctx):
+@pytest.mark.parametrize("lanes", [16, 64])
+def test_handoff_with_event_cap_and_small_grids(ctx, lanes):
     m = W.small_model(seed=14, n_shells=6, n_lines=700)
     _compare_iteration(ctx, m, 3000, 10000.0, max_segments=7,
-                       tune=dict(long_budget=3, blocks_per_cu=1, long_waves_per_cu=1))
+                       tune=dict(long_budget=3, blocks_per_cu=1, long_waves_per_cu=1,
+                                 long_lanes=lanes))
+
+
+def test_hot_model_handoff_widths_agree(ctx):
+    """At the paper-scale model's converged inner temperature most of the
+    work is in long histories: every group width gives the oracle's
+    histories on a sample of packet ids that includes the longest ones."""
+    w = W.config2()
+    # 183460, 862690 and 782077 take 90256, 80124 and 13018 segments
+    ids = np.array([183460, 862690, 782077, 5, 77, 1234, 98765, 400000], dtype=np.uint64)
+    for lanes in (16, 32, 64):
+        _compare_iteration(ctx, w.model, w.n_packets, 36000.0, ids=ids,
+                           tune=dict(long_budget=64, long_lanes=lanes))
 
 
 @pytest.mark.parametrize("n", [1, 63, 65, 257, 1000])
@@ -190,5 +210,7 @@ def test_invalid_inputs_raise(ctx):
     good = smc.Model(ctx, m, 10)
     with pytest.raises(smc.SmcError):
         good.run_iteration(10, 0.0)  # no T_inner on the first iteration
+    with pytest.raises(smc.SmcError):
+        good.set_tune(long_lanes=8)  # 16, 32 or 64 lanes per handed-off history
     with pytest.raises(smc.SmcError):
         good.run_iteration(100, 10000.0, flags=smc.F_PACKETS | smc.F_JBLUE)  # > n_packets_max
