@@ -39,7 +39,7 @@ class _Model(C.Structure):
 class _Iter(C.Structure):
     _fields_ = [("n_packets", C.c_uint64), ("iteration", C.c_uint32), ("T_inner", C.c_double),
                 ("max_segments", C.c_uint64), ("packet_ids", _u64p), ("n_ids", C.c_uint64),
-                ("want_jblue", C.c_int32)]
+                ("want_jblue", C.c_int32), ("n_virtual", C.c_uint32)]
 
 
 PACKET_DTYPE = np.dtype([("id", np.uint64), ("status", np.int32), ("shell", np.int32),
@@ -58,13 +58,15 @@ EVENT_DTYPE = np.dtype([("packet_id", np.uint64), ("kind", np.int32), ("shell", 
 
 class _Out(C.Structure):
     _fields_ = [("J_raw", _dp), ("nubar_raw", _dp), ("jblue_raw", _dp), ("spec_raw", _dp),
-                ("L_raw", _dp), ("counters", _u64p), ("packets", C.c_void_p),
+                ("L_raw", _dp), ("counters", _u64p), ("vspec_raw", _dp),
+                ("vcounts", C.c_uint64 * 3), ("packets", C.c_void_p),
                 ("trace", C.c_void_p), ("trace_cap", C.c_uint64), ("trace_len", C.c_uint64)]
 
 
 class _Final(C.Structure):
     _fields_ = [("J", _dp), ("nubar", _dp), ("jblue", _dp), ("T_R", _dp), ("W", _dp),
-                ("L_nu", _dp), ("L_emitted", C.c_double), ("L_reabsorbed", C.c_double),
+                ("L_nu", _dp), ("L_nu_virtual", _dp), ("L_virtual", C.c_double),
+                ("L_emitted", C.c_double), ("L_reabsorbed", C.c_double),
                 ("L_capped", C.c_double), ("L_inner", C.c_double),
                 ("T_inner_next", C.c_double)]
 
@@ -139,9 +141,10 @@ def _model_struct(model, keep: _Keep) -> _Model:
 
 
 def run(model, T_inner, n_packets, iteration=0, packet_ids=None, max_segments=10**9,
-        want_jblue=True, want_packets=True, trace_cap=0):
+        want_jblue=True, want_packets=True, trace_cap=0, n_virtual=0):
     """One oracle iteration.  Returns a dict of raw (un-normalised) tallies,
-    counters, per-packet records and the optional event trace."""
+    counters, per-packet records and the optional event trace; with
+    n_virtual > 0 also the v-packet spectrum (section 2.9) and its counts."""
     keep = _Keep()
     m = _model_struct(model, keep)
     it = _Iter()
@@ -150,6 +153,7 @@ def run(model, T_inner, n_packets, iteration=0, packet_ids=None, max_segments=10
     it.T_inner = float(T_inner)
     it.max_segments = int(max_segments)
     it.want_jblue = 1 if want_jblue else 0
+    it.n_virtual = int(n_virtual)
     if packet_ids is not None:
         ids = keep.arr(packet_ids, np.uint64)
         it.packet_ids = _ptr(ids, _u64p)
@@ -161,6 +165,7 @@ def run(model, T_inner, n_packets, iteration=0, packet_ids=None, max_segments=10
     res = dict(J_raw=np.zeros(S), nubar_raw=np.zeros(S),
                jblue_raw=np.zeros((S, L)) if want_jblue else None,
                spec_raw=np.zeros(model.n_bins + 2), L_raw=np.zeros(3),
+               vspec_raw=np.zeros(model.n_bins + 2) if n_virtual else None,
                counters=np.zeros(8, dtype=np.uint64),
                packets=np.zeros(n_rec, dtype=PACKET_DTYPE) if want_packets else None,
                trace=np.zeros(trace_cap, dtype=EVENT_DTYPE) if trace_cap else None)
@@ -171,6 +176,7 @@ def run(model, T_inner, n_packets, iteration=0, packet_ids=None, max_segments=10
     o.spec_raw = _ptr(res["spec_raw"], _dp)
     o.L_raw = _ptr(res["L_raw"], _dp)
     o.counters = _ptr(res["counters"], _u64p)
+    o.vspec_raw = _ptr(res["vspec_raw"], _dp) if n_virtual else None
     o.packets = res["packets"].ctypes.data if want_packets else None
     o.trace = res["trace"].ctypes.data if trace_cap else None
     o.trace_cap = int(trace_cap)
@@ -181,6 +187,8 @@ def run(model, T_inner, n_packets, iteration=0, packet_ids=None, max_segments=10
         res["trace_len"] = int(o.trace_len)
         res["trace"] = res["trace"][: min(int(o.trace_len), trace_cap)]
     res["counters"] = {k: int(v) for k, v in zip(COUNTER_NAMES, res["counters"])}
+    res["vcounts"] = dict(launched=int(o.vcounts[0]), counted=int(o.vcounts[1]),
+                          passes=int(o.vcounts[2]))
     return res
 
 
@@ -205,12 +213,15 @@ def finalise(model, raw, T_inner, L_requested=0.0, T_R_prev=None, W_prev=None, d
     o.jblue_raw = _ptr(keep.arr(raw["jblue_raw"], np.float64), _dp) if has_jb else None
     o.spec_raw = _ptr(keep.arr(raw["spec_raw"], np.float64), _dp)
     o.L_raw = _ptr(keep.arr(raw["L_raw"], np.float64), _dp)
+    has_v = raw.get("vspec_raw") is not None
+    o.vspec_raw = _ptr(keep.arr(raw["vspec_raw"], np.float64), _dp) if has_v else None
     if T_R_prev is None or W_prev is None:
         T_R_prev, W_prev = initial_radiation_field(model)
     out = dict(J=np.zeros(S), nubar=np.zeros(S), jblue=np.zeros((S, L)) if has_jb else None,
                T_R=np.array(T_R_prev, dtype=np.float64, copy=True),
                W=np.array(W_prev, dtype=np.float64, copy=True),
-               L_nu=np.zeros(model.n_bins + 2))
+               L_nu=np.zeros(model.n_bins + 2),
+               L_nu_virtual=np.zeros(model.n_bins + 2) if has_v else None)
     f = _Final()
     f.J = _ptr(out["J"], _dp)
     f.nubar = _ptr(out["nubar"], _dp)
@@ -218,10 +229,11 @@ def finalise(model, raw, T_inner, L_requested=0.0, T_R_prev=None, W_prev=None, d
     f.T_R = _ptr(out["T_R"], _dp)
     f.W = _ptr(out["W"], _dp)
     f.L_nu = _ptr(out["L_nu"], _dp)
+    f.L_nu_virtual = _ptr(out["L_nu_virtual"], _dp) if has_v else None
     lib().oracle_finalise(C.byref(m), float(T_inner), float(L_requested), float(damping),
                           C.byref(o), C.byref(f))
     out.update(L_emitted=f.L_emitted, L_reabsorbed=f.L_reabsorbed, L_capped=f.L_capped,
-               L_inner=f.L_inner, T_inner_next=f.T_inner_next)
+               L_inner=f.L_inner, T_inner_next=f.T_inner_next, L_virtual=f.L_virtual)
     return out
 
 

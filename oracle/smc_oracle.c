@@ -102,6 +102,22 @@ static void orc_stream_init(orc_stream* s, uint64_t seed, uint64_t packet, uint3
   s->draw = 0;
 }
 
+/* Direction draws of the v-packets of packet p in iteration i come from a
+ * second stream: draw dv is word dv%2 of the block with counter
+ * {dv/2, p_lo, p_hi, i} and key {seed_lo ^ 0x56504B54, seed_hi}.  The v-packet
+ * j of the e-th launch of the packet (e = 0 at injection, then one per
+ * interaction) takes draw dv = e * N_v + j, so v-packets never disturb the
+ * r-packet's own draws. */
+static double orc_virtual_uniform(uint64_t seed, uint64_t packet, uint32_t iteration,
+                                  uint64_t dv) {
+  uint32_t key[2] = {(uint32_t)seed ^ 0x56504B54u, (uint32_t)(seed >> 32)};
+  uint32_t ctr[4] = {(uint32_t)(dv / 2), (uint32_t)packet, (uint32_t)(packet >> 32), iteration};
+  uint32_t out[4];
+  oracle_philox4x32_10(ctr, key, out);
+  int j = (int)(dv % 2);
+  return oracle_uniform(((uint64_t)out[2 * j + 1] << 32) | (uint64_t)out[2 * j]);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Compensated (Neumaier) accumulation                                      */
 /* ------------------------------------------------------------------------ */
@@ -232,8 +248,101 @@ void oracle_inject(const oracle_model* m, double T_inner, uint64_t n_packets, ui
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-  double *J, *Jc, *nb, *nbc, *jb, *jbc, *sp, *spc, *L, *Lc;
+  double *J, *Jc, *nb, *nbc, *jb, *jbc, *sp, *spc, *L, *Lc, *vs, *vsc;
 } orc_tally;
+
+static size_t spectrum_bin(const oracle_model* m, double nu) {
+  const int nb = m->n_bins;
+  const double dnu = (m->nu_max - m->nu_min) / (double)nb;
+  if (nu < m->nu_min) return (size_t)nb;
+  double f = floor((nu - m->nu_min) / dnu);
+  return (f >= (double)nb) ? (size_t)nb + 1 : (size_t)f;
+}
+
+/* Section 2.9: follow one v-packet from (r, mu) in `shell`, lines from
+ * index k on, along its straight path to the outer boundary, adding the
+ * Sobolev depth of every resonance it reaches and the Thomson depth of every
+ * shell piece, with the conventions of the r-packet flight (quantities at the
+ * start of each shell piece, a line counts when its resonance lies before the
+ * shell boundary).  Returns 1 with *tau when the v-packet leaves the outer
+ * boundary with tau_v <= ORACLE_TAU_VIRTUAL_MAX, else 0.  This is exactly the
+ * probability exp(-tau_v) that an r-packet launched on that path escapes
+ * without interacting, segment by segment. */
+static int virtual_path(const oracle_model* m, double r, double mu, int shell, int64_t k,
+                        double nu_lab, double* tau, uint64_t* passes) {
+  const int S = m->n_shells;
+  const int64_t L = m->n_lines;
+  const double ct = ORC_C * m->t_exp;
+  double t = 0.0;
+  for (;;) {
+    const double r_in = m->v_bounds[shell] * m->t_exp;
+    const double r_out = m->v_bounds[shell + 1] * m->t_exp;
+    const double D = doppler(r, mu, ct);
+    const double nu_cmf = nu_lab * D;
+    const double d_shell = oracle_distance_to_shell(r, mu, r_in, r_out);
+    const double kappa = ORC_SIGMA_T * m->n_e[shell] * D;
+    const double ct_over_nu = ct / nu_lab;
+    while (k < L) {
+      double d_line = (nu_cmf - m->line_nu[k]) * ct_over_nu;
+      if (d_line < 0.0) d_line = 0.0;
+      if (!(d_line < d_shell)) break;
+      t += m->tau_sobolev[(size_t)shell * (size_t)L + (size_t)k];
+      *passes += 1;
+      if (t > ORACLE_TAU_VIRTUAL_MAX) return 0;
+      k += 1;
+    }
+    t += kappa * d_shell;
+    if (t > ORACLE_TAU_VIRTUAL_MAX) return 0;
+    const int inward = heads_inward(r, mu, r_in);
+    const double r_new = sqrt(r * r + d_shell * d_shell + 2.0 * r * d_shell * mu);
+    double mu_new = (r * mu + d_shell) / r_new;
+    if (mu_new > 1.0) mu_new = 1.0;
+    if (mu_new < -1.0) mu_new = -1.0;
+    r = inward ? r_in : r_out;
+    mu = mu_new;
+    shell += inward ? -1 : 1;
+    if (shell >= S) {
+      *tau = t;
+      return 1;
+    }
+    if (shell < 0) return 0; /* only a ray grazing the inner boundary by rounding */
+  }
+}
+
+/* Section 2.9: the v-packets of one packet launch.  They share the launching
+ * r-packet's position, comoving frequency and next redward line, take
+ * directions mu_v uniform in (mu_min, 1) with mu_min = -sqrt(1 - (r_i/r)^2)
+ * (so that no v-packet meets the inner boundary), and comoving energies
+ * E 2 mu_v / N_v at injection or E (1 - mu_min) / (2 N_v) after an
+ * interaction.  READING: a v-packet's energy and frequency enter the
+ * spectrum in the lab frame (E_v / D, nu_cmf / D at launch), as those of an
+ * escaping r-packet do; this makes the v-packet spectrum an unbiased
+ * estimate of the r-packet one. */
+static void launch_virtual(const oracle_model* m, const oracle_iter* it, uint64_t pid,
+                           uint64_t e, int injection, double r, int shell, int64_t next_line,
+                           double nu_cmf, double e_cmf, orc_tally* t, oracle_out* out) {
+  const double ct = ORC_C * m->t_exp;
+  const double r_inner = m->v_bounds[0] * m->t_exp;
+  const uint32_t nv = it->n_virtual;
+  double q = 1.0 - (r_inner / r) * (r_inner / r);
+  if (q < 0.0) q = 0.0;
+  const double mu_min = -sqrt(q);
+  for (uint32_t j = 0; j < nv; ++j) {
+    const double u = orc_virtual_uniform(m->seed, pid, it->iteration, e * nv + j);
+    const double mu_v = mu_min + (1.0 - mu_min) * u;
+    const double w = injection ? 2.0 * mu_v / (double)nv : (1.0 - mu_min) / (2.0 * (double)nv);
+    const double D = doppler(r, mu_v, ct);
+    const double nu_lab = nu_cmf / D;
+    const double e_lab = e_cmf * w / D;
+    double tau = 0.0;
+    out->vcounts[0] += 1;
+    if (virtual_path(m, r, mu_v, shell, next_line, nu_lab, &tau, &out->vcounts[2])) {
+      out->vcounts[1] += 1;
+      const size_t bin = spectrum_bin(m, nu_lab);
+      nsum_add(&t->vs[bin], &t->vsc[bin], e_lab * exp(-tau));
+    }
+  }
+}
 
 static void record_event(oracle_out* out, uint64_t pid, int kind, int shell, int64_t line,
                          int64_t emit, double r, double d, double mu_in, double mu_out,
@@ -279,6 +388,9 @@ static void run_packet(const oracle_model* m, const oracle_iter* it, uint64_t pi
   int64_t last_line = -1;
   int status = ORACLE_LIVE;
   record_event(out, pid, ORACLE_EV_INJECT, 0, -1, -1, r, 0.0, mu, mu, nu, nu, E, E);
+  if (t->vs)
+    launch_virtual(m, it, pid, 0, 1, r, 0, next_line, nu_cmf0, 1.0 / (double)it->n_packets, t,
+                   out);
 
   for (;;) {
     if (n_seg >= it->max_segments) {
@@ -398,6 +510,9 @@ static void run_packet(const oracle_model* m, const oracle_iter* it, uint64_t pi
       out->counters[ORACLE_C_ESCATTERS] += 1;
       hash = hash_event(hash, kind, shell, -1, -1);
       record_event(out, pid, kind, shell, -1, -1, r, d, mu_before, mu, nu_before, nu, e_before, E);
+      if (t->vs)
+        launch_virtual(m, it, pid, n_esc + n_line, 0, r, shell, next_line, nu_cmf_ev, e_cmf_ev, t,
+                       out);
       continue;
     }
 
@@ -426,21 +541,16 @@ static void run_packet(const oracle_model* m, const oracle_iter* it, uint64_t pi
     out->counters[ORACLE_C_LINE_EVENTS] += 1;
     hash = hash_event(hash, kind, shell, k, emit);
     record_event(out, pid, kind, shell, k, emit, r, d, mu_before, mu, nu_before, nu, e_before, E);
+    if (t->vs)
+      launch_virtual(m, it, pid, n_esc + n_line, 0, r, shell, next_line, m->line_nu[emit],
+                     e_cmf_ev, t, out);
   }
 
   if (status == ORACLE_ESCAPED) {
     out->counters[ORACLE_C_ESCAPED] += 1;
     nsum_add(&t->L[0], &t->Lc[0], E);
     /* section 2.9: bin the escaping packet in lab-frame frequency */
-    const int nb = m->n_bins;
-    const double dnu = (m->nu_max - m->nu_min) / (double)nb;
-    size_t bin;
-    if (nu < m->nu_min) {
-      bin = (size_t)nb;
-    } else {
-      double f = floor((nu - m->nu_min) / dnu);
-      bin = (f >= (double)nb) ? (size_t)nb + 1 : (size_t)f;
-    }
+    const size_t bin = spectrum_bin(m, nu);
     nsum_add(&t->sp[bin], &t->spc[bin], E);
   } else if (status == ORACLE_REABSORBED) {
     out->counters[ORACLE_C_REABSORBED] += 1;
@@ -516,6 +626,12 @@ int oracle_run(const oracle_model* m, const oracle_iter* it, oracle_out* out) {
     t.jbc = calloc(S * L > 0 ? S * L : 1, sizeof(double));
   }
   out->trace_len = 0;
+  memset(out->vcounts, 0, sizeof out->vcounts);
+  if (it->n_virtual > 0 && out->vspec_raw) {
+    t.vs = out->vspec_raw;
+    memset(t.vs, 0, NB * sizeof(double));
+    t.vsc = calloc(NB, sizeof(double));
+  }
 
   uint64_t n = it->packet_ids ? it->n_ids : it->n_packets;
   for (uint64_t i = 0; i < n; ++i) {
@@ -528,6 +644,8 @@ int oracle_run(const oracle_model* m, const oracle_iter* it, oracle_out* out) {
     t.nb[i] += t.nbc[i];
   }
   for (size_t i = 0; i < NB; ++i) t.sp[i] += t.spc[i];
+  if (t.vs)
+    for (size_t i = 0; i < NB; ++i) t.vs[i] += t.vsc[i];
   for (size_t i = 0; i < 3; ++i) t.L[i] += t.Lc[i];
   if (t.jb)
     for (size_t i = 0; i < S * L; ++i) t.jb[i] += t.jbc[i];
@@ -536,6 +654,7 @@ int oracle_run(const oracle_model* m, const oracle_iter* it, oracle_out* out) {
   free(t.spc);
   free(t.Lc);
   free(t.jbc);
+  free(t.vsc);
   return 0;
 }
 
@@ -585,6 +704,16 @@ int oracle_finalise(const oracle_model* m, double T_inner, double L_requested, d
   }
   const double dnu = (m->nu_max - m->nu_min) / (double)m->n_bins;
   for (int b = 0; b < m->n_bins + 2; ++b) fin->L_nu[b] = L_inner * raw->spec_raw[b] / dnu;
+  /* section 2.9: L_v = E_v exp(-tau_v) / (dt dnu), summed per bin */
+  fin->L_virtual = 0.0;
+  if (fin->L_nu_virtual && raw->vspec_raw) {
+    double sum = 0.0, comp = 0.0;
+    for (int b = 0; b < m->n_bins + 2; ++b) {
+      fin->L_nu_virtual[b] = L_inner * raw->vspec_raw[b] / dnu;
+      nsum_add(&sum, &comp, raw->vspec_raw[b]);
+    }
+    fin->L_virtual = L_inner * (sum + comp);
+  }
   fin->L_emitted = L_inner * raw->L_raw[0];
   fin->L_reabsorbed = L_inner * raw->L_raw[1];
   fin->L_capped = L_inner * raw->L_raw[2];

@@ -75,6 +75,7 @@ typedef struct {
   const uint64_t* packet_ids;  /* subset of ids to run, NULL = all of [0,N) */
   uint64_t n_ids;
   int32_t want_jblue;
+  uint32_t n_virtual;          /* v-packets per packet launch (section 2.9), 0 = none */
 } oracle_iter;
 
 typedef struct {
@@ -107,6 +108,9 @@ typedef struct {
   double* spec_raw;            /* n_bins+2: lab energy per bin, then under, over */
   double* L_raw;               /* 3: escaped, reabsorbed, capped lab energy */
   uint64_t* counters;          /* ORACLE_N_COUNTERS */
+  double* vspec_raw;           /* n_bins+2: v-packet lab energy * exp(-tau_v) per bin, then
+                                  under, over; NULL when no v-packets are run */
+  uint64_t vcounts[3];         /* v-packets launched, v-packets counted, resonances they swept */
   oracle_packet* packets;      /* n_ids (or N) records, or NULL */
   oracle_event* trace;         /* event trace, or NULL */
   uint64_t trace_cap;
@@ -120,6 +124,8 @@ typedef struct {
   double* T_R;                 /* S  in: previous value, out: new value */
   double* W;                   /* S  in: previous value, out: new value */
   double* L_nu;                /* n_bins+2 [erg s^-1 Hz^-1] (under/over as luminosity) */
+  double* L_nu_virtual;        /* n_bins+2 v-packet spectrum, or NULL */
+  double L_virtual;            /* v-packet estimate of the emergent luminosity [erg/s] */
   double L_emitted, L_reabsorbed, L_capped;
   double L_inner;
   double T_inner_next;
@@ -134,6 +140,10 @@ int oracle_finalise(const oracle_model* m, double T_inner, double L_requested, d
 
 /* Initial radiation-field guess of section 2.8: T_R = 10^4 K, geometric W. */
 void oracle_initial_radiation_field(const oracle_model* m, double* T_R, double* W);
+
+/* v-packets whose accumulated optical depth exceeds this are not counted
+ * (their weight exp(-tau_v) would be below 1e-13). */
+#define ORACLE_TAU_VIRTUAL_MAX 30.0
 
 /* Helpers exposed so that the pins can test each step on its own. */
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

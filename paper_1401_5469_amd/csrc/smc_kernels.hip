@@ -298,6 +298,15 @@ __device__ __forceinline__ void write_record(const DevModel& m, uint64_t slot, u
   static_cast<smc_packet_out*>(m.packets)[slot] = rec;
 }
 
+// Make the values available in registers at this point (the compiler
+// inserts the wait for any load that produced them here).
+__device__ __forceinline__ void settle() {}
+template <typename T, typename... R>
+__device__ __forceinline__ void settle(const T& x, const R&... rest) {
+  asm volatile("" ::"v"(x));
+  settle(rest...);
+}
+
 // per-lane tally slot in LDS: luminosity sums and event counters of the
 // lane's current model
 struct LaneTally {
@@ -566,6 +575,9 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(LaunchArgs a) {
         c_rin = v.r_bounds[sh];
         c_rout = v.r_bounds[sh + 1];
         c_ne = v.n_e[sh];
+        // wait for these loads here, on a shell change, rather than at every
+        // segment (where the wait would also cover the J_blue atomics in flight)
+        settle(c_rin, c_rout, c_ne);
       }
       const double rmu = r * mu;
       const double D = 1.0 - rmu * v.inv_ct;
@@ -836,15 +848,6 @@ __device__ __forceinline__ double dpp_f64(double x) {
   const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
       0, (int)(uint32_t)(b >> 32), kCtrl, kRowMask, 0xF, false);
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-// Make the values available in registers at this point (the compiler
-// inserts the wait for any load that produced them here).
-__device__ __forceinline__ void settle() {}
-template <typename T, typename... R>
-__device__ __forceinline__ void settle(const T& x, const R&... rest) {
-  asm volatile("" ::"v"(x));
-  settle(rest...);
 }
 
 __device__ __forceinline__ double join_u32(uint32_t lo, uint32_t hi) {

@@ -1,6 +1,6 @@
 """Pins of the CPU oracle against what the paper and the mathematics fix.
 
-Each test checks the oracle against something other than itself: numpy's
+Each test checks the oracle against something other than itself: rocRAND's
 Philox (an independent implementation of the published generator), closed
 forms, quadrature, brute force on tiny inputs, invariants the paper states and
 special cases.  None of these tests needs a GPU.
