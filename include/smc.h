@@ -109,6 +109,12 @@ typedef struct {
   uint64_t max_segments;     /* flight segments before a packet is CAPPED, 1 .. 2^30 */
   const uint64_t* packet_ids;/* device [n_ids] subset of ids in [0, N), or NULL for all N */
   uint64_t n_ids;
+  /* section 2.9: virtual packets per packet launch (injection and every
+   * interaction), 0 .. 16; 0 = none.  With v-packets every history runs in
+   * the group-per-packet kernel (the hand-off budget is ignored), and the
+   * v-packet spectrum is read with smc_read_virtual_spectrum. */
+  uint32_t n_virtual;
+  uint32_t reserved;         /* must be 0 */
 } smc_iter_params;
 
 /* Per-packet record (SMC_F_PACKETS), in work-list order.  hash is a
@@ -177,6 +183,21 @@ int smc_read_spectrum(smc_model* model, double* L_nu, double* scalars6, void* st
 
 /* Copy the SMC_N_COUNTERS event counters of the last iteration. */
 int smc_read_counters(smc_model* model, uint64_t* counters, void* stream);
+
+/* The virtual-packet spectrum of the last iteration (section 2.9): each
+ * v-packet leaves from the launching packet's position with a direction
+ * uniform in (mu_min, 1), mu_min = -sqrt(1 - (r_inner/r)^2), comoving
+ * energy E 2 mu_v / N_v (injection) or E (1 - mu_min) / (2 N_v)
+ * (interaction), and adds its lab energy times exp(-tau_v) to the bin of its
+ * lab frequency, tau_v being the Thomson and Sobolev depth of its straight
+ * path to the outer boundary; v-packets with tau_v > 30 are not counted.
+ * L_nu [n_bins + 2] in erg/s/Hz as smc_read_spectrum; *L_total the summed
+ * luminosity [erg/s]; counts[3] (may be NULL): v-packets launched, counted,
+ * and line resonances they swept.  Directions come from a second Philox
+ * stream of the packet (key {seed_lo ^ 0x56504B54, seed_hi}, draw e*N_v + j
+ * for v-packet j of the e-th launch).  Synchronises `stream`. */
+int smc_read_virtual_spectrum(smc_model* model, double* L_nu, double* L_total, uint64_t* counts,
+                              void* stream);
 
 /* Copy the first n per-packet records of the last iteration
  * (requires SMC_F_PACKETS in both the load and the iteration flags). */

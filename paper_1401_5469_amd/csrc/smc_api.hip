@@ -47,6 +47,7 @@ struct smc_model {
   bool ran;          // at least one iteration ran
   uint32_t last_flags;
   uint64_t last_work;
+  bool last_virtual;  // the last iteration ran v-packets
   hipEvent_t ev_start, ev_stop;  // created on the first timed iteration
   bool timed;                    // the last iteration recorded ev_start/ev_stop
   smc_tune tune;
@@ -173,6 +174,9 @@ int make_iter(const smc_model* m, const smc_iter_params* p, uint32_t budget, smc
     return fail(SMC_EINVAL, "damping must lie in (0, 1]");
   if (p->max_segments < 1 || p->max_segments > (1ull << 30))
     return fail(SMC_EINVAL, "max_segments must lie in [1, 2^30]");
+  if (p->n_virtual > smc::kMaxVirtual)
+    return fail(SMC_EINVAL, "n_virtual=%u exceeds %u", p->n_virtual, smc::kMaxVirtual);
+  if (p->reserved != 0) return fail(SMC_EINVAL, "reserved must be 0");
   it->n_packets = p->n_packets;
   it->n_work = n_work;
   it->ids = p->packet_ids;
@@ -180,7 +184,7 @@ int make_iter(const smc_model* m, const smc_iter_params* p, uint32_t budget, smc
   it->iteration = p->iteration;
   it->flags = p->flags;
   it->long_budget = budget;
-  it->pad = 0;
+  it->n_virtual = p->n_virtual;
   it->T_param = p->T_inner;
   it->L_requested = p->L_requested;
   it->damping = p->damping;
@@ -293,6 +297,9 @@ smc::Layout layout_of(const smc_model_desc* d, uint64_t n_packets_max, uint32_t 
   l.jblue = (flags & SMC_F_JBLUE) ? take(S * L * 8) : 0;
   l.out_shell = take(6 * S * 8);
   l.out_spec = take(NB * 8);
+  l.vraw = take(NB * 8);
+  l.vcounts = take(4 * 8);
+  l.out_vspec = take((NB + 1) * 8);
   l.scalars = take(8 * 8);
   l.packets = (flags & SMC_F_PACKETS) ? take(n_packets_max * sizeof(smc_packet_out)) : 0;
   l.total = off;
@@ -462,6 +469,9 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
   dm.jblue = (flags & SMC_F_JBLUE) ? (double*)(base + lay.jblue) : nullptr;
   dm.out_shell = (double*)(base + lay.out_shell);
   dm.out_spec = (double*)(base + lay.out_spec);
+  dm.vraw = (double*)(base + lay.vraw);
+  dm.vcounts = (unsigned long long*)(base + lay.vcounts);
+  dm.out_vspec = (double*)(base + lay.out_vspec);
   dm.scalars = (double*)(base + lay.scalars);
   dm.packets = (flags & SMC_F_PACKETS) ? (void*)(base + lay.packets) : nullptr;
   dm.longs = (smc::LongState*)(base + lay.longs);
@@ -512,7 +522,8 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   a.max_lines = (uint32_t)m->dev.L;
   a.hot = hot_of(m->ctx);
   const smc::Shape sh =
-      shape_of(m->ctx, m->tune, false, a.total_work, a.single.it.long_budget > 0);
+      shape_of(m->ctx, m->tune, false, a.total_work,
+               a.single.it.long_budget > 0 || a.single.it.n_virtual > 0);
   HIP_TRY(smc::launch_iteration(a, false, sh, jblue_entries(m, p->flags),
                                 timed ? m->ev_start : nullptr, timed ? m->ev_stop : nullptr, s),
           "iteration launch");
@@ -521,6 +532,7 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   m->ran = true;
   m->last_flags = p->flags;
   m->last_work = a.single.it.n_work;
+  m->last_virtual = p->n_virtual > 0;
   return ok();
 }
 
@@ -542,6 +554,7 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
   smc::BatchEntry* tab = ctx->host_table[slot];
   uint64_t work = 0, max_jb = 0;
   uint32_t max_lines = 0;
+  bool any_virtual = false;
   for (int k = 0; k < n_models; ++k) {
     smc_model* m = models[k];
     if (!m) return fail(SMC_EINVAL, "model %d is null", k);
@@ -559,6 +572,7 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
     tab[k].long_begin = 0;
     work += tab[k].it.n_work;
     if ((uint32_t)m->dev.L > max_lines) max_lines = (uint32_t)m->dev.L;
+    if (tab[k].it.n_virtual > 0) any_virtual = true;
     const uint64_t jb = jblue_entries(m, params[k].flags);
     if (jb > max_jb) max_jb = jb;
   }
@@ -580,7 +594,7 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
   a.order_hist = (unsigned int*)(ctx->dev_ctr[slot] + 4);
   a.max_lines = max_lines;
   a.hot = hot_of(ctx);
-  const smc::Shape sh = shape_of(ctx, t, true, work, budget > 0);
+  const smc::Shape sh = shape_of(ctx, t, true, work, budget > 0 || any_virtual);
   HIP_TRY(smc::launch_iteration(a, true, sh, max_jb, timed ? ctx->ev_start : nullptr,
                                 timed ? ctx->ev_stop : nullptr, s),
           "batch launch");
@@ -595,6 +609,7 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
     m->timed = false;
     m->last_flags = params[k].flags & ~SMC_F_TIMING;
     m->last_work = tab[k].it.n_work;
+    m->last_virtual = params[k].n_virtual > 0;
   }
   return ok();
 }
@@ -715,6 +730,22 @@ int smc_read_counters(smc_model* m, uint64_t* counters, void* stream) {
   return ok();
 }
 
+int smc_read_virtual_spectrum(smc_model* m, double* L_nu, double* L_total, uint64_t* counts,
+                              void* stream) {
+  if (!m || !L_nu || !L_total) return fail(SMC_EINVAL, "null model or output");
+  if (!m->ran) return fail(SMC_EINVAL, "no iteration has run");
+  if (!m->last_virtual) return fail(SMC_EINVAL, "the last iteration ran no virtual packets");
+  HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t NB = (size_t)m->dev.n_bins + 2;
+  int rc;
+  if ((rc = sync_copy_out(L_nu, m->dev.out_vspec, NB * 8, s))) return rc;
+  if ((rc = sync_copy_out(L_total, m->dev.out_vspec + NB, 8, s))) return rc;
+  if (counts && (rc = sync_copy_out(counts, m->dev.vcounts, 3 * 8, s))) return rc;
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return ok();
+}
+
 int smc_read_packets(smc_model* m, smc_packet_out* out, uint64_t n, void* stream) {
   if (!m || !out) return fail(SMC_EINVAL, "null model or output");
   if (!m->ran) return fail(SMC_EINVAL, "no iteration has run");
@@ -823,6 +854,7 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
     return hip_fail(e, "graph table allocation");
   }
   std::vector<uint64_t> work(n_iter, 0), max_jb(n_iter, 0);
+  std::vector<char> any_virtual(n_iter, 0);
   uint32_t max_lines = 0;
   for (int k = 0; k < n_models; ++k)
     if ((uint32_t)models[k]->dev.L > max_lines) max_lines = (uint32_t)models[k]->dev.L;
@@ -843,6 +875,7 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
       be.work_begin = work[i];
       be.long_begin = 0;
       work[i] += be.it.n_work;
+      if (be.it.n_virtual > 0) any_virtual[i] = 1;
       const uint64_t jb = jblue_entries(models[k], p.flags);
       if (jb > max_jb[i]) max_jb[i] = jb;
       if (i == n_iter - 1) g->last.push_back(p);
@@ -886,7 +919,7 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
     }
     a.max_lines = max_lines;
     a.hot = hot_of(ctx);
-    const smc::Shape sh = shape_of(ctx, t, multi, work[i], budget > 0);
+    const smc::Shape sh = shape_of(ctx, t, multi, work[i], budget > 0 || any_virtual[i]);
     le = smc::launch_iteration(a, multi, sh, max_jb[i], nullptr, nullptr, s);
   }
   e = hipStreamEndCapture(s, &g->graph);
@@ -915,6 +948,7 @@ int smc_graph_launch(smc_graph* g, void* stream) {
     m->timed = false;
     m->last_flags = g->last[k].flags;
     m->last_work = g->last[k].packet_ids ? g->last[k].n_ids : g->last[k].n_packets;
+    m->last_virtual = g->last[k].n_virtual > 0;
   }
   return ok();
 }

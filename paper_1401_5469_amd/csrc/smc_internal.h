@@ -23,6 +23,9 @@ struct Layout {
   uint64_t jblue;      // [S*L] raw, normalised in place by the finaliser
   uint64_t out_shell;  // [6S] J, nubar, T_R, W, jblue scale, pad
   uint64_t out_spec;   // [NB + 2] L_nu
+  uint64_t vraw;       // [NB + 2] v-packet lab energy * exp(-tau_v) per bin
+  uint64_t vcounts;    // [4] u64 v-packets launched, counted, resonances swept (+ pad)
+  uint64_t out_vspec;  // [NB + 3] v-packet L_nu, then the summed luminosity
   uint64_t scalars;    // [8] L_emitted, L_reabsorbed, L_capped, L_inner, T_used, T_next, ...
   uint64_t packets;    // [n_packets_max] smc_packet_out
   uint64_t total;
@@ -37,6 +40,10 @@ struct LongState {
   int32_t shell, next_line, last_line;
   uint32_t n_esc, n_line, pad;
 };
+
+// v-packets whose optical depth exceeds this are not counted
+constexpr double kTauVirtualMax = 30.0;
+constexpr uint32_t kMaxVirtual = 16;
 
 // Luminosity sums are kept in fixed point (energy x 2^60 rounded to an
 // integer), so that their totals, and the T_inner update that follows from
@@ -78,6 +85,9 @@ struct DevModel {
   double* jblue;           // [S*L] or nullptr
   double* out_shell;       // J, nubar, T_R, W, jblue scale, each [S]
   double* out_spec;        // [NB+2]
+  double* vraw;            // [NB+2]
+  unsigned long long* vcounts;  // [4]
+  double* out_vspec;       // [NB+3]
   double* scalars;         // [8]
   void* packets;           // smc_packet_out records or nullptr
   LongState* longs;        // hand-off buffer
@@ -94,7 +104,8 @@ struct DevIter {
   uint32_t iteration;
   uint32_t flags;
   uint32_t long_budget;    // segments before a history moves to the group kernel (0: never)
-  uint32_t pad;
+  uint32_t n_virtual;      // v-packets per packet launch (0: none; then every history is
+                           // handed to the group kernel right after injection)
   double T_param;          // > 0 overrides the device-resident T_inner
   double L_requested;
   double damping;

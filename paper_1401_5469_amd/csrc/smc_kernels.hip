@@ -133,6 +133,8 @@ __global__ void reset_kernel(LaunchArgs a) {
   const size_t n_raw = 2 * (size_t)m.S + (size_t)m.n_bins + 2;
   for (size_t i = tid; i < n_raw; i += stride) m.raw[i] = 0.0;
   if (tid < 4) m.lsum[tid] = 0ull;
+  for (size_t i = tid; i < n_raw - 2 * (size_t)m.S; i += stride) m.vraw[i] = 0.0;
+  if (tid < 4) m.vcounts[tid] = 0ull;
   if (tid < CTR_TOTAL) m.counters[tid] = 0ull;
   if (m.jblue && (it.flags & SMC_F_JBLUE)) {
     const size_t n = (size_t)m.S * (size_t)m.L;
@@ -312,10 +314,12 @@ __device__ __forceinline__ void settle(const T& x, const R&... rest) {
 struct LaneTally {
   unsigned long long L[3];  // fixed-point escaped, reabsorbed, capped energy
   unsigned long long c[SMC_N_COUNTERS];
+  unsigned long long vc[3];  // v-packets launched, counted, resonances swept
 };
 
 __device__ __forceinline__ void lane_tally_clear(LaneTally& t) {
   t.L[0] = t.L[1] = t.L[2] = 0ull;
+  t.vc[0] = t.vc[1] = t.vc[2] = 0ull;
 #pragma unroll
   for (int i = 0; i < SMC_N_COUNTERS; ++i) t.c[i] = 0ull;
 }
@@ -327,6 +331,9 @@ __device__ __forceinline__ void lane_tally_flush(const DevModel& m, LaneTally& t
 #pragma unroll
   for (int i = 0; i < SMC_N_COUNTERS; ++i)
     if (t.c[i]) atomicAdd(&m.counters[i], t.c[i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (t.vc[i]) atomicAdd(&m.vcounts[i], t.vc[i]);
   lane_tally_clear(t);
 }
 
@@ -373,6 +380,8 @@ struct View {
   bool downbranch;
   bool records;           // per-packet records (and their event hash) are kept
   uint32_t k0, k1, iter;  // random-number key and counter word
+  uint32_t n_virtual;     // v-packets per packet launch
+  double e_unit;          // comoving energy of an injected packet, 1/N
 };
 
 __device__ __forceinline__ View make_view(const DevModel& m, const DevIter& it) {
@@ -389,7 +398,9 @@ __device__ __forceinline__ View make_view(const DevModel& m, const DevIter& it) 
   v.ct = m.ct;
   v.inv_ct = 1.0 / m.ct;
   v.max_segments = it.max_segments;
-  v.budget = (it.long_budget > 0 && m.longs) ? it.long_budget : ~0ull;
+  // with v-packets every history goes to the group kernel before its first
+  // segment; otherwise after long_budget segments (never when 0)
+  v.budget = it.n_virtual ? 0ull : ((it.long_budget > 0 && m.longs) ? it.long_budget : ~0ull);
   v.S = m.S;
   v.L = m.L;
   v.Lp = m.Lp;
@@ -398,6 +409,8 @@ __device__ __forceinline__ View make_view(const DevModel& m, const DevIter& it) 
   v.k0 = (uint32_t)m.seed;
   v.k1 = (uint32_t)(m.seed >> 32);
   v.iter = it.iteration;
+  v.n_virtual = it.n_virtual;
+  v.e_unit = 1.0 / (double)it.n_packets;
   return v;
 }
 
@@ -905,6 +918,118 @@ struct Group {
   }
 };
 
+// ---------------------------------------------------------------------------
+// virtual packets (section 2.9), run by a group for its history's launches
+// ---------------------------------------------------------------------------
+
+// Follow one v-packet from (r, mu) in `shell`, lines from index k on, along
+// its straight path to the outer boundary; tau_v is the Sobolev depth of
+// every resonance reached before each shell boundary plus the Thomson depth
+// of every shell piece, with the quantities of each piece taken at its start
+// as for the packets themselves.  The group tests G lines per step: the
+// reached lines of a window form a prefix (d_line grows along the list), a
+// prefix sum over the group gives their running depth.  Returns true with
+// tau when the v-packet leaves the outer boundary with tau <= kTauVirtualMax;
+// `passes` counts the resonances swept (up to the one that passes the cut).
+template <int G>
+__device__ bool virtual_path(const Group<G>& grp, const View& v, double r, double mu, int shell,
+                             int32_t k, double nu_lab, double& tau_out, uint64_t& passes) {
+  const double inv_nu = recip(nu_lab);
+  double tau = 0.0;
+  for (;;) {
+    const double r_in = v.r_bounds[shell], r_out = v.r_bounds[shell + 1];
+    const double ne = v.n_e[shell];
+    const double rmu = r * mu;
+    const double D = 1.0 - rmu * v.inv_ct;
+    const double nu_cmf = nu_lab * D;
+    bool inward;
+    const double d_shell = shell_distance(r, mu, rmu, r_in, r_out, inward);
+    const double kappa = kSigmaT * ne * D;
+    const double ct_over_nu = v.ct * inv_nu;
+    const size_t row = (size_t)shell * (size_t)v.Lp;
+    while (k < v.L) {
+      const int32_t line = k + grp.lane;
+      const bool in = line < v.L;
+      const int32_t lc = in ? line : v.L - 1;
+      const double nk = v.line_nu[lc];
+      const double tk = v.tau[row + lc];
+      double dl = (nu_cmf - nk) * ct_over_nu;
+      dl = dl < 0.0 ? 0.0 : dl;
+      const bool reach = in && dl < d_shell;
+      const int n_reach = __popcll(grp.bits(__ballot(reach)));
+      const double cum = grp.prefix_sum(reach ? tk : 0.0);
+      const unsigned long long over =
+          grp.bits(__ballot(reach && tau + cum > kTauVirtualMax));
+      if (over) {
+        passes += (uint64_t)(__builtin_ctzll(over) + 1);
+        return false;
+      }
+      passes += (uint64_t)n_reach;
+      if (n_reach > 0) tau += grp.bcast(cum, grp.uni(n_reach - 1));
+      k += n_reach;
+      if (n_reach < G) break;
+    }
+    tau += kappa * d_shell;
+    if (tau > kTauVirtualMax) return false;
+    const double r_new = sqrt(r * r + d_shell * d_shell + 2.0 * r * d_shell * mu);
+    double mu_new = (rmu + d_shell) * recip(r_new);
+    mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
+    r = inward ? r_in : r_out;
+    mu = mu_new;
+    shell += inward ? -1 : 1;
+    if (shell >= v.S) {
+      tau_out = tau;
+      return true;
+    }
+    if (shell < 0) return false;  // only a ray grazing the inner boundary by rounding
+  }
+}
+
+// The N_v v-packets of one packet launch (injection, e = 0, or the e-th
+// interaction): the launching packet's position, comoving frequency, energy
+// and next redward line; directions uniform in (mu_min, 1) from the packet's
+// second stream (draw e * N_v + j, key word 0 xor 0x56504B54); comoving
+// weights 2 mu_v / N_v at injection, (1 - mu_min) / (2 N_v) otherwise; lab
+// energy E_v / D and frequency nu_cmf / D into the v-packet spectrum.
+template <int G>
+__device__ void launch_virtual(const Group<G>& grp, const View& v, const DevModel& m,
+                               const StreamKey& sk, uint64_t e, bool injection, double r,
+                               int shell, int32_t k, double nu_cmf, double e_cmf,
+                               LaneTally& tly, bool leader) {
+  const uint32_t nv = v.n_virtual;
+  StreamKey vk = sk;
+  vk.k0 ^= 0x56504B54u;
+  // group lane j < N_v holds draw e * N_v + j
+  const uint64_t dv = e * (uint64_t)nv + (uint64_t)(grp.lane < (int)nv ? grp.lane : 0);
+  const Block b = stream_block(vk, (uint32_t)(dv >> 1));
+  const double u_lane = to_uniform((dv & 1) ? b.b : b.a);
+  // a true division: at injection r = r_inner gives exactly mu_min = 0
+  const double x = v.r_bounds[0] / r;
+  double q = 1.0 - x * x;
+  q = q < 0.0 ? 0.0 : q;
+  const double mu_min = -sqrt(q);
+  const double inv_nv = 1.0 / (double)nv;
+  uint64_t passes = 0, counted = 0;
+  for (uint32_t j = 0; j < nv; ++j) {
+    const double u = grp.bcast(u_lane, grp.uni((int)j));
+    const double mu_v = mu_min + (1.0 - mu_min) * u;
+    const double w = injection ? 2.0 * mu_v * inv_nv : (1.0 - mu_min) * (0.5 * inv_nv);
+    const double D = 1.0 - (mu_v * r) * v.inv_ct;
+    const double inv_D = recip(D);
+    const double nu_lab = nu_cmf * inv_D;
+    double tau = 0.0;
+    if (virtual_path(grp, v, r, mu_v, shell, k, nu_lab, tau, passes)) {
+      counted += 1;
+      if (leader) unsafeAtomicAdd(&m.vraw[spectrum_bin(m, nu_lab)], e_cmf * w * inv_D * exp(-tau));
+    }
+  }
+  if (leader) {
+    tly.vc[0] += nv;
+    tly.vc[1] += counted;
+    tly.vc[2] += passes;
+  }
+}
+
 constexpr int kLongBlock = 64;
 
 // One handed-off history per group of G lanes, 64/G histories per wavefront.
@@ -1008,6 +1133,9 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
         wshell = -1;
         c_shell = -1;
         have = true;
+        if (v.n_virtual && st.n_seg == 0)
+          launch_virtual(grp, v, ENTRY(a, model).m, sk, 0, true, r, 0, next_line, nu_cmf0,
+                         v.e_unit, tly, leader);
         // wait for the history's loads here, once per history, so that the
         // segment loop never inherits a pending load (and with it a wait for
         // the copies and atomics it issues itself)
@@ -1229,6 +1357,9 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
           n_esc += 1;
           if (v.records) hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
         }
+        if (v.n_virtual)
+          launch_virtual(grp, v, ENTRY(a, model).m, sk, (uint64_t)n_esc + n_line, false, r, sh,
+                         next_line, nu_cmf_out, e_cmf_ev, tly, leader);
       }
     } while (false);
 
@@ -1287,6 +1418,15 @@ __global__ void finalise_kernel(LaunchArgs a) {
   const double dnu = (m.nu_max - m.nu_min) / (double)m.n_bins;
   for (int b = threadIdx.x; b < m.n_bins + 2; b += blockDim.x)
     m.out_spec[b] = L_inner * m.raw[2 * S + b] / dnu;
+  if (it.n_virtual) {
+    for (int b = threadIdx.x; b < m.n_bins + 2; b += blockDim.x)
+      m.out_vspec[b] = L_inner * m.vraw[b] / dnu;
+    if (threadIdx.x == 0) {
+      double sum = 0.0;
+      for (int b = 0; b < m.n_bins + 2; ++b) sum += m.vraw[b];
+      m.out_vspec[m.n_bins + 2] = L_inner * sum;
+    }
+  }
   if (threadIdx.x == 0) {
     const double L_emit = L_inner * ((double)m.lsum[0] / kLScale);
     m.scalars[SC_L_EMITTED] = L_emit;

@@ -47,7 +47,8 @@ class smc_tune(C.Structure):
 class smc_iter_params(C.Structure):
     _fields_ = [("n_packets", C.c_uint64), ("iteration", C.c_uint32), ("flags", C.c_uint32),
                 ("T_inner", C.c_double), ("L_requested", C.c_double), ("damping", C.c_double),
-                ("max_segments", C.c_uint64), ("packet_ids", C.c_void_p), ("n_ids", C.c_uint64)]
+                ("max_segments", C.c_uint64), ("packet_ids", C.c_void_p), ("n_ids", C.c_uint64),
+                ("n_virtual", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 PACKET_DTYPE = np.dtype([("id", np.uint64), ("status", np.int32), ("shell", np.int32),
@@ -61,7 +62,8 @@ EXPORTS = ("smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_model_wor
            "smc_model_load", "smc_model_free", "smc_run_iteration", "smc_read_estimators",
            "smc_read_spectrum", "smc_read_counters", "smc_read_packets", "smc_read_timing",
            "smc_model_set_tune", "smc_model_get_tune", "smc_batch_run", "smc_batch_read_timing",
-           "smc_batch_autotune", "smc_graph_capture", "smc_graph_launch", "smc_graph_destroy")
+           "smc_batch_autotune", "smc_graph_capture", "smc_graph_launch", "smc_graph_destroy",
+           "smc_read_virtual_spectrum")
 
 
 class SmcError(RuntimeError):
@@ -96,6 +98,7 @@ def load_library(path: str = LIB_PATH):
     L.smc_read_estimators.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, vp]
     L.smc_read_spectrum.argtypes = [vp, _dp, _dp, vp]
     L.smc_read_counters.argtypes = [vp, _u64p, vp]
+    L.smc_read_virtual_spectrum.argtypes = [vp, _dp, _dp, _u64p, vp]
     L.smc_read_packets.argtypes = [vp, vp, C.c_uint64, vp]
     L.smc_read_timing.argtypes = [vp, _dp]
     L.smc_model_set_tune.argtypes = [vp, C.POINTER(smc_tune)]
@@ -316,7 +319,7 @@ class Model:
 
     def _params(self, n_packets: int, T_inner: float, iteration: int = 0,
                 flags: Optional[int] = None, L_requested: float = 0.0, damping: float = 1.0,
-                max_segments: int = 10**7, packet_ids=None):
+                max_segments: int = 10**7, packet_ids=None, n_virtual: int = 0):
         import torch
         p = smc_iter_params()
         p.n_packets = int(n_packets)
@@ -326,6 +329,7 @@ class Model:
         p.L_requested = float(L_requested)
         p.damping = float(damping)
         p.max_segments = int(max_segments)
+        p.n_virtual = int(n_virtual)
         if packet_ids is not None:
             if not isinstance(packet_ids, torch.Tensor):
                 packet_ids = torch.as_tensor(np.asarray(packet_ids, dtype=np.int64))
@@ -338,11 +342,12 @@ class Model:
     def run_iteration(self, n_packets: int, T_inner: float, iteration: int = 0,
                       flags: Optional[int] = None, L_requested: float = 0.0,
                       damping: float = 1.0, max_segments: int = 10**7, packet_ids=None,
-                      stream=None):
+                      n_virtual: int = 0, stream=None):
         """Enqueue one iteration.  packet_ids: optional torch int64/uint64
-        CUDA tensor or numpy array of ids (copied to the device)."""
+        CUDA tensor or numpy array of ids (copied to the device); n_virtual:
+        virtual packets per packet launch (section 2.9)."""
         p = self._params(n_packets, T_inner, iteration, flags, L_requested, damping,
-                         max_segments, packet_ids)
+                         max_segments, packet_ids, n_virtual)
         _check(_lib.smc_run_iteration(self.handle, C.byref(p), _stream_ptr(stream)))
 
     def read_estimators(self, jblue: bool = True, stream=None):
@@ -361,6 +366,17 @@ class Model:
                                       _stream_ptr(stream)))
         return dict(L_nu=L_nu, L_emitted=sc[0], L_reabsorbed=sc[1], L_capped=sc[2],
                     L_inner=sc[3], T_inner=sc[4], T_inner_next=sc[5])
+
+    def read_virtual_spectrum(self, stream=None):
+        """v-packet spectrum of the last iteration: L_nu [n_bins + 2], the
+        summed luminosity and the counts (launched, counted, passes)."""
+        L_nu = np.zeros(self.n_bins + 2)
+        tot = np.zeros(1)
+        c = np.zeros(3, dtype=np.uint64)
+        _check(_lib.smc_read_virtual_spectrum(self.handle, _ptr(L_nu, _dp), _ptr(tot, _dp),
+                                              _ptr(c, _u64p), _stream_ptr(stream)))
+        return dict(L_nu=L_nu, L_total=float(tot[0]),
+                    counts=dict(launched=int(c[0]), counted=int(c[1]), passes=int(c[2])))
 
     def read_counters(self, stream=None):
         c = np.zeros(8, dtype=np.uint64)
