@@ -5,6 +5,9 @@
     python bench.py --workload served [--duration 10]
     python bench.py --workload copy      (plain 1 GiB device copies: the
                                           reference for HBM byte counters)
+    python bench.py --workload virtual [--n-virtual 3]
+                                         (the final spectrum iteration with
+                                          virtual packets, section 2.9)
 
 One step is one Monte Carlo iteration of the paper-scale scatter model
 (20 shells 10000-25000 km/s at 13 d, 3e5 lines, 1e6 packets; Kerzendorf & Sim
@@ -51,7 +54,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-jblue", action="store_true")
     ap.add_argument("--workload", default="paper-scale",
-                    choices=["paper-scale", "batched", "served", "copy"])
+                    choices=["paper-scale", "batched", "served", "copy", "virtual"])
+    ap.add_argument("--n-virtual", type=int, default=3,
+                    help="virtual packets per packet launch in the virtual mode")
     ap.add_argument("--models", type=int, default=64, help="models in the batched mix")
     ap.add_argument("--duration", type=float, default=10.0,
                     help="seconds of Poisson arrivals (20 per second) in the served mode")
@@ -94,6 +99,72 @@ def copy_reference(args):
     print(json.dumps({"metric": "device copy bandwidth", "value": 2 * n / dt / 1e9,
                       "unit": "GB/s", "bytes_read_per_copy": n, "bytes_written_per_copy": n,
                       "copies": 5}), flush=True)
+
+
+def virtual(args):
+    """The paper-scale model: the iterative sequence (T_inner carried on the
+    device) without virtual packets, then the final spectrum iteration once
+    plain and once with N_v virtual packets per packet launch (section 2.9).
+    Reports the cost of the v-packet iteration and its v-packet rates."""
+    import numpy as np
+    import torch
+
+    from paper_1401_5469_amd import smc
+    from paper_1401_5469_amd import workloads as W
+
+    w = W.config2(n_packets=args.packets)
+    N = w.n_packets
+    flags = 0 if args.no_jblue else smc.F_JBLUE
+    ctx = smc.Context(0)
+    model = smc.Model(ctx, w.model, N, flags=flags)
+    for i in range(args.steps):
+        model.run_iteration(N, w.T_inner if i == 0 else 0.0, iteration=i, flags=flags,
+                            L_requested=w.L_requested, damping=w.damping)
+    torch.cuda.synchronize()
+    T_final = model.read_spectrum()["T_inner_next"]
+    print(f"# {args.steps} iterations, T_inner -> {T_final:.1f} K", file=sys.stderr, flush=True)
+    out_runs = {}
+    for nv in (0, args.n_virtual):
+        t0 = time.perf_counter()
+        model.run_iteration(N, T_final, iteration=args.steps, flags=flags | smc.F_TIMING,
+                            n_virtual=nv)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        rec = dict(wall_ms=wall * 1e3, transport_ms=model.read_timing(),
+                   counters=model.read_counters())
+        if nv:
+            vs = model.read_virtual_spectrum()
+            rec.update(v_counts=vs["counts"], L_virtual=vs["L_total"],
+                       L_emitted=model.read_spectrum()["L_emitted"])
+        out_runs[nv] = rec
+        print(f"# final iteration with n_virtual={nv}: {wall * 1e3:.1f} ms", file=sys.stderr,
+              flush=True)
+    v = out_runs[args.n_virtual]
+    wall = v["wall_ms"] * 1e-3
+    out = {
+        "metric": "virtual packets/sec (final spectrum iteration)",
+        "value": v["v_counts"]["launched"] / wall,
+        "unit": "v-packets/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": args.steps,
+        "ms_per_step": v["wall_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}-final-spectrum-nv{args.n_virtual}",
+                   "packets": N, "n_virtual": args.n_virtual, "T_inner": T_final},
+        "virtual": {"v_packets_launched": v["v_counts"]["launched"],
+                    "v_packets_counted": v["v_counts"]["counted"],
+                    "v_line_resonances": v["v_counts"]["passes"],
+                    "v_line_resonances_per_s": v["v_counts"]["passes"] / wall,
+                    "L_virtual": v["L_virtual"], "L_emitted": v["L_emitted"]},
+        "plain_final_iteration_ms": out_runs[0]["wall_ms"],
+        "cost_ratio": v["wall_ms"] / out_runs[0]["wall_ms"],
+    }
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(w, n_sample):
@@ -305,6 +376,8 @@ def main():
         return served(args)
     if args.workload == "copy":
         return copy_reference(args)
+    if args.workload == "virtual":
+        return virtual(args)
 
     import numpy as np
     import torch
