@@ -43,6 +43,7 @@ extern "C" {
 
 #define SMC_SCATTER 0    /* resonance scattering (Table 1, "scatter") */
 #define SMC_DOWNBRANCH 1 /* macro atom without internal jumps (Table 1, "downbranch") */
+#define SMC_MACROATOM 2  /* macro atom with internal jumps (Table 1, "macroatom"; section 2.5) */
 
 /* packet status */
 #define SMC_LIVE 0
@@ -80,16 +81,23 @@ typedef struct {
   int64_t n_lines;           /* L >= 0 */
   const double* line_nu;     /* [L] line frequencies [Hz], non-increasing */
   const double* tau_sobolev; /* [S*L] Sobolev optical depth, shell-major (shell s at s*L), >= 0 */
-  int32_t line_mode;         /* SMC_SCATTER or SMC_DOWNBRANCH */
-  /* downbranch only (ignored for SMC_SCATTER): upper level of each line and,
-   * per level, the downward lines it may emit in with cumulative
-   * probabilities (CSR rows; the last entry of each used row is 1). */
+  int32_t line_mode;         /* SMC_SCATTER, SMC_DOWNBRANCH or SMC_MACROATOM */
+  /* macro-atom tables (ignored for SMC_SCATTER): the upper level of each line
+   * (where an absorption activates the macro atom) and, per level, a CSR row
+   * of transitions with cumulative probabilities (the last entry of each
+   * used row is 1).  Downbranch: every entry is a downward line to emit in,
+   * one probability set for all shells.  Macroatom: an entry em_line >= 0
+   * deactivates by emission in that line, em_line = -(j+1) jumps to level j
+   * (which then draws from its own row), and em_cum holds one probability
+   * set per shell (shell-major).  A macro atom that makes 100000 internal
+   * jumps without deactivating ends its packet as CAPPED. */
   const int32_t* line_upper; /* [L] in [0, n_levels) */
   int32_t n_levels;
   const int64_t* level_ptr;  /* [n_levels+1] row offsets into em_line / em_cum */
   int64_t n_em;              /* level_ptr[n_levels] */
-  const int32_t* em_line;    /* [n_em] emitted line index in [0, L) */
-  const double* em_cum;      /* [n_em] cumulative probability, non-decreasing within a row */
+  const int32_t* em_line;    /* [n_em] emitted line in [0, L), or -(level+1) (macroatom) */
+  const double* em_cum;      /* [n_em] (downbranch) or [S*n_em] (macroatom) cumulative
+                                probabilities, non-decreasing within a row */
   /* emergent spectrum: n_bins bins linear in lab frequency over
    * [nu_min, nu_max), plus underflow and overflow (section 2.9) */
   double nu_min, nu_max;

@@ -14,7 +14,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-SCATTER, DOWNBRANCH = 0, 1
+SCATTER, DOWNBRANCH, MACROATOM = 0, 1, 2
 LIVE, ESCAPED, REABSORBED, CAPPED = 0, 1, 2, 3
 EV_INJECT, EV_SHELL_OUT, EV_SHELL_IN, EV_ESCATTER, EV_LINE = 0, 1, 2, 3, 4
 COUNTER_NAMES = ("segments", "line_passes", "line_events", "escatters", "escaped",
@@ -127,7 +127,7 @@ def _model_struct(model, keep: _Keep) -> _Model:
     tau = model.tau_sobolev if L else np.zeros((S, 1))
     m.tau_sobolev = _ptr(keep.arr(tau, np.float64), _dp)
     m.line_mode = int(model.line_mode)
-    if model.line_mode == DOWNBRANCH:
+    if model.line_mode in (DOWNBRANCH, MACROATOM):
         m.line_upper = _ptr(keep.arr(model.line_upper, np.int32), _i32p)
         m.n_levels = int(model.n_levels)
         m.level_ptr = _ptr(keep.arr(model.level_ptr, np.int64), _i64p)

@@ -516,10 +516,10 @@ static void run_packet(const oracle_model* m, const oracle_iter* it, uint64_t pi
       continue;
     }
 
-    /* line interaction with line k (section 2.5).  Two draws in both modes:
-     * the branch draw (unused in scatter mode), then the new direction. */
+    /* line interaction with line k (section 2.5).  Draws: the branch draw
+     * (unused in scatter mode), one more per internal macro-atom jump, then
+     * the new direction. */
     double u_branch = orc_next_uniform(&s);
-    double u_mu = orc_next_uniform(&s);
     int64_t emit = k;
     if (m->line_mode == ORACLE_DOWNBRANCH) {
       /* downbranch: the macro atom activated in the upper level of line k
@@ -530,7 +530,42 @@ static void run_packet(const oracle_model* m, const oracle_iter* it, uint64_t pi
       int64_t j = a;
       while (j < b - 1 && !(m->em_cum[j] > u_branch)) j += 1;
       emit = m->em_line[j];
+    } else if (m->line_mode == ORACLE_MACROATOM) {
+      /* macroatom: the macro atom activated in the upper level of line k
+       * makes internal jumps between levels until it deactivates by
+       * emission in one of the current level's downward lines (section 2.5,
+       * after Lucy 2002, 2003); each step draws from the level's row of this
+       * shell's transition probabilities. */
+      const int64_t n_em = m->level_ptr[m->n_levels];
+      const double* cum = m->em_cum + (size_t)shell * (size_t)n_em;
+      int32_t level = m->line_upper[k];
+      double u = u_branch;
+      uint64_t steps = 0;
+      for (;;) {
+        int64_t a = m->level_ptr[level], b = m->level_ptr[level + 1];
+        int64_t j = a;
+        while (j < b - 1 && !(cum[j] > u)) j += 1;
+        int32_t target = m->em_line[j];
+        if (target >= 0) {
+          emit = target;
+          break;
+        }
+        level = -target - 1;
+        steps += 1;
+        if (steps >= ORACLE_MACRO_MAX_STEPS) {
+          emit = -1;
+          break;
+        }
+        u = orc_next_uniform(&s);
+      }
+      if (emit < 0) {
+        /* never deactivated: the packet ends at the interaction point */
+        mu = mu_new;
+        status = ORACLE_CAPPED;
+        break;
+      }
     }
+    double u_mu = orc_next_uniform(&s);
     mu = 2.0 * u_mu - 1.0;
     double D_new = doppler(r, mu, ct);
     nu = m->line_nu[emit] / D_new;
@@ -589,12 +624,24 @@ static int validate(const oracle_model* m) {
   for (int64_t k = 1; k < m->n_lines; ++k)
     if (!(m->line_nu[k] <= m->line_nu[k - 1])) return -1;
   if (!(m->nu_max > m->nu_min)) return -1;
-  if (m->line_mode == ORACLE_DOWNBRANCH) {
+  if (m->line_mode == ORACLE_DOWNBRANCH || m->line_mode == ORACLE_MACROATOM) {
     for (int64_t k = 0; k < m->n_lines; ++k) {
       int32_t up = m->line_upper[k];
       if (up < 0 || up >= m->n_levels) return -1;
       if (!(m->level_ptr[up + 1] > m->level_ptr[up])) return -1;
     }
+    const int64_t n_em = m->level_ptr[m->n_levels];
+    for (int64_t j = 0; j < n_em; ++j) {
+      int32_t t = m->em_line[j];
+      if (t >= m->n_lines) return -1;
+      if (t < 0) {
+        if (m->line_mode != ORACLE_MACROATOM) return -1;
+        int32_t lv = -t - 1;
+        if (lv >= m->n_levels || !(m->level_ptr[lv + 1] > m->level_ptr[lv])) return -1;
+      }
+    }
+  } else if (m->line_mode != ORACLE_SCATTER) {
+    return -1;
   }
   return 0;
 }

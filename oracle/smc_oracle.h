@@ -20,7 +20,11 @@
 extern "C" {
 #endif
 
-enum { ORACLE_SCATTER = 0, ORACLE_DOWNBRANCH = 1 };
+enum { ORACLE_SCATTER = 0, ORACLE_DOWNBRANCH = 1, ORACLE_MACROATOM = 2 };
+
+/* A macro atom that has made this many internal jumps without deactivating
+ * ends its packet as CAPPED. */
+#define ORACLE_MACRO_MAX_STEPS 100000
 
 enum { ORACLE_LIVE = 0, ORACLE_ESCAPED = 1, ORACLE_REABSORBED = 2, ORACLE_CAPPED = 3 };
 
@@ -54,13 +58,17 @@ typedef struct {
   int64_t n_lines;             /* L */
   const double* line_nu;       /* L line frequencies [Hz], non-increasing */
   const double* tau_sobolev;   /* S*L Sobolev optical depths, shell-major */
-  int32_t line_mode;           /* ORACLE_SCATTER or ORACLE_DOWNBRANCH */
-  /* downbranch emission tables (ignored in scatter mode) */
-  const int32_t* line_upper;   /* L: upper level of each line */
+  int32_t line_mode;           /* ORACLE_SCATTER, ORACLE_DOWNBRANCH or ORACLE_MACROATOM */
+  /* macro-atom tables (ignored in scatter mode): one row per level.  In
+   * downbranch mode every entry is an emission line and em_cum holds one
+   * row set; in macroatom mode an entry em_line = -(j+1) is an internal jump
+   * to level j, and em_cum holds one row set per shell (shell-major,
+   * S * level_ptr[n_levels] entries). */
+  const int32_t* line_upper;   /* L: upper level of each line (the activated level) */
   int32_t n_levels;
   const int64_t* level_ptr;    /* n_levels+1 row offsets */
-  const int32_t* em_line;      /* emission line index of each row entry */
-  const double* em_cum;        /* cumulative emission probability, last entry of a row is 1 */
+  const int32_t* em_line;      /* emission line index (>= 0) or internal jump (< 0) */
+  const double* em_cum;        /* cumulative probability, last entry of a row is 1 */
   /* emergent spectrum grid, linear in lab-frame frequency */
   double nu_min, nu_max;
   int32_t n_bins;

@@ -199,6 +199,11 @@ constexpr int kMaxShells = 4096;
 
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+uint64_t em_cum_entries(const smc_model_desc* d) {
+  return d->line_mode == SMC_MACROATOM ? (uint64_t)d->n_shells * (uint64_t)d->n_em
+                                       : (uint64_t)d->n_em;
+}
+
 int validate(const smc_model_desc* d) {
   if (!d) return fail(SMC_EINVAL, "null model description");
   if (d->n_shells < 1 || d->n_shells > kMaxShells)
@@ -236,22 +241,33 @@ int validate(const smc_model_desc* d) {
   for (int64_t i = 0; i < n_tau; ++i)
     if (!(d->tau_sobolev[i] >= 0.0) || !isfinite(d->tau_sobolev[i]))
       return fail(SMC_EINVAL, "tau_sobolev[%lld] must be finite and >= 0", (long long)i);
-  if (d->line_mode != SMC_SCATTER && d->line_mode != SMC_DOWNBRANCH)
+  if (d->line_mode != SMC_SCATTER && d->line_mode != SMC_DOWNBRANCH &&
+      d->line_mode != SMC_MACROATOM)
     return fail(SMC_EINVAL, "unknown line_mode %d", d->line_mode);
-  if (d->line_mode == SMC_DOWNBRANCH && d->n_lines > 0) {
+  if (d->line_mode != SMC_SCATTER && d->n_lines > 0) {
+    const bool macro = d->line_mode == SMC_MACROATOM;
     if (!d->line_upper || !d->level_ptr || !d->em_line || !d->em_cum || d->n_levels < 1)
-      return fail(SMC_EINVAL, "downbranch mode needs line_upper, level_ptr, em_line, em_cum");
+      return fail(SMC_EINVAL, "macro-atom modes need line_upper, level_ptr, em_line, em_cum");
     if (d->level_ptr[0] != 0 || d->level_ptr[d->n_levels] != d->n_em)
       return fail(SMC_EINVAL, "level_ptr must run from 0 to n_em");
     for (int32_t v = 0; v < d->n_levels; ++v)
       if (d->level_ptr[v + 1] < d->level_ptr[v])
         return fail(SMC_EINVAL, "level_ptr must be non-decreasing (level %d)", v);
     for (int64_t j = 0; j < d->n_em; ++j) {
-      if (d->em_line[j] < 0 || d->em_line[j] >= d->n_lines)
+      const int32_t t = d->em_line[j];
+      if (t >= d->n_lines || (t < 0 && !macro))
         return fail(SMC_EINVAL, "em_line[%lld] out of range", (long long)j);
+      if (t < 0) {
+        const int64_t lv = -(int64_t)t - 1;
+        if (lv >= d->n_levels || !(d->level_ptr[lv + 1] > d->level_ptr[lv]))
+          return fail(SMC_EINVAL, "em_line[%lld] jumps to level %lld, which has no row",
+                      (long long)j, (long long)lv);
+      }
+    }
+    const int64_t n_cum = macro ? (int64_t)d->n_shells * d->n_em : d->n_em;
+    for (int64_t j = 0; j < n_cum; ++j)
       if (!(d->em_cum[j] >= 0.0 && d->em_cum[j] <= 1.0))
         return fail(SMC_EINVAL, "em_cum[%lld] must lie in [0, 1]", (long long)j);
-    }
     for (int64_t k = 0; k < d->n_lines; ++k) {
       const int32_t u = d->line_upper[k];
       if (u < 0 || u >= d->n_levels)
@@ -282,11 +298,11 @@ smc::Layout layout_of(const smc_model_desc* d, uint64_t n_packets_max, uint32_t 
   const uint64_t Lp = (L + 3) / 4 * 4;  // rows padded for aligned 4-line loads
   l.line_nu = take(Lp * 8);
   l.tau = take(S * Lp * 8);
-  if (d->line_mode == SMC_DOWNBRANCH) {
+  if (d->line_mode != SMC_SCATTER) {
     l.line_upper = take(L * 4);
     l.level_ptr = take(((uint64_t)d->n_levels + 1) * 8);
     l.em_line = take((uint64_t)d->n_em * 4);
-    l.em_cum = take((uint64_t)d->n_em * 8);
+    l.em_cum = take(em_cum_entries(d) * 8);
   }
   l.raw = take((2 * S + NB) * 8);
   l.lsum = take(4 * 8);
@@ -418,7 +434,7 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
                              hipMemcpyHostToDevice, s),
             "upload tau_sobolev");
   }
-  if (d->line_mode == SMC_DOWNBRANCH && L > 0) {
+  if (d->line_mode != SMC_SCATTER && L > 0) {
     HIP_TRY(hipMemcpyAsync(base + lay.line_upper, d->line_upper, L * 4, hipMemcpyHostToDevice, s),
             "upload line_upper");
     HIP_TRY(hipMemcpyAsync(base + lay.level_ptr, d->level_ptr, ((uint64_t)d->n_levels + 1) * 8,
@@ -427,7 +443,7 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
     HIP_TRY(hipMemcpyAsync(base + lay.em_line, d->em_line, (uint64_t)d->n_em * 4,
                            hipMemcpyHostToDevice, s),
             "upload em_line");
-    HIP_TRY(hipMemcpyAsync(base + lay.em_cum, d->em_cum, (uint64_t)d->n_em * 8,
+    HIP_TRY(hipMemcpyAsync(base + lay.em_cum, d->em_cum, em_cum_entries(d) * 8,
                            hipMemcpyHostToDevice, s),
             "upload em_cum");
   }
@@ -447,6 +463,7 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
   dm.Lp = (int32_t)((d->n_lines + 3) / 4 * 4);
   dm.n_bins = d->n_bins;
   dm.mode = d->line_mode;
+  dm.n_em = d->line_mode != SMC_SCATTER ? d->n_em : 0;
   dm.t_exp = d->t_exp;
   dm.ct = 2.99792458e10 * d->t_exp;
   dm.nu_min = d->nu_min;
@@ -457,7 +474,7 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
   dm.volume = (const double*)(base + lay.volume);
   dm.line_nu = (const double*)(base + lay.line_nu);
   dm.tau = (const double*)(base + lay.tau);
-  if (d->line_mode == SMC_DOWNBRANCH) {
+  if (d->line_mode != SMC_SCATTER) {
     dm.line_upper = (const int32_t*)(base + lay.line_upper);
     dm.level_ptr = (const int64_t*)(base + lay.level_ptr);
     dm.em_line = (const int32_t*)(base + lay.em_line);

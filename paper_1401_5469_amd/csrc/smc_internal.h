@@ -44,6 +44,9 @@ struct LongState {
 // v-packets whose optical depth exceeds this are not counted
 constexpr double kTauVirtualMax = 30.0;
 constexpr uint32_t kMaxVirtual = 16;
+// a macro atom making this many internal jumps without deactivating ends its
+// packet as CAPPED
+constexpr uint32_t kMacroMaxSteps = 100000;
 
 // Luminosity sums are kept in fixed point (energy x 2^60 rounded to an
 // integer), so that their totals, and the T_inner update that follows from
@@ -70,6 +73,7 @@ struct DevModel {
   double ct;
   double nu_min, nu_max;
   uint64_t seed;
+  int64_t n_em;            // macro-atom table entries per probability set
   const double* r_bounds;  // [S+1] radii
   const double* n_e;       // [S]
   const double* volume;    // [S]

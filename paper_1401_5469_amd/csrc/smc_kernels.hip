@@ -342,7 +342,7 @@ __device__ __forceinline__ void lane_tally_flush(const DevModel& m, LaneTally& t
 __device__ __forceinline__ void lane_tally_end(const DevModel& m, LaneTally& t, int status,
                                                double nu, double E, uint64_t n_seg,
                                                uint64_t n_pass, uint32_t n_line,
-                                               uint32_t n_esc) {
+                                               uint32_t n_esc, bool dead_atom) {
   const unsigned long long q = (unsigned long long)__double2ll_rn(E * kLScale);
   if (status == SMC_ESCAPED) {
     unsafeAtomicAdd(&m.raw[2 * m.S + spectrum_bin(m, nu)], E);
@@ -355,12 +355,13 @@ __device__ __forceinline__ void lane_tally_end(const DevModel& m, LaneTally& t, 
     t.L[2] += q;
     t.c[SMC_C_CAPPED] += 1;
   }
-  // every segment ends in exactly one of line event, Thomson or crossing
+  // every segment ends in exactly one of line event, Thomson or crossing,
+  // except a last one whose macro atom never deactivated
   t.c[SMC_C_SEGMENTS] += n_seg;
   t.c[SMC_C_LINE_PASSES] += n_pass;
   t.c[SMC_C_LINE_EVENTS] += n_line;
   t.c[SMC_C_ESCATTERS] += n_esc;
-  t.c[SMC_C_CROSSINGS] += n_seg - n_line - n_esc;
+  t.c[SMC_C_CROSSINGS] += n_seg - n_line - n_esc - (dead_atom ? 1 : 0);
 }
 
 // the per-model values the segment loop of a lane reads
@@ -377,7 +378,9 @@ struct View {
   double ct, inv_ct;
   uint64_t max_segments, budget;
   int32_t S, L, Lp;
-  bool downbranch;
+  bool downbranch;         // emission rows shared by all shells, no internal jumps
+  bool macroatom;          // internal jumps, one probability set per shell
+  int64_t n_em;
   bool records;           // per-packet records (and their event hash) are kept
   uint32_t k0, k1, iter;  // random-number key and counter word
   uint32_t n_virtual;     // v-packets per packet launch
@@ -405,6 +408,8 @@ __device__ __forceinline__ View make_view(const DevModel& m, const DevIter& it) 
   v.L = m.L;
   v.Lp = m.Lp;
   v.downbranch = m.mode == SMC_DOWNBRANCH;
+  v.macroatom = m.mode == SMC_MACROATOM;
+  v.n_em = m.n_em;
   v.records = m.packets != nullptr && (it.flags & SMC_F_PACKETS);
   v.k0 = (uint32_t)m.seed;
   v.k1 = (uint32_t)(m.seed >> 32);
@@ -545,6 +550,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(LaunchArgs a) {
     }
 
     int status = SMC_LIVE;
+    bool dead_atom = false;  // the history ended in a macro atom that never deactivated
     if (n_seg >= v.max_segments) {
       status = SMC_CAPPED;
     } else if (n_seg >= v.budget && !handoff_tried) {
@@ -702,37 +708,67 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(LaunchArgs a) {
           const double u_branch = rng_next(g);
           nu_cmf_out = nu_hit;
           if (v.downbranch) {
-            const DevModel& m = ENTRY(a, model).m;
-            const int32_t up = m.line_upper[k];
-            const int64_t lo = m.level_ptr[up], hi = m.level_ptr[up + 1];
+            const int32_t up = v.line_upper[k];
+            const int64_t lo = v.level_ptr[up], hi = v.level_ptr[up + 1];
             int64_t j = lo;
-            while (j < hi - 1 && !(m.em_cum[j] > u_branch)) ++j;
-            emit = m.em_line[j];
+            while (j < hi - 1 && !(v.em_cum[j] > u_branch)) ++j;
+            emit = v.em_line[j];
             nu_cmf_out = v.line_nu[emit];
+          } else if (v.macroatom) {
+            // internal jumps until deactivation, one draw per step from this
+            // shell's rows (section 2.5)
+            const double* cum = v.em_cum + (size_t)sh * (size_t)v.n_em;
+            int32_t level = v.line_upper[k];
+            double u = u_branch;
+            uint32_t steps = 0;
+            emit = -1;
+            for (;;) {
+              const int64_t lo = v.level_ptr[level], hi = v.level_ptr[level + 1];
+              int64_t j = lo;
+              while (j < hi - 1 && !(cum[j] > u)) ++j;
+              const int32_t target = v.em_line[j];
+              if (target >= 0) {
+                emit = target;
+                break;
+              }
+              level = -target - 1;
+              if (++steps >= kMacroMaxSteps) break;
+              rng_topup(g, 2, sk);  // this step's draw and the direction draw
+              u = rng_next(g);
+            }
+            if (emit >= 0) nu_cmf_out = v.line_nu[emit];
           }
         }
-        const double mu_out = 2.0 * rng_next(g) - 1.0;
-        const double D_new = 1.0 - (mu_out * r_new) * v.inv_ct;
-        const double inv_D = recip(D_new);
-        r = r_new;
-        mu = mu_out;
-        nu = nu_cmf_out * inv_D;
-        E = e_cmf_ev * inv_D;
-        if (line_hit) {
-          next_line = emit + 1;
-          n_line += 1;
-          last_line = k;
-          if (v.records) hash = fnv_event(hash, EV_LINE, sh, k, emit);
+        if (emit < 0) {
+          // a macro atom that never deactivated: the packet ends here
+          r = r_new;
+          mu = mu_new;
+          status = SMC_CAPPED;
+          dead_atom = true;
         } else {
-          n_esc += 1;
-          if (v.records) hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
+          const double mu_out = 2.0 * rng_next(g) - 1.0;
+          const double D_new = 1.0 - (mu_out * r_new) * v.inv_ct;
+          const double inv_D = recip(D_new);
+          r = r_new;
+          mu = mu_out;
+          nu = nu_cmf_out * inv_D;
+          E = e_cmf_ev * inv_D;
+          if (line_hit) {
+            next_line = emit + 1;
+            n_line += 1;
+            last_line = k;
+            if (v.records) hash = fnv_event(hash, EV_LINE, sh, k, emit);
+          } else {
+            n_esc += 1;
+            if (v.records) hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
+          }
         }
       }
     }
 
     if (status != SMC_LIVE) {
       const DevModel& m = ENTRY(a, model).m;
-      lane_tally_end(m, tly, status, nu, E, n_seg, n_pass, n_line, n_esc);
+      lane_tally_end(m, tly, status, nu, E, n_seg, n_pass, n_line, n_esc, dead_atom);
       if (m.packets != nullptr && (ENTRY(a, model).it.flags & SMC_F_PACKETS))
         write_record(m, slot, pid, status, shell, nu, E, mu, r, mu0, nu_cmf0, n_seg, n_esc,
                      n_line, n_pass, hash, last_line);
@@ -1078,6 +1114,16 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
   int32_t c_shell = -1;
   double c_rin = 0.0, c_rout = 0.0, c_ne = 0.0;
 
+  // move the group's window of 2G draws to start at the next one
+  auto refill_draws = [&]() {
+    rb = draw >> 1;
+    const Block blk = stream_block(sk, rb + grp.lane);
+    ua = to_uniform(blk.a);
+    ub = to_uniform(blk.b);
+    la = -log(ua);
+    lb = -log(ub);
+  };
+
   for (;;) {
     bool fetched = false;
     if (!have && !drained) {
@@ -1143,7 +1189,7 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
                next_line, last_line, n_esc, n_line);
         settle(v.r_bounds, v.n_e, v.line_nu, v.tau, v.jblue, v.line_upper, v.level_ptr,
                v.em_line, v.em_cum, v.ct, v.inv_ct, v.max_segments, v.S, v.L, v.Lp,
-               (int)v.downbranch, (int)v.records, sk.k0, sk.k1, sk.iter);
+               (int)v.downbranch, (int)v.macroatom, (int)v.records, sk.k0, sk.k1, sk.iter);
       }
     }
     if (__ballot(have) == 0ull) break;  // every group drained
@@ -1162,20 +1208,14 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
 
     // ---- one flight segment of the group's history
     int status = SMC_LIVE;
+    bool dead_atom = false;  // the history ended in a macro atom that never deactivated
     do {
       if (n_seg >= v.max_segments) {
         status = SMC_CAPPED;
         break;
       }
       n_seg += 1;
-      if (draw + 3 > 2u * (rb + G)) {
-        rb = draw >> 1;
-        const Block blk = stream_block(sk, rb + grp.lane);
-        ua = to_uniform(blk.a);
-        ub = to_uniform(blk.b);
-        la = -log(ua);
-        lb = -log(ub);
-      }
+      if (draw + 3 > 2u * (rb + G)) refill_draws();
       const double tau0 = grp.bcast((draw & 1) ? lb : la, grp.uni((int)((draw >> 1) - rb)));
       draw += 1;
       const int sh = shell;
@@ -1333,6 +1373,40 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
             emit = v.em_line[j];
             nu_cmf_out = v.line_nu[emit];
             inv_cmf_out = recip(nu_cmf_out);
+          } else if (v.macroatom) {
+            // internal jumps until deactivation, one draw per step from this
+            // shell's rows (section 2.5)
+            const double* cum = v.em_cum + (size_t)sh * (size_t)v.n_em;
+            int32_t level = v.line_upper[k];
+            double u = u_branch;
+            uint32_t steps = 0;
+            emit = -1;
+            for (;;) {
+              const int64_t lo = v.level_ptr[level], hi = v.level_ptr[level + 1];
+              int64_t j = lo;
+              while (j < hi - 1 && !(cum[j] > u)) ++j;
+              const int32_t target = v.em_line[j];
+              if (target >= 0) {
+                emit = target;
+                break;
+              }
+              level = -target - 1;
+              if (++steps >= kMacroMaxSteps) break;
+              if (draw + 2 > 2u * (rb + G)) refill_draws();  // this step's and the direction's
+              u = grp.bcast((draw & 1) ? ub : ua, grp.uni((int)((draw >> 1) - rb)));
+              draw += 1;
+            }
+            if (emit < 0) {
+              // a macro atom that never deactivated: the packet ends here
+              double mu_new = (rmu + d) * recip(r_new);
+              mu = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
+              r = r_new;
+              status = SMC_CAPPED;
+              dead_atom = true;
+              break;
+            }
+            nu_cmf_out = v.line_nu[emit];
+            inv_cmf_out = recip(nu_cmf_out);
           }
         } else {
           nu_cmf_out = nu * D_old;
@@ -1370,7 +1444,7 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
       wshell = -1;
       if (leader) {
         const DevModel& m = ENTRY(a, model).m;
-        lane_tally_end(m, tly, status, nu, E, n_seg, n_pass, n_line, n_esc);
+        lane_tally_end(m, tly, status, nu, E, n_seg, n_pass, n_line, n_esc, dead_atom);
         if (v.records)
           write_record(m, slot, pid, status, shell, nu, E, mu, r, mu0, nu_cmf0, n_seg, n_esc,
                        n_line, n_pass, hash, last_line);

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmc.so")
 
 SMC_OK, SMC_EINVAL, SMC_ENOMEM, SMC_EDEVICE, SMC_EBUSY = 0, -1, -2, -3, -4
-SCATTER, DOWNBRANCH = 0, 1
+SCATTER, DOWNBRANCH, MACROATOM = 0, 1, 2
 LIVE, ESCAPED, REABSORBED, CAPPED = 0, 1, 2, 3
 F_JBLUE, F_PACKETS, F_TIMING = 1, 2, 4
 COUNTER_NAMES = ("segments", "line_passes", "line_events", "escatters", "escaped",
@@ -259,7 +259,7 @@ def _desc(model, keep: list) -> smc_model_desc:
     d.line_nu = _ptr(arr(model.line_nu if L else np.zeros(1), np.float64), _dp)
     d.tau_sobolev = _ptr(arr(model.tau_sobolev if L else np.zeros(1), np.float64), _dp)
     d.line_mode = int(model.line_mode)
-    if model.line_mode == DOWNBRANCH:
+    if model.line_mode in (DOWNBRANCH, MACROATOM):
         d.line_upper = _ptr(arr(model.line_upper, np.int32), _i32p)
         d.n_levels = int(model.n_levels)
         d.level_ptr = _ptr(arr(model.level_ptr, np.int64), _i64p)

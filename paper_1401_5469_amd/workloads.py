@@ -29,9 +29,12 @@ ANGSTROM = 1.0e-8  # cm
 DAY = 86400.0  # s
 KM = 1.0e5  # cm
 L_SUN = 3.828e33  # erg/s
+H = 6.62607015e-27  # erg s
+K_B = 1.380649e-16  # erg/K
 
 SCATTER = 0
 DOWNBRANCH = 1
+MACROATOM = 2
 
 # emergent spectrum grid: 1000 bins linear in frequency, 500-20000 Angstrom
 SPEC_NU_MIN = C_LIGHT / (20000.0 * ANGSTROM)
@@ -189,6 +192,131 @@ def synthetic_atom(rng, n_ions=30, n_levels_per_ion=40, n_lines=20_000):
     return dict(line_nu=_contig(nu, np.float64), line_upper=_contig(up_global, np.int32),
                 n_levels=int(n_levels), level_ptr=_contig(level_ptr, np.int64),
                 em_line=_contig(em_line, np.int32), em_cum=_contig(em_cum, np.float64))
+
+
+def _atom_levels(rng, n_ions, n_levels_per_ion, n_lines):
+    """Levels and lines of the synthetic atom (same draws as synthetic_atom):
+    level energies in frequency units, and per line (sorted by
+    non-increasing frequency) its frequency, global lower and upper level and
+    A_ul."""
+    nl = n_levels_per_ion
+    e = np.zeros((n_ions, nl))
+    for i in range(n_ions):
+        e[i, 1:] = np.sort(rng.uniform(0.0, C_LIGHT / (500.0 * ANGSTROM), nl - 1))
+    pairs = [(i, lo, up) for i in range(n_ions) for up in range(nl) for lo in range(up)]
+    pick = rng.choice(len(pairs), size=n_lines, replace=False)
+    ion = np.array([pairs[p][0] for p in pick])
+    lower = np.array([pairs[p][1] for p in pick])
+    upper = np.array([pairs[p][2] for p in pick])
+    nu = e[ion, upper] - e[ion, lower]
+    a_ul = 10.0 ** rng.uniform(5.0, 9.0, n_lines)
+    order = np.argsort(-nu, kind="stable")
+    nu, ion, lower, upper, a_ul = nu[order], ion[order], lower[order], upper[order], a_ul[order]
+    return (e.reshape(-1), nu, (ion * nl + lower).astype(np.int32),
+            (ion * nl + upper).astype(np.int32), a_ul, n_ions * nl)
+
+
+def planck_nu(nu, T):
+    """Planck function B_nu(T) [erg s^-1 cm^-2 Hz^-1 sr^-1]."""
+    x = H * nu / (K_B * T)
+    return 2.0 * H * nu ** 3 / C_LIGHT ** 2 / np.expm1(x)
+
+
+def macroatom_tables(level_e, nu, lower, upper, a_ul, n_levels, tau, W, T_R):
+    """Macro-atom transition probabilities per shell in the form of Lucy
+    (2002, 2003) for bound-bound radiative processes only: from level i,
+    radiative deactivation in a downward line i->l with weight
+    A_il beta (e_i - e_l), an internal downward jump to l with weight
+    A_il beta e_l, an internal upward jump along an upward line i->u with
+    weight B_iu J_b beta e_i, where beta = (1 - exp(-tau_S)) / tau_S is the
+    Sobolev escape probability of the line in the shell, J_b = W B_nu(T_R)
+    the (dilute blackbody) radiation field at the line and B_iu = A_ui c^2 /
+    (2 h nu^3) (equal statistical weights).  This is the plasma side of the
+    method: here it only prepares the transport's input tables.
+
+    Returns level_ptr [n_levels+1], em_line [n_em] (line index for a
+    deactivation, -(j+1) for an internal jump to level j) and em_cum
+    [S, n_em] (cumulative within each level's row, last entry 1)."""
+    S, L = tau.shape
+    # rows: per level its downward lines (deactivation, then internal down)
+    # and its upward lines (internal up)
+    entries = [[] for _ in range(n_levels)]
+    for k in range(L):
+        entries[upper[k]].append(("emit", k))
+    for k in range(L):
+        entries[upper[k]].append(("down", k))
+    for k in range(L):
+        entries[lower[k]].append(("up", k))
+    level_ptr = np.zeros(n_levels + 1, dtype=np.int64)
+    level_ptr[1:] = np.cumsum([len(x) for x in entries])
+    n_em = int(level_ptr[-1])
+    em_line = np.zeros(n_em, dtype=np.int32)
+    kind = np.zeros(n_em, dtype=np.int8)
+    line_of = np.zeros(n_em, dtype=np.int64)
+    row_level = np.zeros(n_em, dtype=np.int64)
+    j = 0
+    for lev in range(n_levels):
+        for what, k in entries[lev]:
+            line_of[j] = k
+            row_level[j] = lev
+            if what == "emit":
+                em_line[j] = k
+                kind[j] = 0
+            elif what == "down":
+                em_line[j] = -(int(lower[k]) + 1)
+                kind[j] = 1
+            else:
+                em_line[j] = -(int(upper[k]) + 1)
+                kind[j] = 2
+            j += 1
+    with np.errstate(divide="ignore", invalid="ignore"):
+        beta = np.where(tau > 1e-12, -np.expm1(-tau) / tau, 1.0)  # [S, L]
+    b_lu = a_ul * C_LIGHT ** 2 / (2.0 * H * nu ** 3)
+    em_cum = np.zeros((S, n_em), dtype=np.float64)
+    e_i = level_e[row_level]
+    e_lo = level_e[lower[line_of]]
+    for s in range(S):
+        jb = W[s] * planck_nu(nu, T_R[s])
+        bt = beta[s, line_of]
+        wgt = np.where(kind == 0, a_ul[line_of] * bt * (e_i - e_lo),
+                       np.where(kind == 1, a_ul[line_of] * bt * e_lo,
+                                b_lu[line_of] * jb[line_of] * bt * e_i))
+        for lev in range(n_levels):
+            a, b = level_ptr[lev], level_ptr[lev + 1]
+            if b > a:
+                c = np.cumsum(wgt[a:b])
+                em_cum[s, a:b] = c / c[-1] if c[-1] > 0 else np.linspace(1.0 / (b - a), 1.0,
+                                                                          b - a)
+                em_cum[s, b - 1] = 1.0
+    return level_ptr, em_line, em_cum
+
+
+def macroatom_model(seed: int = 0, n_shells: int = 30, n_ions: int = 30,
+                    n_levels_per_ion: int = 40, n_lines: int = 20_000, T_R: float = 10000.0):
+    """Macroatom mode: the synthetic atom of the downbranch workload with
+    Lucy-form transition probabilities per shell (W geometric at the shell
+    centre, T_R uniform), tau log-normal as the paper-scale model."""
+    rng = np.random.default_rng(seed)
+    v, t, n_e = shells(n_shells, 10000.0, 25000.0, 13.0)
+    level_e, nu, lower, upper, a_ul, n_levels = _atom_levels(rng, n_ions, n_levels_per_ion,
+                                                              n_lines)
+    tau = tau_log_normal(rng, n_shells, n_lines)
+    q = v[0] / (0.5 * (v[:-1] + v[1:]))
+    W = 0.5 * (1.0 - np.sqrt(1.0 - q * q))
+    level_ptr, em_line, em_cum = macroatom_tables(level_e, nu, lower, upper, a_ul, n_levels, tau,
+                                                  W, np.full(n_shells, T_R))
+    return Model(v_bounds=v, t_exp=t, n_e=n_e, line_nu=_contig(nu, np.float64),
+                 tau_sobolev=tau, line_mode=MACROATOM, line_upper=_contig(upper, np.int32),
+                 n_levels=int(n_levels), level_ptr=_contig(level_ptr, np.int64),
+                 em_line=_contig(em_line, np.int32), em_cum=_contig(em_cum, np.float64),
+                 seed=seed)
+
+
+def config_macroatom(seed: int = 0, n_packets: int = 500_000) -> Workload:
+    """Macroatom mode at the size of the downbranch workload: 30 shells,
+    30 ions x 40 levels, 2e4 lines, T_i = 9000 K."""
+    return Workload("macroatom-30shell-20kline", macroatom_model(seed), T_inner=9000.0,
+                    n_packets=n_packets, n_iterations=1)
 
 
 def config3(seed: int = 0, n_packets: int = 500_000, n_lines: int = 20_000,

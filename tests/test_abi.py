@@ -140,6 +140,28 @@ def test_host_validation_rejects_bad_downbranch_tables(lib):
     assert "em_line" in _expect_invalid(bad)
 
 
+def test_host_validation_of_macroatom_tables(lib):
+    m = W.macroatom_model(seed=1, n_shells=4, n_ions=3, n_levels_per_ion=10, n_lines=100)
+    base = smc.workspace_bytes(m, 10, 0)
+    assert base > 0
+    bad = W.Model(**{**m.__dict__})
+    el = m.em_line.copy()
+    el[np.nonzero(el < 0)[0][0]] = -(m.n_levels + 5)
+    bad.em_line = el
+    assert "no row" in _expect_invalid(bad)
+    # internal jumps are not allowed in downbranch mode
+    bad = W.Model(**{**m.__dict__})
+    bad.line_mode = W.DOWNBRANCH
+    bad.em_cum = np.ascontiguousarray(m.em_cum[0])
+    assert "em_line" in _expect_invalid(bad)
+    # one probability set per shell
+    bad = W.Model(**{**m.__dict__})
+    ec = m.em_cum.copy()
+    ec[-1, 3] = 1.5
+    bad.em_cum = ec
+    assert "em_cum" in _expect_invalid(bad)
+
+
 def test_no_gpu_means_a_loud_error_not_a_fallback(lib):
     import torch
     if torch.cuda.is_available():
