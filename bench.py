@@ -8,6 +8,8 @@
     python bench.py --workload virtual [--n-virtual 3]
                                          (the final spectrum iteration with
                                           virtual packets, section 2.9)
+    python bench.py --workload macroatom (macroatom vs downbranch line modes
+                                          on the 30-shell 2e4-line atom)
 
 One step is one Monte Carlo iteration of the paper-scale scatter model
 (20 shells 10000-25000 km/s at 13 d, 3e5 lines, 1e6 packets; Kerzendorf & Sim
@@ -54,7 +56,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-jblue", action="store_true")
     ap.add_argument("--workload", default="paper-scale",
-                    choices=["paper-scale", "batched", "served", "copy", "virtual"])
+                    choices=["paper-scale", "batched", "served", "copy", "virtual",
+                             "macroatom"])
     ap.add_argument("--n-virtual", type=int, default=3,
                     help="virtual packets per packet launch in the virtual mode")
     ap.add_argument("--models", type=int, default=64, help="models in the batched mix")
@@ -163,6 +166,63 @@ def virtual(args):
                     "L_virtual": v["L_virtual"], "L_emitted": v["L_emitted"]},
         "plain_final_iteration_ms": out_runs[0]["wall_ms"],
         "cost_ratio": v["wall_ms"] / out_runs[0]["wall_ms"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def macroatom(args):
+    """One iteration of 5e5 packets through the 30-shell model with the
+    synthetic 30-ion atom (2e4 lines) in macroatom mode (Lucy-form internal
+    jumps, per-shell tables) and in downbranch mode (the same-size
+    downbranch workload): interactions/s of each and the cost ratio (the
+    paper quotes about +10% for macroatom over downbranch)."""
+    import numpy as np
+    import torch
+
+    from paper_1401_5469_amd import smc
+    from paper_1401_5469_amd import workloads as W
+
+    ctx = smc.Context(0)
+    res = {}
+    for name, w in (("macroatom", W.config_macroatom()), ("downbranch", W.config3())):
+        N = w.n_packets
+        model = smc.Model(ctx, w.model, N, flags=smc.F_JBLUE)
+        for _ in range(args.warmup):
+            model.run_iteration(N, w.T_inner, flags=smc.F_JBLUE)
+        torch.cuda.synchronize()
+        walls, inter = [], []
+        for i in range(args.steps):
+            t0 = time.perf_counter()
+            model.run_iteration(N, w.T_inner, iteration=i, flags=smc.F_JBLUE)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+            c = model.read_counters()
+            inter.append(c["line_events"] + c["escatters"])
+        wall = float(np.mean(walls))
+        res[name] = dict(workload=w.name, packets=N, ms=wall * 1e3,
+                         interactions_per_s=float(np.mean(inter)) / wall,
+                         packets_per_s=N / wall, counters=c)
+        print(f"# {name}: {wall * 1e3:.2f} ms per iteration", file=sys.stderr, flush=True)
+        model.free()
+    ma = res["macroatom"]
+    out = {
+        "metric": "packet-interactions/sec (macroatom mode)",
+        "value": ma["interactions_per_s"],
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ma["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": ma["workload"], "packets": ma["packets"], "shells": 30,
+                   "lines": 20000, "levels": 1200},
+        "macroatom": ma,
+        "downbranch": res["downbranch"],
+        "ms_ratio_macroatom_over_downbranch": ma["ms"] / res["downbranch"]["ms"],
     }
     print(json.dumps(out), flush=True)
 
@@ -378,6 +438,10 @@ def main():
         return copy_reference(args)
     if args.workload == "virtual":
         return virtual(args)
+    if args.workload == "macroatom":
+        if args.steps == 10:
+            args.steps = 3
+        return macroatom(args)
 
     import numpy as np
     import torch
