@@ -23,7 +23,8 @@ struct smc_ctx {
   int device;
   int n_cu;
   int transport_blocks_per_cu[2];  // occupancy of the lane-per-packet kernel (single, multi)
-  int long_blocks_per_cu[2][3];    // occupancy of the group-per-packet kernel (16, 32, 64 lanes)
+  int long_blocks_per_cu[2][3][2];  // occupancy of the group-per-packet kernel
+                                    // [multi][16, 32, 64 lanes][plain, extended]
   smc::BatchEntry* host_table[kBatchSlots];   // pinned
   smc::BatchEntry* dev_table[kBatchSlots];
   unsigned long long* dev_ctr[kBatchSlots];   // launch-wide control blocks (kCtlBytes)
@@ -110,8 +111,8 @@ void release_ctx(smc_ctx* c) {
 int lanes_of(const smc_tune& t) { return t.long_lanes == 0 ? kDefaultLongLanes : (int)t.long_lanes; }
 int lanes_index(int lanes) { return lanes == 16 ? 0 : (lanes == 32 ? 1 : 2); }
 
-int default_long_waves(const smc_ctx* c, bool multi, const smc_tune& t) {
-  const int occ = c->long_blocks_per_cu[multi][lanes_index(lanes_of(t))];
+int default_long_waves(const smc_ctx* c, bool multi, const smc_tune& t, bool ext) {
+  const int occ = c->long_blocks_per_cu[multi][lanes_index(lanes_of(t))][ext];
   return occ < kDefaultLongWaves ? occ : kDefaultLongWaves;
 }
 
@@ -134,7 +135,7 @@ uint32_t budget_of(const smc_tune& t) {
 
 // launch shape from the tuning (0 = occupancy default), capped by the work
 smc::Shape shape_of(const smc_ctx* c, const smc_tune& t, bool multi, uint64_t n_work,
-                    bool handoff) {
+                    bool handoff, bool ext) {
   smc::Shape sh;
   const int block = smc::transport_block_threads();
   uint64_t want = (n_work + block - 1) / block;
@@ -143,12 +144,14 @@ smc::Shape shape_of(const smc_ctx* c, const smc_tune& t, bool multi, uint64_t n_
   sh.transport_grid = (int)(want > cap ? cap : want);
   uint64_t lgrid = 0;
   if (handoff && n_work > 0) {
-    const int lper = t.long_waves_per_cu > 0 ? t.long_waves_per_cu : default_long_waves(c, multi, t);
+    const int lper =
+        t.long_waves_per_cu > 0 ? t.long_waves_per_cu : default_long_waves(c, multi, t, ext);
     lgrid = (uint64_t)c->n_cu * (uint64_t)lper;
     if (lgrid > n_work) lgrid = n_work;
   }
   sh.long_grid = (int)lgrid;
   sh.long_lanes = lanes_of(t);
+  sh.long_ext = ext;
   return sh;
 }
 
@@ -361,12 +364,14 @@ int smc_ctx_create(smc_ctx** out, int hip_device) {
     }
     c->transport_blocks_per_cu[multi] = occ > 0 ? occ : 1;
     for (int li = 0; li < 3; ++li) {
-      e = smc::long_occupancy(multi != 0, 16 << li, &occ);
-      if (e != hipSuccess) {
-        release_ctx(c);
-        return hip_fail(e, "occupancy query");
+      for (int ext = 0; ext < 2; ++ext) {
+        e = smc::long_occupancy(multi != 0, 16 << li, ext != 0, &occ);
+        if (e != hipSuccess) {
+          release_ctx(c);
+          return hip_fail(e, "occupancy query");
+        }
+        c->long_blocks_per_cu[multi][li][ext] = occ > 0 ? occ : 1;
       }
-      c->long_blocks_per_cu[multi][li] = occ > 0 ? occ : 1;
     }
   }
   for (int i = 0; i < kBatchSlots; ++i) {
@@ -540,7 +545,8 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   a.hot = hot_of(m->ctx);
   const smc::Shape sh =
       shape_of(m->ctx, m->tune, false, a.total_work,
-               a.single.it.long_budget > 0 || a.single.it.n_virtual > 0);
+               a.single.it.long_budget > 0 || a.single.it.n_virtual > 0,
+               a.single.it.n_virtual > 0 || m->dev.mode == SMC_MACROATOM);
   HIP_TRY(smc::launch_iteration(a, false, sh, jblue_entries(m, p->flags),
                                 timed ? m->ev_start : nullptr, timed ? m->ev_stop : nullptr, s),
           "iteration launch");
@@ -571,7 +577,7 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
   smc::BatchEntry* tab = ctx->host_table[slot];
   uint64_t work = 0, max_jb = 0;
   uint32_t max_lines = 0;
-  bool any_virtual = false;
+  bool any_virtual = false, any_ext = false;
   for (int k = 0; k < n_models; ++k) {
     smc_model* m = models[k];
     if (!m) return fail(SMC_EINVAL, "model %d is null", k);
@@ -590,6 +596,7 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
     work += tab[k].it.n_work;
     if ((uint32_t)m->dev.L > max_lines) max_lines = (uint32_t)m->dev.L;
     if (tab[k].it.n_virtual > 0) any_virtual = true;
+    if (tab[k].it.n_virtual > 0 || m->dev.mode == SMC_MACROATOM) any_ext = true;
     const uint64_t jb = jblue_entries(m, params[k].flags);
     if (jb > max_jb) max_jb = jb;
   }
@@ -611,7 +618,7 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
   a.order_hist = (unsigned int*)(ctx->dev_ctr[slot] + 4);
   a.max_lines = max_lines;
   a.hot = hot_of(ctx);
-  const smc::Shape sh = shape_of(ctx, t, true, work, budget > 0 || any_virtual);
+  const smc::Shape sh = shape_of(ctx, t, true, work, budget > 0 || any_virtual, any_ext);
   HIP_TRY(smc::launch_iteration(a, true, sh, max_jb, timed ? ctx->ev_start : nullptr,
                                 timed ? ctx->ev_stop : nullptr, s),
           "batch launch");
@@ -795,7 +802,8 @@ int smc_model_get_tune(smc_model* m, smc_tune* t) {
   *t = m->tune;
   if (t->blocks_per_cu == 0) t->blocks_per_cu = m->ctx->transport_blocks_per_cu[0];
   if (t->long_lanes == 0) t->long_lanes = kDefaultLongLanes;
-  if (t->long_waves_per_cu == 0) t->long_waves_per_cu = default_long_waves(m->ctx, false, *t);
+  if (t->long_waves_per_cu == 0)
+    t->long_waves_per_cu = default_long_waves(m->ctx, false, *t, m->dev.mode == SMC_MACROATOM);
   if (t->long_budget == 0) t->long_budget = kDefaultLongBudget;
   return ok();
 }
@@ -871,7 +879,7 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
     return hip_fail(e, "graph table allocation");
   }
   std::vector<uint64_t> work(n_iter, 0), max_jb(n_iter, 0);
-  std::vector<char> any_virtual(n_iter, 0);
+  std::vector<char> any_virtual(n_iter, 0), any_ext(n_iter, 0);
   uint32_t max_lines = 0;
   for (int k = 0; k < n_models; ++k)
     if ((uint32_t)models[k]->dev.L > max_lines) max_lines = (uint32_t)models[k]->dev.L;
@@ -893,6 +901,7 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
       be.long_begin = 0;
       work[i] += be.it.n_work;
       if (be.it.n_virtual > 0) any_virtual[i] = 1;
+      if (be.it.n_virtual > 0 || models[k]->dev.mode == SMC_MACROATOM) any_ext[i] = 1;
       const uint64_t jb = jblue_entries(models[k], p.flags);
       if (jb > max_jb[i]) max_jb[i] = jb;
       if (i == n_iter - 1) g->last.push_back(p);
@@ -936,7 +945,8 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
     }
     a.max_lines = max_lines;
     a.hot = hot_of(ctx);
-    const smc::Shape sh = shape_of(ctx, t, multi, work[i], budget > 0 || any_virtual[i]);
+    const smc::Shape sh =
+        shape_of(ctx, t, multi, work[i], budget > 0 || any_virtual[i], any_ext[i]);
     le = smc::launch_iteration(a, multi, sh, max_jb[i], nullptr, nullptr, s);
   }
   e = hipStreamEndCapture(s, &g->graph);

@@ -148,6 +148,8 @@ struct Shape {
   int transport_grid;
   int long_grid;   // wavefronts of the group-per-packet kernel
   int long_lanes;  // lanes per handed-off history: 16, 32 or 64
+  bool long_ext;   // some model of the launch runs v-packets or the macroatom mode: the
+                   // group kernel variant with that code (more registers)
 };
 
 // Host-side launchers implemented in smc_kernels.hip.  `multi` selects the
@@ -157,7 +159,7 @@ hipError_t launch_iteration(const LaunchArgs& a, bool multi, const Shape& shape,
                             uint64_t max_jblue, hipEvent_t ev_start, hipEvent_t ev_stop,
                             hipStream_t s);
 hipError_t transport_occupancy(bool multi, int* blocks_per_cu);
-hipError_t long_occupancy(bool multi, int lanes, int* blocks_per_cu);
+hipError_t long_occupancy(bool multi, int lanes, bool ext, int* blocks_per_cu);
 int transport_block_threads();
 int long_block_threads();
 constexpr int kMaxBatchModels = 1024;

@@ -1075,7 +1075,7 @@ constexpr int kLongBlock = 64;
 // live lines below it), and J_blue updates leave from every reached lane
 // together.  A group whose packet ends takes the next one from the hand-off
 // queue while the other groups of its wavefront keep marching.
-template <bool kMulti, int G>
+template <bool kMulti, int G, bool kExt>
 __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
   constexpr int kGroups = kWave / G;
   __shared__ LaneTally tly_all[kGroups];  // one tally slot per group, its lane 0 writes it
@@ -1179,7 +1179,7 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
         wshell = -1;
         c_shell = -1;
         have = true;
-        if (v.n_virtual && st.n_seg == 0)
+        if (kExt && v.n_virtual && st.n_seg == 0)
           launch_virtual(grp, v, ENTRY(a, model).m, sk, 0, true, r, 0, next_line, nu_cmf0,
                          v.e_unit, tly, leader);
         // wait for the history's loads here, once per history, so that the
@@ -1373,7 +1373,7 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
             emit = v.em_line[j];
             nu_cmf_out = v.line_nu[emit];
             inv_cmf_out = recip(nu_cmf_out);
-          } else if (v.macroatom) {
+          } else if (kExt && v.macroatom) {
             // internal jumps until deactivation, one draw per step from this
             // shell's rows (section 2.5)
             const double* cum = v.em_cum + (size_t)sh * (size_t)v.n_em;
@@ -1431,7 +1431,7 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
           n_esc += 1;
           if (v.records) hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
         }
-        if (v.n_virtual)
+        if (kExt && v.n_virtual)
           launch_virtual(grp, v, ENTRY(a, model).m, sk, (uint64_t)n_esc + n_line, false, r, sh,
                          next_line, nu_cmf_out, e_cmf_ev, tly, leader);
       }
@@ -1557,25 +1557,47 @@ hipError_t transport_occupancy(bool multi, int* blocks_per_cu) {
                                                               transport_lds_bytes(false, 1));
 }
 
-template <bool kMulti>
+template <bool kMulti, bool kExt>
 static hipError_t long_occupancy_of(int lanes, int* blocks_per_cu) {
   switch (lanes) {
     case 16:
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, long_kernel<kMulti, 16>,
-                                                          kLongBlock, 0);
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          blocks_per_cu, long_kernel<kMulti, 16, kExt>, kLongBlock, 0);
     case 32:
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, long_kernel<kMulti, 32>,
-                                                          kLongBlock, 0);
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          blocks_per_cu, long_kernel<kMulti, 32, kExt>, kLongBlock, 0);
     case 64:
-      return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, long_kernel<kMulti, 64>,
-                                                          kLongBlock, 0);
+      return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          blocks_per_cu, long_kernel<kMulti, 64, kExt>, kLongBlock, 0);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t long_occupancy(bool multi, int lanes, int* blocks_per_cu) {
-  return multi ? long_occupancy_of<true>(lanes, blocks_per_cu)
-               : long_occupancy_of<false>(lanes, blocks_per_cu);
+hipError_t long_occupancy(bool multi, int lanes, bool ext, int* blocks_per_cu) {
+  if (multi)
+    return ext ? long_occupancy_of<true, true>(lanes, blocks_per_cu)
+               : long_occupancy_of<true, false>(lanes, blocks_per_cu);
+  return ext ? long_occupancy_of<false, true>(lanes, blocks_per_cu)
+             : long_occupancy_of<false, false>(lanes, blocks_per_cu);
+}
+
+template <bool kMulti, bool kExt>
+static hipError_t launch_long(int lanes, dim3 grid, dim3 block, const LaunchArgs& a,
+                              hipStream_t s) {
+  switch (lanes) {
+    case 16:
+      hipLaunchKernelGGL((long_kernel<kMulti, 16, kExt>), grid, block, 0, s, a);
+      break;
+    case 32:
+      hipLaunchKernelGGL((long_kernel<kMulti, 32, kExt>), grid, block, 0, s, a);
+      break;
+    case 64:
+      hipLaunchKernelGGL((long_kernel<kMulti, 64, kExt>), grid, block, 0, s, a);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <bool kMulti>
@@ -1613,19 +1635,11 @@ static hipError_t launch_all(const LaunchArgs& a, const Shape& shape, uint64_t m
       hipLaunchKernelGGL(order_place_kernel<kMulti>, dim3(og), dim3(256), 0, s, a);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       const dim3 grid(shape.long_grid), block(kLongBlock);
-      switch (shape.long_lanes) {
-        case 16:
-          hipLaunchKernelGGL((long_kernel<kMulti, 16>), grid, block, 0, s, a);
-          break;
-        case 32:
-          hipLaunchKernelGGL((long_kernel<kMulti, 32>), grid, block, 0, s, a);
-          break;
-        case 64:
-          hipLaunchKernelGGL((long_kernel<kMulti, 64>), grid, block, 0, s, a);
-          break;
-        default:
-          return hipErrorInvalidValue;
-      }
+      if (shape.long_ext)
+        e = launch_long<kMulti, true>(shape.long_lanes, grid, block, a, s);
+      else
+        e = launch_long<kMulti, false>(shape.long_lanes, grid, block, a, s);
+      if (e != hipSuccess) return e;
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }
