@@ -382,3 +382,159 @@ def small_downbranch_model(seed: int = 0, n_shells: int = 6, n_ions: int = 4,
     tau = tau_log_normal(rng, n_shells, n_lines)
     return Model(v_bounds=v, t_exp=t, n_e=n_e, tau_sobolev=tau, line_mode=DOWNBRANCH,
                  seed=seed, **atom)
+
+
+# ---------------------------------------------------------------------------
+# plasma inputs: a synthetic atom (elements, ion stages, levels, lines with
+# oscillator strengths) and element number densities per shell
+# ---------------------------------------------------------------------------
+EV = 1.602176634e-12  # erg
+M_U = 1.66053906660e-24  # g
+
+ION_LTE, ION_NEBULAR = 0, 1
+EXC_LTE, EXC_DILUTE_LTE = 0, 1
+
+# (atomic number, mass number, first ionization energy [eV]) of the
+# synthetic elements; the energies of the higher stages follow _CHI_SCALE
+PLASMA_ELEMENTS = ((8, 16.0, 13.62), (12, 24.3, 7.65), (14, 28.1, 8.15), (16, 32.1, 10.36),
+                   (20, 40.1, 6.11), (26, 55.8, 7.90), (27, 58.9, 7.88), (28, 58.7, 7.64))
+_CHI_SCALE = (1.0, 2.0, 3.9, 5.8, 8.0, 10.5, 13.0, 16.0)
+
+
+@dataclasses.dataclass
+class PlasmaAtom:
+    """Atomic data of the plasma update, in the layout both implementations
+    consume.  Ions of an element are consecutive, stage j (charge j) at
+    element_ion_ptr[e] + j; levels of an ion are consecutive, its ground
+    state (energy 0, metastable) first."""
+
+    element_ion_ptr: np.ndarray  # [E+1] int32
+    ion_chi: np.ndarray  # [n_ions] ionization energy from this stage to the next [erg]
+    ion_zeta: np.ndarray  # [n_ions] fraction of recombinations into this stage's ground state
+    ion_level_ptr: np.ndarray  # [n_ions+1] int32
+    level_energy: np.ndarray  # [n_levels] excitation energy above the ion's ground state [erg]
+    level_g: np.ndarray  # [n_levels] statistical weight
+    level_metastable: np.ndarray  # [n_levels] uint8
+    line_lower: np.ndarray  # [L] int32, global level index
+    line_upper: np.ndarray  # [L] int32
+    line_f: np.ndarray  # [L] absorption oscillator strength
+
+    @property
+    def n_elements(self) -> int:
+        return int(self.element_ion_ptr.shape[0] - 1)
+
+    @property
+    def n_ions(self) -> int:
+        return int(self.ion_chi.shape[0])
+
+    @property
+    def n_levels(self) -> int:
+        return int(self.level_energy.shape[0])
+
+    def level_ion(self) -> np.ndarray:
+        return np.repeat(np.arange(self.n_ions, dtype=np.int32), np.diff(self.ion_level_ptr))
+
+    def nbytes(self) -> int:
+        return sum(getattr(self, f.name).nbytes for f in dataclasses.fields(self))
+
+
+@dataclasses.dataclass
+class PlasmaSpec:
+    atom: PlasmaAtom
+    number_density: np.ndarray  # [S, E] element number densities [cm^-3]
+
+
+def synthetic_plasma_atom(rng, n_elements: int = 8, n_stages: int = 5,
+                          n_levels_per_ion: int = 60, n_lines: int = 20_000,
+                          lam=(300.0, 25000.0)):
+    """Synthetic atom: the first n_elements of PLASMA_ELEMENTS with stages
+    0 .. n_stages-1 each; ionization energies chi_0 * _CHI_SCALE[j]; per ion
+    the ground state plus n_levels_per_ion-1 levels with energies U(0,
+    0.95 chi) (sorted), statistical weights uniform in 1..9 (ground 1..5),
+    metastable with probability 0.25 below 0.3 chi and 0.02 above; zeta
+    U(0.1, 0.9).  Lines: n_lines distinct (ion, lower < upper) pairs whose
+    wavelength h c / (e_u - e_l) lies in [lam] Angstrom, drawn without
+    replacement, f log-uniform in [1e-4, 1].  Returns the atom with lines
+    sorted by non-increasing frequency, and the line frequencies."""
+    elems = PLASMA_ELEMENTS[:n_elements]
+    nl = n_levels_per_ion
+    n_ions = n_elements * n_stages
+    chi = np.array([z[2] * _CHI_SCALE[j] * EV for z in elems for j in range(n_stages)])
+    zeta = rng.uniform(0.1, 0.9, n_ions)
+    energy = np.zeros((n_ions, nl))
+    g = np.zeros((n_ions, nl))
+    meta = np.zeros((n_ions, nl), dtype=np.uint8)
+    for i in range(n_ions):
+        energy[i, 1:] = np.sort(rng.uniform(0.0, 0.95 * chi[i], nl - 1))
+        g[i, 0] = rng.integers(1, 6)
+        g[i, 1:] = rng.integers(1, 10, nl - 1)
+        meta[i, 0] = 1
+        low = energy[i, 1:] < 0.3 * chi[i]
+        u = rng.uniform(0.0, 1.0, nl - 1)
+        meta[i, 1:] = np.where(low, u < 0.25, u < 0.02)
+    lo_i, up_i = np.triu_indices(nl, k=1)
+    ion = np.repeat(np.arange(n_ions), lo_i.size)
+    lower = np.tile(lo_i, n_ions)
+    upper = np.tile(up_i, n_ions)
+    de = energy[ion, upper] - energy[ion, lower]
+    with np.errstate(divide="ignore"):
+        lam_aa = np.where(de > 0.0, H * C_LIGHT / np.where(de > 0.0, de, 1.0) / ANGSTROM, np.inf)
+    ok = np.flatnonzero((lam_aa >= lam[0]) & (lam_aa <= lam[1]))
+    if ok.size < n_lines:
+        raise ValueError(f"only {ok.size} level pairs in the wavelength window")
+    pick = np.sort(rng.choice(ok, size=n_lines, replace=False))
+    ion, lower, upper = ion[pick], lower[pick], upper[pick]
+    f = 10.0 ** rng.uniform(-4.0, 0.0, n_lines)
+    nu = (energy[ion, upper] - energy[ion, lower]) / H
+    order = np.argsort(-nu, kind="stable")
+    ion, lower, upper, f, nu = ion[order], lower[order], upper[order], f[order], nu[order]
+    atom = PlasmaAtom(
+        element_ion_ptr=_contig(np.arange(n_elements + 1) * n_stages, np.int32),
+        ion_chi=_contig(chi, np.float64), ion_zeta=_contig(zeta, np.float64),
+        ion_level_ptr=_contig(np.arange(n_ions + 1) * nl, np.int32),
+        level_energy=_contig(energy.reshape(-1), np.float64),
+        level_g=_contig(g.reshape(-1), np.float64),
+        level_metastable=_contig(meta.reshape(-1), np.uint8),
+        line_lower=_contig(ion * nl + lower, np.int32),
+        line_upper=_contig(ion * nl + upper, np.int32),
+        line_f=_contig(f, np.float64))
+    return atom, _contig(nu, np.float64)
+
+
+def element_densities(rho, n_elements: int):
+    """Number densities [S, E] of equal mass fractions of the first
+    n_elements of PLASMA_ELEMENTS at mass densities rho [S]."""
+    mass = np.array([z[1] for z in PLASMA_ELEMENTS[:n_elements]])
+    return _contig(np.asarray(rho)[:, None] / n_elements / (mass[None, :] * M_U), np.float64)
+
+
+def plasma_model(seed: int = 0, n_shells: int = 20, n_elements: int = 8, n_stages: int = 5,
+                 n_levels_per_ion: int = 60, n_lines: int = 20_000,
+                 v_lo: float = 10000.0, v_hi: float = 25000.0, t_exp_days: float = 13.0,
+                 rho_inner: float = 3.0e-14):
+    """Scatter-mode model whose Sobolev depths and electron densities come
+    from the plasma update: shells as config 2 (rho ~ v^-7), equal mass
+    fractions of the synthetic elements.  tau_sobolev and n_e start at zero
+    and are filled by the plasma state of the initial radiation field."""
+    rng = np.random.default_rng(seed)
+    v = np.linspace(v_lo * KM, v_hi * KM, n_shells + 1)
+    v_mid = 0.5 * (v[:-1] + v[1:])
+    rho = rho_inner * (v_mid / v_mid[0]) ** -7.0
+    atom, nu = synthetic_plasma_atom(rng, n_elements, n_stages, n_levels_per_ion, n_lines)
+    model = Model(v_bounds=_contig(v, np.float64), t_exp=t_exp_days * DAY,
+                  n_e=np.zeros(n_shells), line_nu=nu,
+                  tau_sobolev=np.zeros((n_shells, n_lines)), seed=seed)
+    return model, PlasmaSpec(atom=atom, number_density=element_densities(rho, n_elements))
+
+
+def config_plasma(seed: int = 0, n_packets: int = 1_000_000, n_lines: int = 300_000,
+                  n_levels_per_ion: int = 150) -> tuple:
+    """Plasma feedback at the size of the paper-scale model: 20 shells, 3e5
+    lines of 8 elements x 5 stages x 150 levels, 1e6 packets, nebular
+    ionization with dilute-LTE excitation (section 5.3's choice for all but
+    the NLTE ion)."""
+    model, spec = plasma_model(seed, n_shells=20, n_lines=n_lines,
+                               n_levels_per_ion=n_levels_per_ion)
+    w = Workload("plasma-20shell-300kline", model, T_inner=9000.0, n_packets=n_packets,
+                 n_iterations=10)
+    return w, spec
