@@ -267,6 +267,99 @@ int smc_model_get_tune(smc_model* model, smc_tune* tune);
  * SMC_F_TIMING in that iteration's flags).  Waits for the kernel to end. */
 int smc_read_timing(smc_model* model, double* transport_ms);
 
+/* ---------------------------------------------------------------------------
+ * Plasma state (section 2.3) and Sobolev optical depths (section 2.5)
+ *
+ * A plasma object recomputes a model's tau_sobolev and n_e on the device from
+ * a radiation field (T_R, W per shell), closing the loop of section 2.8: the
+ * estimators of one iteration set the opacities of the next.  Per shell:
+ *   1. partition functions Z of every ion: the sum over its levels of
+ *      g exp(-e / k T_R), with the factor W on every level that is not
+ *      metastable in dilute-LTE excitation;
+ *   2. ionization ratios N_{j+1} n_e / N_j: the Saha factor
+ *      Phi = 2 Z_{j+1} / Z_j (2 pi m_e k T_R / h^2)^{3/2} exp(-chi_j / k T_R),
+ *      times W [delta zeta_j + W (1 - zeta_j)] (T_e / T_R)^{1/2} with
+ *      T_e = 0.9 T_R in the nebular mode;
+ *   3. ion densities from the ratios, each element's total density and
+ *      charge conservation, which fixes n_e (the unique root of the charge
+ *      balance; an n_e below 1e-260 of the largest possible charge density
+ *      is returned as that floor);
+ *   4. level populations g / Z N exp(-e / k T_R), times W for levels that
+ *      are not metastable in dilute-LTE excitation;
+ *   5. tau_S = (pi e^2 / m_e c) f lambda t_exp n_l (1 - g_l n_u / (g_u n_l))
+ *      with lambda = c / nu of the model's line list; a negative value
+ *      (population inversion) is stored as 0 and counted.
+ * The model's line-interaction tables (downbranch, macroatom) are not
+ * changed.  Calls on a plasma and on its model must not overlap.
+ * ------------------------------------------------------------------------- */
+#define SMC_ION_LTE 0        /* Saha ionization balance at T_R */
+#define SMC_ION_NEBULAR 1    /* modified nebular approximation */
+#define SMC_EXC_LTE 0        /* Boltzmann level populations at T_R */
+#define SMC_EXC_DILUTE_LTE 1 /* Boltzmann, times W for levels that are not metastable */
+
+typedef struct smc_plasma smc_plasma;
+
+/* Atomic data and composition; host pointers read during smc_plasma_load
+ * only.  S and L are the model's shells and lines. */
+typedef struct {
+  int32_t n_elements;              /* E, 1 .. 256 */
+  int32_t n_ions;                  /* ion stages of all elements, E .. 2048 */
+  int32_t n_levels;                /* levels of all ions, >= n_ions */
+  int32_t reserved;                /* must be 0 */
+  const int32_t* element_ion_ptr;  /* [E+1] the stages of element e are ions ptr[e] .. ptr[e+1]-1,
+                                      stage j (charge j) at ptr[e] + j; ptr[0] = 0, increasing,
+                                      ptr[E] = n_ions */
+  const double* ion_chi;           /* [n_ions] energy to ionize stage j to j+1 [erg], > 0
+                                      (the last stage of an element: unused) */
+  const double* ion_zeta;          /* [n_ions] in [0, 1]: fraction of recombinations from stage
+                                      j+1 that go to stage j's ground state (nebular mode) */
+  const int32_t* ion_level_ptr;    /* [n_ions+1] the levels of ion i are ptr[i] .. ptr[i+1]-1,
+                                      at least one; ptr[0] = 0, ptr[n_ions] = n_levels */
+  const double* level_energy;      /* [n_levels] above the ion's ground state [erg], finite,
+                                      >= 0; each ion's first level is its ground state
+                                      (energy 0, metastable) */
+  const double* level_g;           /* [n_levels] statistical weight, > 0 */
+  const uint8_t* level_metastable; /* [n_levels] nonzero = metastable */
+  const int32_t* line_lower;       /* [L] lower level of line k */
+  const int32_t* line_upper;       /* [L] upper level of line k: same ion, higher energy */
+  const double* line_f;            /* [L] absorption oscillator strength, >= 0 */
+  const double* number_density;    /* [S*E] element number densities [cm^-3], >= 0,
+                                      shell-major */
+} smc_plasma_desc;
+
+typedef struct {
+  int32_t ionization;  /* SMC_ION_LTE or SMC_ION_NEBULAR */
+  int32_t excitation;  /* SMC_EXC_LTE or SMC_EXC_DILUTE_LTE */
+  double delta;        /* nebular-mode correction factor, finite, >= 0 (unused in LTE) */
+  const double* T_R;   /* host [S] radiation temperatures [K] > 0, or NULL (and W NULL):
+                          the model's current T_R and W on the device (the last
+                          iteration's, or the initial field of smc_model_load) */
+  const double* W;     /* host [S] dilution factors > 0, or NULL */
+} smc_plasma_params;
+
+/* Device workspace of a plasma object for a model of n_shells shells and
+ * n_lines lines.  Writes *bytes. */
+int smc_plasma_workspace_bytes(const smc_plasma_desc* desc, int32_t n_shells, int64_t n_lines,
+                               uint64_t* bytes);
+/* Validate the description against the model, copy it into the caller's
+ * device workspace (256-byte aligned, borrowed until smc_plasma_free) and
+ * derive the per-line constants on the device.  The model must outlive the
+ * plasma object.  Synchronises `stream`; changes nothing in the model. */
+int smc_plasma_load(smc_model* model, const smc_plasma_desc* desc, void* d_workspace,
+                    uint64_t ws_bytes, void* stream, smc_plasma** out);
+/* Enqueue steps 1-5 on `stream`, overwriting the model's tau_sobolev [S*L]
+ * and n_e [S] on the device.  Host T_R / W arrays are copied before the call
+ * returns; otherwise asynchronous. */
+int smc_plasma_update(smc_plasma* plasma, const smc_plasma_params* params, void* stream);
+/* Copy the state of the last update to host buffers (any may be NULL):
+ * n_e [S], ion densities and partition functions [S*n_ions], level
+ * populations [S*n_levels], tau_sobolev [S*L] (all shell-major) and the
+ * number of inverted lines stored as 0.  Synchronises `stream`. */
+int smc_plasma_read(smc_plasma* plasma, double* n_e, double* ion_density, double* partition,
+                    double* level_pop, double* tau_sobolev, uint64_t* n_clamped, void* stream);
+/* Release the handle; never frees the caller's workspace. */
+int smc_plasma_free(smc_plasma* plasma);
+
 #ifdef __cplusplus
 }
 #endif

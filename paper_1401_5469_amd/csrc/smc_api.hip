@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -982,6 +983,297 @@ int smc_graph_launch(smc_graph* g, void* stream) {
 
 int smc_graph_destroy(smc_graph* g) {
   release_graph(g);
+  return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// plasma state and Sobolev depths
+// ---------------------------------------------------------------------------
+struct smc_plasma {
+  smc_model* model;
+  smc::PlasmaLayout lay;
+  smc::DevPlasma dev;
+  uint8_t* base;
+  bool updated;
+};
+
+namespace {
+
+int validate_plasma(const smc_plasma_desc* d, int32_t S, int64_t L) {
+  if (!d) return fail(SMC_EINVAL, "null plasma description");
+  if (d->reserved != 0) return fail(SMC_EINVAL, "reserved field must be 0");
+  if (S < 1 || S > kMaxShells) return fail(SMC_EINVAL, "n_shells=%d outside [1, %d]", S, kMaxShells);
+  if (L < 0 || L > INT32_MAX) return fail(SMC_EINVAL, "n_lines=%lld outside [0, 2^31)", (long long)L);
+  const int32_t E = d->n_elements, NI = d->n_ions, NL = d->n_levels;
+  if (E < 1 || E > smc::kPlasmaMaxElements)
+    return fail(SMC_EINVAL, "n_elements=%d outside [1, %d]", E, smc::kPlasmaMaxElements);
+  if (NI < E || NI > smc::kPlasmaMaxIons)
+    return fail(SMC_EINVAL, "n_ions=%d outside [n_elements, %d]", NI, smc::kPlasmaMaxIons);
+  if (NL < NI) return fail(SMC_EINVAL, "n_levels=%d below n_ions=%d", NL, NI);
+  if (!d->element_ion_ptr || !d->ion_chi || !d->ion_zeta || !d->ion_level_ptr ||
+      !d->level_energy || !d->level_g || !d->level_metastable || !d->number_density)
+    return fail(SMC_EINVAL, "null atomic-data or density array");
+  if (L > 0 && (!d->line_lower || !d->line_upper || !d->line_f))
+    return fail(SMC_EINVAL, "null line arrays");
+  if (d->element_ion_ptr[0] != 0 || d->element_ion_ptr[E] != NI)
+    return fail(SMC_EINVAL, "element_ion_ptr must run from 0 to n_ions");
+  for (int32_t e = 0; e < E; ++e)
+    if (!(d->element_ion_ptr[e + 1] > d->element_ion_ptr[e]))
+      return fail(SMC_EINVAL, "element %d has no ion stage", e);
+  if (d->ion_level_ptr[0] != 0 || d->ion_level_ptr[NI] != NL)
+    return fail(SMC_EINVAL, "ion_level_ptr must run from 0 to n_levels");
+  for (int32_t i = 0; i < NI; ++i) {
+    if (!(d->ion_level_ptr[i + 1] > d->ion_level_ptr[i]))
+      return fail(SMC_EINVAL, "ion %d has no level", i);
+    const int32_t g0 = d->ion_level_ptr[i];
+    if (d->level_energy[g0] != 0.0 || !d->level_metastable[g0])
+      return fail(SMC_EINVAL, "the first level of ion %d must be a metastable ground state "
+                  "(energy 0)", i);
+    if (!(d->ion_zeta[i] >= 0.0 && d->ion_zeta[i] <= 1.0))
+      return fail(SMC_EINVAL, "ion_zeta[%d] must lie in [0, 1]", i);
+  }
+  for (int32_t e = 0; e < E; ++e)
+    for (int32_t i = d->element_ion_ptr[e]; i < d->element_ion_ptr[e + 1] - 1; ++i)
+      if (!(d->ion_chi[i] > 0.0) || !isfinite(d->ion_chi[i]))
+        return fail(SMC_EINVAL, "ion_chi[%d] must be finite and > 0", i);
+  for (int32_t l = 0; l < NL; ++l) {
+    if (!(d->level_energy[l] >= 0.0) || !isfinite(d->level_energy[l]))
+      return fail(SMC_EINVAL, "level_energy[%d] must be finite and >= 0", l);
+    if (!(d->level_g[l] > 0.0) || !isfinite(d->level_g[l]))
+      return fail(SMC_EINVAL, "level_g[%d] must be finite and > 0", l);
+  }
+  for (int64_t k = 0; k < L; ++k) {
+    const int32_t lo = d->line_lower[k], up = d->line_upper[k];
+    if (lo < 0 || lo >= NL || up < 0 || up >= NL)
+      return fail(SMC_EINVAL, "line %lld: level index out of range", (long long)k);
+    // same ion: the ion whose level range holds lo also holds up
+    const int32_t* it = std::upper_bound(d->ion_level_ptr, d->ion_level_ptr + NI + 1, lo);
+    const int32_t ion = (int32_t)(it - d->ion_level_ptr) - 1;
+    if (up < d->ion_level_ptr[ion] || up >= d->ion_level_ptr[ion + 1])
+      return fail(SMC_EINVAL, "line %lld joins levels of different ions", (long long)k);
+    if (!(d->level_energy[up] > d->level_energy[lo]))
+      return fail(SMC_EINVAL, "line %lld: upper level must lie above the lower", (long long)k);
+    if (!(d->line_f[k] >= 0.0) || !isfinite(d->line_f[k]))
+      return fail(SMC_EINVAL, "line_f[%lld] must be finite and >= 0", (long long)k);
+  }
+  const int64_t n_dens = (int64_t)S * E;
+  for (int64_t j = 0; j < n_dens; ++j)
+    if (!(d->number_density[j] >= 0.0) || !isfinite(d->number_density[j]))
+      return fail(SMC_EINVAL, "number_density[%lld] must be finite and >= 0", (long long)j);
+  return SMC_OK;
+}
+
+smc::PlasmaLayout plasma_layout_of(const smc_plasma_desc* d, int32_t S, int64_t L) {
+  smc::PlasmaLayout l;
+  memset(&l, 0, sizeof l);
+  const uint64_t E = (uint64_t)d->n_elements, NI = (uint64_t)d->n_ions;
+  const uint64_t NL = (uint64_t)d->n_levels, SS = (uint64_t)S, LL = (uint64_t)L;
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t o = off;
+    off = align_up(off + (bytes ? bytes : 1));
+    return o;
+  };
+  l.elem_ion_ptr = take((E + 1) * 4);
+  l.ion_chi = take(NI * 8);
+  l.ion_zeta = take(NI * 8);
+  l.ion_level_ptr = take((NI + 1) * 4);
+  l.level_energy = take(NL * 8);
+  l.level_g = take(NL * 8);
+  l.level_meta = take(NL);
+  l.level_ion = take(NL * 4);
+  l.line_f = take(LL * 8);
+  l.lines = take(LL * sizeof(smc::PlasmaLine));
+  l.density = take(SS * E * 8);
+  l.field = take(2 * SS * 8);
+  l.partition = take(SS * NI * 8);
+  l.ion_density = take(SS * NI * 8);
+  l.level_pop = take(SS * NL * 8);
+  l.clamped = take(2 * 8);
+  l.total = off;
+  return l;
+}
+
+int h2d(uint8_t* base, uint64_t off, const void* src, size_t bytes, hipStream_t s,
+        const char* what) {
+  if (bytes == 0) return SMC_OK;
+  HIP_TRY(hipMemcpyAsync(base + off, src, bytes, hipMemcpyHostToDevice, s), what);
+  return SMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int smc_plasma_workspace_bytes(const smc_plasma_desc* desc, int32_t n_shells, int64_t n_lines,
+                               uint64_t* bytes) {
+  if (!bytes) return fail(SMC_EINVAL, "null output pointer");
+  int rc = validate_plasma(desc, n_shells, n_lines);
+  if (rc) return rc;
+  *bytes = plasma_layout_of(desc, n_shells, n_lines).total;
+  return ok();
+}
+
+int smc_plasma_load(smc_model* model, const smc_plasma_desc* d, void* d_workspace,
+                    uint64_t ws_bytes, void* stream, smc_plasma** out) {
+  if (!model || !out) return fail(SMC_EINVAL, "null model or output pointer");
+  *out = nullptr;
+  const int32_t S = model->dev.S;
+  const int64_t L = model->dev.L;
+  int rc = validate_plasma(d, S, L);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace % kAlign) != 0)
+    return fail(SMC_EINVAL, "workspace must be a non-null, 256-byte aligned device pointer");
+  const smc::PlasmaLayout lay = plasma_layout_of(d, S, L);
+  if (ws_bytes < lay.total)
+    return fail(SMC_ENOMEM, "workspace of %llu bytes is smaller than the %llu needed",
+                (unsigned long long)ws_bytes, (unsigned long long)lay.total);
+  HIP_TRY(hipSetDevice(model->ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* base = (uint8_t*)d_workspace;
+  const size_t E = (size_t)d->n_elements, NI = (size_t)d->n_ions, NL = (size_t)d->n_levels;
+
+  // host-side index tables: the ion of every level, and the per-line
+  // record (weights and level indices; the coefficient is set on the device)
+  std::vector<int32_t> level_ion(NL);
+  for (size_t i = 0; i < NI; ++i)
+    for (int32_t l = d->ion_level_ptr[i]; l < d->ion_level_ptr[i + 1]; ++l)
+      level_ion[(size_t)l] = (int32_t)i;
+  std::vector<smc::PlasmaLine> lines((size_t)L);
+  for (int64_t k = 0; k < L; ++k) {
+    smc::PlasmaLine& r = lines[(size_t)k];
+    r.coef = 0.0;
+    r.lower = d->line_lower[k];
+    r.upper = d->line_upper[k];
+    r.g_l = d->level_g[r.lower];
+    r.g_u = d->level_g[r.upper];
+  }
+  if ((rc = h2d(base, lay.elem_ion_ptr, d->element_ion_ptr, (E + 1) * 4, s, "upload ions")) ||
+      (rc = h2d(base, lay.ion_chi, d->ion_chi, NI * 8, s, "upload ion_chi")) ||
+      (rc = h2d(base, lay.ion_zeta, d->ion_zeta, NI * 8, s, "upload ion_zeta")) ||
+      (rc = h2d(base, lay.ion_level_ptr, d->ion_level_ptr, (NI + 1) * 4, s, "upload levels")) ||
+      (rc = h2d(base, lay.level_energy, d->level_energy, NL * 8, s, "upload level_energy")) ||
+      (rc = h2d(base, lay.level_g, d->level_g, NL * 8, s, "upload level_g")) ||
+      (rc = h2d(base, lay.level_meta, d->level_metastable, NL, s, "upload metastable")) ||
+      (rc = h2d(base, lay.level_ion, level_ion.data(), NL * 4, s, "upload level_ion")) ||
+      (rc = h2d(base, lay.line_f, d->line_f, (size_t)L * 8, s, "upload line_f")) ||
+      (rc = h2d(base, lay.lines, lines.data(), (size_t)L * sizeof(smc::PlasmaLine), s,
+                "upload lines")) ||
+      (rc = h2d(base, lay.density, d->number_density, (size_t)S * E * 8, s, "upload density")))
+    return rc;
+
+  smc_plasma* p = new (std::nothrow) smc_plasma;
+  if (!p) return fail(SMC_ENOMEM, "host allocation failed");
+  memset(p, 0, sizeof *p);
+  p->model = model;
+  p->lay = lay;
+  p->base = base;
+  smc::DevPlasma& dp = p->dev;
+  dp.S = S;
+  dp.E = d->n_elements;
+  dp.n_ions = d->n_ions;
+  dp.n_levels = d->n_levels;
+  dp.L = (int32_t)L;
+  dp.Lp = model->dev.Lp;
+  dp.t_exp = model->dev.t_exp;
+  dp.elem_ion_ptr = (const int32_t*)(base + lay.elem_ion_ptr);
+  dp.ion_chi = (const double*)(base + lay.ion_chi);
+  dp.ion_zeta = (const double*)(base + lay.ion_zeta);
+  dp.ion_level_ptr = (const int32_t*)(base + lay.ion_level_ptr);
+  dp.level_energy = (const double*)(base + lay.level_energy);
+  dp.level_g = (const double*)(base + lay.level_g);
+  dp.level_meta = (const uint8_t*)(base + lay.level_meta);
+  dp.level_ion = (const int32_t*)(base + lay.level_ion);
+  dp.line_f = (const double*)(base + lay.line_f);
+  dp.lines = (smc::PlasmaLine*)(base + lay.lines);
+  dp.density = (const double*)(base + lay.density);
+  dp.partition = (double*)(base + lay.partition);
+  dp.ion_density = (double*)(base + lay.ion_density);
+  dp.level_pop = (double*)(base + lay.level_pop);
+  dp.clamped = (unsigned long long*)(base + lay.clamped);
+  dp.n_e = const_cast<double*>(model->dev.n_e);
+  dp.tau = const_cast<double*>(model->dev.tau);
+  dp.line_nu = model->dev.line_nu;
+  hipError_t e = smc::launch_plasma_lines(dp, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "plasma set-up");
+  }
+  *out = p;
+  return ok();
+}
+
+int smc_plasma_update(smc_plasma* p, const smc_plasma_params* pp, void* stream) {
+  if (!p || !pp) return fail(SMC_EINVAL, "null plasma or parameters");
+  if (pp->ionization != SMC_ION_LTE && pp->ionization != SMC_ION_NEBULAR)
+    return fail(SMC_EINVAL, "unknown ionization mode %d", pp->ionization);
+  if (pp->excitation != SMC_EXC_LTE && pp->excitation != SMC_EXC_DILUTE_LTE)
+    return fail(SMC_EINVAL, "unknown excitation mode %d", pp->excitation);
+  if (!(pp->delta >= 0.0) || !isfinite(pp->delta))
+    return fail(SMC_EINVAL, "delta must be finite and >= 0");
+  if ((pp->T_R == nullptr) != (pp->W == nullptr))
+    return fail(SMC_EINVAL, "give both T_R and W, or neither");
+  const int32_t S = p->dev.S;
+  if (pp->T_R) {
+    for (int32_t i = 0; i < S; ++i) {
+      if (!(pp->T_R[i] > 0.0) || !isfinite(pp->T_R[i]))
+        return fail(SMC_EINVAL, "T_R[%d] must be finite and > 0", i);
+      if (!(pp->W[i] > 0.0) || !isfinite(pp->W[i]))
+        return fail(SMC_EINVAL, "W[%d] must be finite and > 0", i);
+    }
+  }
+  HIP_TRY(hipSetDevice(p->model->ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  smc::DevPlasma d = p->dev;
+  d.ionization = pp->ionization;
+  d.excitation = pp->excitation;
+  d.delta = pp->delta;
+  if (pp->T_R) {
+    double* field = (double*)(p->base + p->lay.field);
+    HIP_TRY(hipMemcpyAsync(field, pp->T_R, (size_t)S * 8, hipMemcpyHostToDevice, s),
+            "upload T_R");
+    HIP_TRY(hipMemcpyAsync(field + S, pp->W, (size_t)S * 8, hipMemcpyHostToDevice, s),
+            "upload W");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    d.T_R = field;
+    d.W = field + S;
+  } else {
+    d.T_R = p->model->dev.out_shell + 2 * (size_t)S;
+    d.W = p->model->dev.out_shell + 3 * (size_t)S;
+  }
+  HIP_TRY(smc::launch_plasma_update(d, s), "plasma update");
+  p->updated = true;
+  return ok();
+}
+
+int smc_plasma_read(smc_plasma* p, double* n_e, double* ion_density, double* partition,
+                    double* level_pop, double* tau_sobolev, uint64_t* n_clamped, void* stream) {
+  if (!p) return fail(SMC_EINVAL, "null plasma");
+  if (!p->updated) return fail(SMC_EINVAL, "the plasma has not been updated");
+  HIP_TRY(hipSetDevice(p->model->ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const smc::DevPlasma& d = p->dev;
+  const size_t S = (size_t)d.S, NI = (size_t)d.n_ions, NL = (size_t)d.n_levels;
+  const size_t L = (size_t)d.L;
+  int rc;
+  if ((rc = sync_copy_out(n_e, d.n_e, S * 8, s))) return rc;
+  if ((rc = sync_copy_out(ion_density, d.ion_density, S * NI * 8, s))) return rc;
+  if ((rc = sync_copy_out(partition, d.partition, S * NI * 8, s))) return rc;
+  if ((rc = sync_copy_out(level_pop, d.level_pop, S * NL * 8, s))) return rc;
+  if ((rc = sync_copy_out(n_clamped, d.clamped, 8, s))) return rc;
+  if (tau_sobolev && L > 0)
+    HIP_TRY(hipMemcpy2DAsync(tau_sobolev, L * 8, d.tau, (size_t)d.Lp * 8, L * 8, S,
+                             hipMemcpyDeviceToHost, s),
+            "hipMemcpy2DAsync");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return ok();
+}
+
+int smc_plasma_free(smc_plasma* p) {
+  delete p;
   return ok();
 }
 

@@ -164,4 +164,66 @@ int transport_block_threads();
 int long_block_threads();
 constexpr int kMaxBatchModels = 1024;
 
+// ---------------------------------------------------------------------------
+// plasma state and Sobolev depths
+// ---------------------------------------------------------------------------
+constexpr int kPlasmaMaxIons = 2048;     // per-shell ion tables live in LDS
+constexpr int kPlasmaMaxElements = 256;
+
+// Per-line constants of the Sobolev depth, derived once at load (32 bytes).
+struct PlasmaLine {
+  double coef;             // (pi e^2 / m_e c) f (c / nu) t_exp
+  double g_l, g_u;         // statistical weights of the lower and upper level
+  int32_t lower, upper;    // global level indices
+};
+
+struct PlasmaLayout {
+  uint64_t elem_ion_ptr;   // [E+1] i32
+  uint64_t ion_chi, ion_zeta;  // [n_ions]
+  uint64_t ion_level_ptr;  // [n_ions+1] i32
+  uint64_t level_energy, level_g;  // [n_levels]
+  uint64_t level_meta;     // [n_levels] u8
+  uint64_t level_ion;      // [n_levels] i32
+  uint64_t line_f;         // [L] staging of the oscillator strengths
+  uint64_t lines;          // [L] PlasmaLine
+  uint64_t density;        // [S*E]
+  uint64_t field;          // [2S] T_R, W given by the host
+  uint64_t partition, ion_density;  // [S*n_ions]
+  uint64_t level_pop;      // [S*n_levels]
+  uint64_t clamped;        // [1] u64 (+ pad)
+  uint64_t total;
+};
+
+struct DevPlasma {
+  int32_t S, E, n_ions, n_levels;
+  int32_t L, Lp;
+  int32_t ionization, excitation;
+  double delta;
+  double t_exp;
+  const int32_t* elem_ion_ptr;
+  const double* ion_chi;
+  const double* ion_zeta;
+  const int32_t* ion_level_ptr;
+  const double* level_energy;
+  const double* level_g;
+  const uint8_t* level_meta;
+  const int32_t* level_ion;
+  const double* line_f;
+  PlasmaLine* lines;
+  const double* density;
+  const double* T_R;       // [S] radiation field of this update
+  const double* W;         // [S]
+  double* partition;
+  double* ion_density;
+  double* level_pop;
+  unsigned long long* clamped;
+  double* n_e;             // the model's [S]
+  double* tau;             // the model's [S*Lp]
+  const double* line_nu;   // the model's [Lp]
+};
+
+// Launchers implemented in smc_plasma.hip.
+hipError_t launch_plasma_lines(const DevPlasma& p, hipStream_t s);
+hipError_t launch_plasma_update(const DevPlasma& p, hipStream_t s);
+
 }  // namespace smc

@@ -51,6 +51,24 @@ class smc_iter_params(C.Structure):
                 ("n_virtual", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+ION_LTE, ION_NEBULAR = 0, 1
+EXC_LTE, EXC_DILUTE_LTE = 0, 1
+_u8p = C.POINTER(C.c_uint8)
+
+
+class smc_plasma_desc(C.Structure):
+    _fields_ = [("n_elements", C.c_int32), ("n_ions", C.c_int32), ("n_levels", C.c_int32),
+                ("reserved", C.c_int32), ("element_ion_ptr", _i32p), ("ion_chi", _dp),
+                ("ion_zeta", _dp), ("ion_level_ptr", _i32p), ("level_energy", _dp),
+                ("level_g", _dp), ("level_metastable", _u8p), ("line_lower", _i32p),
+                ("line_upper", _i32p), ("line_f", _dp), ("number_density", _dp)]
+
+
+class smc_plasma_params(C.Structure):
+    _fields_ = [("ionization", C.c_int32), ("excitation", C.c_int32), ("delta", C.c_double),
+                ("T_R", _dp), ("W", _dp)]
+
+
 PACKET_DTYPE = np.dtype([("id", np.uint64), ("status", np.int32), ("shell", np.int32),
                          ("nu", np.float64), ("energy", np.float64), ("mu", np.float64),
                          ("r", np.float64), ("mu0", np.float64), ("nu_cmf0", np.float64),
@@ -63,7 +81,8 @@ EXPORTS = ("smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_model_wor
            "smc_read_spectrum", "smc_read_counters", "smc_read_packets", "smc_read_timing",
            "smc_model_set_tune", "smc_model_get_tune", "smc_batch_run", "smc_batch_read_timing",
            "smc_batch_autotune", "smc_graph_capture", "smc_graph_launch", "smc_graph_destroy",
-           "smc_read_virtual_spectrum")
+           "smc_read_virtual_spectrum", "smc_plasma_workspace_bytes", "smc_plasma_load",
+           "smc_plasma_update", "smc_plasma_read", "smc_plasma_free")
 
 
 class SmcError(RuntimeError):
@@ -112,6 +131,13 @@ def load_library(path: str = LIB_PATH):
     L.smc_graph_launch.argtypes = [vp, vp]
     L.smc_graph_destroy.argtypes = [vp]
     L.smc_model_get_tune.argtypes = [vp, C.POINTER(smc_tune)]
+    L.smc_plasma_workspace_bytes.argtypes = [C.POINTER(smc_plasma_desc), C.c_int32, C.c_int64,
+                                             C.POINTER(C.c_uint64)]
+    L.smc_plasma_load.argtypes = [vp, C.POINTER(smc_plasma_desc), vp, C.c_uint64, vp,
+                                  C.POINTER(vp)]
+    L.smc_plasma_update.argtypes = [vp, C.POINTER(smc_plasma_params), vp]
+    L.smc_plasma_read.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _u64p, vp]
+    L.smc_plasma_free.argtypes = [vp]
     for name in EXPORTS:
         if name != "smc_last_error":
             getattr(L, name).restype = C.c_int
@@ -408,3 +434,109 @@ class Model:
         _check(_lib.smc_read_packets(self.handle, C.c_void_p(out.ctypes.data), int(n),
                                      _stream_ptr(stream)))
         return out
+
+
+def _plasma_desc(spec, keep: list) -> smc_plasma_desc:
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a
+
+    atom = spec.atom
+    d = smc_plasma_desc()
+    d.n_elements = atom.n_elements
+    d.n_ions = atom.n_ions
+    d.n_levels = atom.n_levels
+    d.element_ion_ptr = _ptr(arr(atom.element_ion_ptr, np.int32), _i32p)
+    d.ion_chi = _ptr(arr(atom.ion_chi, np.float64), _dp)
+    d.ion_zeta = _ptr(arr(atom.ion_zeta, np.float64), _dp)
+    d.ion_level_ptr = _ptr(arr(atom.ion_level_ptr, np.int32), _i32p)
+    d.level_energy = _ptr(arr(atom.level_energy, np.float64), _dp)
+    d.level_g = _ptr(arr(atom.level_g, np.float64), _dp)
+    d.level_metastable = _ptr(arr(atom.level_metastable, np.uint8), _u8p)
+    n_lines = atom.line_lower.shape[0]
+    d.line_lower = _ptr(arr(atom.line_lower if n_lines else np.zeros(1), np.int32), _i32p)
+    d.line_upper = _ptr(arr(atom.line_upper if n_lines else np.zeros(1), np.int32), _i32p)
+    d.line_f = _ptr(arr(atom.line_f if n_lines else np.zeros(1), np.float64), _dp)
+    d.number_density = _ptr(arr(spec.number_density, np.float64), _dp)
+    return d
+
+
+def plasma_workspace_bytes(spec, n_shells: int, n_lines: int) -> int:
+    lib = load_library()
+    keep = []
+    d = _plasma_desc(spec, keep)
+    out = C.c_uint64()
+    _check(lib.smc_plasma_workspace_bytes(C.byref(d), int(n_shells), int(n_lines), C.byref(out)))
+    return int(out.value)
+
+
+class Plasma:
+    """Plasma state of a loaded model (section 2.3) that rewrites its Sobolev
+    depths and electron densities on the device (section 2.5)."""
+
+    def __init__(self, model: Model, spec, workspace=None, stream=None):
+        import torch
+        lib = load_library()
+        # the C description carries no array lengths: check them here
+        if spec.atom.line_lower.shape[0] != model.L:
+            raise ValueError(f"the atom lists {spec.atom.line_lower.shape[0]} lines, "
+                             f"the model {model.L}")
+        if np.shape(spec.number_density) != (model.S, spec.atom.n_elements):
+            raise ValueError("number_density must be [n_shells, n_elements]")
+        keep = []
+        d = _plasma_desc(spec, keep)
+        need = plasma_workspace_bytes(spec, model.S, model.L)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=model.workspace.device)
+        self.workspace = workspace
+        h = C.c_void_p()
+        _check(lib.smc_plasma_load(model.handle, C.byref(d), C.c_void_p(workspace.data_ptr()),
+                                   int(workspace.numel()), _stream_ptr(stream), C.byref(h)))
+        self.handle = h
+        self.model = model  # must outlive the plasma object
+        self.S, self.L = model.S, model.L
+        self.n_ions, self.n_levels = spec.atom.n_ions, spec.atom.n_levels
+
+    def update(self, ionization: int = ION_NEBULAR, excitation: int = EXC_DILUTE_LTE,
+               delta: float = 1.0, T_R=None, W=None, stream=None):
+        """Recompute the model's tau_sobolev and n_e from T_R, W (host arrays)
+        or, when both are None, from the model's current radiation field."""
+        p = smc_plasma_params()
+        p.ionization = int(ionization)
+        p.excitation = int(excitation)
+        p.delta = float(delta)
+        keep = []
+        if T_R is not None or W is not None:
+            t = np.ascontiguousarray(T_R, dtype=np.float64) if T_R is not None else None
+            w = np.ascontiguousarray(W, dtype=np.float64) if W is not None else None
+            for a in (t, w):
+                if a is not None and a.shape != (self.S,):
+                    raise ValueError("T_R and W need one value per shell")
+            keep += [t, w]
+            p.T_R = _ptr(t, _dp)
+            p.W = _ptr(w, _dp)
+        _check(_lib.smc_plasma_update(self.handle, C.byref(p), _stream_ptr(stream)))
+
+    def read(self, tau: bool = True, level_pop: bool = True, stream=None):
+        S, NI, NL, L = self.S, self.n_ions, self.n_levels, self.L
+        out = dict(n_e=np.zeros(S), N_ion=np.zeros((S, NI)), Z=np.zeros((S, NI)),
+                   level_pop=np.zeros((S, NL)) if level_pop else None,
+                   tau=np.zeros((S, L)) if tau else None)
+        c = np.zeros(1, dtype=np.uint64)
+        _check(_lib.smc_plasma_read(self.handle, _ptr(out["n_e"], _dp), _ptr(out["N_ion"], _dp),
+                                    _ptr(out["Z"], _dp), _ptr(out["level_pop"], _dp),
+                                    _ptr(out["tau"], _dp), _ptr(c, _u64p), _stream_ptr(stream)))
+        out["n_clamped"] = int(c[0])
+        return out
+
+    def free(self):
+        if self.handle:
+            _lib.smc_plasma_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

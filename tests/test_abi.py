@@ -51,6 +51,10 @@ int main(void) {
   F(smc_model_desc, seed); F(smc_model_desc, n_em); F(smc_model_desc, nu_min);
   F(smc_iter_params, packet_ids); F(smc_iter_params, n_ids); F(smc_iter_params, damping);
   F(smc_packet_out, hash); F(smc_packet_out, last_line); F(smc_packet_out, nu_cmf0);
+  printf("smc_plasma_desc %zu\n", sizeof(smc_plasma_desc));
+  printf("smc_plasma_params %zu\n", sizeof(smc_plasma_params));
+  F(smc_plasma_desc, element_ion_ptr); F(smc_plasma_desc, level_metastable);
+  F(smc_plasma_desc, number_density); F(smc_plasma_params, delta); F(smc_plasma_params, W);
   return 0;
 }
 """
@@ -78,6 +82,12 @@ def test_python_structs_match_header_layout():
     assert lay["smc_packet_out.hash"] == smc.PACKET_DTYPE.fields["hash"][1]
     assert lay["smc_packet_out.last_line"] == smc.PACKET_DTYPE.fields["last_line"][1]
     assert lay["smc_packet_out.nu_cmf0"] == smc.PACKET_DTYPE.fields["nu_cmf0"][1]
+    assert lay["smc_plasma_desc"] == C.sizeof(smc.smc_plasma_desc)
+    assert lay["smc_plasma_params"] == C.sizeof(smc.smc_plasma_params)
+    for st, f in (("smc_plasma_desc", "element_ion_ptr"), ("smc_plasma_desc", "level_metastable"),
+                  ("smc_plasma_desc", "number_density"), ("smc_plasma_params", "delta"),
+                  ("smc_plasma_params", "W")):
+        assert lay[f"{st}.{f}"] == getattr(getattr(smc, st), f).offset
 
 
 def test_workspace_size_grows_with_flags_and_packets(lib):
@@ -160,6 +170,65 @@ def test_host_validation_of_macroatom_tables(lib):
     ec[-1, 3] = 1.5
     bad.em_cum = ec
     assert "em_cum" in _expect_invalid(bad)
+
+
+def _plasma_spec():
+    model, spec = W.plasma_model(seed=2, n_shells=3, n_elements=3, n_stages=3,
+                                 n_levels_per_ion=8, n_lines=60)
+    return model, spec
+
+
+def _expect_plasma_invalid(spec, S=3, L=60):
+    with pytest.raises(smc.SmcError) as ei:
+        smc.plasma_workspace_bytes(spec, S, L)
+    assert ei.value.code == smc.SMC_EINVAL
+    return str(ei.value)
+
+
+def _with_atom(spec, **kw):
+    import dataclasses
+    return W.PlasmaSpec(atom=dataclasses.replace(spec.atom, **kw),
+                        number_density=spec.number_density)
+
+
+def test_host_validation_of_plasma_descriptions(lib):
+    model, spec = _plasma_spec()
+    a = spec.atom
+    base = smc.plasma_workspace_bytes(spec, 3, 60)
+    assert base >= 3 * (a.n_levels + 2 * a.n_ions) * 8 + 60 * 32
+    assert smc.plasma_workspace_bytes(spec, 6, 60) > base
+    e = a.level_energy.copy()
+    e[a.ion_level_ptr[1]] = 1e-12  # ground state above zero
+    assert "ground state" in _expect_plasma_invalid(_with_atom(spec, level_energy=e))
+    m = a.level_metastable.copy()
+    m[a.ion_level_ptr[2]] = 0
+    assert "ground state" in _expect_plasma_invalid(_with_atom(spec, level_metastable=m))
+    lu = a.line_upper.copy()
+    lu[0] = a.ion_level_ptr[-1] - 1 if a.line_lower[0] < a.ion_level_ptr[-2] else 0
+    assert "different ions" in _expect_plasma_invalid(_with_atom(spec, line_upper=lu))
+    lu = a.line_upper.copy()
+    lu[3] = a.line_lower[3]
+    assert "above the lower" in _expect_plasma_invalid(_with_atom(spec, line_upper=lu))
+    z = a.ion_zeta.copy()
+    z[1] = 1.5
+    assert "zeta" in _expect_plasma_invalid(_with_atom(spec, ion_zeta=z))
+    chi = a.ion_chi.copy()
+    chi[0] = 0.0
+    assert "ion_chi" in _expect_plasma_invalid(_with_atom(spec, ion_chi=chi))
+    f = a.line_f.copy()
+    f[5] = -1.0
+    assert "line_f" in _expect_plasma_invalid(_with_atom(spec, line_f=f))
+    g = a.level_g.copy()
+    g[4] = 0.0
+    assert "level_g" in _expect_plasma_invalid(_with_atom(spec, level_g=g))
+    ptr = a.element_ion_ptr.copy()
+    ptr[1] = ptr[0]
+    assert "no ion stage" in _expect_plasma_invalid(_with_atom(spec, element_ion_ptr=ptr))
+    d = spec.number_density.copy()
+    d[2, 1] = -1.0
+    assert "number_density" in _expect_plasma_invalid(W.PlasmaSpec(atom=a, number_density=d))
+    # a model without lines needs no line records
+    assert smc.plasma_workspace_bytes(spec, 3, 0) < base
 
 
 def test_no_gpu_means_a_loud_error_not_a_fallback(lib):
