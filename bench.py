@@ -10,6 +10,8 @@
                                           virtual packets, section 2.9)
     python bench.py --workload macroatom (macroatom vs downbranch line modes
                                           on the 30-shell 2e4-line atom)
+    python bench.py --workload plasma    (iterations with the plasma update of
+                                          sections 2.3 and 2.5 between them)
 
 One step is one Monte Carlo iteration of the paper-scale scatter model
 (20 shells 10000-25000 km/s at 13 d, 3e5 lines, 1e6 packets; Kerzendorf & Sim
@@ -57,7 +59,7 @@ def parse():
     ap.add_argument("--no-jblue", action="store_true")
     ap.add_argument("--workload", default="paper-scale",
                     choices=["paper-scale", "batched", "served", "copy", "virtual",
-                             "macroatom"])
+                             "macroatom", "plasma"])
     ap.add_argument("--n-virtual", type=int, default=3,
                     help="virtual packets per packet launch in the virtual mode")
     ap.add_argument("--models", type=int, default=64, help="models in the batched mix")
@@ -223,6 +225,116 @@ def macroatom(args):
         "macroatom": ma,
         "downbranch": res["downbranch"],
         "ms_ratio_macroatom_over_downbranch": ma["ms"] / res["downbranch"]["ms"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def plasma(args):
+    """Iterations of the paper-scale plasma model (20 shells, 3e5 lines of 8
+    synthetic elements x 5 stages x 150 levels, 1e6 packets): after every
+    iteration the plasma update (nebular ionization, dilute-LTE excitation)
+    rewrites tau_S and n_e from the iteration's T_R and W; T_inner moves
+    toward the requested luminosity after every third iteration (the scheme
+    of section 5.3).  The first timed iteration starts again from T_inner =
+    9000 K and the opacities of the initial field.  The value is
+    interactions per second over the whole loop, plasma updates included;
+    the roofline entry prices the plasma update (state and depth kernels,
+    timed together with HIP events on the launch stream) at its algorithmic
+    bytes: tau_S written once, the per-line records and the level
+    populations read once, the atomic data and densities read per shell."""
+    import numpy as np
+    import torch
+
+    from oracle import plasma as OP
+    from paper_1401_5469_amd import smc
+    from paper_1401_5469_amd import workloads as W
+
+    w, spec = W.config_plasma(n_packets=args.packets)
+    m_in, a = w.model, spec.atom
+    N, S, L = w.n_packets, m_in.n_shells, m_in.n_lines
+    ion, exc = W.ION_NEBULAR, W.EXC_DILUTE_LTE
+    flags = 0 if args.no_jblue else smc.F_JBLUE
+    ctx = smc.Context(0)
+    model = smc.Model(ctx, m_in, N, flags=flags)
+    pl = smc.Plasma(model, spec)
+    v = m_in.v_bounds
+    q = v[0] / (0.5 * (v[:-1] + v[1:]))
+    T0, W0 = np.full(S, 1.0e4), 0.5 * (1.0 - np.sqrt(1.0 - q * q))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def run(k, record):
+        pl.update(ion, exc, T_R=T0, W=W0)
+        for i in range(k):
+            model.run_iteration(N, w.T_inner if i == 0 else 0.0, iteration=i,
+                                flags=flags | smc.F_TIMING,
+                                L_requested=w.L_requested if i % 3 == 2 else 0.0,
+                                damping=w.damping)
+            ev0.record()
+            pl.update(ion, exc)
+            ev1.record()
+            c = model.read_counters()
+            ms = model.read_timing()
+            ev1.synchronize()
+            pms = ev0.elapsed_time(ev1)
+            s = model.read_spectrum()
+            if record is not None:
+                record.append((c, ms, pms, s["T_inner"]))
+            print(f"# iteration {i}: {ms:.2f} ms transport, {pms:.3f} ms plasma update, "
+                  f"T_inner {s['T_inner']:.0f} K", file=sys.stderr, flush=True)
+
+    run(args.warmup, None)
+    torch.cuda.synchronize()
+    rec = []
+    t0 = time.perf_counter()
+    run(args.steps, rec)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = pl.read(tau=False, level_pop=False)
+
+    inter = sum(c["line_events"] + c["escatters"] for c, _, _, _ in rec)
+    pms = [p for _, _, p, _ in rec]
+    mean_pms = float(np.mean(pms))
+    NI, NL, E = a.n_ions, a.n_levels, a.n_elements
+    # tau_S written; 16-byte line records read; n and n / g written, n / g
+    # read back; level data (energy, g, flag, ion) read; ion densities and
+    # partition functions written; element densities read
+    bytes_update = (S * L * 8 + L * 16 + S * NL * 8 * 3 + NL * (8 + 8 + 1 + 4)
+                    + S * NI * 8 * 2 + S * E * 8)
+    achieved = bytes_update / (mean_pms * 1e-3) / 1e9
+    # the plasma oracle on the same inputs (numpy FP64, one update)
+    t1 = time.perf_counter()
+    OP.plasma_state(a, spec.number_density, m_in.line_nu, m_in.t_exp, T0, W0, ion, exc)
+    cpu_s = time.perf_counter() - t1
+    out = {
+        "metric": "packet-interactions/sec (with plasma feedback)",
+        "value": inter / wall,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "shells": S, "lines": L, "elements": E, "ions": NI,
+                   "levels": NL, "packets_per_iteration": N, "ionization": "nebular",
+                   "excitation": "dilute-lte", "T_inner_start": w.T_inner},
+        "transport_ms": [m for _, m, _, _ in rec],
+        "plasma_update_ms": pms,
+        "T_inner": [t for _, _, _, t in rec],
+        "n_e_final": st["n_e"].tolist(),
+        "inverted_lines_final": st["n_clamped"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "plasma update: plasma_state_kernel + plasma_tau_kernel",
+                     "bytes_per_launch": bytes_update},
+        "cpu_baseline": {"value": 1.0 / cpu_s, "unit": "plasma updates/s", "cores": 1,
+                         "kind": "oracle",
+                         "sample": f"one plasma update of the whole model on the initial field "
+                                   f"({S} shells x {L} lines, numpy FP64, {cpu_s:.2f} s)"},
+        "plasma_updates_per_s": 1e3 / mean_pms,
     }
     print(json.dumps(out), flush=True)
 
@@ -442,6 +554,8 @@ def main():
         if args.steps == 10:
             args.steps = 3
         return macroatom(args)
+    if args.workload == "plasma":
+        return plasma(args)
 
     import numpy as np
     import torch

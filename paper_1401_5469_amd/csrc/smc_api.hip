@@ -1091,6 +1091,7 @@ smc::PlasmaLayout plasma_layout_of(const smc_plasma_desc* d, int32_t S, int64_t 
   l.partition = take(SS * NI * 8);
   l.ion_density = take(SS * NI * 8);
   l.level_pop = take(SS * NL * 8);
+  l.level_x = take(SS * NL * 8);
   l.clamped = take(2 * 8);
   l.total = off;
   return l;
@@ -1136,7 +1137,7 @@ int smc_plasma_load(smc_model* model, const smc_plasma_desc* d, void* d_workspac
   const size_t E = (size_t)d->n_elements, NI = (size_t)d->n_ions, NL = (size_t)d->n_levels;
 
   // host-side index tables: the ion of every level, and the per-line
-  // record (weights and level indices; the coefficient is set on the device)
+  // record (level indices; the coefficient is set on the device)
   std::vector<int32_t> level_ion(NL);
   for (size_t i = 0; i < NI; ++i)
     for (int32_t l = d->ion_level_ptr[i]; l < d->ion_level_ptr[i + 1]; ++l)
@@ -1144,11 +1145,9 @@ int smc_plasma_load(smc_model* model, const smc_plasma_desc* d, void* d_workspac
   std::vector<smc::PlasmaLine> lines((size_t)L);
   for (int64_t k = 0; k < L; ++k) {
     smc::PlasmaLine& r = lines[(size_t)k];
-    r.coef = 0.0;
+    r.coef_g = 0.0;
     r.lower = d->line_lower[k];
     r.upper = d->line_upper[k];
-    r.g_l = d->level_g[r.lower];
-    r.g_u = d->level_g[r.upper];
   }
   if ((rc = h2d(base, lay.elem_ion_ptr, d->element_ion_ptr, (E + 1) * 4, s, "upload ions")) ||
       (rc = h2d(base, lay.ion_chi, d->ion_chi, NI * 8, s, "upload ion_chi")) ||
@@ -1192,6 +1191,7 @@ int smc_plasma_load(smc_model* model, const smc_plasma_desc* d, void* d_workspac
   dp.partition = (double*)(base + lay.partition);
   dp.ion_density = (double*)(base + lay.ion_density);
   dp.level_pop = (double*)(base + lay.level_pop);
+  dp.level_x = (double*)(base + lay.level_x);
   dp.clamped = (unsigned long long*)(base + lay.clamped);
   dp.n_e = const_cast<double*>(model->dev.n_e);
   dp.tau = const_cast<double*>(model->dev.tau);

@@ -170,10 +170,9 @@ constexpr int kMaxBatchModels = 1024;
 constexpr int kPlasmaMaxIons = 2048;     // per-shell ion tables live in LDS
 constexpr int kPlasmaMaxElements = 256;
 
-// Per-line constants of the Sobolev depth, derived once at load (32 bytes).
+// Per-line constants of the Sobolev depth, derived once at load (16 bytes).
 struct PlasmaLine {
-  double coef;             // (pi e^2 / m_e c) f (c / nu) t_exp
-  double g_l, g_u;         // statistical weights of the lower and upper level
+  double coef_g;           // (pi e^2 / m_e c) f (c / nu) t_exp g_l
   int32_t lower, upper;    // global level indices
 };
 
@@ -189,7 +188,8 @@ struct PlasmaLayout {
   uint64_t density;        // [S*E]
   uint64_t field;          // [2S] T_R, W given by the host
   uint64_t partition, ion_density;  // [S*n_ions]
-  uint64_t level_pop;      // [S*n_levels]
+  uint64_t level_pop;      // [S*n_levels] populations n
+  uint64_t level_x;        // [S*n_levels] n / g
   uint64_t clamped;        // [1] u64 (+ pad)
   uint64_t total;
 };
@@ -216,6 +216,7 @@ struct DevPlasma {
   double* partition;
   double* ion_density;
   double* level_pop;
+  double* level_x;
   unsigned long long* clamped;
   double* n_e;             // the model's [S]
   double* tau;             // the model's [S*Lp]

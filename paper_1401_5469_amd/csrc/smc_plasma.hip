@@ -8,11 +8,12 @@
 //                        (one wavefront, lanes over elements, safeguarded
 //                        Newton in ln n_e), ion densities and level
 //                        populations.  Latency-bound and small: S workgroups
-//                        of a few microseconds each.
-//   plasma_tau_kernel    one lane per line, looping over shells: two
-//                        population gathers (L2-resident, S * n_levels
-//                        doubles) and one coalesced 8-byte store per
-//                        (shell, line).  HBM-bound on the tau_S stores.
+//                        of 16 wavefronts.
+//   plasma_tau_kernel    one workgroup per (shell, 8192 lines): the shell's
+//                        table of populations per statistical weight staged
+//                        in LDS, then per line a 16-byte record, two LDS
+//                        gathers and one coalesced 8-byte store.  HBM-bound
+//                        on the tau_S stores.
 // plasma_lines_kernel runs once at load and folds the oscillator strength,
 // the wavelength and t_exp into one coefficient per line.
 #include <hip/hip_runtime.h>
@@ -42,8 +43,16 @@ constexpr double kLogNeRange = 600.0;
 constexpr int kNewtonMax = 200;
 
 constexpr int kWave = 64;
-constexpr int kStateThreads = 256;
+// one workgroup per shell: 16 wavefronts keep many level loads in flight
+constexpr int kStateThreads = 1024;
 constexpr int kTauThreads = 256;
+// lines per workgroup of the depth kernel (32 per lane, in batches of 8)
+constexpr int kTauChunk = 8192;
+constexpr int kTauBatch = 8;
+// independent loads a lane issues before using any of them
+constexpr int kBatch = 4;
+// the depth kernel stages a shell's n / g table in LDS up to this many levels
+constexpr int kTauLdsLevels = 8192;
 
 __device__ inline double wave_sum(double v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -53,15 +62,6 @@ __device__ inline double wave_sum(double v) {
 __device__ inline unsigned long long wave_sum_u64(unsigned long long v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
-}
-
-// Boltzmann weight of a level, with the dilution factor on levels that are
-// not metastable in dilute-LTE excitation
-__device__ inline double level_weight(const DevPlasma& p, int l, double kT, double W,
-                                      bool dilute) {
-  double b = p.level_g[l] * exp(-p.level_energy[l] / kT);
-  if (dilute && !p.level_meta[l]) b = W * b;
-  return b;
 }
 
 // Charge moments of one element at ln n_e = u: stage j has log weight
@@ -101,11 +101,29 @@ __global__ __launch_bounds__(kStateThreads) void plasma_state_kernel(DevPlasma p
   const bool dilute = p.excitation == SMC_EXC_DILUTE_LTE;
   const double* dens = p.density + (size_t)s * p.E;
 
-  // step 1: partition functions, one wavefront per ion
+  // step 1: partition functions, one wavefront per ion; a lane's levels are
+  // loaded kBatch at a time so that their latencies overlap
   for (int i = wave; i < p.n_ions; i += kStateThreads / kWave) {
+    const int l0 = p.ion_level_ptr[i], l1 = p.ion_level_ptr[i + 1];
     double z = 0.0;
-    for (int l = p.ion_level_ptr[i] + lane; l < p.ion_level_ptr[i + 1]; l += kWave)
-      z += level_weight(p, l, kT, W, dilute);
+    for (int lb = l0 + lane; lb < l1; lb += kBatch * kWave) {
+      double g[kBatch], en[kBatch];
+      uint8_t meta[kBatch];
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) {
+        const int l = lb + j * kWave;
+        const bool in = l < l1;
+        g[j] = in ? p.level_g[l] : 0.0;
+        en[j] = in ? p.level_energy[l] : 0.0;
+        meta[j] = in ? p.level_meta[l] : 1;
+      }
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) {
+        double b = g[j] * exp(-en[j] / kT);
+        if (dilute && !meta[j]) b = W * b;
+        z += b;
+      }
+    }
     z = wave_sum(z);
     if (lane == 0) Z[i] = z;
   }
@@ -155,11 +173,14 @@ __global__ __launch_bounds__(kStateThreads) void plasma_state_kernel(DevPlasma p
         const double g = sq - xu;
         if (g > 0.0) lo = u;
         else hi = u;
+        // a Newton step that no longer moves u ends the search (it may touch
+        // the bracket end it converges to); otherwise a step leaving the
+        // bracket is replaced by bisection
         double un = u - g / (-sv - xu);
-        if (!(un > lo && un < hi)) un = 0.5 * (lo + hi);
-        const bool done = fabs(un - u) <= 1e-15 * fmax(1.0, fabs(u)) || !(hi > lo);
+        const bool done = fabs(un - u) <= 1e-15 * fmax(1.0, fabs(u));
+        if (!done && !(un > lo && un < hi)) un = 0.5 * (lo + hi);
         u = un;
-        if (done) break;
+        if (done || !(hi > lo)) break;
       }
       x = exp(u);
     }
@@ -203,33 +224,88 @@ __global__ __launch_bounds__(kStateThreads) void plasma_state_kernel(DevPlasma p
     p.n_e[s] = s_ne;
     if (s == 0) p.clamped[0] = 0ull;  // the depth kernel runs after this one
   }
-  // step 4: level populations
+  // step 4: level populations n, and n / g, the form the depth kernel uses
   double* pop = p.level_pop + (size_t)s * p.n_levels;
-  for (int l = threadIdx.x; l < p.n_levels; l += kStateThreads) {
-    const int i = p.level_ion[l];
-    pop[l] = N[i] / Z[i] * level_weight(p, l, kT, W, dilute);
+  double* xg = p.level_x + (size_t)s * p.n_levels;
+  for (int lb = threadIdx.x; lb < p.n_levels; lb += kBatch * kStateThreads) {
+    int ion[kBatch];
+    double g[kBatch], en[kBatch];
+    uint8_t meta[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int l = lb + j * kStateThreads;
+      const bool in = l < p.n_levels;
+      ion[j] = in ? p.level_ion[l] : 0;
+      g[j] = in ? p.level_g[l] : 0.0;
+      en[j] = in ? p.level_energy[l] : 0.0;
+      meta[j] = in ? p.level_meta[l] : 1;
+    }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int l = lb + j * kStateThreads;
+      if (l < p.n_levels) {
+        const double nz = N[ion[j]] / Z[ion[j]];
+        double e = exp(-en[j] / kT);
+        if (dilute && !meta[j]) e = W * e;
+        pop[l] = nz * (g[j] * e);
+        xg[l] = nz * e;
+      }
+    }
   }
 }
 
-// step 5: Sobolev depths, one lane per line
+// step 5: Sobolev depths.  With x = n / g per level,
+//   n_l (1 - g_l n_u / (g_u n_l)) = g_l (x_l - x_u),
+// so tau_S = (coef g_l) (x_l - x_u): two gathers and one store per (shell,
+// line).  One workgroup takes one shell and kTauChunk lines; with kLds the
+// shell's x table is staged in LDS first, so the gathers are LDS reads
+// instead of divergent cache-line fetches.
+template <bool kLds>
 __global__ __launch_bounds__(kTauThreads) void plasma_tau_kernel(DevPlasma p) {
-  const int k = blockIdx.x * kTauThreads + threadIdx.x;
-  unsigned long long neg = 0;
-  if (k < p.L) {
-    const PlasmaLine ln = p.lines[k];
-    const double* pop = p.level_pop;
-    double* tau = p.tau + k;
-    for (int s = 0; s < p.S; ++s) {
-      const double nl = pop[ln.lower], nu = pop[ln.upper];
-      const double stim = nl > 0.0 ? 1.0 - ln.g_l * nu / (ln.g_u * nl) : 0.0;
-      double t = ln.coef * nl * stim;
-      if (t < 0.0) {
-        t = 0.0;
-        ++neg;
+  extern __shared__ double xs[];
+  const int s = blockIdx.y;
+  const double* x = p.level_x + (size_t)s * p.n_levels;
+  if (kLds) {
+    for (int lb = threadIdx.x; lb < p.n_levels; lb += kBatch * kTauThreads) {
+      double v[kBatch];
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) {
+        const int l = lb + j * kTauThreads;
+        v[j] = l < p.n_levels ? x[l] : 0.0;
       }
-      *tau = t;
-      pop += p.n_levels;
-      tau += p.Lp;
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) {
+        const int l = lb + j * kTauThreads;
+        if (l < p.n_levels) xs[l] = v[j];
+      }
+    }
+    __syncthreads();
+    x = xs;
+  }
+  const int k0 = blockIdx.x * kTauChunk;
+  const int k1 = min(k0 + kTauChunk, p.L);
+  double* tau = p.tau + (size_t)s * p.Lp;
+  unsigned long long neg = 0;
+  // kTauBatch records are loaded before any of them is used, so their
+  // latencies overlap
+  for (int kb = k0 + threadIdx.x; kb < k1; kb += kTauBatch * kTauThreads) {
+    PlasmaLine ln[kTauBatch];
+#pragma unroll
+    for (int j = 0; j < kTauBatch; ++j) {
+      const int k = kb + j * kTauThreads;
+      if (k < k1) ln[j] = p.lines[k];
+    }
+#pragma unroll
+    for (int j = 0; j < kTauBatch; ++j) {
+      const int k = kb + j * kTauThreads;
+      if (k < k1) {
+        double t = ln[j].coef_g * (x[ln[j].lower] - x[ln[j].upper]);
+        if (t < 0.0) {
+          t = 0.0;
+          ++neg;
+        }
+        tau[k] = t;
+      }
     }
   }
   neg = wave_sum_u64(neg);
@@ -239,7 +315,8 @@ __global__ __launch_bounds__(kTauThreads) void plasma_tau_kernel(DevPlasma p) {
 __global__ void plasma_lines_kernel(DevPlasma p) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= p.L) return;
-  p.lines[k].coef = kLineConst * p.line_f[k] * (kC / p.line_nu[k]) * p.t_exp;
+  const double coef = kLineConst * p.line_f[k] * (kC / p.line_nu[k]) * p.t_exp;
+  p.lines[k].coef_g = coef * p.level_g[p.lines[k].lower];
 }
 
 }  // namespace
@@ -255,8 +332,12 @@ hipError_t launch_plasma_update(const DevPlasma& p, hipStream_t s) {
   hipLaunchKernelGGL(plasma_state_kernel, dim3(p.S), dim3(kStateThreads), lds, s, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || p.L == 0) return e;
-  hipLaunchKernelGGL(plasma_tau_kernel, dim3((p.L + kTauThreads - 1) / kTauThreads),
-                     dim3(kTauThreads), 0, s, p);
+  const dim3 grid((p.L + kTauChunk - 1) / kTauChunk, p.S);
+  if (p.n_levels <= kTauLdsLevels)
+    hipLaunchKernelGGL(plasma_tau_kernel<true>, grid, dim3(kTauThreads),
+                       (size_t)p.n_levels * sizeof(double), s, p);
+  else
+    hipLaunchKernelGGL(plasma_tau_kernel<false>, grid, dim3(kTauThreads), 0, s, p);
   return hipGetLastError();
 }
 
