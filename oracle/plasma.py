@@ -30,12 +30,29 @@ order, then the Sobolev depth of section 2.5:
    model's line list.  A negative result (population inversion) is set to 0
    and counted.
 
+In the NLTE excitation mode (section 2.3), chosen ions take their level
+populations from statistical equilibrium instead of step 4: for every line
+l -> u of the ion, the downward rate per upper-level atom is
+beta A_ul + beta B_ul J_b + C_ul n_e and the upward rate per lower-level atom
+beta B_lu J_b + C_lu n_e, with beta = (1 - exp(-tau)) / tau of the line's
+current tau_S and J_b either W B_nu(T_R) or the J_blue estimator; every
+level's inflow equals its outflow and the populations sum to the ion
+density.  The system is solved by LU decomposition (numpy's LAPACK solve),
+one equation replaced by the sum.
+
 Readings where the paper is silent: T_e / T_R = 0.9 as the paper states for
 the nebular mode; zeta is a per-ion constant and delta one scalar (the paper
 takes both from its references without formulas); the partition function
 used in the Saha factor is the one of the excitation mode; the highest
 stage of each element is whatever the atom lists last (its ionization
-energy is unused).
+energy is unused).  NLTE: the printed downward rate carries n_l in its two
+radiative terms, a slip for n_u (spontaneous and stimulated emission scale
+with the upper population; with n_l the equations would not have the
+Boltzmann populations as their solution in thermodynamic equilibrium);
+electron collisions use one thermally averaged collision strength Upsilon
+per line, C_ul = 8.629e-6 Upsilon / (g_u T_e^{1/2}) and C_lu by detailed
+balance (the paper interpolates tabulated rates in temperature); T_e = 0.9
+T_R; populations below zero from rounding are set to zero.
 """
 from __future__ import annotations
 
@@ -185,16 +202,103 @@ def sobolev_tau(atom, line_nu, t_exp, pop):
     return np.where(neg, 0.0, tau), int(neg.sum())
 
 
+# ---------------------------------------------------------------------------
+# NLTE statistical equilibrium
+# ---------------------------------------------------------------------------
+# h^2 / ((2 pi m_e)^{3/2} k^{1/2}): C_ul = COLL_CONST Upsilon / (g_u T^{1/2})
+COLL_CONST = H * H / ((2.0 * math.pi * M_E) ** 1.5 * math.sqrt(K_B))
+JB_DILUTE_BLACKBODY, JB_DETAILED = 0, 1
+
+
+def planck(nu, T):
+    """B_nu(T) [erg s^-1 cm^-2 Hz^-1 sr^-1]."""
+    return 2.0 * H * nu ** 3 / C_LIGHT ** 2 / np.expm1(H * nu / (K_B * T))
+
+
+def sobolev_beta(tau):
+    """(1 - exp(-tau)) / tau, 1 at tau = 0."""
+    tau = np.asarray(tau, dtype=np.float64)
+    safe = np.where(tau > 0.0, tau, 1.0)
+    return np.where(tau > 0.0, -np.expm1(-safe) / safe, 1.0)
+
+
+def einstein_coefficients(f, nu, g_l, g_u):
+    """B_lu (for J in intensity units), B_ul and A_ul from the absorption
+    oscillator strength."""
+    B_lu = 4.0 * math.pi ** 2 * E_CHARGE ** 2 * f / (M_E * C_LIGHT * H * nu)
+    B_ul = g_l / g_u * B_lu
+    A_ul = 2.0 * H * nu ** 3 / C_LIGHT ** 2 * B_ul
+    return A_ul, B_ul, B_lu
+
+
+def collision_coefficients(upsilon, nu, g_l, g_u, T_e):
+    """C_ul and C_lu [cm^3 s^-1] from the thermally averaged collision
+    strength."""
+    C_ul = COLL_CONST * upsilon / (g_u * math.sqrt(T_e))
+    C_lu = C_ul * g_u / g_l * np.exp(-H * nu / (K_B * T_e))
+    return C_ul, C_lu
+
+
+def ion_lines(atom, ion):
+    """Indices of the lines whose levels belong to `ion`, in line order."""
+    l0, l1 = atom.ion_level_ptr[ion], atom.ion_level_ptr[ion + 1]
+    return np.flatnonzero((atom.line_lower >= l0) & (atom.line_lower < l1))
+
+
+def rate_matrix(atom, ion, line_nu, N_ion, n_e, T_R, W, tau, J_b):
+    """The statistical-equilibrium system of one ion in one shell: M n = r
+    with M[k, i] the rate from level i into level k (i != k), M[k, k] minus
+    the total rate out of k, and equation 0 replaced by sum_k n_k = N_ion."""
+    l0, l1 = atom.ion_level_ptr[ion], atom.ion_level_ptr[ion + 1]
+    n = l1 - l0
+    M = np.zeros((n, n))
+    T_e = TE_OVER_TR * T_R
+    for k in ion_lines(atom, ion):
+        lo, up = atom.line_lower[k] - l0, atom.line_upper[k] - l0
+        g_l, g_u = atom.level_g[atom.line_lower[k]], atom.level_g[atom.line_upper[k]]
+        A_ul, B_ul, B_lu = einstein_coefficients(atom.line_f[k], line_nu[k], g_l, g_u)
+        C_ul, C_lu = collision_coefficients(atom.line_upsilon[k], line_nu[k], g_l, g_u, T_e)
+        b = float(sobolev_beta(tau[k]))
+        r_ul = b * A_ul + b * B_ul * J_b[k] + C_ul * n_e
+        r_lu = b * B_lu * J_b[k] + C_lu * n_e
+        M[lo, up] += r_ul
+        M[up, up] -= r_ul
+        M[up, lo] += r_lu
+        M[lo, lo] -= r_lu
+    M[0, :] = 1.0
+    rhs = np.zeros(n)
+    rhs[0] = N_ion
+    return M, rhs
+
+
+def nlte_populations(atom, ion, line_nu, N_ion, n_e, T_R, W, tau, J_b):
+    """Level populations of one ion in one shell from statistical
+    equilibrium (LU solve)."""
+    M, rhs = rate_matrix(atom, ion, line_nu, N_ion, n_e, T_R, W, tau, J_b)
+    return np.maximum(np.linalg.solve(M, rhs), 0.0)
+
+
 def plasma_state(atom, number_density, line_nu, t_exp, T_R, W, ionization, excitation,
-                 delta=1.0):
+                 delta=1.0, nlte_ions=(), tau_prev=None, jblue=None):
     """Steps 1-5 for every shell; returns a dict with n_e [S], Z and N_ion
-    [S, n_ions], level_pop [S, n_levels], tau [S, L] and n_clamped."""
+    [S, n_ions], level_pop [S, n_levels], tau [S, L] and n_clamped.
+    nlte_ions: ions whose populations come from statistical equilibrium,
+    with beta from tau_prev [S, L] (zeros if None) and J_b from jblue [S, L]
+    (None: W B_nu(T_R))."""
     T_R = np.asarray(T_R, dtype=np.float64)
     W = np.asarray(W, dtype=np.float64)
     Z = partition_functions(atom, T_R, W, excitation)
     lr = log_ionization_ratios(atom, Z, T_R, W, ionization, delta)
     n_e, N_ion = ion_densities(atom, lr, np.asarray(number_density, dtype=np.float64))
     pop = level_populations(atom, Z, N_ion, T_R, W, excitation)
+    S, L = T_R.shape[0], len(line_nu)
+    for ion in nlte_ions:
+        l0, l1 = atom.ion_level_ptr[ion], atom.ion_level_ptr[ion + 1]
+        for s in range(S):
+            tau_s = np.zeros(L) if tau_prev is None else tau_prev[s]
+            J_b = W[s] * planck(np.asarray(line_nu), T_R[s]) if jblue is None else jblue[s]
+            pop[s, l0:l1] = nlte_populations(atom, ion, line_nu, N_ion[s, ion], n_e[s], T_R[s],
+                                             W[s], tau_s, J_b)
     tau, n_clamped = sobolev_tau(atom, line_nu, t_exp, pop)
     return dict(n_e=n_e, Z=Z, N_ion=N_ion, level_pop=pop, tau=tau, n_clamped=n_clamped,
                 log_ratio=lr)

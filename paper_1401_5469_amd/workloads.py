@@ -418,6 +418,7 @@ class PlasmaAtom:
     line_lower: np.ndarray  # [L] int32, global level index
     line_upper: np.ndarray  # [L] int32
     line_f: np.ndarray  # [L] absorption oscillator strength
+    line_upsilon: Optional[np.ndarray] = None  # [L] collision strengths (NLTE ions' lines)
 
     @property
     def n_elements(self) -> int:
@@ -435,18 +436,20 @@ class PlasmaAtom:
         return np.repeat(np.arange(self.n_ions, dtype=np.int32), np.diff(self.ion_level_ptr))
 
     def nbytes(self) -> int:
-        return sum(getattr(self, f.name).nbytes for f in dataclasses.fields(self))
+        return sum(getattr(self, f.name).nbytes for f in dataclasses.fields(self)
+                   if getattr(self, f.name) is not None)
 
 
 @dataclasses.dataclass
 class PlasmaSpec:
     atom: PlasmaAtom
     number_density: np.ndarray  # [S, E] element number densities [cm^-3]
+    nlte_ions: tuple = ()  # ions whose populations come from statistical equilibrium
 
 
 def synthetic_plasma_atom(rng, n_elements: int = 8, n_stages: int = 5,
                           n_levels_per_ion: int = 60, n_lines: int = 20_000,
-                          lam=(300.0, 25000.0)):
+                          lam=(300.0, 25000.0), nlte_ions=(), n_levels_nlte: int = 40):
     """Synthetic atom: the first n_elements of PLASMA_ELEMENTS with stages
     0 .. n_stages-1 each; ionization energies chi_0 * _CHI_SCALE[j]; per ion
     the ground state plus n_levels_per_ion-1 levels with energies U(0,
@@ -454,50 +457,69 @@ def synthetic_plasma_atom(rng, n_elements: int = 8, n_stages: int = 5,
     metastable with probability 0.25 below 0.3 chi and 0.02 above; zeta
     U(0.1, 0.9).  Lines: n_lines distinct (ion, lower < upper) pairs whose
     wavelength h c / (e_u - e_l) lies in [lam] Angstrom, drawn without
-    replacement, f log-uniform in [1e-4, 1].  Returns the atom with lines
-    sorted by non-increasing frequency, and the line frequencies."""
+    replacement, f log-uniform in [1e-4, 1], collision strengths
+    log-uniform in [0.1, 10].  Ions listed in nlte_ions (global ion
+    indices) get n_levels_nlte levels with excited energies U(0.6 eV,
+    0.95 chi), and a line from the ground state to every excited level is
+    always among the lines, so that statistical equilibrium connects all of
+    their levels.  Returns the atom with lines sorted by non-increasing
+    frequency, and the line frequencies."""
     elems = PLASMA_ELEMENTS[:n_elements]
-    nl = n_levels_per_ion
     n_ions = n_elements * n_stages
+    nlte = set(int(i) for i in nlte_ions)
+    nls = np.array([n_levels_nlte if i in nlte else n_levels_per_ion for i in range(n_ions)])
+    lptr = np.zeros(n_ions + 1, dtype=np.int64)
+    lptr[1:] = np.cumsum(nls)
     chi = np.array([z[2] * _CHI_SCALE[j] * EV for z in elems for j in range(n_stages)])
     zeta = rng.uniform(0.1, 0.9, n_ions)
-    energy = np.zeros((n_ions, nl))
-    g = np.zeros((n_ions, nl))
-    meta = np.zeros((n_ions, nl), dtype=np.uint8)
+    energy = np.zeros(lptr[-1])
+    g = np.zeros(lptr[-1])
+    meta = np.zeros(lptr[-1], dtype=np.uint8)
     for i in range(n_ions):
-        energy[i, 1:] = np.sort(rng.uniform(0.0, 0.95 * chi[i], nl - 1))
-        g[i, 0] = rng.integers(1, 6)
-        g[i, 1:] = rng.integers(1, 10, nl - 1)
-        meta[i, 0] = 1
-        low = energy[i, 1:] < 0.3 * chi[i]
+        a, nl = lptr[i], nls[i]
+        lo_e = 0.6 * EV if i in nlte else 0.0
+        energy[a + 1:a + nl] = np.sort(rng.uniform(lo_e, 0.95 * chi[i], nl - 1))
+        g[a] = rng.integers(1, 6)
+        g[a + 1:a + nl] = rng.integers(1, 10, nl - 1)
+        meta[a] = 1
+        low = energy[a + 1:a + nl] < 0.3 * chi[i]
         u = rng.uniform(0.0, 1.0, nl - 1)
-        meta[i, 1:] = np.where(low, u < 0.25, u < 0.02)
-    lo_i, up_i = np.triu_indices(nl, k=1)
-    ion = np.repeat(np.arange(n_ions), lo_i.size)
-    lower = np.tile(lo_i, n_ions)
-    upper = np.tile(up_i, n_ions)
-    de = energy[ion, upper] - energy[ion, lower]
+        meta[a + 1:a + nl] = np.where(low, u < 0.25, u < 0.02)
+    ions, lowers, uppers = [], [], []
+    for i in range(n_ions):
+        lo_i, up_i = np.triu_indices(nls[i], k=1)
+        ions.append(np.full(lo_i.size, i))
+        lowers.append(lptr[i] + lo_i)
+        uppers.append(lptr[i] + up_i)
+    ion, lower, upper = np.concatenate(ions), np.concatenate(lowers), np.concatenate(uppers)
+    de = energy[upper] - energy[lower]
     with np.errstate(divide="ignore"):
         lam_aa = np.where(de > 0.0, H * C_LIGHT / np.where(de > 0.0, de, 1.0) / ANGSTROM, np.inf)
-    ok = np.flatnonzero((lam_aa >= lam[0]) & (lam_aa <= lam[1]))
-    if ok.size < n_lines:
+    window = (lam_aa >= lam[0]) & (lam_aa <= lam[1])
+    star = np.isin(ion, list(nlte)) & (lower == lptr[ion])
+    ok = np.flatnonzero(window & ~star)
+    must = np.flatnonzero(star)
+    if ok.size < n_lines - must.size:
         raise ValueError(f"only {ok.size} level pairs in the wavelength window")
-    pick = np.sort(rng.choice(ok, size=n_lines, replace=False))
+    pick = np.sort(np.concatenate([rng.choice(ok, size=n_lines - must.size, replace=False),
+                                   must]))
     ion, lower, upper = ion[pick], lower[pick], upper[pick]
     f = 10.0 ** rng.uniform(-4.0, 0.0, n_lines)
-    nu = (energy[ion, upper] - energy[ion, lower]) / H
+    nu = (energy[upper] - energy[lower]) / H
     order = np.argsort(-nu, kind="stable")
     ion, lower, upper, f, nu = ion[order], lower[order], upper[order], f[order], nu[order]
+    upsilon = 10.0 ** rng.uniform(-1.0, 1.0, n_lines)
     atom = PlasmaAtom(
         element_ion_ptr=_contig(np.arange(n_elements + 1) * n_stages, np.int32),
         ion_chi=_contig(chi, np.float64), ion_zeta=_contig(zeta, np.float64),
-        ion_level_ptr=_contig(np.arange(n_ions + 1) * nl, np.int32),
-        level_energy=_contig(energy.reshape(-1), np.float64),
-        level_g=_contig(g.reshape(-1), np.float64),
-        level_metastable=_contig(meta.reshape(-1), np.uint8),
-        line_lower=_contig(ion * nl + lower, np.int32),
-        line_upper=_contig(ion * nl + upper, np.int32),
-        line_f=_contig(f, np.float64))
+        ion_level_ptr=_contig(lptr, np.int32),
+        level_energy=_contig(energy, np.float64),
+        level_g=_contig(g, np.float64),
+        level_metastable=_contig(meta, np.uint8),
+        line_lower=_contig(lower, np.int32),
+        line_upper=_contig(upper, np.int32),
+        line_f=_contig(f, np.float64),
+        line_upsilon=_contig(upsilon, np.float64))
     return atom, _contig(nu, np.float64)
 
 
@@ -511,7 +533,7 @@ def element_densities(rho, n_elements: int):
 def plasma_model(seed: int = 0, n_shells: int = 20, n_elements: int = 8, n_stages: int = 5,
                  n_levels_per_ion: int = 60, n_lines: int = 20_000,
                  v_lo: float = 10000.0, v_hi: float = 25000.0, t_exp_days: float = 13.0,
-                 rho_inner: float = 3.0e-14):
+                 rho_inner: float = 3.0e-14, nlte_ions=(), n_levels_nlte: int = 40):
     """Scatter-mode model whose Sobolev depths and electron densities come
     from the plasma update: shells as config 2 (rho ~ v^-7), equal mass
     fractions of the synthetic elements.  tau_sobolev and n_e start at zero
@@ -520,11 +542,13 @@ def plasma_model(seed: int = 0, n_shells: int = 20, n_elements: int = 8, n_stage
     v = np.linspace(v_lo * KM, v_hi * KM, n_shells + 1)
     v_mid = 0.5 * (v[:-1] + v[1:])
     rho = rho_inner * (v_mid / v_mid[0]) ** -7.0
-    atom, nu = synthetic_plasma_atom(rng, n_elements, n_stages, n_levels_per_ion, n_lines)
+    atom, nu = synthetic_plasma_atom(rng, n_elements, n_stages, n_levels_per_ion, n_lines,
+                                     nlte_ions=nlte_ions, n_levels_nlte=n_levels_nlte)
     model = Model(v_bounds=_contig(v, np.float64), t_exp=t_exp_days * DAY,
                   n_e=np.zeros(n_shells), line_nu=nu,
                   tau_sobolev=np.zeros((n_shells, n_lines)), seed=seed)
-    return model, PlasmaSpec(atom=atom, number_density=element_densities(rho, n_elements))
+    return model, PlasmaSpec(atom=atom, number_density=element_densities(rho, n_elements),
+                             nlte_ions=tuple(int(i) for i in nlte_ions))
 
 
 def config_plasma(seed: int = 0, n_packets: int = 1_000_000, n_lines: int = 300_000,

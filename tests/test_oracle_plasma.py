@@ -225,3 +225,153 @@ def test_electron_density_grows_with_temperature_to_full_ionization():
         prev = ne
     hot = P.plasma_state(atom, N, nu, 1e6, [3e6], [1.0], P.ION_LTE, P.EXC_LTE)["n_e"][0]
     assert hot == pytest.approx(full, rel=1e-3)
+
+
+# ---------------------------------------------------------------------------
+# NLTE statistical equilibrium (section 2.3)
+# ---------------------------------------------------------------------------
+SIGMA_SB = 5.670374419e-5
+A_CONST_AA = 6.670e15     # A_ul = 6.670e15 (g_l / g_u) f / lambda[A]^2 s^-1 (textbook value)
+COLL_TEXTBOOK = 8.629e-6  # C_ul = 8.629e-6 Upsilon / (g_u T^{1/2}) cm^3 s^-1 (textbook value)
+
+
+def test_collision_and_einstein_constants():
+    assert P.COLL_CONST == pytest.approx(COLL_TEXTBOOK, rel=2e-4)
+    # H-alpha: f = 0.6407, g_l = 8, g_u = 18, 6562.8 A -> A_ul = 4.41e7 s^-1
+    lam = 6562.8
+    A, B_ul, B_lu = P.einstein_coefficients(0.6407, C / (lam * 1e-8), 8.0, 18.0)
+    assert A == pytest.approx(A_CONST_AA * 8.0 / 18.0 * 0.6407 / lam ** 2, rel=1e-3)
+    assert A == pytest.approx(4.41e7, rel=5e-3)
+    assert B_ul * 18.0 == pytest.approx(B_lu * 8.0, rel=1e-14)
+
+
+def test_planck_and_escape_probability():
+    from scipy import integrate
+    for T in (5000.0, 12000.0, 30000.0):
+        x = np.linspace(1e-4, 60.0, 200001)
+        nu = x * K_B * T / H
+        tot = integrate.simpson(P.planck(nu, T), x=nu)
+        assert tot == pytest.approx(SIGMA_SB * T ** 4 / math.pi, rel=1e-7)
+    b = P.sobolev_beta(np.array([0.0, 1e-8, 1.0, 50.0, 1e4]))
+    np.testing.assert_allclose(b, [1.0, 1.0 - 5e-9, 1.0 - math.exp(-1.0), 1.0 / 50.0, 1e-4],
+                               rtol=1e-14)
+
+
+def _nlte_atom(n_levels=6, seed=0, all_pairs=False):
+    rng = np.random.default_rng(seed)
+    e = np.concatenate([[0.0], np.sort(rng.uniform(1.0, 9.0, n_levels - 1))])
+    g = rng.integers(1, 8, n_levels).astype(float)
+    if all_pairs:
+        pairs = [(l, u) for u in range(n_levels) for l in range(u)]
+    else:
+        pairs = [(0, u) for u in range(1, n_levels)] + [(1, 3), (2, 4)][: max(0, n_levels - 4)]
+    de = np.array([e[u] - e[l] for l, u in pairs])
+    order = np.argsort(-de, kind="stable")
+    pairs = [pairs[i] for i in order]
+    f = rng.uniform(0.01, 0.5, len(pairs))
+    levels = [(float(e[i]), float(g[i]), 1 if i == 0 else 0) for i in range(n_levels)]
+    atom = _atom([[(levels, 20.0, 0.5), ([(0.0, 1.0, 1)], 0.0, 0.0)]], pairs, line_f=f)
+    atom.line_upsilon = rng.uniform(0.1, 5.0, len(pairs))
+    nu = de[order] * EV / H
+    return atom, nu, e * EV, g
+
+
+def _boltzmann(e, g, T, N):
+    w = g * np.exp(-e / (K_B * T))
+    return N * w / w.sum()
+
+
+@pytest.mark.parametrize("tau", [0.0, 3.0, 1e3])
+def test_nlte_radiative_equilibrium_is_boltzmann(tau):
+    # no electrons, an undiluted Planck field: detailed balance line by line
+    # at T_R for any escape probability
+    atom, nu, e, g = _nlte_atom(all_pairs=True)
+    T, N = 9000.0, 1e7
+    taus = np.full(len(nu), tau)
+    pop = P.nlte_populations(atom, 0, nu, N, 0.0, T, 1.0, taus, P.planck(nu, T))
+    np.testing.assert_allclose(pop, _boltzmann(e, g, T, N), rtol=1e-9)
+
+
+def test_nlte_collisional_equilibrium_is_boltzmann_at_te():
+    # collisions dominate (huge n_e, negligible field): Boltzmann at T_e = 0.9 T_R
+    atom, nu, e, g = _nlte_atom(seed=1)
+    T, N = 12000.0, 1e7
+    pop = P.nlte_populations(atom, 0, nu, N, 1e30, T, 1e-300, np.zeros(len(nu)),
+                             np.zeros(len(nu)))
+    np.testing.assert_allclose(pop, _boltzmann(e, g, 0.9 * T, N), rtol=1e-8)
+
+
+@pytest.mark.parametrize("n_e,W,tau", [(0.0, 0.3, 0.0), (1e9, 0.3, 5.0), (1e12, 0.05, 100.0)])
+def test_nlte_two_levels_closed_form(n_e, W, tau):
+    atom, nu, e, g = _nlte_atom(n_levels=2, seed=2)
+    T, N = 10000.0, 1e8
+    lam_aa = C / nu[0] / 1e-8
+    f, ups = atom.line_f[0], atom.line_upsilon[0]
+    A = A_CONST_AA * g[0] / g[1] * f / lam_aa ** 2
+    B_ul = A * C ** 2 / (2.0 * H * nu[0] ** 3)
+    B_lu = g[1] / g[0] * B_ul
+    J = W * 2.0 * H * nu[0] ** 3 / C ** 2 / math.expm1(H * nu[0] / (K_B * T))
+    Te = 0.9 * T
+    C_ul = COLL_TEXTBOOK * ups / (g[1] * math.sqrt(Te))
+    C_lu = C_ul * g[1] / g[0] * math.exp(-H * nu[0] / (K_B * Te))
+    b = 1.0 if tau == 0.0 else -math.expm1(-tau) / tau
+    ratio = (b * B_lu * J + C_lu * n_e) / (b * A + b * B_ul * J + C_ul * n_e)
+    pop = P.nlte_populations(atom, 0, nu, N, n_e, T, W, np.array([tau]),
+                             W * P.planck(nu, T))
+    np.testing.assert_allclose(pop, [N / (1 + ratio), N * ratio / (1 + ratio)], rtol=2e-3)
+    assert pop.sum() == pytest.approx(N, rel=1e-14)
+
+
+def test_nlte_flux_balance_and_detailed_j():
+    # a J_blue array per line (as the estimator gives it): every level's
+    # inflow equals its outflow, computed line by line from the oracle's
+    # coefficients
+    atom, nu, e, g = _nlte_atom(n_levels=7, seed=3, all_pairs=True)
+    rng = np.random.default_rng(5)
+    T, Wd, n_e, N = 8000.0, 0.4, 3e8, 1e9
+    J = P.planck(nu, T) * rng.uniform(0.05, 2.0, len(nu))
+    taus = 10.0 ** rng.uniform(-2, 3, len(nu))
+    pop = P.nlte_populations(atom, 0, nu, N, n_e, T, Wd, taus, J)
+    flow = np.zeros(7)
+    scale = np.zeros(7)
+    for k in range(len(nu)):
+        lo, up = atom.line_lower[k], atom.line_upper[k]
+        A, B_ul, B_lu = P.einstein_coefficients(atom.line_f[k], nu[k], g[lo], g[up])
+        C_ul, C_lu = P.collision_coefficients(atom.line_upsilon[k], nu[k], g[lo], g[up], 0.9 * T)
+        b = float(P.sobolev_beta(taus[k]))
+        down = pop[up] * (b * A + b * B_ul * J[k] + C_ul * n_e)
+        upw = pop[lo] * (b * B_lu * J[k] + C_lu * n_e)
+        flow[lo] += down - upw
+        flow[up] += upw - down
+        scale[lo] += down + upw
+        scale[up] += down + upw
+    assert np.all(np.abs(flow) <= 1e-9 * scale)
+    assert pop.sum() == pytest.approx(N, rel=1e-13)
+    assert np.all(pop > 0)
+
+
+def test_plasma_state_with_an_nlte_ion():
+    rng = np.random.default_rng(6)
+    atom, nu = W.synthetic_plasma_atom(rng, n_elements=4, n_stages=4, n_levels_per_ion=20,
+                                       n_lines=1500, nlte_ions=(9,), n_levels_nlte=12)
+    S = 3
+    N = 10.0 ** rng.uniform(7.0, 9.0, (S, atom.n_elements))
+    T, Wd = rng.uniform(7000, 15000, S), rng.uniform(0.1, 0.5, S)
+    base = P.plasma_state(atom, N, nu, 1e6, T, Wd, P.ION_NEBULAR, P.EXC_DILUTE_LTE)
+    r = P.plasma_state(atom, N, nu, 1e6, T, Wd, P.ION_NEBULAR, P.EXC_DILUTE_LTE,
+                       nlte_ions=(9,), tau_prev=base["tau"])
+    l0, l1 = atom.ion_level_ptr[9], atom.ion_level_ptr[10]
+    np.testing.assert_array_equal(r["level_pop"][:, :l0], base["level_pop"][:, :l0])
+    np.testing.assert_array_equal(r["level_pop"][:, l1:], base["level_pop"][:, l1:])
+    np.testing.assert_allclose(r["level_pop"][:, l0:l1].sum(axis=1), r["N_ion"][:, 9],
+                               rtol=1e-12)
+    assert not np.allclose(r["level_pop"][:, l0:l1], base["level_pop"][:, l0:l1])
+    # the dilute-blackbody J_b = W B_nu(T_R) and the previous depths reach the
+    # solve of every shell
+    for s in range(S):
+        want = P.nlte_populations(atom, 9, nu, r["N_ion"][s, 9], r["n_e"][s], T[s], Wd[s],
+                                  base["tau"][s], Wd[s] * P.planck(nu, T[s]))
+        np.testing.assert_array_equal(r["level_pop"][s, l0:l1], want)
+    mine = (atom.line_lower >= l0) & (atom.line_lower < l1)
+    assert mine.sum() >= 11
+    np.testing.assert_array_equal(r["tau"][:, ~mine], base["tau"][:, ~mine])
