@@ -289,6 +289,19 @@ int smc_read_timing(smc_model* model, double* transport_ms);
  *   5. tau_S = (pi e^2 / m_e c) f lambda t_exp n_l (1 - g_l n_u / (g_u n_l))
  *      with lambda = c / nu of the model's line list; a negative value
  *      (population inversion) is stored as 0 and counted.
+ * NLTE excitation (section 2.3): the ions listed in the description may
+ * instead take their level populations from statistical equilibrium.  For
+ * every line l -> u of such an ion the downward rate per upper-level atom is
+ * beta A_ul + beta B_ul J_b + C_ul n_e and the upward rate per lower-level
+ * atom beta B_lu J_b + C_lu n_e, with beta = (1 - e^-tau) / tau of the line's
+ * tau_S in the model when the update starts (1 at tau = 0), J_b = W B_nu(T_R)
+ * or the model's J_blue estimator, A and B from f, and
+ * C_ul = 8.629e-6 Upsilon / (g_u T_e^{1/2}), C_lu = C_ul (g_u / g_l)
+ * exp(-h nu / k T_e), T_e = 0.9 T_R.  Inflow equals outflow for every level
+ * and the populations sum to the ion density; the system is solved by LU
+ * decomposition with partial pivoting, one workgroup per (ion, shell).
+ * Populations below zero from rounding are stored as 0; a singular system
+ * leaves that ion's populations from step 4 and is counted.
  * The model's line-interaction tables (downbranch, macroatom) are not
  * changed.  Calls on a plasma and on its model must not overlap.
  * ------------------------------------------------------------------------- */
@@ -296,6 +309,9 @@ int smc_read_timing(smc_model* model, double* transport_ms);
 #define SMC_ION_NEBULAR 1    /* modified nebular approximation */
 #define SMC_EXC_LTE 0        /* Boltzmann level populations at T_R */
 #define SMC_EXC_DILUTE_LTE 1 /* Boltzmann, times W for levels that are not metastable */
+#define SMC_JB_DILUTE_BLACKBODY 0 /* NLTE rates with J_b = W B_nu(T_R) */
+#define SMC_JB_DETAILED 1         /* NLTE rates with the J_blue estimator of the model's last
+                                     iteration (W B_nu(T_R) before its first iteration) */
 
 typedef struct smc_plasma smc_plasma;
 
@@ -305,7 +321,7 @@ typedef struct {
   int32_t n_elements;              /* E, 1 .. 256 */
   int32_t n_ions;                  /* ion stages of all elements, E .. 2048 */
   int32_t n_levels;                /* levels of all ions, >= n_ions */
-  int32_t reserved;                /* must be 0 */
+  int32_t n_nlte_ions;             /* ions that may take NLTE populations, 0 .. 64 */
   const int32_t* element_ion_ptr;  /* [E+1] the stages of element e are ions ptr[e] .. ptr[e+1]-1,
                                       stage j (charge j) at ptr[e] + j; ptr[0] = 0, increasing,
                                       ptr[E] = n_ions */
@@ -325,6 +341,12 @@ typedef struct {
   const double* line_f;            /* [L] absorption oscillator strength, >= 0 */
   const double* number_density;    /* [S*E] element number densities [cm^-3], >= 0,
                                       shell-major */
+  const int32_t* nlte_ions;        /* [n_nlte_ions] distinct ion indices, each with 1 .. 64
+                                      levels all joined to its ground state by its lines
+                                      (NULL when n_nlte_ions = 0) */
+  const double* line_upsilon;      /* [L] thermally averaged collision strength of each line,
+                                      >= 0; read for the lines of NLTE ions only (NULL when
+                                      n_nlte_ions = 0) */
 } smc_plasma_desc;
 
 typedef struct {
@@ -335,6 +357,11 @@ typedef struct {
                           the model's current T_R and W on the device (the last
                           iteration's, or the initial field of smc_model_load) */
   const double* W;     /* host [S] dilution factors > 0, or NULL */
+  int32_t nlte;        /* 1: statistical equilibrium for the description's NLTE ions;
+                          0: they follow `excitation` like every other ion */
+  int32_t jblue_mode;  /* SMC_JB_DILUTE_BLACKBODY or SMC_JB_DETAILED (NLTE only; detailed
+                          needs a model loaded with SMC_F_JBLUE whose last iteration, if
+                          any, tallied J_blue) */
 } smc_plasma_params;
 
 /* Device workspace of a plasma object for a model of n_shells shells and
@@ -353,10 +380,11 @@ int smc_plasma_load(smc_model* model, const smc_plasma_desc* desc, void* d_works
 int smc_plasma_update(smc_plasma* plasma, const smc_plasma_params* params, void* stream);
 /* Copy the state of the last update to host buffers (any may be NULL):
  * n_e [S], ion densities and partition functions [S*n_ions], level
- * populations [S*n_levels], tau_sobolev [S*L] (all shell-major) and the
- * number of inverted lines stored as 0.  Synchronises `stream`. */
+ * populations [S*n_levels], tau_sobolev [S*L] (all shell-major) and
+ * counts[2]: inverted (shell, line) pairs stored as 0, and singular NLTE
+ * systems.  Synchronises `stream`. */
 int smc_plasma_read(smc_plasma* plasma, double* n_e, double* ion_density, double* partition,
-                    double* level_pop, double* tau_sobolev, uint64_t* n_clamped, void* stream);
+                    double* level_pop, double* tau_sobolev, uint64_t* counts, void* stream);
 /* Release the handle; never frees the caller's workspace. */
 int smc_plasma_free(smc_plasma* plasma);
 

@@ -996,6 +996,7 @@ struct smc_plasma {
   smc::PlasmaLayout lay;
   smc::DevPlasma dev;
   uint8_t* base;
+  int32_t n_nlte;
   bool updated;
 };
 
@@ -1003,7 +1004,6 @@ namespace {
 
 int validate_plasma(const smc_plasma_desc* d, int32_t S, int64_t L) {
   if (!d) return fail(SMC_EINVAL, "null plasma description");
-  if (d->reserved != 0) return fail(SMC_EINVAL, "reserved field must be 0");
   if (S < 1 || S > kMaxShells) return fail(SMC_EINVAL, "n_shells=%d outside [1, %d]", S, kMaxShells);
   if (L < 0 || L > INT32_MAX) return fail(SMC_EINVAL, "n_lines=%lld outside [0, 2^31)", (long long)L);
   const int32_t E = d->n_elements, NI = d->n_ions, NL = d->n_levels;
@@ -1062,7 +1062,67 @@ int validate_plasma(const smc_plasma_desc* d, int32_t S, int64_t L) {
   for (int64_t j = 0; j < n_dens; ++j)
     if (!(d->number_density[j] >= 0.0) || !isfinite(d->number_density[j]))
       return fail(SMC_EINVAL, "number_density[%lld] must be finite and >= 0", (long long)j);
+  // NLTE ions: distinct, small enough for the LDS system, every level joined
+  // to the ground state by the ion's lines
+  const int32_t NN = d->n_nlte_ions;
+  if (NN < 0 || NN > smc::kNlteMaxIons || NN > NI)
+    return fail(SMC_EINVAL, "n_nlte_ions=%d outside [0, min(n_ions, %d)]", NN, smc::kNlteMaxIons);
+  if (NN > 0 && (!d->nlte_ions || (L > 0 && !d->line_upsilon)))
+    return fail(SMC_EINVAL, "NLTE ions need nlte_ions and line_upsilon");
+  for (int32_t j = 0; j < NN; ++j) {
+    const int32_t ion = d->nlte_ions[j];
+    if (ion < 0 || ion >= NI) return fail(SMC_EINVAL, "nlte_ions[%d]=%d out of range", j, ion);
+    for (int32_t q = 0; q < j; ++q)
+      if (d->nlte_ions[q] == ion) return fail(SMC_EINVAL, "NLTE ion %d listed twice", ion);
+    const int32_t l0 = d->ion_level_ptr[ion], n = d->ion_level_ptr[ion + 1] - l0;
+    if (n > smc::kNlteMaxLevels)
+      return fail(SMC_EINVAL, "NLTE ion %d has %d levels (at most %d)", ion, n,
+                  smc::kNlteMaxLevels);
+    std::vector<int32_t> root(n);
+    for (int32_t v = 0; v < n; ++v) root[v] = v;
+    auto find = [&](int32_t v) {
+      while (root[v] != v) v = root[v] = root[root[v]];
+      return v;
+    };
+    for (int64_t k = 0; k < L; ++k) {
+      const int32_t lo = d->line_lower[k] - l0, up = d->line_upper[k] - l0;
+      if (lo < 0 || lo >= n) continue;
+      if (!(d->line_upsilon[k] >= 0.0) || !isfinite(d->line_upsilon[k]))
+        return fail(SMC_EINVAL, "line_upsilon[%lld] must be finite and >= 0", (long long)k);
+      root[find(lo)] = find(up);
+    }
+    for (int32_t v = 1; v < n; ++v)
+      if (find(v) != find(0))
+        return fail(SMC_EINVAL, "level %d of NLTE ion %d is not joined to its ground state by "
+                    "lines", v, ion);
+  }
   return SMC_OK;
+}
+
+// lines of each NLTE ion (the lines whose lower level is in the ion), in
+// line order
+std::vector<int64_t> nlte_line_offsets(const smc_plasma_desc* d, int64_t L,
+                                       std::vector<smc::NlteLine>* recs) {
+  std::vector<int64_t> ptr(1, 0);
+  for (int32_t j = 0; j < d->n_nlte_ions; ++j) {
+    const int32_t ion = d->nlte_ions[j];
+    const int32_t l0 = d->ion_level_ptr[ion], l1 = d->ion_level_ptr[ion + 1];
+    int64_t count = 0;
+    for (int64_t k = 0; k < L; ++k) {
+      if (d->line_lower[k] < l0 || d->line_lower[k] >= l1) continue;
+      ++count;
+      if (recs) {
+        smc::NlteLine r;
+        memset(&r, 0, sizeof r);
+        r.line = (int32_t)k;
+        r.lo = (int16_t)(d->line_lower[k] - l0);
+        r.up = (int16_t)(d->line_upper[k] - l0);
+        recs->push_back(r);
+      }
+    }
+    ptr.push_back(ptr.back() + count);
+  }
+  return ptr;
 }
 
 smc::PlasmaLayout plasma_layout_of(const smc_plasma_desc* d, int32_t S, int64_t L) {
@@ -1093,6 +1153,12 @@ smc::PlasmaLayout plasma_layout_of(const smc_plasma_desc* d, int32_t S, int64_t 
   l.level_pop = take(SS * NL * 8);
   l.level_x = take(SS * NL * 8);
   l.clamped = take(2 * 8);
+  const uint64_t NN = (uint64_t)d->n_nlte_ions;
+  const uint64_t n_nlte_lines = NN ? (uint64_t)nlte_line_offsets(d, L, nullptr).back() : 0;
+  l.nlte_ions = take(NN * 4);
+  l.nlte_line_ptr = take((NN + 1) * 4);
+  l.nlte_lines = take(n_nlte_lines * sizeof(smc::NlteLine));
+  l.line_upsilon = take(NN ? LL * 8 : 0);
   l.total = off;
   return l;
 }
@@ -1162,6 +1228,21 @@ int smc_plasma_load(smc_model* model, const smc_plasma_desc* d, void* d_workspac
                 "upload lines")) ||
       (rc = h2d(base, lay.density, d->number_density, (size_t)S * E * 8, s, "upload density")))
     return rc;
+  const int32_t NN = d->n_nlte_ions;
+  std::vector<smc::NlteLine> nlte_recs;
+  std::vector<int32_t> nlte_ptr32;
+  if (NN > 0) {
+    const std::vector<int64_t> ptr = nlte_line_offsets(d, L, &nlte_recs);
+    nlte_ptr32.assign(ptr.begin(), ptr.end());
+    if ((rc = h2d(base, lay.nlte_ions, d->nlte_ions, (size_t)NN * 4, s, "upload nlte_ions")) ||
+        (rc = h2d(base, lay.nlte_line_ptr, nlte_ptr32.data(), (size_t)(NN + 1) * 4, s,
+                  "upload NLTE line offsets")) ||
+        (rc = h2d(base, lay.nlte_lines, nlte_recs.data(),
+                  nlte_recs.size() * sizeof(smc::NlteLine), s, "upload NLTE lines")) ||
+        (rc = h2d(base, lay.line_upsilon, d->line_upsilon, (size_t)L * 8, s,
+                  "upload line_upsilon")))
+      return rc;
+  }
 
   smc_plasma* p = new (std::nothrow) smc_plasma;
   if (!p) return fail(SMC_ENOMEM, "host allocation failed");
@@ -1196,7 +1277,14 @@ int smc_plasma_load(smc_model* model, const smc_plasma_desc* d, void* d_workspac
   dp.n_e = const_cast<double*>(model->dev.n_e);
   dp.tau = const_cast<double*>(model->dev.tau);
   dp.line_nu = model->dev.line_nu;
-  hipError_t e = smc::launch_plasma_lines(dp, s);
+  p->n_nlte = NN;
+  dp.n_nlte = 0;  // set per update
+  dp.nlte_ions = (const int32_t*)(base + lay.nlte_ions);
+  dp.nlte_line_ptr = (const int32_t*)(base + lay.nlte_line_ptr);
+  dp.nlte_lines = (smc::NlteLine*)(base + lay.nlte_lines);
+  dp.line_upsilon = (const double*)(base + lay.line_upsilon);
+  // the host staging vectors must stay alive until the copies have run
+  hipError_t e = smc::launch_plasma_lines(dp, (int)nlte_recs.size(), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     delete p;
@@ -1216,6 +1304,15 @@ int smc_plasma_update(smc_plasma* p, const smc_plasma_params* pp, void* stream) 
     return fail(SMC_EINVAL, "delta must be finite and >= 0");
   if ((pp->T_R == nullptr) != (pp->W == nullptr))
     return fail(SMC_EINVAL, "give both T_R and W, or neither");
+  if (pp->nlte != 0 && pp->nlte != 1) return fail(SMC_EINVAL, "nlte must be 0 or 1");
+  if (pp->jblue_mode != SMC_JB_DILUTE_BLACKBODY && pp->jblue_mode != SMC_JB_DETAILED)
+    return fail(SMC_EINVAL, "unknown J_b mode %d", pp->jblue_mode);
+  const smc_model* m = p->model;
+  const bool detailed = pp->nlte && p->n_nlte > 0 && pp->jblue_mode == SMC_JB_DETAILED;
+  if (detailed && !m->dev.jblue)
+    return fail(SMC_EINVAL, "detailed J_b needs a model loaded with SMC_F_JBLUE");
+  if (detailed && m->ran && !(m->last_flags & SMC_F_JBLUE))
+    return fail(SMC_EINVAL, "the model's last iteration did not tally J_blue");
   const int32_t S = p->dev.S;
   if (pp->T_R) {
     for (int32_t i = 0; i < S; ++i) {
@@ -1231,6 +1328,9 @@ int smc_plasma_update(smc_plasma* p, const smc_plasma_params* pp, void* stream) 
   d.ionization = pp->ionization;
   d.excitation = pp->excitation;
   d.delta = pp->delta;
+  d.n_nlte = pp->nlte ? p->n_nlte : 0;
+  d.jb_detailed = detailed && m->ran ? 1 : 0;  // before any iteration: W B_nu(T_R)
+  d.jblue = m->dev.jblue;
   if (pp->T_R) {
     double* field = (double*)(p->base + p->lay.field);
     HIP_TRY(hipMemcpyAsync(field, pp->T_R, (size_t)S * 8, hipMemcpyHostToDevice, s),
@@ -1250,7 +1350,7 @@ int smc_plasma_update(smc_plasma* p, const smc_plasma_params* pp, void* stream) 
 }
 
 int smc_plasma_read(smc_plasma* p, double* n_e, double* ion_density, double* partition,
-                    double* level_pop, double* tau_sobolev, uint64_t* n_clamped, void* stream) {
+                    double* level_pop, double* tau_sobolev, uint64_t* counts, void* stream) {
   if (!p) return fail(SMC_EINVAL, "null plasma");
   if (!p->updated) return fail(SMC_EINVAL, "the plasma has not been updated");
   HIP_TRY(hipSetDevice(p->model->ctx->device), "hipSetDevice");
@@ -1263,7 +1363,7 @@ int smc_plasma_read(smc_plasma* p, double* n_e, double* ion_density, double* par
   if ((rc = sync_copy_out(ion_density, d.ion_density, S * NI * 8, s))) return rc;
   if ((rc = sync_copy_out(partition, d.partition, S * NI * 8, s))) return rc;
   if ((rc = sync_copy_out(level_pop, d.level_pop, S * NL * 8, s))) return rc;
-  if ((rc = sync_copy_out(n_clamped, d.clamped, 8, s))) return rc;
+  if ((rc = sync_copy_out(counts, d.clamped, 2 * 8, s))) return rc;
   if (tau_sobolev && L > 0)
     HIP_TRY(hipMemcpy2DAsync(tau_sobolev, L * 8, d.tau, (size_t)d.Lp * 8, L * 8, S,
                              hipMemcpyDeviceToHost, s),

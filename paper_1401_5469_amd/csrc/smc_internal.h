@@ -169,11 +169,24 @@ constexpr int kMaxBatchModels = 1024;
 // ---------------------------------------------------------------------------
 constexpr int kPlasmaMaxIons = 2048;     // per-shell ion tables live in LDS
 constexpr int kPlasmaMaxElements = 256;
+constexpr int kNlteMaxIons = 64;
+constexpr int kNlteMaxLevels = 64;       // an NLTE system (n x n+1) lives in LDS
 
 // Per-line constants of the Sobolev depth, derived once at load (16 bytes).
 struct PlasmaLine {
   double coef_g;           // (pi e^2 / m_e c) f (c / nu) t_exp g_l
   int32_t lower, upper;    // global level indices
+};
+
+// Per-line constants of an NLTE ion's rates, derived once at load (64 bytes).
+struct NlteLine {
+  double A_ul, B_ul, B_lu;  // Einstein coefficients (B for J in intensity units)
+  double c_ul;              // 8.629e-6 Upsilon / g_u: C_ul = c_ul / T_e^{1/2}
+  double g_ratio;           // g_u / g_l: C_lu = C_ul g_ratio exp(-h nu / k T_e)
+  double nu;
+  int32_t line;             // global line index
+  int16_t lo, up;           // level indices within the ion
+  int32_t pad[2];
 };
 
 struct PlasmaLayout {
@@ -190,7 +203,11 @@ struct PlasmaLayout {
   uint64_t partition, ion_density;  // [S*n_ions]
   uint64_t level_pop;      // [S*n_levels] populations n
   uint64_t level_x;        // [S*n_levels] n / g
-  uint64_t clamped;        // [1] u64 (+ pad)
+  uint64_t clamped;        // [2] u64: inverted lines, singular NLTE systems
+  uint64_t nlte_ions;      // [n_nlte] i32
+  uint64_t nlte_line_ptr;  // [n_nlte+1] i32 offsets into nlte_lines
+  uint64_t nlte_lines;     // NlteLine records of every NLTE ion's lines
+  uint64_t line_upsilon;   // [L] staging of the collision strengths
   uint64_t total;
 };
 
@@ -218,13 +235,20 @@ struct DevPlasma {
   double* level_pop;
   double* level_x;
   unsigned long long* clamped;
+  int32_t n_nlte;          // NLTE ions of this update (0: none)
+  int32_t jb_detailed;     // J_b from `jblue` (else W B_nu(T_R))
+  const int32_t* nlte_ions;
+  const int32_t* nlte_line_ptr;
+  NlteLine* nlte_lines;
+  const double* line_upsilon;
+  const double* jblue;     // the model's normalised J_blue [S*L], or nullptr
   double* n_e;             // the model's [S]
   double* tau;             // the model's [S*Lp]
   const double* line_nu;   // the model's [Lp]
 };
 
 // Launchers implemented in smc_plasma.hip.
-hipError_t launch_plasma_lines(const DevPlasma& p, hipStream_t s);
+hipError_t launch_plasma_lines(const DevPlasma& p, int n_nlte_lines, hipStream_t s);
 hipError_t launch_plasma_update(const DevPlasma& p, hipStream_t s);
 
 }  // namespace smc

@@ -1,7 +1,7 @@
 // smc_plasma.hip -- plasma state (Kerzendorf & Sim 2014, section 2.3) and
 // Sobolev optical depths (section 2.5) on the device.
 //
-// Two launches per update:
+// Two launches per update (three with NLTE ions):
 //   plasma_state_kernel  one workgroup per shell: partition functions (one
 //                        wavefront per ion, lanes over its levels), the log
 //                        ionization ratios, n_e from charge conservation
@@ -14,8 +14,12 @@
 //                        in LDS, then per line a 16-byte record, two LDS
 //                        gathers and one coalesced 8-byte store.  HBM-bound
 //                        on the tau_S stores.
+//   plasma_nlte_kernel   (NLTE ions only, between the two) one workgroup per
+//                        (ion, shell): rate matrix in LDS, LU solve.
 // plasma_lines_kernel runs once at load and folds the oscillator strength,
-// the wavelength and t_exp into one coefficient per line.
+// the wavelength and t_exp into one coefficient per line;
+// plasma_nlte_lines_kernel derives the Einstein coefficients and collision
+// constants of the NLTE ions' lines.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -51,6 +55,10 @@ constexpr int kTauChunk = 8192;
 constexpr int kTauBatch = 8;
 // independent loads a lane issues before using any of them
 constexpr int kBatch = 4;
+// NLTE solve: one workgroup per (ion, shell); rates of this many lines are
+// staged in LDS at a time
+constexpr int kNlteThreads = 256;
+constexpr int kNlteChunk = 256;
 // the depth kernel stages a shell's n / g table in LDS up to this many levels
 constexpr int kTauLdsLevels = 8192;
 
@@ -222,7 +230,10 @@ __global__ __launch_bounds__(kStateThreads) void plasma_state_kernel(DevPlasma p
   }
   if (threadIdx.x == 0) {
     p.n_e[s] = s_ne;
-    if (s == 0) p.clamped[0] = 0ull;  // the depth kernel runs after this one
+    if (s == 0) {  // the NLTE and depth kernels run after this one
+      p.clamped[0] = 0ull;
+      p.clamped[1] = 0ull;
+    }
   }
   // step 4: level populations n, and n / g, the form the depth kernel uses
   double* pop = p.level_pop + (size_t)s * p.n_levels;
@@ -312,6 +323,149 @@ __global__ __launch_bounds__(kTauThreads) void plasma_tau_kernel(DevPlasma p) {
   if ((threadIdx.x % kWave) == 0 && neg) atomicAdd(p.clamped, neg);
 }
 
+// NLTE statistical equilibrium of one ion in one shell (one workgroup):
+// rates of kNlteChunk lines at a time in LDS (one thread per line), the
+// n x (n+1) augmented system assembled row by row in line order (thread r
+// owns row r, so the sums have a fixed order), equation 0 replaced by the
+// ion's total, then Gaussian elimination with partial pivoting (wavefront 0
+// finds the pivot, the first of equal magnitudes; all threads update the
+// trailing block) and back substitution.
+__global__ __launch_bounds__(kNlteThreads) void plasma_nlte_kernel(DevPlasma p) {
+  extern __shared__ double sm[];
+  __shared__ double r_ul[kNlteChunk], r_lu[kNlteChunk];
+  __shared__ int16_t c_lo[kNlteChunk], c_up[kNlteChunk];
+  __shared__ int s_piv, s_fail;
+  const int j = blockIdx.x, s = blockIdx.y, t = threadIdx.x;
+  const int ion = p.nlte_ions[j];
+  const int l0 = p.ion_level_ptr[ion], n = p.ion_level_ptr[ion + 1] - l0;
+  const int ld = n + 1;
+  double* M = sm;  // [n][n+1]: rates, then the right-hand side in column n
+  const double T = p.T_R[s], W = p.W[s], ne = p.n_e[s];
+  const double Te = kTeOverTr * T;
+  const double sqrt_te = sqrt(Te);
+  for (int i = t; i < n * ld; i += kNlteThreads) M[i] = 0.0;
+  if (t == 0) s_fail = 0;
+  __syncthreads();
+
+  const int e0 = p.nlte_line_ptr[j], e1 = p.nlte_line_ptr[j + 1];
+  for (int c0 = e0; c0 < e1; c0 += kNlteChunk) {
+    const int c1 = min(c0 + kNlteChunk, e1);
+    if (c0 + t < c1) {
+      const NlteLine ln = p.nlte_lines[c0 + t];
+      const double tau = p.tau[(size_t)s * p.Lp + ln.line];
+      const double b = tau > 0.0 ? -expm1(-tau) / tau : 1.0;
+      double J;
+      if (p.jb_detailed) {
+        J = p.jblue[(size_t)s * p.L + ln.line];
+      } else {
+        const double nu = ln.nu;
+        J = W * (2.0 * kH * (nu * nu * nu) / (kC * kC) / expm1(kH * nu / (kKB * T)));
+      }
+      const double C_ul = ln.c_ul / sqrt_te;
+      const double C_lu = C_ul * ln.g_ratio * exp(-kH * ln.nu / (kKB * Te));
+      r_ul[t] = b * ln.A_ul + b * ln.B_ul * J + C_ul * ne;
+      r_lu[t] = b * ln.B_lu * J + C_lu * ne;
+      c_lo[t] = ln.lo;
+      c_up[t] = ln.up;
+    }
+    __syncthreads();
+    if (t < n) {
+      for (int e = 0; e < c1 - c0; ++e) {
+        const int lo = c_lo[e], up = c_up[e];
+        if (t == lo) {
+          M[lo * ld + up] += r_ul[e];
+          M[lo * ld + lo] -= r_lu[e];
+        } else if (t == up) {
+          M[up * ld + up] -= r_ul[e];
+          M[up * ld + lo] += r_lu[e];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (t <= n) M[t] = t < n ? 1.0 : p.ion_density[(size_t)s * p.n_ions + ion];
+  __syncthreads();
+
+  for (int k = 0; k < n; ++k) {
+    if (t < kWave) {
+      double best = -1.0;
+      int bi = n;
+      for (int r = k + t; r < n; r += kWave) {
+        const double v = fabs(M[r * ld + k]);
+        if (v > best) {
+          best = v;
+          bi = r;
+        }
+      }
+      for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o, kWave);
+        const int oi = __shfl_xor(bi, o, kWave);
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (t == 0) {
+        s_piv = bi;
+        if (!(best > 0.0)) s_fail = 1;
+      }
+    }
+    __syncthreads();
+    if (s_fail) break;
+    const int pr = s_piv;
+    if (pr != k) {
+      for (int c = k + t; c <= n; c += kNlteThreads) {
+        const double a = M[k * ld + c];
+        M[k * ld + c] = M[pr * ld + c];
+        M[pr * ld + c] = a;
+      }
+    }
+    __syncthreads();
+    const double piv = M[k * ld + k];
+    const int cols = n - k;  // columns k+1 .. n
+    for (int idx = t; idx < (n - k - 1) * cols; idx += kNlteThreads) {
+      const int r = k + 1 + idx / cols, c = k + 1 + idx % cols;
+      M[r * ld + c] -= M[r * ld + k] / piv * M[k * ld + c];
+    }
+    __syncthreads();
+  }
+  if (s_fail) {
+    if (t == 0) atomicAdd(&p.clamped[1], 1ull);
+    return;
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    if (t == 0) M[k * ld + n] = M[k * ld + n] / M[k * ld + k];
+    __syncthreads();
+    const double xk = M[k * ld + n];
+    for (int r = t; r < k; r += kNlteThreads) M[r * ld + n] -= M[r * ld + k] * xk;
+    __syncthreads();
+  }
+  double* pop = p.level_pop + (size_t)s * p.n_levels + l0;
+  double* xg = p.level_x + (size_t)s * p.n_levels + l0;
+  for (int r = t; r < n; r += kNlteThreads) {
+    const double v = fmax(M[r * ld + n], 0.0);
+    pop[r] = v;
+    xg[r] = v / p.level_g[l0 + r];
+  }
+}
+
+// Per-line constants of the NLTE rates, once at load.
+__global__ void plasma_nlte_lines_kernel(DevPlasma p, int count) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  NlteLine& r = p.nlte_lines[e];
+  const int k = r.line;
+  const double g_l = p.level_g[p.lines[k].lower], g_u = p.level_g[p.lines[k].upper];
+  const double nu = p.line_nu[k];
+  const double coll = kH * kH / (pow(2.0 * kPi * kME, 1.5) * sqrt(kKB));
+  r.B_lu = 4.0 * (kPi * kPi) * (kECharge * kECharge) * p.line_f[k] / (kME * kC * kH * nu);
+  r.B_ul = g_l / g_u * r.B_lu;
+  r.A_ul = 2.0 * kH * (nu * nu * nu) / (kC * kC) * r.B_ul;
+  r.c_ul = coll * p.line_upsilon[k] / g_u;
+  r.g_ratio = g_u / g_l;
+  r.nu = nu;
+}
+
 __global__ void plasma_lines_kernel(DevPlasma p) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= p.L) return;
@@ -321,9 +475,13 @@ __global__ void plasma_lines_kernel(DevPlasma p) {
 
 }  // namespace
 
-hipError_t launch_plasma_lines(const DevPlasma& p, hipStream_t s) {
+hipError_t launch_plasma_lines(const DevPlasma& p, int n_nlte_lines, hipStream_t s) {
   if (p.L == 0) return hipSuccess;
   hipLaunchKernelGGL(plasma_lines_kernel, dim3((p.L + 255) / 256), dim3(256), 0, s, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n_nlte_lines == 0) return e;
+  hipLaunchKernelGGL(plasma_nlte_lines_kernel, dim3((n_nlte_lines + 255) / 256), dim3(256), 0,
+                     s, p, n_nlte_lines);
   return hipGetLastError();
 }
 
@@ -331,7 +489,13 @@ hipError_t launch_plasma_update(const DevPlasma& p, hipStream_t s) {
   const size_t lds = 3 * (size_t)p.n_ions * sizeof(double);
   hipLaunchKernelGGL(plasma_state_kernel, dim3(p.S), dim3(kStateThreads), lds, s, p);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || p.L == 0) return e;
+  if (e != hipSuccess) return e;
+  if (p.n_nlte > 0) {
+    const size_t lds = (size_t)kNlteMaxLevels * (kNlteMaxLevels + 1) * sizeof(double);
+    hipLaunchKernelGGL(plasma_nlte_kernel, dim3(p.n_nlte, p.S), dim3(kNlteThreads), lds, s, p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (p.L == 0) return hipSuccess;
   const dim3 grid((p.L + kTauChunk - 1) / kTauChunk, p.S);
   if (p.n_levels <= kTauLdsLevels)
     hipLaunchKernelGGL(plasma_tau_kernel<true>, grid, dim3(kTauThreads),

@@ -53,20 +53,22 @@ class smc_iter_params(C.Structure):
 
 ION_LTE, ION_NEBULAR = 0, 1
 EXC_LTE, EXC_DILUTE_LTE = 0, 1
+JB_DILUTE_BLACKBODY, JB_DETAILED = 0, 1
 _u8p = C.POINTER(C.c_uint8)
 
 
 class smc_plasma_desc(C.Structure):
     _fields_ = [("n_elements", C.c_int32), ("n_ions", C.c_int32), ("n_levels", C.c_int32),
-                ("reserved", C.c_int32), ("element_ion_ptr", _i32p), ("ion_chi", _dp),
+                ("n_nlte_ions", C.c_int32), ("element_ion_ptr", _i32p), ("ion_chi", _dp),
                 ("ion_zeta", _dp), ("ion_level_ptr", _i32p), ("level_energy", _dp),
                 ("level_g", _dp), ("level_metastable", _u8p), ("line_lower", _i32p),
-                ("line_upper", _i32p), ("line_f", _dp), ("number_density", _dp)]
+                ("line_upper", _i32p), ("line_f", _dp), ("number_density", _dp),
+                ("nlte_ions", _i32p), ("line_upsilon", _dp)]
 
 
 class smc_plasma_params(C.Structure):
     _fields_ = [("ionization", C.c_int32), ("excitation", C.c_int32), ("delta", C.c_double),
-                ("T_R", _dp), ("W", _dp)]
+                ("T_R", _dp), ("W", _dp), ("nlte", C.c_int32), ("jblue_mode", C.c_int32)]
 
 
 PACKET_DTYPE = np.dtype([("id", np.uint64), ("status", np.int32), ("shell", np.int32),
@@ -459,6 +461,12 @@ def _plasma_desc(spec, keep: list) -> smc_plasma_desc:
     d.line_upper = _ptr(arr(atom.line_upper if n_lines else np.zeros(1), np.int32), _i32p)
     d.line_f = _ptr(arr(atom.line_f if n_lines else np.zeros(1), np.float64), _dp)
     d.number_density = _ptr(arr(spec.number_density, np.float64), _dp)
+    nlte = tuple(getattr(spec, "nlte_ions", ()) or ())
+    d.n_nlte_ions = len(nlte)
+    if nlte:
+        d.nlte_ions = _ptr(arr(np.asarray(nlte), np.int32), _i32p)
+        ups = atom.line_upsilon if atom.line_upsilon is not None else np.zeros(max(n_lines, 1))
+        d.line_upsilon = _ptr(arr(ups if n_lines else np.zeros(1), np.float64), _dp)
     return d
 
 
@@ -499,13 +507,18 @@ class Plasma:
         self.n_ions, self.n_levels = spec.atom.n_ions, spec.atom.n_levels
 
     def update(self, ionization: int = ION_NEBULAR, excitation: int = EXC_DILUTE_LTE,
-               delta: float = 1.0, T_R=None, W=None, stream=None):
+               delta: float = 1.0, T_R=None, W=None, nlte: bool = False,
+               jblue_mode: int = JB_DILUTE_BLACKBODY, stream=None):
         """Recompute the model's tau_sobolev and n_e from T_R, W (host arrays)
-        or, when both are None, from the model's current radiation field."""
+        or, when both are None, from the model's current radiation field;
+        nlte: statistical equilibrium for the spec's NLTE ions, with J_b
+        from jblue_mode."""
         p = smc_plasma_params()
         p.ionization = int(ionization)
         p.excitation = int(excitation)
         p.delta = float(delta)
+        p.nlte = 1 if nlte else 0
+        p.jblue_mode = int(jblue_mode)
         keep = []
         if T_R is not None or W is not None:
             t = np.ascontiguousarray(T_R, dtype=np.float64) if T_R is not None else None
@@ -523,11 +536,12 @@ class Plasma:
         out = dict(n_e=np.zeros(S), N_ion=np.zeros((S, NI)), Z=np.zeros((S, NI)),
                    level_pop=np.zeros((S, NL)) if level_pop else None,
                    tau=np.zeros((S, L)) if tau else None)
-        c = np.zeros(1, dtype=np.uint64)
+        c = np.zeros(2, dtype=np.uint64)
         _check(_lib.smc_plasma_read(self.handle, _ptr(out["n_e"], _dp), _ptr(out["N_ion"], _dp),
                                     _ptr(out["Z"], _dp), _ptr(out["level_pop"], _dp),
                                     _ptr(out["tau"], _dp), _ptr(c, _u64p), _stream_ptr(stream)))
         out["n_clamped"] = int(c[0])
+        out["n_singular"] = int(c[1])
         return out
 
     def free(self):

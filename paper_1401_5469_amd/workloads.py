@@ -562,3 +562,17 @@ def config_plasma(seed: int = 0, n_packets: int = 1_000_000, n_lines: int = 300_
     w = Workload("plasma-20shell-300kline", model, T_inner=9000.0, n_packets=n_packets,
                  n_iterations=10)
     return w, spec
+
+
+def config_plasma_nlte(seed: int = 0, n_packets: int = 1_000_000, n_lines: int = 300_000,
+                       n_levels_per_ion: int = 150, n_levels_nlte: int = 40) -> tuple:
+    """The plasma benchmark with the stage-1 ions of the Mg, Si, S and Ca
+    analogues (Mg II, Si II, S II, Ca II: the ions of the paper's NLTE study)
+    in NLTE excitation with n_levels_nlte levels each."""
+    nlte = (1 * 5 + 1, 2 * 5 + 1, 3 * 5 + 1, 4 * 5 + 1)
+    model, spec = plasma_model(seed, n_shells=20, n_lines=n_lines,
+                               n_levels_per_ion=n_levels_per_ion, nlte_ions=nlte,
+                               n_levels_nlte=n_levels_nlte)
+    w = Workload("plasma-nlte-20shell-300kline", model, T_inner=9000.0, n_packets=n_packets,
+                 n_iterations=10)
+    return w, spec

@@ -55,6 +55,8 @@ int main(void) {
   printf("smc_plasma_params %zu\n", sizeof(smc_plasma_params));
   F(smc_plasma_desc, element_ion_ptr); F(smc_plasma_desc, level_metastable);
   F(smc_plasma_desc, number_density); F(smc_plasma_params, delta); F(smc_plasma_params, W);
+  F(smc_plasma_desc, n_nlte_ions); F(smc_plasma_desc, line_upsilon);
+  F(smc_plasma_params, jblue_mode);
   return 0;
 }
 """
@@ -86,7 +88,8 @@ def test_python_structs_match_header_layout():
     assert lay["smc_plasma_params"] == C.sizeof(smc.smc_plasma_params)
     for st, f in (("smc_plasma_desc", "element_ion_ptr"), ("smc_plasma_desc", "level_metastable"),
                   ("smc_plasma_desc", "number_density"), ("smc_plasma_params", "delta"),
-                  ("smc_plasma_params", "W")):
+                  ("smc_plasma_params", "W"), ("smc_plasma_desc", "n_nlte_ions"),
+                  ("smc_plasma_desc", "line_upsilon"), ("smc_plasma_params", "jblue_mode")):
         assert lay[f"{st}.{f}"] == getattr(getattr(smc, st), f).offset
 
 
@@ -238,3 +241,40 @@ def test_no_gpu_means_a_loud_error_not_a_fallback(lib):
     with pytest.raises(smc.SmcError) as ei:
         smc.Context(0)
     assert ei.value.code in (smc.SMC_EDEVICE, smc.SMC_EINVAL)
+
+
+def test_host_validation_of_nlte_ions(lib):
+    import dataclasses
+    model, spec = W.plasma_model(seed=3, n_shells=3, n_elements=3, n_stages=3,
+                                 n_levels_per_ion=8, n_lines=60, nlte_ions=(4,),
+                                 n_levels_nlte=6)
+    L = model.n_lines
+    assert smc.plasma_workspace_bytes(spec, 3, L) > smc.plasma_workspace_bytes(
+        dataclasses.replace(spec, nlte_ions=()), 3, L)
+    assert "listed twice" in _expect_plasma_invalid(dataclasses.replace(spec, nlte_ions=(4, 4)),
+                                                    L=L)
+    assert "out of range" in _expect_plasma_invalid(dataclasses.replace(spec, nlte_ions=(9,)),
+                                                    L=L)
+    a = spec.atom
+    ups = a.line_upsilon.copy()
+    l0, l1 = a.ion_level_ptr[4], a.ion_level_ptr[5]
+    k = int(np.flatnonzero((a.line_lower >= l0) & (a.line_lower < l1))[0])
+    ups[k] = -1.0
+    bad = W.PlasmaSpec(atom=dataclasses.replace(a, line_upsilon=ups),
+                       number_density=spec.number_density, nlte_ions=(4,))
+    assert "line_upsilon" in _expect_plasma_invalid(bad, L=L)
+    # an ion with more levels than the NLTE system holds
+    big, bspec = W.plasma_model(seed=3, n_shells=3, n_elements=3, n_stages=3,
+                                n_levels_per_ion=8, n_lines=300, nlte_ions=(4,),
+                                n_levels_nlte=65)
+    assert "levels" in _expect_plasma_invalid(bspec, L=big.n_lines)
+    # a level that no line of the ion reaches
+    ions = np.repeat(np.arange(a.n_ions), np.diff(a.ion_level_ptr))
+    keep = ~((a.line_upper == l0 + 5) & (ions[a.line_lower] == 4))
+    cut = W.PlasmaSpec(atom=dataclasses.replace(a, line_lower=a.line_lower[keep],
+                                                line_upper=a.line_upper[keep],
+                                                line_f=a.line_f[keep],
+                                                line_upsilon=a.line_upsilon[keep]),
+                       number_density=spec.number_density, nlte_ions=(4,))
+    if not np.any((cut.atom.line_lower == l0 + 5) & (ions[cut.atom.line_upper] == 4)):
+        assert "not joined" in _expect_plasma_invalid(cut, L=int(keep.sum()))

@@ -269,3 +269,158 @@ def test_errors(ctx):
         smc.Plasma(m, ospec)
     pl.update(W.ION_LTE, W.EXC_LTE, T_R=T_R, W=Wd)
     assert pl.read()["n_e"].min() > 0
+
+
+# ---------------------------------------------------------------------------
+# NLTE statistical equilibrium (section 2.3): the HIP LU solve against the
+# oracle's LAPACK solve.  Eliminating the same systems in the kernel's order
+# on the CPU differs from LAPACK by < 4e-15 relative on these atoms, so the
+# tolerance above holds for the NLTE populations too.
+# ---------------------------------------------------------------------------
+def _nlte_small(seed=21, n_levels_nlte=20, n_lines=3000):
+    return W.plasma_model(seed=seed, n_shells=6, n_elements=6, n_stages=5, n_levels_per_ion=25,
+                          n_lines=n_lines, nlte_ions=(6, 11, 27), n_levels_nlte=n_levels_nlte)
+
+
+def _oracle_nlte(model, spec, T_R, Wd, ion, exc, tau_prev, jblue=None, delta=1.0):
+    return P.plasma_state(spec.atom, spec.number_density, model.line_nu, model.t_exp, T_R, Wd,
+                          ion, exc, delta, nlte_ions=spec.nlte_ions, tau_prev=tau_prev,
+                          jblue=jblue)
+
+
+@pytest.mark.parametrize("n_levels_nlte", [1, 20, 64])
+@pytest.mark.parametrize("ion,exc", [MODES[1], MODES[0]], ids=MODE_IDS[:2][::-1])
+def test_nlte_host_field(ctx, n_levels_nlte, ion, exc):
+    model, spec = _nlte_small(n_levels_nlte=n_levels_nlte,
+                              n_lines=5000 if n_levels_nlte == 64 else 3000)
+    m = smc.Model(ctx, model, 16)
+    pl = smc.Plasma(m, spec)
+    T_R, Wd = _field(model, 31)
+    # a first update gives the depths that the escape probabilities use
+    pl.update(ion, exc, T_R=T_R, W=Wd)
+    tau0 = pl.read()["tau"]
+    pl.update(ion, exc, T_R=T_R, W=Wd, nlte=True)
+    g = pl.read()
+    o = _oracle_nlte(model, spec, T_R, Wd, ion, exc, tau0)
+    _assert_state(g, o, model, spec)
+    assert g["n_singular"] == 0
+    base = _oracle(model, spec, T_R, Wd, ion, exc)
+    if n_levels_nlte > 1:
+        lp = spec.atom.ion_level_ptr
+        assert not np.allclose(o["level_pop"][:, lp[6]:lp[7]], base["level_pop"][:, lp[6]:lp[7]])
+
+
+def test_nlte_paper_scale(ctx):
+    w, spec = W.config_plasma_nlte()
+    model = w.model
+    m = smc.Model(ctx, model, 16)
+    pl = smc.Plasma(m, spec)
+    pl.update(W.ION_NEBULAR, W.EXC_DILUTE_LTE, nlte=True)  # initial field, tau_S = 0: beta = 1
+    g = pl.read()
+    T_R, Wd = O.initial_radiation_field(model)
+    o = _oracle_nlte(model, spec, T_R, Wd, W.ION_NEBULAR, W.EXC_DILUTE_LTE,
+                     np.zeros((model.n_shells, model.n_lines)))
+    _assert_state(g, o, model, spec)
+    pl.update(W.ION_NEBULAR, W.EXC_DILUTE_LTE, nlte=True)  # now with the depths just written
+    g2 = pl.read()
+    o2 = _oracle_nlte(model, spec, T_R, Wd, W.ION_NEBULAR, W.EXC_DILUTE_LTE, g["tau"])
+    _assert_state(g2, o2, model, spec)
+
+
+def test_nlte_detailed_jblue_after_an_iteration(ctx):
+    model, spec = _nlte_small(seed=22)
+    flags = smc.F_JBLUE
+    m = smc.Model(ctx, model, 30000, flags=flags)
+    pl = smc.Plasma(m, spec)
+    ion, exc = W.ION_NEBULAR, W.EXC_DILUTE_LTE
+    # before any iteration the detailed mode starts from W B_nu(T_R)
+    pl.update(ion, exc, nlte=True, jblue_mode=smc.JB_DETAILED)
+    T0, W0 = O.initial_radiation_field(model)
+    g0 = pl.read()
+    _assert_state(g0, _oracle_nlte(model, spec, T0, W0, ion, exc,
+                                   np.zeros((model.n_shells, model.n_lines))), model, spec)
+    m.run_iteration(30000, 12000.0, flags=flags)
+    est = m.read_estimators(jblue=True)
+    pl.update(ion, exc, nlte=True, jblue_mode=smc.JB_DETAILED)
+    g = pl.read()
+    o = _oracle_nlte(model, spec, est["T_R"], est["W"], ion, exc, g0["tau"], jblue=est["jblue"])
+    _assert_state(g, o, model, spec)
+    d = _oracle_nlte(model, spec, est["T_R"], est["W"], ion, exc, g0["tau"])
+    lp = spec.atom.ion_level_ptr
+    assert not np.allclose(o["level_pop"][:, lp[6]:lp[7]], d["level_pop"][:, lp[6]:lp[7]])
+
+
+def test_nlte_feedback_loop_packet_by_packet(ctx):
+    model, spec = _nlte_small(seed=23, n_lines=2000)
+    N, T = 3000, 11000.0
+    ion, exc = W.ION_NEBULAR, W.EXC_DILUTE_LTE
+    flags = smc.F_JBLUE | smc.F_PACKETS
+    m = smc.Model(ctx, model, N, flags=flags)
+    pl = smc.Plasma(m, spec)
+    pl.update(ion, exc, nlte=True)
+    g_state0 = pl.read()
+    m.run_iteration(N, T, iteration=0, flags=flags)
+    g0 = m.read_packets(N)
+    pl.update(ion, exc, nlte=True, jblue_mode=smc.JB_DETAILED)
+    g_state1 = pl.read()
+    m.run_iteration(N, T, iteration=1, flags=flags)
+    g1 = m.read_packets(N)
+
+    T0, W0 = O.initial_radiation_field(model)
+    o0 = _oracle_nlte(model, spec, T0, W0, ion, exc, np.zeros((model.n_shells, model.n_lines)))
+    _assert_state(g_state0, o0, model, spec)
+    m0 = _with(model, o0["tau"], o0["n_e"])
+    raw0 = O.run(m0, T, N, iteration=0)
+    fin0 = O.finalise(m0, raw0, T, T_R_prev=T0, W_prev=W0)
+    assert_packets_match(g0, raw0["packets"])
+    o1 = _oracle_nlte(model, spec, fin0["T_R"], fin0["W"], ion, exc, o0["tau"],
+                      jblue=fin0["jblue"])
+    if divergent(g0, raw0["packets"]).size == 0:
+        _assert_state(g_state1, o1, model, spec)
+    m1 = _with(model, o1["tau"], o1["n_e"])
+    raw1 = O.run(m1, T, N, iteration=1)
+    assert_packets_match(g1, raw1["packets"])
+
+
+def test_nlte_singular_system_keeps_the_excitation_populations(ctx):
+    import dataclasses
+    model, spec = _nlte_small(seed=24)
+    a = spec.atom
+    lp = a.ion_level_ptr
+    mine = (a.line_lower >= lp[11]) & (a.line_lower < lp[12])
+    f = a.line_f.copy()
+    ups = a.line_upsilon.copy()
+    f[mine] = 0.0
+    ups[mine] = 0.0  # no rate at all: the system of ion 11 is singular
+    spec = W.PlasmaSpec(atom=dataclasses.replace(a, line_f=f, line_upsilon=ups),
+                        number_density=spec.number_density, nlte_ions=spec.nlte_ions)
+    m = smc.Model(ctx, model, 16)
+    pl = smc.Plasma(m, spec)
+    T_R, Wd = _field(model, 32)
+    pl.update(W.ION_LTE, W.EXC_LTE, T_R=T_R, W=Wd, nlte=True)
+    g = pl.read()
+    assert g["n_singular"] == model.n_shells
+    base = _oracle(model, spec, T_R, Wd, W.ION_LTE, W.EXC_LTE)
+    np.testing.assert_allclose(g["level_pop"][:, lp[11]:lp[12]],
+                               base["level_pop"][:, lp[11]:lp[12]], rtol=TOL)
+    with_nlte = dataclasses.replace(spec, nlte_ions=(6, 27))
+    o = _oracle_nlte(model, with_nlte, T_R, Wd, W.ION_LTE, W.EXC_LTE,
+                     np.zeros((model.n_shells, model.n_lines)))
+    np.testing.assert_allclose(g["level_pop"][:, lp[6]:lp[7]], o["level_pop"][:, lp[6]:lp[7]],
+                               rtol=TOL)
+
+
+def test_nlte_errors(ctx):
+    model, spec = _nlte_small(seed=25, n_lines=2000)
+    m = smc.Model(ctx, model, 16, flags=0)
+    pl = smc.Plasma(m, spec)
+    with pytest.raises(smc.SmcError):  # no J_blue tally in this model
+        pl.update(W.ION_LTE, W.EXC_LTE, nlte=True, jblue_mode=smc.JB_DETAILED)
+    with pytest.raises(smc.SmcError):
+        pl.update(W.ION_LTE, W.EXC_LTE, nlte=True, jblue_mode=3)
+    m2 = smc.Model(ctx, model, 1000, flags=smc.F_JBLUE)
+    pl2 = smc.Plasma(m2, spec)
+    m2.run_iteration(1000, 10000.0, flags=0)  # this iteration does not tally J_blue
+    with pytest.raises(smc.SmcError):
+        pl2.update(W.ION_LTE, W.EXC_LTE, nlte=True, jblue_mode=smc.JB_DETAILED)
+    pl2.update(W.ION_LTE, W.EXC_LTE, nlte=True)  # dilute blackbody is fine
