@@ -10,8 +10,11 @@
                                           virtual packets, section 2.9)
     python bench.py --workload macroatom (macroatom vs downbranch line modes
                                           on the 30-shell 2e4-line atom)
-    python bench.py --workload plasma    (iterations with the plasma update of
-                                          sections 2.3 and 2.5 between them)
+    python bench.py --workload plasma [--nlte]
+                                         (iterations with the plasma update of
+                                          sections 2.3 and 2.5 between them;
+                                          --nlte: Mg II, Si II, S II, Ca II
+                                          analogues in NLTE excitation)
 
 One step is one Monte Carlo iteration of the paper-scale scatter model
 (20 shells 10000-25000 km/s at 13 d, 3e5 lines, 1e6 packets; Kerzendorf & Sim
@@ -62,6 +65,8 @@ def parse():
                              "macroatom", "plasma"])
     ap.add_argument("--n-virtual", type=int, default=3,
                     help="virtual packets per packet launch in the virtual mode")
+    ap.add_argument("--nlte", action="store_true",
+                    help="plasma mode: NLTE excitation for four ions, J_b from J_blue")
     ap.add_argument("--models", type=int, default=64, help="models in the batched mix")
     ap.add_argument("--duration", type=float, default=10.0,
                     help="seconds of Poisson arrivals (20 per second) in the served mode")
@@ -241,7 +246,11 @@ def plasma(args):
     the roofline entry prices the plasma update (state and depth kernels,
     timed together with HIP events on the launch stream) at its algorithmic
     bytes: tau_S written once, the per-line records and the level
-    populations read once, the atomic data and densities read per shell."""
+    populations read once, the atomic data and densities read per shell.
+    With --nlte the stage-1 ions of the Mg, Si, S and Ca analogues (40
+    levels each) take their populations from statistical equilibrium, with
+    J_b from the J_blue estimator of the iteration before (W B_nu(T_R) before
+    the first) and escape probabilities from the depths in the model."""
     import numpy as np
     import torch
 
@@ -249,11 +258,13 @@ def plasma(args):
     from paper_1401_5469_amd import smc
     from paper_1401_5469_amd import workloads as W
 
-    w, spec = W.config_plasma(n_packets=args.packets)
+    nlte = bool(args.nlte)
+    w, spec = (W.config_plasma_nlte if nlte else W.config_plasma)(n_packets=args.packets)
     m_in, a = w.model, spec.atom
     N, S, L = w.n_packets, m_in.n_shells, m_in.n_lines
     ion, exc = W.ION_NEBULAR, W.EXC_DILUTE_LTE
     flags = 0 if args.no_jblue else smc.F_JBLUE
+    jb = smc.JB_DETAILED if (nlte and flags) else smc.JB_DILUTE_BLACKBODY
     ctx = smc.Context(0)
     model = smc.Model(ctx, m_in, N, flags=flags)
     pl = smc.Plasma(model, spec)
@@ -263,14 +274,14 @@ def plasma(args):
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def run(k, record):
-        pl.update(ion, exc, T_R=T0, W=W0)
+        pl.update(ion, exc, T_R=T0, W=W0, nlte=nlte)
         for i in range(k):
             model.run_iteration(N, w.T_inner if i == 0 else 0.0, iteration=i,
                                 flags=flags | smc.F_TIMING,
                                 L_requested=w.L_requested if i % 3 == 2 else 0.0,
                                 damping=w.damping)
             ev0.record()
-            pl.update(ion, exc)
+            pl.update(ion, exc, nlte=nlte, jblue_mode=jb)
             ev1.record()
             c = model.read_counters()
             ms = model.read_timing()
@@ -300,13 +311,21 @@ def plasma(args):
     # partition functions written; element densities read
     bytes_update = (S * L * 8 + L * 16 + S * NL * 8 * 3 + NL * (8 + 8 + 1 + 4)
                     + S * NI * 8 * 2 + S * E * 8)
+    n_nlte_lines = 0
+    for i in spec.nlte_ions if nlte else ():
+        l0, l1 = a.ion_level_ptr[i], a.ion_level_ptr[i + 1]
+        n_nlte_lines += int(((a.line_lower >= l0) & (a.line_lower < l1)).sum())
+    # NLTE: per line a 64-byte record, tau_S and J_blue read in every shell
+    bytes_update += n_nlte_lines * 64 + S * n_nlte_lines * 16
     achieved = bytes_update / (mean_pms * 1e-3) / 1e9
     # the plasma oracle on the same inputs (numpy FP64, one update)
     t1 = time.perf_counter()
-    OP.plasma_state(a, spec.number_density, m_in.line_nu, m_in.t_exp, T0, W0, ion, exc)
+    OP.plasma_state(a, spec.number_density, m_in.line_nu, m_in.t_exp, T0, W0, ion, exc,
+                    nlte_ions=spec.nlte_ions if nlte else ())
     cpu_s = time.perf_counter() - t1
     out = {
-        "metric": "packet-interactions/sec (with plasma feedback)",
+        "metric": "packet-interactions/sec (with plasma feedback"
+                  + (", NLTE)" if nlte else ")"),
         "value": inter / wall,
         "unit": "interactions/s",
         "n_gpus": 1,
@@ -320,20 +339,26 @@ def plasma(args):
         "data": "synthetic",
         "config": {"workload": w.name, "shells": S, "lines": L, "elements": E, "ions": NI,
                    "levels": NL, "packets_per_iteration": N, "ionization": "nebular",
-                   "excitation": "dilute-lte", "T_inner_start": w.T_inner},
+                   "excitation": "dilute-lte", "T_inner_start": w.T_inner,
+                   "nlte_ions": list(spec.nlte_ions) if nlte else [],
+                   "jblue_mode": "detailed" if jb == smc.JB_DETAILED else "dilute-blackbody"},
         "transport_ms": [m for _, m, _, _ in rec],
         "plasma_update_ms": pms,
         "T_inner": [t for _, _, _, t in rec],
         "n_e_final": st["n_e"].tolist(),
         "inverted_lines_final": st["n_clamped"],
+        "singular_nlte_systems_final": st["n_singular"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "plasma update: plasma_state_kernel + plasma_tau_kernel",
+                     "kernel": "plasma update: plasma_state_kernel + "
+                               + ("plasma_nlte_kernel + " if nlte else "") + "plasma_tau_kernel",
                      "bytes_per_launch": bytes_update},
         "cpu_baseline": {"value": 1.0 / cpu_s, "unit": "plasma updates/s", "cores": 1,
                          "kind": "oracle",
                          "sample": f"one plasma update of the whole model on the initial field "
-                                   f"({S} shells x {L} lines, numpy FP64, {cpu_s:.2f} s)"},
+                                   f"({S} shells x {L} lines"
+                                   + (f", {len(spec.nlte_ions)} NLTE ions" if nlte else "")
+                                   + f", numpy FP64, {cpu_s:.2f} s)"},
         "plasma_updates_per_s": 1e3 / mean_pms,
     }
     print(json.dumps(out), flush=True)

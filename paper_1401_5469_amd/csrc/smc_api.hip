@@ -1095,6 +1095,12 @@ int validate_plasma(const smc_plasma_desc* d, int32_t S, int64_t L) {
       if (find(v) != find(0))
         return fail(SMC_EINVAL, "level %d of NLTE ion %d is not joined to its ground state by "
                     "lines", v, ion);
+    int64_t count = 0;
+    for (int64_t k = 0; k < L; ++k)
+      count += d->line_lower[k] >= l0 && d->line_lower[k] < l0 + n;
+    if (count > smc::kNlteMaxLines)
+      return fail(SMC_EINVAL, "NLTE ion %d has %lld lines (at most %d)", ion, (long long)count,
+                  smc::kNlteMaxLines);
   }
   return SMC_OK;
 }
@@ -1158,6 +1164,8 @@ smc::PlasmaLayout plasma_layout_of(const smc_plasma_desc* d, int32_t S, int64_t 
   l.nlte_ions = take(NN * 4);
   l.nlte_line_ptr = take((NN + 1) * 4);
   l.nlte_lines = take(n_nlte_lines * sizeof(smc::NlteLine));
+  l.nlte_lev_ptr = take(NN * (smc::kNlteMaxLevels + 1) * 4);
+  l.nlte_ent = take(2 * n_nlte_lines * 4);
   l.line_upsilon = take(NN ? LL * 8 : 0);
   l.total = off;
   return l;
@@ -1230,15 +1238,42 @@ int smc_plasma_load(smc_model* model, const smc_plasma_desc* d, void* d_workspac
     return rc;
   const int32_t NN = d->n_nlte_ions;
   std::vector<smc::NlteLine> nlte_recs;
-  std::vector<int32_t> nlte_ptr32;
+  std::vector<int32_t> nlte_ptr32, lev_ptr, ent;
   if (NN > 0) {
     const std::vector<int64_t> ptr = nlte_line_offsets(d, L, &nlte_recs);
     nlte_ptr32.assign(ptr.begin(), ptr.end());
+    // per level of each NLTE ion, its lines in line order: the assembly of
+    // row r visits only these
+    const int32_t LP = smc::kNlteMaxLevels + 1;
+    lev_ptr.assign((size_t)NN * LP, 0);
+    ent.resize(2 * nlte_recs.size());
+    for (int32_t j = 0; j < NN; ++j) {
+      const int32_t ion = d->nlte_ions[j];
+      const int32_t n = d->ion_level_ptr[ion + 1] - d->ion_level_ptr[ion];
+      int32_t* lp = &lev_ptr[(size_t)j * LP];
+      for (int64_t e = ptr[j]; e < ptr[j + 1]; ++e) {
+        ++lp[nlte_recs[e].lo + 1];
+        ++lp[nlte_recs[e].up + 1];
+      }
+      for (int32_t r = 0; r < n; ++r) lp[r + 1] += lp[r];
+      for (int32_t r = n + 1; r < LP; ++r) lp[r] = lp[n];
+      std::vector<int32_t> fill(lp, lp + n);
+      int32_t* out = &ent[2 * (size_t)ptr[j]];
+      for (int64_t e = ptr[j]; e < ptr[j + 1]; ++e) {
+        const int32_t pos = (int32_t)(e - ptr[j]);
+        const smc::NlteLine& r = nlte_recs[e];
+        out[fill[r.lo]++] = (pos << 16) | (r.up << 1) | 1;
+        out[fill[r.up]++] = (pos << 16) | (r.lo << 1);
+      }
+    }
     if ((rc = h2d(base, lay.nlte_ions, d->nlte_ions, (size_t)NN * 4, s, "upload nlte_ions")) ||
         (rc = h2d(base, lay.nlte_line_ptr, nlte_ptr32.data(), (size_t)(NN + 1) * 4, s,
                   "upload NLTE line offsets")) ||
         (rc = h2d(base, lay.nlte_lines, nlte_recs.data(),
                   nlte_recs.size() * sizeof(smc::NlteLine), s, "upload NLTE lines")) ||
+        (rc = h2d(base, lay.nlte_lev_ptr, lev_ptr.data(), lev_ptr.size() * 4, s,
+                  "upload NLTE level offsets")) ||
+        (rc = h2d(base, lay.nlte_ent, ent.data(), ent.size() * 4, s, "upload NLTE entries")) ||
         (rc = h2d(base, lay.line_upsilon, d->line_upsilon, (size_t)L * 8, s,
                   "upload line_upsilon")))
       return rc;
@@ -1282,6 +1317,8 @@ int smc_plasma_load(smc_model* model, const smc_plasma_desc* d, void* d_workspac
   dp.nlte_ions = (const int32_t*)(base + lay.nlte_ions);
   dp.nlte_line_ptr = (const int32_t*)(base + lay.nlte_line_ptr);
   dp.nlte_lines = (smc::NlteLine*)(base + lay.nlte_lines);
+  dp.nlte_lev_ptr = (const int32_t*)(base + lay.nlte_lev_ptr);
+  dp.nlte_ent = (const int32_t*)(base + lay.nlte_ent);
   dp.line_upsilon = (const double*)(base + lay.line_upsilon);
   // the host staging vectors must stay alive until the copies have run
   hipError_t e = smc::launch_plasma_lines(dp, (int)nlte_recs.size(), s);

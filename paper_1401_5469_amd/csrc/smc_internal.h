@@ -171,6 +171,7 @@ constexpr int kPlasmaMaxIons = 2048;     // per-shell ion tables live in LDS
 constexpr int kPlasmaMaxElements = 256;
 constexpr int kNlteMaxIons = 64;
 constexpr int kNlteMaxLevels = 64;       // an NLTE system (n x n+1) lives in LDS
+constexpr int kNlteMaxLines = 2048;      // lines of one NLTE ion (their level entries too)
 
 // Per-line constants of the Sobolev depth, derived once at load (16 bytes).
 struct PlasmaLine {
@@ -207,6 +208,10 @@ struct PlasmaLayout {
   uint64_t nlte_ions;      // [n_nlte] i32
   uint64_t nlte_line_ptr;  // [n_nlte+1] i32 offsets into nlte_lines
   uint64_t nlte_lines;     // NlteLine records of every NLTE ion's lines
+  uint64_t nlte_lev_ptr;   // [n_nlte][kNlteMaxLevels+1] i32: level r's entries of ion j are
+                           // nlte_ent[2 nlte_line_ptr[j] + ptr[r] .. + ptr[r+1])
+  uint64_t nlte_ent;       // [2 * NLTE lines] i32: (line position << 16) | (other level << 1) |
+                           // (1 if the level is the line's lower one), by level, in line order
   uint64_t line_upsilon;   // [L] staging of the collision strengths
   uint64_t total;
 };
@@ -240,6 +245,8 @@ struct DevPlasma {
   const int32_t* nlte_ions;
   const int32_t* nlte_line_ptr;
   NlteLine* nlte_lines;
+  const int32_t* nlte_lev_ptr;
+  const int32_t* nlte_ent;
   const double* line_upsilon;
   const double* jblue;     // the model's normalised J_blue [S*L], or nullptr
   double* n_e;             // the model's [S]

@@ -14,7 +14,7 @@
 //                        in LDS, then per line a 16-byte record, two LDS
 //                        gathers and one coalesced 8-byte store.  HBM-bound
 //                        on the tau_S stores.
-//   plasma_nlte_kernel   (NLTE ions only, between the two) one workgroup per
+//   plasma_nlte_kernel   (NLTE ions only, between the two) one wavefront per
 //                        (ion, shell): rate matrix in LDS, LU solve.
 // plasma_lines_kernel runs once at load and folds the oscillator strength,
 // the wavelength and t_exp into one coefficient per line;
@@ -55,9 +55,8 @@ constexpr int kTauChunk = 8192;
 constexpr int kTauBatch = 8;
 // independent loads a lane issues before using any of them
 constexpr int kBatch = 4;
-// NLTE solve: one workgroup per (ion, shell); rates of this many lines are
+// NLTE solve: one wavefront per (ion, shell); rates of this many lines are
 // staged in LDS at a time
-constexpr int kNlteThreads = 256;
 constexpr int kNlteChunk = 256;
 // the depth kernel stages a shell's n / g table in LDS up to this many levels
 constexpr int kTauLdsLevels = 8192;
@@ -323,35 +322,42 @@ __global__ __launch_bounds__(kTauThreads) void plasma_tau_kernel(DevPlasma p) {
   if ((threadIdx.x % kWave) == 0 && neg) atomicAdd(p.clamped, neg);
 }
 
-// NLTE statistical equilibrium of one ion in one shell (one workgroup):
-// rates of kNlteChunk lines at a time in LDS (one thread per line), the
-// n x (n+1) augmented system assembled row by row in line order (thread r
-// owns row r, so the sums have a fixed order), equation 0 replaced by the
-// ion's total, then Gaussian elimination with partial pivoting (wavefront 0
-// finds the pivot, the first of equal magnitudes; all threads update the
-// trailing block) and back substitution.
-__global__ __launch_bounds__(kNlteThreads) void plasma_nlte_kernel(DevPlasma p) {
+// NLTE statistical equilibrium of one ion in one shell, one wavefront:
+// rates of kNlteChunk lines at a time in LDS (lanes over lines); lane r
+// assembles row r from the lines of level r only (a per-level list staged in
+// LDS, in line order, so every sum has a fixed order, the diagonal in a
+// register); equation 0 is replaced by the ion's total; then Gaussian
+// elimination with partial pivoting (the pivot is the first row of largest
+// magnitude; lane r eliminates row r) and back substitution.  A single
+// wavefront needs no workgroup barriers; the barriers below only order its
+// LDS accesses.
+__global__ __launch_bounds__(kWave) void plasma_nlte_kernel(DevPlasma p) {
   extern __shared__ double sm[];
   __shared__ double r_ul[kNlteChunk], r_lu[kNlteChunk];
-  __shared__ int16_t c_lo[kNlteChunk], c_up[kNlteChunk];
-  __shared__ int s_piv, s_fail;
   const int j = blockIdx.x, s = blockIdx.y, t = threadIdx.x;
   const int ion = p.nlte_ions[j];
   const int l0 = p.ion_level_ptr[ion], n = p.ion_level_ptr[ion + 1] - l0;
   const int ld = n + 1;
   double* M = sm;  // [n][n+1]: rates, then the right-hand side in column n
+  int32_t* ent = (int32_t*)(sm + kNlteMaxLevels * (kNlteMaxLevels + 1));
   const double T = p.T_R[s], W = p.W[s], ne = p.n_e[s];
   const double Te = kTeOverTr * T;
   const double sqrt_te = sqrt(Te);
-  for (int i = t; i < n * ld; i += kNlteThreads) M[i] = 0.0;
-  if (t == 0) s_fail = 0;
+  const int e0 = p.nlte_line_ptr[j], e1 = p.nlte_line_ptr[j + 1];
+  for (int i = t; i < n * ld; i += kWave) M[i] = 0.0;
+  for (int i = t; i < 2 * (e1 - e0); i += kWave) ent[i] = p.nlte_ent[2 * e0 + i];
+  int cur = 0, end = 0;
+  if (t < n) {
+    cur = p.nlte_lev_ptr[j * (kNlteMaxLevels + 1) + t];
+    end = p.nlte_lev_ptr[j * (kNlteMaxLevels + 1) + t + 1];
+  }
+  double diag = 0.0;
   __syncthreads();
 
-  const int e0 = p.nlte_line_ptr[j], e1 = p.nlte_line_ptr[j + 1];
   for (int c0 = e0; c0 < e1; c0 += kNlteChunk) {
     const int c1 = min(c0 + kNlteChunk, e1);
-    if (c0 + t < c1) {
-      const NlteLine ln = p.nlte_lines[c0 + t];
+    for (int e = c0 + t; e < c1; e += kWave) {
+      const NlteLine ln = p.nlte_lines[e];
       const double tau = p.tau[(size_t)s * p.Lp + ln.line];
       const double b = tau > 0.0 ? -expm1(-tau) / tau : 1.0;
       double J;
@@ -363,86 +369,84 @@ __global__ __launch_bounds__(kNlteThreads) void plasma_nlte_kernel(DevPlasma p) 
       }
       const double C_ul = ln.c_ul / sqrt_te;
       const double C_lu = C_ul * ln.g_ratio * exp(-kH * ln.nu / (kKB * Te));
-      r_ul[t] = b * ln.A_ul + b * ln.B_ul * J + C_ul * ne;
-      r_lu[t] = b * ln.B_lu * J + C_lu * ne;
-      c_lo[t] = ln.lo;
-      c_up[t] = ln.up;
+      r_ul[e - c0] = b * ln.A_ul + b * ln.B_ul * J + C_ul * ne;
+      r_lu[e - c0] = b * ln.B_lu * J + C_lu * ne;
     }
     __syncthreads();
-    if (t < n) {
-      for (int e = 0; e < c1 - c0; ++e) {
-        const int lo = c_lo[e], up = c_up[e];
-        if (t == lo) {
-          M[lo * ld + up] += r_ul[e];
-          M[lo * ld + lo] -= r_lu[e];
-        } else if (t == up) {
-          M[up * ld + up] -= r_ul[e];
-          M[up * ld + lo] += r_lu[e];
-        }
+    // row t: a line where t is the lower level sends r_lu out of t and
+    // brings r_ul in from the upper level; where t is the upper level, r_ul
+    // out and r_lu in
+    for (; cur < end; ++cur) {
+      const int32_t v = ent[cur];
+      const int e = (v >> 16) + e0;
+      if (e >= c1) break;
+      const int other = (v >> 1) & 0x7fff;
+      if (v & 1) {
+        M[t * ld + other] += r_ul[e - c0];
+        diag -= r_lu[e - c0];
+      } else {
+        M[t * ld + other] += r_lu[e - c0];
+        diag -= r_ul[e - c0];
       }
     }
     __syncthreads();
   }
-  if (t <= n) M[t] = t < n ? 1.0 : p.ion_density[(size_t)s * p.n_ions + ion];
+  if (t < n) M[t * ld + t] = diag;
+  __syncthreads();
+  if (t < n) M[t] = 1.0;
+  if (t == 0) M[n] = p.ion_density[(size_t)s * p.n_ions + ion];
   __syncthreads();
 
+  bool singular = false;
   for (int k = 0; k < n; ++k) {
-    if (t < kWave) {
-      double best = -1.0;
-      int bi = n;
-      for (int r = k + t; r < n; r += kWave) {
-        const double v = fabs(M[r * ld + k]);
-        if (v > best) {
-          best = v;
-          bi = r;
-        }
-      }
-      for (int o = kWave / 2; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(best, o, kWave);
-        const int oi = __shfl_xor(bi, o, kWave);
-        if (ov > best || (ov == best && oi < bi)) {
-          best = ov;
-          bi = oi;
-        }
-      }
-      if (t == 0) {
-        s_piv = bi;
-        if (!(best > 0.0)) s_fail = 1;
-      }
+    // pivot: largest |M[r][k]| over r >= k.  The bits of a non-negative
+    // double order like the value, so one 64-bit maximum finds it; the low
+    // 6 mantissa bits carry 63 - r instead, which picks the first row among
+    // magnitudes equal to 2^-46 relative
+    unsigned long long key = 0ull;
+    if (t >= k && t < n)
+      key = ((unsigned long long)__double_as_longlong(fabs(M[t * ld + k])) & ~63ull) |
+            (unsigned long long)(63 - t);
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      const unsigned long long ok = __shfl_xor(key, o, kWave);
+      key = ok > key ? ok : key;
     }
-    __syncthreads();
-    if (s_fail) break;
-    const int pr = s_piv;
-    if (pr != k) {
-      for (int c = k + t; c <= n; c += kNlteThreads) {
+    const int bi = 63 - (int)(key & 63ull);
+    if ((key >> 6) == 0ull) {
+      singular = true;  // the same on every lane
+      break;
+    }
+    if (bi != k) {
+      for (int c = k + t; c <= n; c += kWave) {
         const double a = M[k * ld + c];
-        M[k * ld + c] = M[pr * ld + c];
-        M[pr * ld + c] = a;
+        M[k * ld + c] = M[bi * ld + c];
+        M[bi * ld + c] = a;
       }
+      __syncthreads();
     }
-    __syncthreads();
-    const double piv = M[k * ld + k];
-    const int cols = n - k;  // columns k+1 .. n
-    for (int idx = t; idx < (n - k - 1) * cols; idx += kNlteThreads) {
-      const int r = k + 1 + idx / cols, c = k + 1 + idx % cols;
-      M[r * ld + c] -= M[r * ld + k] / piv * M[k * ld + c];
+    if (t > k && t < n) {
+      double* __restrict__ row = M + t * ld;
+      const double* __restrict__ prow = M + k * ld;
+      const double l = row[k] * (1.0 / prow[k]);
+#pragma unroll 8
+      for (int c = k + 1; c <= n; ++c) row[c] -= l * prow[c];
     }
     __syncthreads();
   }
-  if (s_fail) {
+  if (singular) {
     if (t == 0) atomicAdd(&p.clamped[1], 1ull);
     return;
   }
   for (int k = n - 1; k >= 0; --k) {
-    if (t == 0) M[k * ld + n] = M[k * ld + n] / M[k * ld + k];
+    const double xk = M[k * ld + n] / M[k * ld + k];
     __syncthreads();
-    const double xk = M[k * ld + n];
-    for (int r = t; r < k; r += kNlteThreads) M[r * ld + n] -= M[r * ld + k] * xk;
+    if (t == k) M[k * ld + n] = xk;
+    if (t < k) M[t * ld + n] -= M[t * ld + k] * xk;
     __syncthreads();
   }
   double* pop = p.level_pop + (size_t)s * p.n_levels + l0;
   double* xg = p.level_x + (size_t)s * p.n_levels + l0;
-  for (int r = t; r < n; r += kNlteThreads) {
+  for (int r = t; r < n; r += kWave) {
     const double v = fmax(M[r * ld + n], 0.0);
     pop[r] = v;
     xg[r] = v / p.level_g[l0 + r];
@@ -491,8 +495,9 @@ hipError_t launch_plasma_update(const DevPlasma& p, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (p.n_nlte > 0) {
-    const size_t lds = (size_t)kNlteMaxLevels * (kNlteMaxLevels + 1) * sizeof(double);
-    hipLaunchKernelGGL(plasma_nlte_kernel, dim3(p.n_nlte, p.S), dim3(kNlteThreads), lds, s, p);
+    const size_t lds = (size_t)kNlteMaxLevels * (kNlteMaxLevels + 1) * sizeof(double) +
+                       2 * (size_t)kNlteMaxLines * sizeof(int32_t);
+    hipLaunchKernelGGL(plasma_nlte_kernel, dim3(p.n_nlte, p.S), dim3(kWave), lds, s, p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (p.L == 0) return hipSuccess;
