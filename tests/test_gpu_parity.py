@@ -214,3 +214,30 @@ def test_invalid_inputs_raise(ctx):
         good.set_tune(long_lanes=8)  # 16, 32 or 64 lanes per handed-off history
     with pytest.raises(smc.SmcError):
         good.run_iteration(100, 10000.0, flags=smc.F_PACKETS | smc.F_JBLUE)  # > n_packets_max
+
+
+@pytest.mark.parametrize("T", [9000.0, 36000.0], ids=["T9000", "T36000"])
+def test_paper_scale_full_launch_sampled(ctx, T):
+    """The benchmark's launch: all 1e6 packets of the paper-scale model in one
+    iteration with the library's default tuning (lane kernel, hand-off,
+    ordering, 32-lane groups), per-packet records compared with the oracle
+    on a random sample of ids and on the longest histories known at the
+    converged inner temperature; the counters add up over the whole launch."""
+    w = W.config2()
+    N = w.n_packets
+    m = smc.Model(ctx, w.model, N, flags=smc.F_PACKETS)
+    m.run_iteration(N, T, flags=smc.F_PACKETS)
+    g = m.read_packets(N)
+    c = m.read_counters()
+    assert np.array_equal(g["id"], np.arange(N, dtype=np.uint64))
+    assert c["escaped"] + c["reabsorbed"] + c["capped"] == N
+    assert int((g["status"] == smc.ESCAPED).sum()) == c["escaped"]
+    assert int(g["n_segments"].sum()) == c["segments"]
+    assert int((g["n_escatter"] + g["n_line"]).sum()) == c["escatters"] + c["line_events"]
+    rng = np.random.default_rng(int(T))
+    ids = np.unique(np.concatenate([rng.choice(N, 1500, replace=False),
+                                    [183460, 862690, 782077]])).astype(np.uint64)
+    raw = O.run(w.model, T, N, packet_ids=ids, want_jblue=False)
+    assert_packets_match(g[ids.astype(np.int64)], raw["packets"])
+    if T > 30000.0:
+        assert int(g["n_segments"].max()) > 50000  # the tail is in this launch
