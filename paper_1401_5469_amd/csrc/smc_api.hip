@@ -90,7 +90,7 @@ constexpr uint32_t kDefaultLongBudget = 1024;
 constexpr int kDefaultLongLanes = 32;
 // wavefronts per CU of the group-per-packet kernel unless tuned (fewer when
 // its occupancy allows fewer)
-constexpr int kDefaultLongWaves = 8;
+constexpr int kDefaultLongWaves = 12;
 // launch-wide control block of a multi-model launch: 4 queue counters, then
 // the hand-off order histogram and cursors
 constexpr size_t kCtlBytes = 4 * sizeof(unsigned long long) + 2 * smc::kOrderBuckets * 4;

@@ -53,8 +53,9 @@ constexpr uint32_t kMacroMaxSteps = 100000;
 // them, do not depend on the order in which packets end.
 constexpr double kLScale = 0x1p60;
 
-// The group kernel takes handed-off histories in order of the lines still
-// to their red (more first), sorted by counting into this many buckets.
+// The group kernel takes handed-off histories in order of a predicted
+// length (lines to the red times distance from the inner boundary, larger
+// first), sorted by counting into this many buckets.
 constexpr int kOrderBuckets = 1024;
 
 // counters[] slots after the SMC_N_COUNTERS event counters
