@@ -829,14 +829,16 @@ __device__ __forceinline__ int long_owner(const LaunchArgs& a, uint64_t q) {
 }
 
 // Processing order of the handed-off histories: the larger the product of
-// (a) the fraction of the line list still to the red and (b) the distance
-// from the inner boundary as a fraction of the ejecta's depth, the earlier.
-// Lines to the red bound the work left; a history close to the inner
-// boundary is likely to be reabsorbed soon, one far from it has to diffuse
-// through the line forest first.  On the paper-scale model at its converged
-// inner temperature the product ranks the remaining length far better than
-// the lines alone (rank correlation 0.75 against 0.41), and the longest
-// histories start with the first wave of the group kernel.
+// (a) the fraction of the line list still to the red and (b) 0.1 plus the
+// distance from the inner boundary as a fraction of the ejecta's depth, the
+// earlier.  Lines to the red bound the work left; a history close to the
+// inner boundary is likely to be reabsorbed soon, one far from it has to
+// diffuse through the line forest first.  On the paper-scale model at its
+// converged inner temperature the radius ranks the remaining length far
+// better than the lines alone (rank correlation 0.75 against 0.41), and the
+// longest histories start with the first wave of the group kernel.  The 0.1
+// keeps the lines' order among histories handed over at the inner boundary
+// (all of them, with v-packets).
 template <bool kMulti>
 __device__ __forceinline__ int bucket_of_long(const LaunchArgs& a, uint64_t q) {
   const int k = long_owner<kMulti>(a, q);
@@ -846,7 +848,7 @@ __device__ __forceinline__ int bucket_of_long(const LaunchArgs& a, uint64_t q) {
   double x = (st.r - r0) / (r1 - r0);
   x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
   const double f = (double)(m.L - st.next_line) / ((double)a.max_lines + 1.0);
-  const int b = (int)(x * f * (double)kOrderBuckets);
+  const int b = (int)((x + 0.1) / 1.1 * f * (double)kOrderBuckets);
   return b >= kOrderBuckets ? kOrderBuckets - 1 : (b < 0 ? 0 : b);
 }
 
