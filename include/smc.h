@@ -388,6 +388,20 @@ int smc_plasma_read(smc_plasma* plasma, double* n_e, double* ion_density, double
 /* Release the handle; never frees the caller's workspace. */
 int smc_plasma_free(smc_plasma* plasma);
 
+/* A captured sequence as smc_graph_capture in which every iteration of model
+ * k is followed by the plasma update of plasmas[k] (NULL: none; the plasma
+ * must belong to models[k]) with plasma_params[k], from the model's own
+ * radiation field (its T_R and W must be NULL), so that the whole loop of
+ * section 2.8 (transport, estimators, plasma state, opacities) replays with
+ * no host work.  With detailed J_b every captured iteration of the model must
+ * tally J_blue.  The plasma objects and their workspaces must outlive the
+ * graph. */
+int smc_graph_capture_plasma(smc_ctx* ctx, smc_model* const* models,
+                             const smc_iter_params* params, int n_models, int n_iter,
+                             const smc_tune* tune, smc_plasma* const* plasmas,
+                             const smc_plasma_params* plasma_params, void* stream,
+                             smc_graph** out);
+
 #ifdef __cplusplus
 }
 #endif

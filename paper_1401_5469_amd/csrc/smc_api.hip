@@ -55,6 +55,16 @@ struct smc_model {
   smc_tune tune;
 };
 
+// A plasma object bound to a model (see smc_plasma_load).
+struct smc_plasma {
+  smc_model* model;
+  smc::PlasmaLayout lay;
+  smc::DevPlasma dev;
+  uint8_t* base;
+  int32_t n_nlte;
+  bool updated;
+};
+
 namespace {
 
 thread_local std::string g_err;
@@ -329,6 +339,42 @@ smc::Layout layout_of(const smc_model_desc* d, uint64_t n_packets_max, uint32_t 
 int sync_copy_out(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (!dst || bytes == 0) return SMC_OK;
   HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  return SMC_OK;
+}
+
+// Validate the parameters of a plasma update and fill the kernels' arguments,
+// with the radiation field taken from the model (a caller giving host arrays
+// stages them and repoints T_R and W).  after_iteration: an iteration of the
+// model precedes the update in stream order (always in a captured sequence),
+// so a detailed J_b reads that iteration's J_blue.
+int plasma_args(const smc_plasma* p, const smc_plasma_params* pp, bool after_iteration,
+                smc::DevPlasma* d) {
+  if (!p || !pp) return fail(SMC_EINVAL, "null plasma or parameters");
+  if (pp->ionization != SMC_ION_LTE && pp->ionization != SMC_ION_NEBULAR)
+    return fail(SMC_EINVAL, "unknown ionization mode %d", pp->ionization);
+  if (pp->excitation != SMC_EXC_LTE && pp->excitation != SMC_EXC_DILUTE_LTE)
+    return fail(SMC_EINVAL, "unknown excitation mode %d", pp->excitation);
+  if (!(pp->delta >= 0.0) || !isfinite(pp->delta))
+    return fail(SMC_EINVAL, "delta must be finite and >= 0");
+  if ((pp->T_R == nullptr) != (pp->W == nullptr))
+    return fail(SMC_EINVAL, "give both T_R and W, or neither");
+  if (pp->nlte != 0 && pp->nlte != 1) return fail(SMC_EINVAL, "nlte must be 0 or 1");
+  if (pp->jblue_mode != SMC_JB_DILUTE_BLACKBODY && pp->jblue_mode != SMC_JB_DETAILED)
+    return fail(SMC_EINVAL, "unknown J_b mode %d", pp->jblue_mode);
+  const smc_model* m = p->model;
+  const bool detailed = pp->nlte && p->n_nlte > 0 && pp->jblue_mode == SMC_JB_DETAILED;
+  if (detailed && !m->dev.jblue)
+    return fail(SMC_EINVAL, "detailed J_b needs a model loaded with SMC_F_JBLUE");
+  *d = p->dev;
+  d->ionization = pp->ionization;
+  d->excitation = pp->excitation;
+  d->delta = pp->delta;
+  d->n_nlte = pp->nlte ? p->n_nlte : 0;
+  d->jb_detailed = detailed && after_iteration ? 1 : 0;  // before any iteration: W B_nu(T_R)
+  d->jblue = m->dev.jblue;
+  const size_t S = (size_t)p->dev.S;
+  d->T_R = m->dev.out_shell + 2 * S;
+  d->W = m->dev.out_shell + 3 * S;
   return SMC_OK;
 }
 
@@ -823,6 +869,7 @@ int smc_read_timing(smc_model* m, double* transport_ms) {
 struct smc_graph {
   smc_ctx* ctx;
   std::vector<smc_model*> models;
+  std::vector<smc_plasma*> plasmas;     // per model, or nullptr: updated after each iteration
   std::vector<smc_iter_params> last;   // parameters of the last iteration, per model
   smc::BatchEntry* host_tables;        // pinned, n_iter * n_models
   smc::BatchEntry* dev_tables;
@@ -841,9 +888,10 @@ static void release_graph(smc_graph* g) {
   delete g;
 }
 
-int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
-                      int n_models, int n_iter, const smc_tune* tune, void* stream,
-                      smc_graph** out) {
+static int graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
+                         int n_models, int n_iter, const smc_tune* tune,
+                         smc_plasma* const* plasmas, const smc_plasma_params* plasma_params,
+                         smc_graph** out) {
   if (!ctx || !models || !params || !out) return fail(SMC_EINVAL, "null argument");
   *out = nullptr;
   if (n_models < 1 || n_models > smc::kMaxBatchModels || n_iter < 1 || n_iter > 1000)
@@ -865,11 +913,28 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
     if (!(params[k].T_inner > 0.0) && !models[k]->has_T)
       return fail(SMC_EINVAL, "model %d: the first captured iteration needs T_inner > 0", k);
   }
+  // plasma updates after every iteration, from the model's own field
+  std::vector<smc::DevPlasma> pdev(plasmas ? n_models : 0);
+  for (int k = 0; plasmas && k < n_models; ++k) {
+    if (!plasmas[k]) continue;
+    if (plasmas[k]->model != models[k])
+      return fail(SMC_EINVAL, "plasma %d does not belong to model %d", k, k);
+    if (!plasma_params) return fail(SMC_EINVAL, "plasma updates need their parameters");
+    if (plasma_params[k].T_R || plasma_params[k].W)
+      return fail(SMC_EINVAL, "a captured plasma update takes the model's own field");
+    if (int rc = plasma_args(plasmas[k], &plasma_params[k], true, &pdev[k])) return rc;
+    if (pdev[k].jb_detailed)
+      for (int i = 0; i < n_iter; ++i)
+        if (!(params[(size_t)i * n_models + k].flags & SMC_F_JBLUE))
+          return fail(SMC_EINVAL, "model %d: detailed J_b needs J_blue in every iteration", k);
+  }
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   smc_graph* g = new (std::nothrow) smc_graph();
   if (!g) return fail(SMC_ENOMEM, "host allocation failed");
   g->ctx = ctx;
   g->models.assign(models, models + n_models);
+  g->plasmas.assign((size_t)n_models, nullptr);
+  if (plasmas) g->plasmas.assign(plasmas, plasmas + n_models);
   const size_t n_ent = (size_t)n_iter * (size_t)n_models;
   hipError_t e = hipHostMalloc((void**)&g->host_tables, n_ent * sizeof(smc::BatchEntry),
                                hipHostMallocDefault);
@@ -917,7 +982,6 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
   }
   // record on a private stream (the caller's may be the null stream, which
   // cannot capture); the graph is launched later on the caller's stream
-  (void)stream;
   hipStream_t s = nullptr;
   e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
@@ -949,6 +1013,8 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
     const smc::Shape sh =
         shape_of(ctx, t, multi, work[i], budget > 0 || any_virtual[i], any_ext[i]);
     le = smc::launch_iteration(a, multi, sh, max_jb[i], nullptr, nullptr, s);
+    for (int k = 0; plasmas && k < n_models && le == hipSuccess; ++k)
+      if (plasmas[k]) le = smc::launch_plasma_update(pdev[k], s);
   }
   e = hipStreamEndCapture(s, &g->graph);
   (void)hipStreamDestroy(s);
@@ -965,6 +1031,24 @@ int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_par
   return ok();
 }
 
+int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
+                      int n_models, int n_iter, const smc_tune* tune, void* stream,
+                      smc_graph** out) {
+  (void)stream;
+  return graph_capture(ctx, models, params, n_models, n_iter, tune, nullptr, nullptr, out);
+}
+
+int smc_graph_capture_plasma(smc_ctx* ctx, smc_model* const* models,
+                             const smc_iter_params* params, int n_models, int n_iter,
+                             const smc_tune* tune, smc_plasma* const* plasmas,
+                             const smc_plasma_params* plasma_params, void* stream,
+                             smc_graph** out) {
+  (void)stream;
+  if (!plasmas) return fail(SMC_EINVAL, "null plasma array");
+  return graph_capture(ctx, models, params, n_models, n_iter, tune, plasmas, plasma_params,
+                       out);
+}
+
 int smc_graph_launch(smc_graph* g, void* stream) {
   if (!g) return fail(SMC_EINVAL, "null graph");
   HIP_TRY(hipSetDevice(g->ctx->device), "hipSetDevice");
@@ -977,6 +1061,7 @@ int smc_graph_launch(smc_graph* g, void* stream) {
     m->last_flags = g->last[k].flags;
     m->last_work = g->last[k].packet_ids ? g->last[k].n_ids : g->last[k].n_packets;
     m->last_virtual = g->last[k].n_virtual > 0;
+    if (g->plasmas[k]) g->plasmas[k]->updated = true;
   }
   return ok();
 }
@@ -991,14 +1076,6 @@ int smc_graph_destroy(smc_graph* g) {
 // ---------------------------------------------------------------------------
 // plasma state and Sobolev depths
 // ---------------------------------------------------------------------------
-struct smc_plasma {
-  smc_model* model;
-  smc::PlasmaLayout lay;
-  smc::DevPlasma dev;
-  uint8_t* base;
-  int32_t n_nlte;
-  bool updated;
-};
 
 namespace {
 
@@ -1333,22 +1410,11 @@ int smc_plasma_load(smc_model* model, const smc_plasma_desc* d, void* d_workspac
 
 int smc_plasma_update(smc_plasma* p, const smc_plasma_params* pp, void* stream) {
   if (!p || !pp) return fail(SMC_EINVAL, "null plasma or parameters");
-  if (pp->ionization != SMC_ION_LTE && pp->ionization != SMC_ION_NEBULAR)
-    return fail(SMC_EINVAL, "unknown ionization mode %d", pp->ionization);
-  if (pp->excitation != SMC_EXC_LTE && pp->excitation != SMC_EXC_DILUTE_LTE)
-    return fail(SMC_EINVAL, "unknown excitation mode %d", pp->excitation);
-  if (!(pp->delta >= 0.0) || !isfinite(pp->delta))
-    return fail(SMC_EINVAL, "delta must be finite and >= 0");
-  if ((pp->T_R == nullptr) != (pp->W == nullptr))
-    return fail(SMC_EINVAL, "give both T_R and W, or neither");
-  if (pp->nlte != 0 && pp->nlte != 1) return fail(SMC_EINVAL, "nlte must be 0 or 1");
-  if (pp->jblue_mode != SMC_JB_DILUTE_BLACKBODY && pp->jblue_mode != SMC_JB_DETAILED)
-    return fail(SMC_EINVAL, "unknown J_b mode %d", pp->jblue_mode);
   const smc_model* m = p->model;
-  const bool detailed = pp->nlte && p->n_nlte > 0 && pp->jblue_mode == SMC_JB_DETAILED;
-  if (detailed && !m->dev.jblue)
-    return fail(SMC_EINVAL, "detailed J_b needs a model loaded with SMC_F_JBLUE");
-  if (detailed && m->ran && !(m->last_flags & SMC_F_JBLUE))
+  smc::DevPlasma d;
+  int rc = plasma_args(p, pp, m->ran, &d);
+  if (rc) return rc;
+  if (d.jb_detailed && !(m->last_flags & SMC_F_JBLUE))
     return fail(SMC_EINVAL, "the model's last iteration did not tally J_blue");
   const int32_t S = p->dev.S;
   if (pp->T_R) {
@@ -1359,15 +1425,8 @@ int smc_plasma_update(smc_plasma* p, const smc_plasma_params* pp, void* stream) 
         return fail(SMC_EINVAL, "W[%d] must be finite and > 0", i);
     }
   }
-  HIP_TRY(hipSetDevice(p->model->ctx->device), "hipSetDevice");
+  HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
-  smc::DevPlasma d = p->dev;
-  d.ionization = pp->ionization;
-  d.excitation = pp->excitation;
-  d.delta = pp->delta;
-  d.n_nlte = pp->nlte ? p->n_nlte : 0;
-  d.jb_detailed = detailed && m->ran ? 1 : 0;  // before any iteration: W B_nu(T_R)
-  d.jblue = m->dev.jblue;
   if (pp->T_R) {
     double* field = (double*)(p->base + p->lay.field);
     HIP_TRY(hipMemcpyAsync(field, pp->T_R, (size_t)S * 8, hipMemcpyHostToDevice, s),
@@ -1377,9 +1436,6 @@ int smc_plasma_update(smc_plasma* p, const smc_plasma_params* pp, void* stream) 
     HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
     d.T_R = field;
     d.W = field + S;
-  } else {
-    d.T_R = p->model->dev.out_shell + 2 * (size_t)S;
-    d.W = p->model->dev.out_shell + 3 * (size_t)S;
   }
   HIP_TRY(smc::launch_plasma_update(d, s), "plasma update");
   p->updated = true;

@@ -84,7 +84,7 @@ EXPORTS = ("smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_model_wor
            "smc_model_set_tune", "smc_model_get_tune", "smc_batch_run", "smc_batch_read_timing",
            "smc_batch_autotune", "smc_graph_capture", "smc_graph_launch", "smc_graph_destroy",
            "smc_read_virtual_spectrum", "smc_plasma_workspace_bytes", "smc_plasma_load",
-           "smc_plasma_update", "smc_plasma_read", "smc_plasma_free")
+           "smc_plasma_update", "smc_plasma_read", "smc_plasma_free", "smc_graph_capture_plasma")
 
 
 class SmcError(RuntimeError):
@@ -140,6 +140,9 @@ def load_library(path: str = LIB_PATH):
     L.smc_plasma_update.argtypes = [vp, C.POINTER(smc_plasma_params), vp]
     L.smc_plasma_read.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _u64p, vp]
     L.smc_plasma_free.argtypes = [vp]
+    L.smc_graph_capture_plasma.argtypes = [vp, C.POINTER(vp), C.POINTER(smc_iter_params), C.c_int,
+                                           C.c_int, C.POINTER(smc_tune), C.POINTER(vp),
+                                           C.POINTER(smc_plasma_params), vp, C.POINTER(vp)]
     for name in EXPORTS:
         if name != "smc_last_error":
             getattr(L, name).restype = C.c_int
@@ -235,9 +238,12 @@ class Context:
         return (dict(blocks_per_cu=best.blocks_per_cu, long_waves_per_cu=best.long_waves_per_cu,
                      long_budget=best.long_budget, long_lanes=best.long_lanes), float(ms.value))
 
-    def capture(self, models, params_per_iter, tune=None, stream=None):
+    def capture(self, models, params_per_iter, tune=None, plasmas=None, plasma_params=None,
+                stream=None):
         """Record iterations (a list, one list of per-model parameter dicts per
-        iteration) into a replayable HIP graph."""
+        iteration) into a replayable HIP graph.  plasmas: per model a Plasma
+        (or None) updated after each of its iterations with plasma_params
+        (per model a dict of Plasma.update's mode arguments)."""
         n, n_iter = len(models), len(params_per_iter)
         arr = (smc_iter_params * (n * n_iter))()
         handles = (C.c_void_p * n)()
@@ -250,8 +256,25 @@ class Context:
                 keep.append(m._ids)
         h = C.c_void_p()
         t = _tune(tune) if tune else None
-        _check(_lib.smc_graph_capture(self.handle, handles, arr, n, n_iter,
-                                      C.byref(t) if t else None, _stream_ptr(stream), C.byref(h)))
+        if plasmas is None:
+            _check(_lib.smc_graph_capture(self.handle, handles, arr, n, n_iter,
+                                          C.byref(t) if t else None, _stream_ptr(stream),
+                                          C.byref(h)))
+            return Graph(h, models, keep)
+        ph = (C.c_void_p * n)()
+        pp = (smc_plasma_params * n)()
+        for k, pl in enumerate(plasmas):
+            ph[k] = pl.handle if pl is not None else None
+            q = dict((plasma_params or [{}] * n)[k] or {})
+            pp[k].ionization = int(q.get("ionization", ION_NEBULAR))
+            pp[k].excitation = int(q.get("excitation", EXC_DILUTE_LTE))
+            pp[k].delta = float(q.get("delta", 1.0))
+            pp[k].nlte = 1 if q.get("nlte", False) else 0
+            pp[k].jblue_mode = int(q.get("jblue_mode", JB_DILUTE_BLACKBODY))
+        _check(_lib.smc_graph_capture_plasma(self.handle, handles, arr, n, n_iter,
+                                             C.byref(t) if t else None, ph, pp,
+                                             _stream_ptr(stream), C.byref(h)))
+        keep.append([pl for pl in plasmas if pl is not None])
         return Graph(h, models, keep)
 
     def batch_read_timing(self):
