@@ -96,7 +96,7 @@ int hip_fail(hipError_t e, const char* what) {
   } while (0)
 
 constexpr uint64_t kAlign = 256;
-constexpr uint32_t kDefaultLongBudget = 1024;
+constexpr uint32_t kDefaultLongBudget = 256;
 constexpr int kDefaultLongLanes = 32;
 // wavefronts per CU of the group-per-packet kernel unless tuned (fewer when
 // its occupancy allows fewer)
