@@ -96,7 +96,13 @@ int hip_fail(hipError_t e, const char* what) {
   } while (0)
 
 constexpr uint64_t kAlign = 256;
+// flight segments before a history moves to the group kernel unless tuned:
+// fewer for one model in a plain mode (its longest histories start sooner),
+// more with macro atoms (their group-kernel variant carries more registers
+// and runs fewer histories at once) and in multi-model launches (where
+// throughput matters more than the latency of one history)
 constexpr uint32_t kDefaultLongBudget = 256;
+constexpr uint32_t kDefaultLongBudgetWide = 1024;
 constexpr int kDefaultLongLanes = 32;
 // wavefronts per CU of the group-per-packet kernel unless tuned (fewer when
 // its occupancy allows fewer)
@@ -139,8 +145,8 @@ int check_tune(const smc_tune& t) {
 // hand-off positions run at the highest wave priority: two histories per SIMD
 uint32_t hot_of(const smc_ctx* c) { return 8u * (uint32_t)c->n_cu; }
 
-uint32_t budget_of(const smc_tune& t) {
-  return t.long_budget == 0 ? kDefaultLongBudget
+uint32_t budget_of(const smc_tune& t, bool wide) {
+  return t.long_budget == 0 ? (wide ? kDefaultLongBudgetWide : kDefaultLongBudget)
                             : (t.long_budget == UINT32_MAX ? 0u : t.long_budget);
 }
 
@@ -571,7 +577,7 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   if (!m || !p) return fail(SMC_EINVAL, "null model or parameters");
   smc::LaunchArgs a;
   memset(&a, 0, sizeof a);
-  int rc = make_iter(m, p, budget_of(m->tune), &a.single.it);
+  int rc = make_iter(m, p, budget_of(m->tune, m->dev.mode == SMC_MACROATOM), &a.single.it);
   if (rc) return rc;
   HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
@@ -616,7 +622,10 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
   memset(&t, 0, sizeof t);
   if (tune) t = *tune;
   if (int rc = check_tune(t)) return rc;
-  const uint32_t budget = budget_of(t);
+  bool any_macro = false;
+  for (int k = 0; k < n_models; ++k)
+    if (models[k] && models[k]->dev.mode == SMC_MACROATOM) any_macro = true;
+  const uint32_t budget = budget_of(t, any_macro || n_models > 1);
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   // take the next slot once the launch that last used it has finished
   const int slot = ctx->next_slot;
@@ -851,7 +860,8 @@ int smc_model_get_tune(smc_model* m, smc_tune* t) {
   if (t->long_lanes == 0) t->long_lanes = kDefaultLongLanes;
   if (t->long_waves_per_cu == 0)
     t->long_waves_per_cu = default_long_waves(m->ctx, false, *t, m->dev.mode == SMC_MACROATOM);
-  if (t->long_budget == 0) t->long_budget = kDefaultLongBudget;
+  if (t->long_budget == 0)
+    t->long_budget = m->dev.mode == SMC_MACROATOM ? kDefaultLongBudgetWide : kDefaultLongBudget;
   return ok();
 }
 
@@ -904,7 +914,10 @@ static int graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_
   else if (n_models == 1 && models[0])
     t = models[0]->tune;
   if (int rc = check_tune(t)) return rc;
-  const uint32_t budget = budget_of(t);
+  bool any_macro = false;
+  for (int k = 0; k < n_models; ++k)
+    if (models[k] && models[k]->dev.mode == SMC_MACROATOM) any_macro = true;
+  const uint32_t budget = budget_of(t, any_macro || n_models > 1);
   for (int k = 0; k < n_models; ++k) {
     if (!models[k] || models[k]->ctx != ctx)
       return fail(SMC_EINVAL, "model %d is null or of another context", k);

@@ -64,9 +64,12 @@ def test_batch_equals_alone(ctx, tune):
     together = _batch(ctx, mix, tune)
     for (mdl, N, T), b in zip(mix, together):
         # the same hand-off budget and group width alone: each history takes
-        # the same kernels with the same rounding
+        # the same kernels with the same rounding (untuned, a multi-model
+        # launch hands off after 1024 segments, one model alone after 256)
         same = {k: v for k, v in (tune or {}).items() if k in ("long_budget", "long_lanes")}
-        a = _alone(ctx, mdl, N, T, tune=same or None)
+        if "long_budget" not in same:
+            same["long_budget"] = 1024
+        a = _alone(ctx, mdl, N, T, tune=same)
         assert np.array_equal(a["packets"], b["packets"])
         for k in ("J", "nubar", "T_R", "W"):
             np.testing.assert_allclose(b["est"][k], a["est"][k], rtol=1e-12, atol=0)
