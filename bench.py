@@ -32,7 +32,9 @@ per line resonance: nu_k and tau_S read, J_blue read-modify-write) against
 the HBM peak; `traffic` is the measured HBM bytes per transport pass from
 the committed hardware-counter summary when it was taken on the current
 kernel source (else null).  The CPU baseline times the FP64 oracle on a
-bounded packet sample of the same workload on one host core.
+bounded packet sample of the same workload, once on one host core and once
+split over --cpu-procs oracle processes on disjoint packet-id ranges (the
+host's CPU share); it reports the latter, with the single-core figure inside.
 """
 import argparse
 import json
@@ -59,6 +61,10 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1_000_000,
                     help="packets of iteration 0 the oracle runs for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="oracle processes of the all-cores CPU baseline (the host's CPU share)")
+    ap.add_argument("--cpu-worker", type=int, nargs=2, metavar=("LO", "HI"),
+                    help=argparse.SUPPRESS)
     ap.add_argument("--no-jblue", action="store_true")
     ap.add_argument("--workload", default="paper-scale",
                     choices=["paper-scale", "batched", "served", "copy", "virtual",
@@ -364,26 +370,66 @@ def plasma(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(w, n_sample):
-    from oracle import build as ob
+def _oracle_sample(w, lo, hi):
+    """The oracle on packet ids [lo, hi) of iteration 0: counters and seconds."""
     from oracle import oracle as O
     import numpy as np
 
-    if not os.path.exists(ob.LIB):
-        ob.build()
-    ids = np.arange(n_sample, dtype=np.uint64)
+    ids = np.arange(lo, hi, dtype=np.uint64)
     t0 = time.perf_counter()
     r = O.run(w.model, w.T_inner, w.n_packets, iteration=0, packet_ids=ids, want_jblue=True,
               want_packets=False)
-    dt = time.perf_counter() - t0
-    c = r["counters"]
+    return r["counters"], time.perf_counter() - t0
+
+
+def cpu_worker(args):
+    """One process of the all-cores baseline: no GPU, one JSON line."""
+    from paper_1401_5469_amd import workloads as W
+
+    w = W.config2(n_packets=args.packets)
+    c, dt = _oracle_sample(w, args.cpu_worker[0], args.cpu_worker[1])
+    print(json.dumps({"counters": c, "seconds": dt}), flush=True)
+
+
+def cpu_baseline(w, n_sample, procs):
+    """The FP64 oracle on packet ids 0..n_sample-1 of iteration 0: once in
+    this process on one core, then split into `procs` disjoint id ranges run
+    by as many oracle processes at once (wall time = the slowest)."""
+    import subprocess
+    from oracle import build as ob
+
+    if not os.path.exists(ob.LIB):
+        ob.build()
+    c, dt = _oracle_sample(w, 0, n_sample)
     inter = c["line_events"] + c["escatters"]
-    return {"value": inter / dt, "unit": "interactions/s", "cores": 1, "kind": "oracle",
+    single = {"value": inter / dt, "unit": "interactions/s", "cores": 1, "seconds": dt,
+              "packets_per_s": n_sample / dt, "segments_per_s": c["segments"] / dt,
+              "line_passes_per_s": c["line_passes"] / dt}
+    edges = [n_sample * k // procs for k in range(procs + 1)]
+    workers = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--packets",
+                                 str(w.n_packets), "--cpu-worker", str(a), str(b)],
+                                stdout=subprocess.PIPE, text=True)
+               for a, b in zip(edges[:-1], edges[1:]) if b > a]
+    res = []
+    for p in workers:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle worker failed with status {p.returncode}")
+        res.append(json.loads(out.strip().splitlines()[-1]))
+    wall = max(r["seconds"] for r in res)
+    tot = {k: sum(r["counters"][k] for r in res) for k in res[0]["counters"]}
+    inter_all = tot["line_events"] + tot["escatters"]
+    assert inter_all == inter, "the split sample must hold the same interactions"
+    return {"value": inter_all / wall, "unit": "interactions/s", "cores": len(workers),
+            "kind": "oracle",
             "sample": f"packet ids 0..{n_sample - 1} of iteration 0 at T_inner = {w.T_inner:g} K "
-                      f"({inter} interactions, {c['segments']} segments, {dt:.2f} s, "
-                      f"single-threaded FP64 C oracle)",
-            "packets_per_s": n_sample / dt, "segments_per_s": c["segments"] / dt,
-            "line_passes_per_s": c["line_passes"] / dt, "seconds": dt}
+                      f"({inter} interactions, {c['segments']} segments), split over "
+                      f"{len(workers)} single-threaded FP64 C oracle processes on disjoint id "
+                      f"ranges (slowest {wall:.2f} s); the same sample in one process took "
+                      f"{dt:.2f} s",
+            "packets_per_s": n_sample / wall, "segments_per_s": tot["segments"] / wall,
+            "line_passes_per_s": tot["line_passes"] / wall, "seconds": wall,
+            "single_core": single}
 
 
 def batched(args):
@@ -561,6 +607,8 @@ def served(args):
 
 def main():
     args = parse()
+    if args.cpu_worker:
+        return cpu_worker(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported in this build "
               "(the transport shards by packet ids; see the design notes)", file=sys.stderr)
@@ -656,7 +704,7 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_procs)
     print(json.dumps(out), flush=True)
 
 
