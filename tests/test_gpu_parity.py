@@ -241,3 +241,26 @@ def test_paper_scale_full_launch_sampled(ctx, T):
     assert_packets_match(g[ids.astype(np.int64)], raw["packets"])
     if T > 30000.0:
         assert int(g["n_segments"].max()) > 50000  # the tail is in this launch
+
+
+def test_largest_batched_shape_full_launch_sampled(ctx):
+    """The largest model shape of the batched mix (100 shells, 3e5 lines: a
+    240 MB Sobolev-depth table) with 1e6 packets in one default-tuned launch;
+    per-packet records compared with the oracle on a random sample of ids and
+    on the sample's longest histories, counters checked over the whole launch."""
+    rng = np.random.default_rng(2024)
+    model = W.config2_model(rng, n_shells=100, n_lines=300_000, seed=77)
+    N, T = 1_000_000, 12000.0
+    m = smc.Model(ctx, model, N, flags=smc.F_PACKETS)
+    m.run_iteration(N, T, flags=smc.F_PACKETS)
+    g = m.read_packets(N)
+    c = m.read_counters()
+    assert np.array_equal(g["id"], np.arange(N, dtype=np.uint64))
+    assert c["escaped"] + c["reabsorbed"] + c["capped"] == N
+    assert int(g["n_segments"].sum()) == c["segments"]
+    assert int((g["n_escatter"] + g["n_line"]).sum()) == c["escatters"] + c["line_events"]
+    longest = np.argsort(g["n_segments"])[-5:]
+    ids = np.unique(np.concatenate([np.random.default_rng(7).choice(N, 1000, replace=False),
+                                    longest])).astype(np.uint64)
+    raw = O.run(model, T, N, packet_ids=ids, want_jblue=False)
+    assert_packets_match(g[ids.astype(np.int64)], raw["packets"])
