@@ -605,6 +605,36 @@ def served(args):
     print(json.dumps(out), flush=True)
 
 
+def critical_path(ctx, w, flags, iteration, T_inner, pass_ms):
+    """Latency bound of one transport pass: the longest history of the last
+    timed iteration, found in a replay of that iteration with per-packet
+    records, then run alone (a one-id launch, best of 3).  Histories depend
+    only on (seed, iteration, packet id, T_inner), so the replay and the lone
+    run follow the timed pass's history exactly; no pass can end before its
+    longest history, which runs segment after segment."""
+    import numpy as np
+
+    from paper_1401_5469_amd import smc
+
+    N = w.n_packets
+    pm = smc.Model(ctx, w.model, N, flags=flags | smc.F_PACKETS)
+    pm.run_iteration(N, T_inner, iteration=iteration, flags=flags | smc.F_PACKETS,
+                     L_requested=w.L_requested, damping=w.damping)
+    g = pm.read_packets(N)
+    k = int(np.argmax(g["n_segments"]))
+    pid, n_seg = int(g["id"][k]), int(g["n_segments"][k])
+    alone = []
+    for _ in range(3):
+        pm.run_iteration(N, T_inner, iteration=iteration, flags=flags | smc.F_TIMING,
+                         L_requested=w.L_requested, damping=w.damping,
+                         packet_ids=np.array([pid], dtype=np.uint64))
+        alone.append(pm.read_timing())
+    a = min(alone)
+    return {"packet_id": pid, "T_inner": T_inner, "iteration": iteration, "segments": n_seg,
+            "alone_ms": a, "us_per_segment_alone": a * 1e3 / n_seg, "pass_ms": pass_ms,
+            "frac": a / pass_ms}
+
+
 def main():
     args = parse()
     if args.cpu_worker:
@@ -703,6 +733,8 @@ def main():
                      "bytes_per_launch": bytes_per_launch},
         "cpu_baseline": None,
     }
+    out["critical_path"] = critical_path(ctx, w, flags, args.steps - 1, rec[-1][2], kern_ms[-1])
+    print(f"# critical path: {json.dumps(out['critical_path'])}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_procs)
     print(json.dumps(out), flush=True)
