@@ -65,6 +65,8 @@ def parse():
                     help="oracle processes of the all-cores CPU baseline (the host's CPU share)")
     ap.add_argument("--cpu-worker", type=int, nargs=2, metavar=("LO", "HI"),
                     help=argparse.SUPPRESS)
+    ap.add_argument("--no-critical-path", action="store_true",
+                    help="skip the untimed replay of the longest history (profiling runs)")
     ap.add_argument("--no-jblue", action="store_true")
     ap.add_argument("--workload", default="paper-scale",
                     choices=["paper-scale", "batched", "served", "copy", "virtual",
@@ -733,8 +735,12 @@ def main():
                      "bytes_per_launch": bytes_per_launch},
         "cpu_baseline": None,
     }
-    out["critical_path"] = critical_path(ctx, w, flags, args.steps - 1, rec[-1][2], kern_ms[-1])
-    print(f"# critical path: {json.dumps(out['critical_path'])}", file=sys.stderr, flush=True)
+    out["critical_path"] = None
+    if not args.no_critical_path:
+        out["critical_path"] = critical_path(ctx, w, flags, args.steps - 1, rec[-1][2],
+                                             kern_ms[-1])
+        print(f"# critical path: {json.dumps(out['critical_path'])}", file=sys.stderr,
+              flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_procs)
     print(json.dumps(out), flush=True)

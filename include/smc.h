@@ -97,7 +97,8 @@ typedef struct {
   int64_t n_em;              /* level_ptr[n_levels] */
   const int32_t* em_line;    /* [n_em] emitted line in [0, L), or -(level+1) (macroatom) */
   const double* em_cum;      /* [n_em] (downbranch) or [S*n_em] (macroatom) cumulative
-                                probabilities, non-decreasing within a row */
+                                probabilities in [0, 1], non-decreasing within a row
+                                (SMC_EINVAL otherwise) */
   /* emergent spectrum: n_bins bins linear in lab frequency over
    * [nu_min, nu_max), plus underflow and overflow (section 2.9) */
   double nu_min, nu_max;

@@ -288,6 +288,13 @@ int validate(const smc_model_desc* d) {
     for (int64_t j = 0; j < n_cum; ++j)
       if (!(d->em_cum[j] >= 0.0 && d->em_cum[j] <= 1.0))
         return fail(SMC_EINVAL, "em_cum[%lld] must lie in [0, 1]", (long long)j);
+    // the kernels select an entry by bisection, which needs sorted rows
+    for (int64_t t = 0; t < n_cum; t += d->n_em)
+      for (int32_t v = 0; v < d->n_levels; ++v)
+        for (int64_t j = d->level_ptr[v] + 1; j < d->level_ptr[v + 1]; ++j)
+          if (d->em_cum[t + j] < d->em_cum[t + j - 1])
+            return fail(SMC_EINVAL, "em_cum must be non-decreasing within a row (entry %lld)",
+                        (long long)(t + j));
     for (int64_t k = 0; k < d->n_lines; ++k) {
       const int32_t u = d->line_upper[k];
       if (u < 0 || u >= d->n_levels)

@@ -267,6 +267,24 @@ __device__ __forceinline__ double recip(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
+// The entry a transition row [lo, hi) selects for a uniform draw u: the first
+// j in [lo, hi - 1) with cum[j] > u, else the row's last entry (section 2.5).
+// Rows are non-decreasing (checked when the model is loaded), so bisection
+// finds the entry a scan from lo would stop at, in log2(hi - lo) loads whose
+// count hardly varies between the lanes of a wavefront.
+__device__ __forceinline__ int64_t row_select(const double* cum, int64_t lo, int64_t hi,
+                                              double u) {
+  int64_t a = lo, b = hi - 1;
+  while (a < b) {
+    const int64_t mid = a + ((b - a) >> 1);
+    if (cum[mid] > u)
+      b = mid;
+    else
+      a = mid + 1;
+  }
+  return a;
+}
+
 // spectrum bin of an escaping lab frequency (section 2.9): n_bins is the
 // underflow slot (also taken by a NaN), n_bins+1 the overflow slot
 __device__ __forceinline__ int spectrum_bin(const DevModel& m, double nu) {
@@ -709,9 +727,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(LaunchArgs a) {
           nu_cmf_out = nu_hit;
           if (v.downbranch) {
             const int32_t up = v.line_upper[k];
-            const int64_t lo = v.level_ptr[up], hi = v.level_ptr[up + 1];
-            int64_t j = lo;
-            while (j < hi - 1 && !(v.em_cum[j] > u_branch)) ++j;
+            const int64_t j = row_select(v.em_cum, v.level_ptr[up], v.level_ptr[up + 1], u_branch);
             emit = v.em_line[j];
             nu_cmf_out = v.line_nu[emit];
           } else if (v.macroatom) {
@@ -723,9 +739,7 @@ __global__ __launch_bounds__(kBlock) void transport_kernel(LaunchArgs a) {
             uint32_t steps = 0;
             emit = -1;
             for (;;) {
-              const int64_t lo = v.level_ptr[level], hi = v.level_ptr[level + 1];
-              int64_t j = lo;
-              while (j < hi - 1 && !(cum[j] > u)) ++j;
+              const int64_t j = row_select(cum, v.level_ptr[level], v.level_ptr[level + 1], u);
               const int32_t target = v.em_line[j];
               if (target >= 0) {
                 emit = target;
@@ -951,6 +965,19 @@ struct Group {
   __device__ __forceinline__ unsigned long long bits(unsigned long long w) const {
     if constexpr (G == 64) return w;
     return (w >> base) & kMask;
+  }
+  // the entry of transition row [lo, hi) (group-uniform bounds) a uniform
+  // draw u selects: the first j in [lo, hi - 1) with cum[j] > u, else the
+  // last entry (section 2.5); G entries per round, one coalesced load and a
+  // ballot each
+  __device__ __forceinline__ int64_t row_select(const double* cum, int64_t lo, int64_t hi,
+                                                double u) const {
+    for (int64_t b = lo; b < hi - 1; b += G) {
+      const int64_t j = b + lane;
+      const unsigned long long above = bits(__ballot(j < hi - 1 && cum[j] > u));
+      if (above) return b + (int64_t)__builtin_ctzll(above);
+    }
+    return hi - 1;
   }
   // inclusive prefix sum over the group (row shifts within rows of 16 lanes,
   // then the row broadcasts of lanes 15 and 31)
@@ -1378,9 +1405,8 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
           inv_cmf_out = inv_hit;
           if (v.downbranch) {
             const int32_t up = v.line_upper[k];
-            const int64_t lo = v.level_ptr[up], hi = v.level_ptr[up + 1];
-            int64_t j = lo;
-            while (j < hi - 1 && !(v.em_cum[j] > u_branch)) ++j;
+            const int64_t j =
+                grp.row_select(v.em_cum, v.level_ptr[up], v.level_ptr[up + 1], u_branch);
             emit = v.em_line[j];
             nu_cmf_out = v.line_nu[emit];
             inv_cmf_out = recip(nu_cmf_out);
@@ -1393,9 +1419,7 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
             uint32_t steps = 0;
             emit = -1;
             for (;;) {
-              const int64_t lo = v.level_ptr[level], hi = v.level_ptr[level + 1];
-              int64_t j = lo;
-              while (j < hi - 1 && !(cum[j] > u)) ++j;
+              const int64_t j = grp.row_select(cum, v.level_ptr[level], v.level_ptr[level + 1], u);
               const int32_t target = v.em_line[j];
               if (target >= 0) {
                 emit = target;

@@ -151,6 +151,16 @@ def test_host_validation_rejects_bad_downbranch_tables(lib):
     el[0] = m.n_lines
     bad.em_line = el
     assert "em_line" in _expect_invalid(bad)
+    # rows are searched by bisection: a decreasing pair inside a row is refused,
+    # the step from one row's last entry to the next row's first is not
+    lp = m.level_ptr
+    v = int(np.nonzero(np.diff(lp) >= 2)[0][0])
+    bad = W.Model(**{**m.__dict__})
+    ec = m.em_cum.copy()
+    ec[lp[v]], ec[lp[v] + 1] = 0.75, 0.5
+    bad.em_cum = ec
+    assert "non-decreasing" in _expect_invalid(bad)
+    assert lp[v + 1] < len(m.em_cum) and m.em_cum[lp[v + 1]] < m.em_cum[lp[v + 1] - 1]
 
 
 def test_host_validation_of_macroatom_tables(lib):
@@ -173,6 +183,14 @@ def test_host_validation_of_macroatom_tables(lib):
     ec[-1, 3] = 1.5
     bad.em_cum = ec
     assert "em_cum" in _expect_invalid(bad)
+    # each shell's rows must be sorted (here the last shell's)
+    a, b = m.level_ptr[0], m.level_ptr[1]
+    assert b - a >= 2
+    bad = W.Model(**{**m.__dict__})
+    ec = m.em_cum.copy()
+    ec[-1, a:b] = ec[-1, a:b][::-1].copy()
+    bad.em_cum = ec
+    assert "non-decreasing" in _expect_invalid(bad)
 
 
 def _plasma_spec():
