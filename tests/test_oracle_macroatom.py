@@ -14,7 +14,6 @@ mathematics and the paper fix:
 None of these tests needs a GPU.
 """
 import numpy as np
-import pytest
 from scipy import stats
 
 from oracle import oracle as O

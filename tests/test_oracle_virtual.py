@@ -15,7 +15,6 @@ None of these tests needs a GPU.
 import math
 
 import numpy as np
-import pytest
 
 from oracle import oracle as O
 from paper_1401_5469_amd import workloads as W
