@@ -294,6 +294,16 @@ class Context:
             pass
 
 
+def _need(a, n: int, what: str, at_least: bool = False):
+    """The C descriptions carry counts, not array lengths: an array shorter
+    than its count would be read past its end, so every length is checked
+    here, before a pointer crosses the boundary."""
+    got = -1 if a is None else int(np.size(a))
+    if got < int(n) or (got != int(n) and not at_least):
+        raise ValueError(f"{what} has {'no' if a is None else got} entries where the "
+                         f"description needs {n}")
+
+
 def _desc(model, keep: list) -> smc_model_desc:
     def arr(a, dt):
         a = np.ascontiguousarray(a, dtype=dt)
@@ -302,6 +312,15 @@ def _desc(model, keep: list) -> smc_model_desc:
 
     d = smc_model_desc()
     S, L = model.n_shells, model.n_lines
+    _need(model.n_e, S, "n_e")
+    _need(model.tau_sobolev, S * L, "tau_sobolev")
+    if L and np.ndim(model.tau_sobolev) == 2 and np.shape(model.tau_sobolev) != (S, L):
+        raise ValueError(f"tau_sobolev must be [{S}, {L}], not {np.shape(model.tau_sobolev)}")
+    if model.line_mode in (DOWNBRANCH, MACROATOM):
+        n_em = int(np.size(model.em_line))
+        _need(model.line_upper, L, "line_upper")
+        _need(model.level_ptr, int(model.n_levels) + 1, "level_ptr")
+        _need(model.em_cum, S * n_em if model.line_mode == MACROATOM else n_em, "em_cum")
     d.n_shells = S
     d.v_bounds = _ptr(arr(model.v_bounds, np.float64), _dp)
     d.t_exp = float(model.t_exp)
@@ -461,13 +480,25 @@ class Model:
         return out
 
 
-def _plasma_desc(spec, keep: list) -> smc_plasma_desc:
+def _plasma_desc(spec, keep: list, n_shells: int, n_lines: int) -> smc_plasma_desc:
     def arr(a, dt):
         a = np.ascontiguousarray(a, dtype=dt)
         keep.append(a)
         return a
 
     atom = spec.atom
+    E, NI, NL = atom.n_elements, atom.n_ions, atom.n_levels
+    _need(atom.ion_zeta, NI, "ion_zeta")
+    _need(atom.ion_level_ptr, NI + 1, "ion_level_ptr")
+    _need(atom.level_g, NL, "level_g")
+    _need(atom.level_metastable, NL, "level_metastable")
+    # the library reads the first n_lines line records (none for a model
+    # without lines)
+    for name in ("line_lower", "line_upper", "line_f"):
+        _need(getattr(atom, name), n_lines, name, at_least=True)
+    _need(spec.number_density, int(n_shells) * E, "number_density")
+    if getattr(spec, "nlte_ions", ()) and n_lines and atom.line_upsilon is not None:
+        _need(atom.line_upsilon, n_lines, "line_upsilon", at_least=True)
     d = smc_plasma_desc()
     d.n_elements = atom.n_elements
     d.n_ions = atom.n_ions
@@ -496,7 +527,7 @@ def _plasma_desc(spec, keep: list) -> smc_plasma_desc:
 def plasma_workspace_bytes(spec, n_shells: int, n_lines: int) -> int:
     lib = load_library()
     keep = []
-    d = _plasma_desc(spec, keep)
+    d = _plasma_desc(spec, keep, n_shells, n_lines)
     out = C.c_uint64()
     _check(lib.smc_plasma_workspace_bytes(C.byref(d), int(n_shells), int(n_lines), C.byref(out)))
     return int(out.value)
@@ -516,7 +547,7 @@ class Plasma:
         if np.shape(spec.number_density) != (model.S, spec.atom.n_elements):
             raise ValueError("number_density must be [n_shells, n_elements]")
         keep = []
-        d = _plasma_desc(spec, keep)
+        d = _plasma_desc(spec, keep, model.S, model.L)
         need = plasma_workspace_bytes(spec, model.S, model.L)
         if workspace is None:
             workspace = torch.empty(need, dtype=torch.uint8, device=model.workspace.device)

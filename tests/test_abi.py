@@ -136,6 +136,13 @@ def test_host_validation_rejects_bad_models(lib):
     bad = W.Model(**{**m.__dict__})
     bad.n_bins = 0
     assert "n_bins" in _expect_invalid(bad)
+    # arrays shorter than the description's counts never reach the library
+    for field, short in (("n_e", m.n_e[:-1]), ("tau_sobolev", m.tau_sobolev[:-1]),
+                         ("tau_sobolev", m.tau_sobolev.T.copy())):
+        bad = W.Model(**{**m.__dict__})
+        setattr(bad, field, short)
+        with pytest.raises(ValueError, match="tau_sobolev|n_e"):
+            smc.workspace_bytes(bad, 10, 0)
 
 
 def test_host_validation_rejects_bad_downbranch_tables(lib):
@@ -151,6 +158,11 @@ def test_host_validation_rejects_bad_downbranch_tables(lib):
     el[0] = m.n_lines
     bad.em_line = el
     assert "em_line" in _expect_invalid(bad)
+    for field in ("line_upper", "level_ptr", "em_cum"):
+        bad = W.Model(**{**m.__dict__})
+        setattr(bad, field, getattr(m, field)[:-1].copy())
+        with pytest.raises(ValueError, match=field):
+            smc.workspace_bytes(bad, 10, 0)
     # rows are searched by bisection: a decreasing pair inside a row is refused,
     # the step from one row's last entry to the next row's first is not
     lp = m.level_ptr
@@ -217,7 +229,15 @@ def test_host_validation_of_plasma_descriptions(lib):
     a = spec.atom
     base = smc.plasma_workspace_bytes(spec, 3, 60)
     assert base >= 3 * (a.n_levels + 2 * a.n_ions) * 8 + 60 * 32
-    assert smc.plasma_workspace_bytes(spec, 6, 60) > base
+    six = W.PlasmaSpec(atom=a, number_density=np.vstack([spec.number_density] * 2))
+    assert smc.plasma_workspace_bytes(six, 6, 60) > base
+    # arrays shorter than the description's counts never reach the library
+    with pytest.raises(ValueError, match="number_density"):
+        smc.plasma_workspace_bytes(spec, 6, 60)
+    with pytest.raises(ValueError, match="line_lower"):
+        smc.plasma_workspace_bytes(spec, 3, 61)
+    with pytest.raises(ValueError, match="level_g"):
+        smc.plasma_workspace_bytes(_with_atom(spec, level_g=a.level_g[:-1]), 3, 60)
     e = a.level_energy.copy()
     e[a.ion_level_ptr[1]] = 1e-12  # ground state above zero
     assert "ground state" in _expect_plasma_invalid(_with_atom(spec, level_energy=e))
