@@ -476,11 +476,6 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
   if (ws_bytes < lay.total)
     return fail(SMC_ENOMEM, "workspace of %llu bytes is smaller than the %llu needed",
                 (unsigned long long)ws_bytes, (unsigned long long)lay.total);
-  const size_t lds = sizeof(double) * (2 * (size_t)d->n_shells + (size_t)d->n_bins + 2 + 3 +
-                                       SMC_N_COUNTERS);
-  if (lds > 64 * 1024)
-    return fail(SMC_EINVAL, "2*n_shells + n_bins = %zu tallies exceed the 64 KiB LDS budget",
-                lds / 8);
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   uint8_t* base = (uint8_t*)d_workspace;

@@ -68,12 +68,17 @@ def assert_close_or_zero(gpu, ref, rel=REL, what=""):
     np.testing.assert_allclose(gpu[~zero], ref[~zero], rtol=rel, atol=0, err_msg=what)
 
 
-def spectrum_chi2_pvalue(a, b):
-    """Two-sample chi-square on binned luminosities (treated as counts after
-    scaling to the total), for bins with enough weight."""
+def spectrum_chi2_pvalue(a, b, n_packets):
+    """Two-sample chi-square on binned luminosities, each spectrum scaled to
+    n_packets counts in total (the packets that built it), for bins with
+    enough weight."""
     from scipy import stats
     a = np.asarray(a, dtype=float)
     b = np.asarray(b, dtype=float)
+    if a.sum() <= 0.0 or b.sum() <= 0.0:
+        return 1.0
+    a = a * (n_packets / a.sum())
+    b = b * (n_packets / b.sum())
     keep = (a + b) > 0
     a, b = a[keep], b[keep]
     if a.size < 2:

@@ -25,13 +25,14 @@ def ctx():
 
 
 def _compare_iteration(ctx, model, N, T, iteration=0, ids=None, L_requested=0.0, damping=1.0,
-                       max_segments=10**7, jblue=True, tune=None):
+                       max_segments=10**7, jblue=True, tune=None, rel_packets=REL,
+                       rel_est=REL):
     g = gpu_run(ctx, model, N, T, iteration=iteration, packet_ids=ids, L_requested=L_requested,
                 damping=damping, max_segments=max_segments, jblue=jblue, tune=tune)
     raw, fin = oracle_run(model, N, T, iteration=iteration, packet_ids=ids,
                           L_requested=L_requested, damping=damping,
                           max_segments=max_segments, jblue=jblue)
-    bad = assert_packets_match(g["packets"], raw["packets"])
+    bad = assert_packets_match(g["packets"], raw["packets"], rel=rel_packets)
     if bad.size:
         # rerun both sides without the packets that took a different branch
         all_ids = np.asarray(ids if ids is not None else np.arange(N), dtype=np.uint64)
@@ -44,14 +45,15 @@ def _compare_iteration(ctx, model, N, T, iteration=0, ids=None, L_requested=0.0,
                               max_segments=max_segments, jblue=jblue)
         assert divergent(g["packets"], raw["packets"]).size == 0
     e, s = g["est"], g["spec"]
-    assert_close_or_zero(e["J"], fin["J"], what="J")
-    assert_close_or_zero(e["nubar"], fin["nubar"], what="nubar")
-    np.testing.assert_allclose(e["T_R"], fin["T_R"], rtol=REL)
-    np.testing.assert_allclose(e["W"], fin["W"], rtol=REL)
+    assert_close_or_zero(e["J"], fin["J"], rel=rel_est, what="J")
+    assert_close_or_zero(e["nubar"], fin["nubar"], rel=rel_est, what="nubar")
+    np.testing.assert_allclose(e["T_R"], fin["T_R"], rtol=rel_est)
+    np.testing.assert_allclose(e["W"], fin["W"], rtol=rel_est)
     if jblue:
-        assert_close_or_zero(e["jblue"], fin["jblue"], what="jblue")
-    assert_close_or_zero(s["L_nu"], fin["L_nu"], what="L_nu")
-    assert spectrum_chi2_pvalue(s["L_nu"][:-2], fin["L_nu"][:-2]) > 1e-3
+        assert_close_or_zero(e["jblue"], fin["jblue"], rel=rel_est, what="jblue")
+    assert_close_or_zero(s["L_nu"], fin["L_nu"], rel=rel_est, what="L_nu")
+    assert spectrum_chi2_pvalue(s["L_nu"][:-2], fin["L_nu"][:-2],
+                                raw["counters"]["escaped"]) > 1e-3
     for k in ("L_emitted", "L_reabsorbed", "L_capped", "L_inner"):
         assert s[k] == pytest.approx(fin[k], rel=REL, abs=0 if fin[k] else 1e-300), k
     assert s["T_inner"] == T
@@ -264,3 +266,26 @@ def test_largest_batched_shape_full_launch_sampled(ctx):
                                     longest])).astype(np.uint64)
     raw = O.run(model, T, N, packet_ids=ids, want_jblue=False)
     assert_packets_match(g[ids.astype(np.int64)], raw["packets"])
+
+
+def test_maximum_shells_and_bins(ctx):
+    """The largest model geometry the library accepts: 4096 shells and 8192
+    spectrum bins (2000 packets, 300 lines, ~3400 shell crossings per
+    packet), compared with the oracle packet by packet and in every
+    estimator, with the default hand-off to the group kernel.
+
+    Shells 2.2 km/s thick make a packet's final direction ill-conditioned:
+    grazing crossings magnify a rounding difference in a path length.  With
+    the oracle alone, evaluating the Doppler factor as r mu (1/ct) instead of
+    r mu / ct (one ulp now and then) moves final directions by up to 4e-10
+    and frequencies by 8e-11 on this model; the GPU evaluates that factor
+    and 1/nu and 1/kappa through refined reciprocals.  The same oracle
+    change moves J and nu-bar of single shells by up to 3e-8 (J_blue 2e-10,
+    L_nu 4e-11) once its one divergent packet is left out, and the GPU's
+    differences reach 5e-7 in J.  Final directions, frequencies and
+    energies are held to 1e-7 here and the estimators to 1e-5; event
+    sequences and counts must agree exactly, as everywhere."""
+    m = W.small_model(seed=21, n_shells=4096, n_lines=300)
+    m.n_bins = 8192
+    g, raw, _ = _compare_iteration(ctx, m, 2000, 10000.0, rel_packets=1e-7, rel_est=1e-5)
+    assert raw["counters"]["crossings"] > 1000 * 2000
