@@ -73,7 +73,7 @@ typedef struct smc_model smc_model;
 /* Model description (section 2.1 shells, section 2.5 lines).  All arrays are
  * host pointers read during smc_model_load only. */
 typedef struct {
-  int32_t n_shells;          /* S >= 1 */
+  int32_t n_shells;          /* S in 1 .. 4096 */
   const double* v_bounds;    /* [S+1] boundary velocities [cm/s], > 0, strictly increasing,
                                 below c/2 */
   double t_exp;              /* time since explosion [s], > 0; radii are v * t_exp */
