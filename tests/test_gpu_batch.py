@@ -115,3 +115,27 @@ def test_batch_rejects_bad_calls(ctx):
         ctx.batch_run([m], [dict(n_packets=N + 1, T_inner=T)])  # beyond n_packets_max
     with pytest.raises(smc.SmcError):
         ctx.batch_run([m], [dict(n_packets=N, T_inner=0.0)])  # no T_inner yet
+
+
+def test_batch_of_the_largest_model_count(ctx):
+    """1024 models, the most one launch takes (2-6 shells, 20-49 lines, 1-89
+    packets each, one of them downbranch every 64): every packet of every
+    model matches the oracle, and the counters add up model by model."""
+    mix = []
+    for i in range(1024):
+        if i % 64 == 63:
+            mdl = W.small_downbranch_model(seed=2000 + i, n_shells=3, n_ions=2,
+                                           n_levels_per_ion=6, n_lines=30)
+        else:
+            mdl = W.small_model(seed=2000 + i, n_shells=2 + i % 5, n_lines=20 + i % 30)
+        mix.append((mdl, 1 + (i * 37) % 89, 8000.0 + 5.0 * i))
+    together = _batch(ctx, mix)
+    n_bad = 0
+    for (mdl, N, T), b in zip(mix, together):
+        raw, _ = oracle_run(mdl, N, T, iteration=3)
+        bad = assert_packets_match(b["packets"], raw["packets"])
+        n_bad += bad.size
+        if bad.size == 0:
+            for k, v in raw["counters"].items():
+                assert b["counters"][k] == v, k
+    assert n_bad <= 2
