@@ -111,17 +111,30 @@ def test_paper_scale_plasma_from_the_initial_field(ctx, ion, exc):
 
 
 def test_field_of_the_last_iteration(ctx):
+    """A plasma update from the radiation field the last iteration left on
+    the device (no host field), with delta = 0.5; the oracle takes the same
+    steps: its plasma state from the initial field, its own transport on
+    those depths, its estimators, its plasma state from them."""
     model, spec = _small(seed=2)
-    m = smc.Model(ctx, model, 20000)
+    N, T = 20000, 11000.0
+    m = smc.Model(ctx, model, N, flags=smc.F_PACKETS)
     pl = smc.Plasma(m, spec)
     pl.update(W.ION_NEBULAR, W.EXC_DILUTE_LTE)
-    m.run_iteration(20000, 11000.0)
+    m.run_iteration(N, T, flags=smc.F_PACKETS)
+    g_packets = m.read_packets(N)
     pl.update(W.ION_NEBULAR, W.EXC_DILUTE_LTE, delta=0.5)
     g = pl.read()
-    est = m.read_estimators(jblue=False)
+
     T0, W0 = O.initial_radiation_field(model)
-    assert not np.allclose(est["T_R"], T0)
-    o = _oracle(model, spec, est["T_R"], est["W"], W.ION_NEBULAR, W.EXC_DILUTE_LTE, 0.5)
+    o0 = _oracle(model, spec, T0, W0, W.ION_NEBULAR, W.EXC_DILUTE_LTE)
+    m0 = _with(model, o0["tau"], o0["n_e"])
+    raw0 = O.run(m0, T, N, iteration=0, want_jblue=False)
+    fin0 = O.finalise(m0, raw0, T, T_R_prev=T0, W_prev=W0)
+    assert not np.allclose(fin0["T_R"], T0)
+    # same histories (none taken the other way at a tie for this seed): the
+    # fields agree to the tally tolerance, and so do the plasma states
+    assert assert_packets_match(g_packets, raw0["packets"]).size == 0
+    o = _oracle(model, spec, fin0["T_R"], fin0["W"], W.ION_NEBULAR, W.EXC_DILUTE_LTE, 0.5)
     _assert_state(g, o, model, spec)
 
 
@@ -296,11 +309,12 @@ def test_nlte_host_field(ctx, n_levels_nlte, ion, exc):
     m = smc.Model(ctx, model, 16)
     pl = smc.Plasma(m, spec)
     T_R, Wd = _field(model, 31)
-    # a first update gives the depths that the escape probabilities use
+    # a first update gives the depths that the escape probabilities use;
+    # each side takes its own
     pl.update(ion, exc, T_R=T_R, W=Wd)
-    tau0 = pl.read()["tau"]
     pl.update(ion, exc, T_R=T_R, W=Wd, nlte=True)
     g = pl.read()
+    tau0 = _oracle(model, spec, T_R, Wd, ion, exc)["tau"]
     o = _oracle_nlte(model, spec, T_R, Wd, ion, exc, tau0)
     _assert_state(g, o, model, spec)
     assert g["n_singular"] == 0
@@ -323,13 +337,13 @@ def test_nlte_paper_scale(ctx):
     _assert_state(g, o, model, spec)
     pl.update(W.ION_NEBULAR, W.EXC_DILUTE_LTE, nlte=True)  # now with the depths just written
     g2 = pl.read()
-    o2 = _oracle_nlte(model, spec, T_R, Wd, W.ION_NEBULAR, W.EXC_DILUTE_LTE, g["tau"])
+    o2 = _oracle_nlte(model, spec, T_R, Wd, W.ION_NEBULAR, W.EXC_DILUTE_LTE, o["tau"])
     _assert_state(g2, o2, model, spec)
 
 
 def test_nlte_detailed_jblue_after_an_iteration(ctx):
     model, spec = _nlte_small(seed=22)
-    flags = smc.F_JBLUE
+    flags = smc.F_JBLUE | smc.F_PACKETS
     m = smc.Model(ctx, model, 30000, flags=flags)
     pl = smc.Plasma(m, spec)
     ion, exc = W.ION_NEBULAR, W.EXC_DILUTE_LTE
@@ -340,12 +354,19 @@ def test_nlte_detailed_jblue_after_an_iteration(ctx):
     _assert_state(g0, _oracle_nlte(model, spec, T0, W0, ion, exc,
                                    np.zeros((model.n_shells, model.n_lines))), model, spec)
     m.run_iteration(30000, 12000.0, flags=flags)
-    est = m.read_estimators(jblue=True)
+    g_packets = m.read_packets(30000)
     pl.update(ion, exc, nlte=True, jblue_mode=smc.JB_DETAILED)
     g = pl.read()
-    o = _oracle_nlte(model, spec, est["T_R"], est["W"], ion, exc, g0["tau"], jblue=est["jblue"])
+    # the oracle's own chain: its transport on its depths, its estimators
+    o0 = _oracle_nlte(model, spec, T0, W0, ion, exc, np.zeros((model.n_shells, model.n_lines)))
+    m0 = _with(model, o0["tau"], o0["n_e"])
+    raw0 = O.run(m0, 12000.0, 30000, iteration=0)
+    fin0 = O.finalise(m0, raw0, 12000.0, T_R_prev=T0, W_prev=W0)
+    assert assert_packets_match(g_packets, raw0["packets"]).size == 0
+    o = _oracle_nlte(model, spec, fin0["T_R"], fin0["W"], ion, exc, o0["tau"],
+                     jblue=fin0["jblue"])
     _assert_state(g, o, model, spec)
-    d = _oracle_nlte(model, spec, est["T_R"], est["W"], ion, exc, g0["tau"])
+    d = _oracle_nlte(model, spec, fin0["T_R"], fin0["W"], ion, exc, o0["tau"])
     lp = spec.atom.ion_level_ptr
     assert not np.allclose(o["level_pop"][:, lp[6]:lp[7]], d["level_pop"][:, lp[6]:lp[7]])
 
