@@ -445,3 +445,24 @@ def test_nlte_errors(ctx):
     with pytest.raises(smc.SmcError):
         pl2.update(W.ION_LTE, W.EXC_LTE, nlte=True, jblue_mode=smc.JB_DETAILED)
     pl2.update(W.ION_LTE, W.EXC_LTE, nlte=True)  # dilute blackbody is fine
+
+
+def test_maximum_shells(ctx):
+    """4096 shells, the most a model takes (a 3-element atom, 60 lines, two
+    NLTE ions of 8 levels): the dilute-LTE state, then the NLTE state whose
+    escape probabilities use each side's own first depths."""
+    model, spec = W.plasma_model(seed=5, n_shells=4096, n_elements=3, n_stages=3,
+                                 n_levels_per_ion=8, n_lines=60, nlte_ions=(1, 4),
+                                 n_levels_nlte=8)
+    m = smc.Model(ctx, model, 16)
+    pl = smc.Plasma(m, spec)
+    T_R, Wd = _field(model, 33)
+    ion, exc = W.ION_NEBULAR, W.EXC_DILUTE_LTE
+    pl.update(ion, exc, T_R=T_R, W=Wd)
+    g0 = pl.read()
+    o0 = _oracle(model, spec, T_R, Wd, ion, exc)
+    _assert_state(g0, o0, model, spec)
+    pl.update(ion, exc, T_R=T_R, W=Wd, nlte=True)
+    g1 = pl.read()
+    _assert_state(g1, _oracle_nlte(model, spec, T_R, Wd, ion, exc, o0["tau"]), model, spec)
+    assert g1["n_singular"] == 0
