@@ -466,3 +466,17 @@ def test_maximum_shells(ctx):
     g1 = pl.read()
     _assert_state(g1, _oracle_nlte(model, spec, T_R, Wd, ion, exc, o0["tau"]), model, spec)
     assert g1["n_singular"] == 0
+
+
+@pytest.mark.parametrize("ion,exc", [MODES[1], MODES[0]], ids=MODE_IDS[:2][::-1])
+def test_atom_beyond_the_staged_level_table(ctx, ion, exc):
+    """8800 levels: more than the 8192 whose n/g the depth kernel stages in
+    LDS, so the depths gather the populations from device memory instead."""
+    model, spec = W.plasma_model(seed=6, n_shells=4, n_elements=8, n_stages=5,
+                                 n_levels_per_ion=220, n_lines=5000)
+    assert spec.atom.n_levels > 8192
+    m = smc.Model(ctx, model, 16)
+    pl = smc.Plasma(m, spec)
+    T_R, Wd = _field(model, 34)
+    pl.update(ion, exc, T_R=T_R, W=Wd)
+    _assert_state(pl.read(), _oracle(model, spec, T_R, Wd, ion, exc), model, spec)
