@@ -607,6 +607,33 @@ def served(args):
     print(json.dumps(out), flush=True)
 
 
+def host_boundary(ctx, w, flags, N, interactions, wall, steps):
+    """The same job with the host side of the boundary counted (untimed
+    for `value`): the model handed over from host arrays (validation and
+    upload of the line list and the Sobolev-depth table), and after every
+    iteration the estimators, J_blue included, and the spectrum copied back
+    to host memory."""
+    import torch
+
+    from paper_1401_5469_amd import smc
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m = smc.Model(ctx, w.model, N, flags=flags)
+    torch.cuda.synchronize()
+    load = time.perf_counter() - t0
+    m.run_iteration(N, w.T_inner, iteration=0, flags=flags, L_requested=w.L_requested,
+                    damping=w.damping)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.read_estimators(jblue=bool(flags & smc.F_JBLUE))
+    m.read_spectrum()
+    read = time.perf_counter() - t0
+    total = wall + load + steps * read
+    return {"value": interactions / total, "unit": "interactions/s", "load_s": load,
+            "read_s_per_iteration": read, "seconds": total}
+
+
 def critical_path(ctx, w, flags, iteration, T_inner, pass_ms):
     """Latency bound of one transport pass: the longest history of the last
     timed iteration, found in a replay of that iteration with per-packet
@@ -735,6 +762,7 @@ def main():
                      "bytes_per_launch": bytes_per_launch},
         "cpu_baseline": None,
     }
+    out["pcie_inclusive"] = host_boundary(ctx, w, flags, N, inter, wall, args.steps)
     out["critical_path"] = None
     if not args.no_critical_path:
         out["critical_path"] = critical_path(ctx, w, flags, args.steps - 1, rec[-1][2],
