@@ -669,8 +669,9 @@ def main():
     if args.cpu_worker:
         return cpu_worker(args)
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported in this build "
-              "(the transport shards by packet ids; see the design notes)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (across GPUs "
+              "the transport would shard by packet ids, one replica of the model per GPU, "
+              "with one all-reduce of the tallies per iteration)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
         if args.steps == 10:
