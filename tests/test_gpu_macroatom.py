@@ -106,3 +106,20 @@ def test_macroatom_in_a_multi_model_launch(ctx):
         if assert_packets_match(m.read_packets(N), raw["packets"]).size == 0:
             assert_close_or_zero(m.read_spectrum()["L_nu"], fin["L_nu"], what="L_nu")
             assert m.read_counters() == raw["counters"]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small_macroatom_configurations(ctx, seed):
+    """Seeded random macro-atom models: shells, ions, levels per ion, lines,
+    packets, temperature and launch tuning (including a hand-off at the
+    first segment and none at all)."""
+    rng = np.random.default_rng(500 + seed)
+    n_ions = int(rng.integers(1, 7))
+    nl = int(rng.integers(4, 16))
+    L = int(rng.integers(5, min(400, n_ions * nl * (nl - 1) // 2) + 1))
+    model = W.macroatom_model(seed=500 + seed, n_shells=int(rng.integers(1, 25)), n_ions=n_ions,
+                              n_levels_per_ion=nl, n_lines=L)
+    tune = [None, dict(long_budget=1, long_lanes=int(rng.choice([16, 32, 64]))),
+            dict(long_budget=2**32 - 1)][seed % 3]
+    _compare(ctx, model, int(rng.integers(1, 2500)), float(rng.uniform(6000.0, 30000.0)),
+             tune=tune)

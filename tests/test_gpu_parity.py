@@ -292,3 +292,37 @@ def test_maximum_shells_and_bins(ctx):
     m.n_bins = 8192
     g, raw, _ = _compare_iteration(ctx, m, 2000, 10000.0, rel_packets=1e-7, rel_est=1e-5)
     assert raw["counters"]["crossings"] > 1000 * 2000
+
+
+def _random_case(seed):
+    """A seeded random small configuration: geometry, line count (also 0 and
+    counts that are no multiple of the 4-line or G-line windows), mode,
+    spectrum bins, packet count, temperature and launch tuning."""
+    rng = np.random.default_rng(seed)
+    S = int(rng.integers(1, 41))
+    if rng.random() < 0.25:
+        L = int(rng.integers(8, 400))
+        n_ions = max(1, min(6, L // 20))
+        nl = int(rng.integers(4, 14))
+        while n_ions * nl * (nl - 1) // 2 < L:  # enough (lower, upper) pairs
+            nl += 1
+        m = W.small_downbranch_model(seed=seed, n_shells=S, n_ions=n_ions,
+                                     n_levels_per_ion=nl, n_lines=L)
+    else:
+        L = int(rng.choice([0, 1, 3, 5, 31, 33, 63, 65, int(rng.integers(100, 3000))]))
+        m = W.small_model(seed=seed, n_shells=S, n_lines=L,
+                          tau="lognormal" if rng.random() < 0.5 else "loguniform",
+                          v_lo=float(rng.uniform(5000.0, 12000.0)),
+                          v_hi=float(rng.uniform(14000.0, 30000.0)))
+    m.n_bins = int(rng.integers(1, 600))
+    N = int(rng.integers(1, 2500))
+    T = float(rng.uniform(6000.0, 40000.0))
+    tune = [None, dict(long_budget=int(rng.integers(1, 40)), long_lanes=int(rng.choice([16, 32, 64]))),
+            dict(long_budget=2**32 - 1)][int(rng.integers(0, 3))]
+    return m, N, T, tune
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_small_configurations(ctx, seed):
+    m, N, T, tune = _random_case(seed)
+    _compare_iteration(ctx, m, N, T, iteration=seed % 5, tune=tune, jblue=m.n_lines > 0)

@@ -129,3 +129,16 @@ def test_virtual_rejects_too_many(ctx):
     mm = smc.Model(ctx, m, 10)
     with pytest.raises(smc.SmcError):
         mm.run_iteration(10, 10000.0, n_virtual=17)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small_virtual_configurations(ctx, seed):
+    """Seeded random models with 1-6 v-packets per launch: shells, lines,
+    packets, temperature and group width."""
+    rng = np.random.default_rng(700 + seed)
+    m = W.small_model(seed=700 + seed, n_shells=int(rng.integers(1, 20)),
+                      n_lines=int(rng.integers(1, 1500)),
+                      tau="lognormal" if seed % 2 else "loguniform")
+    m.n_bins = int(rng.integers(1, 400))
+    _compare(ctx, m, int(rng.integers(50, 2000)), float(rng.uniform(8000.0, 30000.0)),
+             int(rng.integers(1, 7)), tune=dict(long_lanes=int(rng.choice([16, 32, 64]))))
