@@ -480,3 +480,35 @@ def test_atom_beyond_the_staged_level_table(ctx, ion, exc):
     T_R, Wd = _field(model, 34)
     pl.update(ion, exc, T_R=T_R, W=Wd)
     _assert_state(pl.read(), _oracle(model, spec, T_R, Wd, ion, exc), model, spec)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small_plasma_configurations(ctx, seed):
+    """Seeded random atoms (elements, stages, levels, lines, NLTE ions and
+    their level counts), shell counts, fields and modes: the state after a
+    plasma update, then after an NLTE update whose escape probabilities use
+    each side's own first depths."""
+    rng = np.random.default_rng(900 + seed)
+    E, St = int(rng.integers(1, 9)), int(rng.integers(1, 6))
+    nl = int(rng.integers(2, 30))
+    n_ions = E * St
+    nlte = tuple(sorted(set(int(i) for i in rng.integers(0, n_ions, int(rng.integers(0, 4))))))
+    nl_nlte = int(rng.integers(1, 65))
+    L = int(rng.integers(0, 400))
+    if nlte:  # room for the ground-state line of every excited NLTE level
+        L = max(L, len(nlte) * (nl_nlte - 1) + 10)
+    model, spec = W.plasma_model(seed=900 + seed, n_shells=int(rng.integers(1, 30)), n_elements=E,
+                                 n_stages=St, n_levels_per_ion=nl, n_lines=L, nlte_ions=nlte,
+                                 n_levels_nlte=nl_nlte)
+    ion, exc = MODES[seed % 4]
+    delta = float(rng.uniform(0.3, 1.5))
+    m = smc.Model(ctx, model, 16)
+    pl = smc.Plasma(m, spec)
+    T_R, Wd = _field(model, 950 + seed)
+    pl.update(ion, exc, T_R=T_R, W=Wd, delta=delta)
+    o0 = _oracle(model, spec, T_R, Wd, ion, exc, delta)
+    _assert_state(pl.read(), o0, model, spec)
+    if nlte and model.n_lines:
+        pl.update(ion, exc, T_R=T_R, W=Wd, delta=delta, nlte=True)
+        o1 = _oracle_nlte(model, spec, T_R, Wd, ion, exc, o0["tau"], delta=delta)
+        _assert_state(pl.read(), o1, model, spec)
