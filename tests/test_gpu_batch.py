@@ -139,3 +139,43 @@ def test_batch_of_the_largest_model_count(ctx):
             for k, v in raw["counters"].items():
                 assert b["counters"][k] == v, k
     assert n_bad <= 2
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_mixed_batches(ctx, seed):
+    """Seeded random batches of 2-24 models mixing scatter, downbranch and
+    macroatom modes, some launching 1-4 v-packets per interaction, under a
+    random tuning: every model's packets, counters and v-packet counts
+    against the oracle."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(1200 + seed)
+    mix, nvs = [], []
+    for i in range(int(rng.integers(2, 25))):
+        s = 1200 + 100 * seed + i
+        kind = int(rng.integers(0, 3))
+        if kind == 0:
+            mdl = W.small_model(seed=s, n_shells=int(rng.integers(1, 15)),
+                                n_lines=int(rng.integers(0, 1500)))
+        elif kind == 1:
+            mdl = W.small_downbranch_model(seed=s, n_shells=int(rng.integers(1, 10)), n_ions=3,
+                                           n_levels_per_ion=10, n_lines=int(rng.integers(5, 120)))
+        else:
+            mdl = W.macroatom_model(seed=s, n_shells=int(rng.integers(1, 10)), n_ions=3,
+                                    n_levels_per_ion=10, n_lines=int(rng.integers(5, 120)))
+        mix.append((mdl, int(rng.integers(1, 1500)), float(rng.uniform(7000.0, 25000.0))))
+        nvs.append(int(rng.integers(1, 5)) if (mdl.n_lines and rng.random() < 0.3) else 0)
+    tune = [None, dict(long_budget=int(rng.integers(1, 64)), long_lanes=int(rng.choice([16, 32, 64]))),
+            dict(long_budget=2**32 - 1)][seed % 3]
+    models = [smc.Model(ctx, mdl, N, flags=F_ALL) for mdl, N, _ in mix]
+    params = [dict(n_packets=N, T_inner=T, iteration=2, flags=F_ALL, n_virtual=nv)
+              for (_, N, T), nv in zip(mix, nvs)]
+    ctx.batch_run(models, params, tune=tune)
+    for m, (mdl, N, T), nv in zip(models, mix, nvs):
+        raw = O.run(mdl, T, N, iteration=2, n_virtual=nv)
+        bad = assert_packets_match(m.read_packets(N), raw["packets"])
+        if bad.size == 0:
+            c = m.read_counters()
+            for k, v in raw["counters"].items():
+                assert c[k] == v, k
+        if nv:
+            assert m.read_virtual_spectrum()["counts"]["launched"] == raw["vcounts"]["launched"]
