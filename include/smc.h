@@ -154,7 +154,12 @@ typedef struct {
 /* Create a context on HIP device `hip_device`.  The context owns a few small
  * device and pinned host buffers for multi-model launches (about 1.5 MB). */
 int smc_ctx_create(smc_ctx** out, int hip_device);
+/* Free a context's buffers once the multi-model launches that use them have
+ * finished (NULL: no-op).  Models, plasmas and graphs made on it are freed
+ * first by the caller. */
 int smc_ctx_destroy(smc_ctx* ctx);
+/* Message of the last failing call on this thread (empty after a success);
+ * valid until the thread's next call into the library. */
 const char* smc_last_error(void);
 
 /* Device workspace a model needs for up to n_packets_max packets per
@@ -254,7 +259,10 @@ typedef struct smc_graph smc_graph;
 int smc_graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
                       int n_models, int n_iter, const smc_tune* tune, void* stream,
                       smc_graph** out);
+/* Replay a captured graph on `stream` (asynchronous). */
 int smc_graph_launch(smc_graph* graph, void* stream);
+/* Free a graph (NULL: no-op); waits for the device's outstanding work, so a
+ * replay still in flight finishes first. */
 int smc_graph_destroy(smc_graph* graph);
 
 /* Set (NULL: reset to defaults) or read the launch tuning of a model.  Tuning

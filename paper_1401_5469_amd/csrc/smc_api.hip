@@ -1082,6 +1082,10 @@ int smc_graph_launch(smc_graph* g, void* stream) {
 }
 
 int smc_graph_destroy(smc_graph* g) {
+  if (g) {
+    HIP_TRY(hipSetDevice(g->ctx->device), "hipSetDevice");
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");  // no replay in flight
+  }
   release_graph(g);
   return ok();
 }
