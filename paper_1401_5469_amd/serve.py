@@ -142,6 +142,17 @@ class Server:
     def result(self, rid: int) -> Optional[dict]:
         return self.requests[rid].result
 
+    def wait(self, rid: int) -> Optional[dict]:
+        """Serve (every admitted request advances with it) until request rid
+        has finished, been cancelled or been rejected; its result, if any."""
+        req = self.requests[rid]
+        while req.state in (QUEUED, RUNNING):
+            if not self.step():
+                if not self.pending:
+                    break
+                self.sleep(max(0.0, self.pending[0].arrival - self.now()))
+        return req.result
+
     def cancel(self, rid: int) -> bool:
         req = self.requests[rid]
         if req.state == QUEUED:

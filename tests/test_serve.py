@@ -124,3 +124,20 @@ def test_plain_path_runs_one_request_at_a_time():
     assert [s[0] for s in be.steps] == [(0, 0), (0, 1), (1, 0), (2, 0), (2, 1), (2, 2)]
     lat = [r.latency for r in reqs]
     assert lat[0] == 2.2 and np.isclose(lat[1], 2.2 + 1.1 - 0.5)
+
+
+def test_wait_serves_until_the_request_is_done():
+    clock = Clock()
+    be = FakeBackend(clock)
+    srv = serve.Server(be, memory_budget=10**9, clock=clock, sleep=clock.sleep)
+    a = srv.submit(_req(100, 2, 0.0))
+    b = srv.submit(_req(100, 5, 0.5))
+    c = srv.submit(_req(100, 1, 100.0))  # arrives long after the others
+    assert srv.wait(a) == dict(iterations=2)
+    assert srv.poll(a) == serve.DONE and srv.poll(b) == serve.RUNNING
+    # b joined at the second step and ran alongside a: it is part-way
+    assert srv.requests[b].iteration == 1
+    assert srv.wait(c) == dict(iterations=1)  # sleeps until c arrives, finishing b first
+    assert srv.poll(b) == serve.DONE and clock.t >= 100.0
+    huge = srv.submit(_req(10**9, 1, 0.0))
+    assert srv.wait(huge) is None and srv.poll(huge) == serve.REJECTED
