@@ -67,3 +67,31 @@ def test_results_are_the_same_alone_and_in_the_mix():
         assert_close_or_zero(rb["L_nu"], ra["L_nu"], what="L_nu")
         assert rb["T_inner"] == pytest.approx(ra["T_inner"], rel=REL, abs=0)
         assert rb["T_inner_next"] == pytest.approx(ra["T_inner_next"], rel=REL, abs=0)
+
+
+def test_wait_returns_each_result():
+    """wait(id) in reverse arrival order: each call serves the whole active
+    set until its request is done, and every result matches run()'s."""
+    def served(use_wait):
+        clk = StepClock()
+
+        class Backend(serve.GpuBackend):
+            def step(self, reqs):
+                super().step(reqs)
+                clk.t += 1.0
+
+        srv = serve.Server(Backend(), memory_budget=200 * 2**30, clock=clk, sleep=clk.sleep)
+        reqs = _requests()
+        ids = [srv.submit(r) for r in reqs]
+        if use_wait:
+            out = {rid: srv.wait(rid) for rid in reversed(ids)}
+            assert all(srv.poll(rid) == serve.DONE for rid in ids)
+            return [out[rid] for rid in ids]
+        srv.run()
+        return [r.result for r in reqs]
+
+    for ra, rb in zip(served(False), served(True)):
+        assert ra["counters"] == rb["counters"]
+        for k in ("J", "nubar", "T_R", "W"):
+            np.testing.assert_allclose(rb[k], ra[k], rtol=REL, atol=0)
+        assert rb["T_inner_next"] == pytest.approx(ra["T_inner_next"], rel=REL, abs=0)
