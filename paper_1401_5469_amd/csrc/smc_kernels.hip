@@ -167,8 +167,11 @@ __global__ void reset_kernel(LaunchArgs a) {
 // of a group, so narrower groups put more histories through each
 // instruction; wider ones march more lines per step.
 //
-// Both follow the arithmetic of the FP64 reference formulation step by step;
-// divisions that only change the last bit are reciprocal multiplies.
+// Both follow the arithmetic of the FP64 reference formulation step by step,
+// with its operand order and correctly rounded quotients and roots, so a
+// history reproduces to the last bit; the one departure is the depth left
+// after the lines a group passes at once, a sum in prefix order (which can
+// change a comparison only when both sides agree to a few ulps).
 // Estimator tallies: J and nu-bar accumulate in registers while a packet
 // stays in one shell of one model, event counters and luminosity sums in a
 // private LDS slot per lane (per group) while it stays on one model; both reach
@@ -247,6 +250,65 @@ __device__ __forceinline__ double planck_from(double u_l, double u1, double u2, 
   return -log(((u1 * u2) * u3) * u4) / (double)l;
 }
 
+// Correctly rounded FP64 quotients and square roots.  Wherever the FP64
+// reference formulation divides or takes a root, the kernels produce the
+// correctly rounded result, bit for bit what an IEEE division or square root
+// gives, so that histories reproduce to the last bit.
+//
+// Division: a reciprocal estimate of the divisor b refined by two Newton
+// steps (y), a product q = a y, and one correction with the exact remainder,
+// q + (a - b q) y, each step a fused multiply-add (Markstein 1990, "Computation
+// of elementary functions on the IBM RISC System/6000 processor").  These are
+// the steps of the general gfx950 division sequence without its operand
+// scaling and special-case fix-up, which are identities when b and 1/b are
+// normal, |a| >= 2^-900 (or a == 0) and a/b is normal: every quotient the
+// transport forms satisfies that.  A divisor used more than once (c t, the
+// Doppler factor of an event) keeps its refined reciprocal.
+struct Divisor {
+  double b, y;  // divisor and its refined reciprocal
+};
+
+__device__ __forceinline__ Divisor divisor(double b) {
+  double y = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-b, y, 1.0);
+  y = fma(y, e, y);
+  return Divisor{b, y};
+}
+
+__device__ __forceinline__ double quot(double a, const Divisor& d) {
+  const double q = a * d.y;
+  const double r = fma(-d.b, q, a);
+  return fma(r, d.y, q);
+}
+
+// a / b where |a| may be arbitrarily small (optical depths left after many
+// lines, tiny opacities): the general sequence outside the range above
+__device__ __forceinline__ double quot_checked(double a, const Divisor& d) {
+  const double aa = fabs(a), ab = fabs(d.b);
+  if (aa >= 0x1p-900 && ab >= 0x1p-900 && aa <= 0x1p900 && ab <= 0x1p900) return quot(a, d);
+  return a / d.b;
+}
+
+// Square root: reciprocal square-root estimate, then the coupled Newton
+// iteration for sqrt(x) and 1/(2 sqrt(x)) with two exact-residual corrections
+// (Markstein 1990; the gfx950 sqrt sequence without its scaling of x below
+// 2^-767).  Zero and tiny arguments take the general sequence.
+__device__ __forceinline__ double root(double x) {
+  if (!(x >= 0x1p-767 && x <= 0x1p1000)) return sqrt(x);
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = y * 0.5;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 // distance along (r, mu) to the boundary of shell [r_in, r_out] met first
 // (ray-sphere intersection; a tangent ray misses the inner sphere)
 __device__ __forceinline__ double shell_distance(double r, double mu, double rmu, double r_in,
@@ -255,17 +317,11 @@ __device__ __forceinline__ double shell_distance(double r, double mu, double rmu
   inward = mu < 0.0 && b < r_in * r_in;
   double q = inward ? r_in * r_in - b : r_out * r_out - b;
   q = q < 0.0 ? 0.0 : q;
-  const double sq = sqrt(q);
+  const double sq = root(q);
   const double d = inward ? -rmu - sq : sq - rmu;
   return d < 0.0 ? 0.0 : d;
 }
 
-// 1/x from the hardware estimate and two Newton steps (last-bit accurate)
-__device__ __forceinline__ double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return fma(r, fma(-x, r, 1.0), r);
-}
 
 // The entry a transition row [lo, hi) selects for a uniform draw u: the first
 // j in [lo, hi - 1) with cum[j] > u, else the row's last entry (section 2.5).
@@ -393,7 +449,8 @@ struct View {
   const int64_t* level_ptr;
   const int32_t* em_line;
   const double* em_cum;
-  double ct, inv_ct;
+  double ct;
+  Divisor rct;            // c t with its refined reciprocal
   uint64_t max_segments, budget;
   int32_t S, L, Lp;
   bool downbranch;         // emission rows shared by all shells, no internal jumps
@@ -417,7 +474,7 @@ __device__ __forceinline__ View make_view(const DevModel& m, const DevIter& it) 
   v.em_line = m.em_line;
   v.em_cum = m.em_cum;
   v.ct = m.ct;
-  v.inv_ct = 1.0 / m.ct;
+  v.rct = divisor(m.ct);
   v.max_segments = it.max_segments;
   // with v-packets every history goes to the group kernel before its first
   // segment; otherwise after long_budget segments (never when 0)
@@ -621,19 +678,20 @@ void transport_kernel(LaunchArgs a) {
         settle(c_rin, c_rout, c_ne);
       }
       const double rmu = r * mu;
-      const double D = 1.0 - rmu * v.inv_ct;
+      const double D = 1.0 - quot(mu * r, v.rct);
       const double nu_cmf = nu * D;
       const double e_cmf = E * D;
       bool inward;
       const double d_shell = shell_distance(r, mu, rmu, c_rin, c_rout, inward);
       const double kappa = kSigmaT * c_ne * D;  // Thomson opacity with D
-      const double inv_nu = 1.0 / nu;
-      const double ct_over_nu = v.ct * inv_nu;
-      const double jb_w = E * inv_nu * inv_nu;  // J_blue weight per unit nu_k
+      const Divisor rkappa = divisor(kappa);
+      const double ct_over_nu = quot(v.ct, divisor(nu));
+      const Divisor rnn = divisor(nu * nu);  // J_blue weight E nu_k / nu^2
 
       // line march: pass redward lines while d_line is the shortest distance;
       // tau_rem is the optical depth left for electrons after the lines passed
       double tau_rem = tau0;
+      double d_electron = kappa > 0.0 ? quot_checked(tau_rem, rkappa) : INFINITY;
       int32_t k = next_line;
       bool line_hit = false;
       double d_line = 0.0, nu_hit = 0.0;
@@ -661,11 +719,11 @@ void transport_kernel(LaunchArgs a) {
             } else {
               double dl = (nu_cmf - nu_k) * ct_over_nu;
               dl = dl < 0.0 ? 0.0 : dl;
-              if (!(kappa * dl < tau_rem && dl < d_shell)) {
+              if (!(dl < d_electron && dl < d_shell)) {
                 stop = true;
               } else {
                 n_pass += 1;
-                if (jb_row) unsafeAtomicAdd(&jb_row[base + j], jb_w * nu_k);
+                if (jb_row) unsafeAtomicAdd(&jb_row[base + j], quot(E * nu_k, rnn));
                 if (tau_k + kappa * dl > tau_rem) {
                   line_hit = true;
                   d_line = dl;
@@ -673,6 +731,7 @@ void transport_kernel(LaunchArgs a) {
                   stop = true;
                 } else {
                   tau_rem -= tau_k;
+                  if (kappa > 0.0) d_electron = quot_checked(tau_rem, rkappa);
                   k = base + j + 1;
                 }
               }
@@ -683,7 +742,6 @@ void transport_kernel(LaunchArgs a) {
       next_line = k;
 
       // event choice: line, else electron, else boundary
-      const double d_electron = (!line_hit && kappa > 0.0) ? tau_rem * recip(kappa) : INFINITY;
       const bool escat = !line_hit && d_electron < d_shell;
       const bool cross = !line_hit && !escat;
       const double d = line_hit ? d_line : (escat ? d_electron : d_shell);
@@ -705,8 +763,8 @@ void transport_kernel(LaunchArgs a) {
       acc_nb += jc * nu_cmf;
 
       // move along the flight path
-      const double r_new = sqrt(r * r + d * d + 2.0 * r * d * mu);
-      double mu_new = (rmu + d) / r_new;
+      const double r_new = root(r * r + d * d + 2.0 * r * d * mu);
+      double mu_new = quot(rmu + d, divisor(r_new));
       mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
 
       if (cross) {
@@ -722,7 +780,7 @@ void transport_kernel(LaunchArgs a) {
       } else {
         // Thomson (coherent, isotropic in the comoving frame) or line
         // interaction (branch draw, then direction; section 2.5)
-        const double D_old = 1.0 - (mu_new * r_new) * v.inv_ct;
+        const double D_old = 1.0 - quot(mu_new * r_new, v.rct);
         const double e_cmf_ev = E * D_old;
         double nu_cmf_out = nu * D_old;
         int32_t emit = k;
@@ -765,12 +823,11 @@ void transport_kernel(LaunchArgs a) {
           dead_atom = true;
         } else {
           const double mu_out = 2.0 * rng_next(g) - 1.0;
-          const double D_new = 1.0 - (mu_out * r_new) * v.inv_ct;
-          const double inv_D = recip(D_new);
+          const Divisor rD = divisor(1.0 - quot(mu_out * r_new, v.rct));
           r = r_new;
           mu = mu_out;
-          nu = nu_cmf_out * inv_D;
-          E = e_cmf_ev * inv_D;
+          nu = quot(nu_cmf_out, rD);
+          E = quot(e_cmf_ev, rD);
           if (line_hit) {
             next_line = emit + 1;
             n_line += 1;
@@ -1012,18 +1069,17 @@ struct Group {
 template <int G>
 __device__ bool virtual_path(const Group<G>& grp, const View& v, double r, double mu, int shell,
                              int32_t k, double nu_lab, double& tau_out, uint64_t& passes) {
-  const double inv_nu = recip(nu_lab);
+  const double ct_over_nu = quot(v.ct, divisor(nu_lab));
   double tau = 0.0;
   for (;;) {
     const double r_in = v.r_bounds[shell], r_out = v.r_bounds[shell + 1];
     const double ne = v.n_e[shell];
     const double rmu = r * mu;
-    const double D = 1.0 - rmu * v.inv_ct;
+    const double D = 1.0 - quot(mu * r, v.rct);
     const double nu_cmf = nu_lab * D;
     bool inward;
     const double d_shell = shell_distance(r, mu, rmu, r_in, r_out, inward);
     const double kappa = kSigmaT * ne * D;
-    const double ct_over_nu = v.ct * inv_nu;
     const size_t row = (size_t)shell * (size_t)v.Lp;
     while (k < v.L) {
       const int32_t line = k + grp.lane;
@@ -1049,8 +1105,8 @@ __device__ bool virtual_path(const Group<G>& grp, const View& v, double r, doubl
     }
     tau += kappa * d_shell;
     if (tau > kTauVirtualMax) return false;
-    const double r_new = sqrt(r * r + d_shell * d_shell + 2.0 * r * d_shell * mu);
-    double mu_new = (rmu + d_shell) * recip(r_new);
+    const double r_new = root(r * r + d_shell * d_shell + 2.0 * r * d_shell * mu);
+    double mu_new = quot(rmu + d_shell, divisor(r_new));
     mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
     r = inward ? r_in : r_out;
     mu = mu_new;
@@ -1086,19 +1142,17 @@ __device__ void launch_virtual(const Group<G>& grp, const View& v, const DevMode
   double q = 1.0 - x * x;
   q = q < 0.0 ? 0.0 : q;
   const double mu_min = -sqrt(q);
-  const double inv_nv = 1.0 / (double)nv;
   uint64_t passes = 0, counted = 0;
   for (uint32_t j = 0; j < nv; ++j) {
     const double u = grp.bcast(u_lane, grp.uni((int)j));
     const double mu_v = mu_min + (1.0 - mu_min) * u;
-    const double w = injection ? 2.0 * mu_v * inv_nv : (1.0 - mu_min) * (0.5 * inv_nv);
-    const double D = 1.0 - (mu_v * r) * v.inv_ct;
-    const double inv_D = recip(D);
-    const double nu_lab = nu_cmf * inv_D;
+    const double w = injection ? 2.0 * mu_v / (double)nv : (1.0 - mu_min) / (2.0 * (double)nv);
+    const Divisor rD = divisor(1.0 - quot(mu_v * r, v.rct));
+    const double nu_lab = quot(nu_cmf, rD);
     double tau = 0.0;
     if (virtual_path(grp, v, r, mu_v, shell, k, nu_lab, tau, passes)) {
       counted += 1;
-      if (leader) unsafeAtomicAdd(&m.vraw[spectrum_bin(m, nu_lab)], e_cmf * w * inv_D * exp(-tau));
+      if (leader) unsafeAtomicAdd(&m.vraw[spectrum_bin(m, nu_lab)], quot(e_cmf * w, rD) * exp(-tau));
     }
   }
   if (leader) {
@@ -1144,15 +1198,15 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
   uint64_t slot = 0, pid = 0, n_seg = 0, n_pass = 0, hash = 0;
   double mu0 = 0.0, nu_cmf0 = 0.0;
   uint32_t draw = 0, rb = 0, n_esc = 0, n_line = 0;
-  double r = 0.0, mu = 0.0, nu = 0.0, E = 0.0, inv_nu = 0.0;
+  double r = 0.0, mu = 0.0, nu = 0.0, E = 0.0;
   int32_t shell = 0, next_line = 0, last_line = -1;
   // draws 2(rb + i) and 2(rb + i) + 1 in group lane i, with -log of each
   double ua = 0.0, ub = 0.0, la = 0.0, lb = 0.0;
-  // line wbase + i of shell wshell in group lane i: frequency, reciprocal,
-  // depth, and the J_blue the history has left on it since the window was
-  // installed (the following window of the same shell waits in pf)
+  // line wbase + i of shell wshell in group lane i: frequency, depth, and
+  // the J_blue the history has left on it since the window was installed
+  // (the following window of the same shell waits in pf)
   int32_t wbase = -1, wshell = -1;
-  double wn = 0.0, wt = 0.0, winv = 0.0, jb_acc = 0.0;
+  double wn = 0.0, wt = 0.0, jb_acc = 0.0;
   int32_t c_shell = -1;
   double c_rin = 0.0, c_rout = 0.0, c_ne = 0.0;
 
@@ -1200,7 +1254,6 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
         mu = st.mu;
         nu = st.nu;
         E = st.E;
-        inv_nu = recip(nu);
         shell = st.shell;
         next_line = st.next_line;
         last_line = st.last_line;
@@ -1230,7 +1283,7 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
         settle(slot, pid, mu0, nu_cmf0, n_seg, n_pass, hash, draw, r, mu, nu, E, shell,
                next_line, last_line, n_esc, n_line);
         settle(v.r_bounds, v.n_e, v.line_nu, v.tau, v.jblue, v.line_upper, v.level_ptr,
-               v.em_line, v.em_cum, v.ct, v.inv_ct, v.max_segments, v.S, v.L, v.Lp,
+               v.em_line, v.em_cum, v.ct, v.rct.y, v.max_segments, v.S, v.L, v.Lp,
                (int)v.downbranch, (int)v.macroatom, (int)v.records, sk.k0, sk.k1, sk.iter);
       }
     }
@@ -1271,14 +1324,15 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
         asm volatile("" ::"v"(c_rin), "v"(c_rout), "v"(c_ne));
       }
       const double rmu = r * mu;
-      const double D = 1.0 - rmu * v.inv_ct;
+      const double D = 1.0 - quot(mu * r, v.rct);
       const double nu_cmf = nu * D;
       const double e_cmf = E * D;
       bool inward;
       const double d_shell = shell_distance(r, mu, rmu, c_rin, c_rout, inward);
       const double kappa = kSigmaT * c_ne * D;
-      const double ct_over_nu = v.ct * inv_nu;
-      const double jb_w = E * inv_nu * inv_nu;
+      const Divisor rkappa = divisor(kappa);
+      const double ct_over_nu = quot(v.ct, divisor(nu));
+      const Divisor rnn = divisor(nu * nu);  // J_blue weight E nu_k / nu^2
       double* jb_row = v.jblue ? v.jblue + (size_t)sh * (size_t)v.L : nullptr;
 
       // line march over the window: lane j tests line wbase+j against the
@@ -1287,7 +1341,7 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
       double tau_ev = tau0;  // left after the windows already passed
       int32_t k = next_line;
       bool line_hit = false;
-      double d_line = 0.0, nu_hit = 0.0, inv_hit = 0.0, tau_rem = tau0;
+      double d_line = 0.0, nu_hit = 0.0, tau_rem = tau0;
       while (k < v.L) {
         if (sh != wshell || k < wbase || k >= wbase + G) {
           // The following window of the same shell was copied ahead from
@@ -1323,7 +1377,6 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
           jb_acc = 0.0;
           wbase = k;
           wshell = sh;
-          winv = recip(wn);
         }
         const int32_t line = wbase + grp.lane;
         const bool live = line >= k && line < v.L;
@@ -1332,14 +1385,15 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
         double dl = (nu_cmf - wn) * ct_over_nu;
         dl = dl < 0.0 ? 0.0 : dl;
         const double rem = tau_ev - before;
-        const bool reach = kappa * dl < rem && dl < d_shell;
+        const double de = kappa > 0.0 ? quot_checked(rem, rkappa) : INFINITY;
+        const bool reach = dl < de && dl < d_shell;
         const bool hit = reach && wt + kappa * dl > rem;
         const unsigned long long stop = grp.bits(__ballot(live && (!reach || hit)));
         const unsigned long long hits = grp.bits(__ballot(live && hit));
         const int first = stop ? (int)__builtin_ctzll(stop) : -1;
         // J_blue: every line reached up to the stop, the interacting one included
         const int end = first < 0 ? G : first + ((hits >> first) & 1ull ? 1 : 0);
-        if (jb_row && live && grp.lane < end) jb_acc += jb_w * wn;
+        if (jb_row && live && grp.lane < end) jb_acc += quot(E * wn, rnn);
         const int passed = end - (k - wbase) > 0 ? end - (k - wbase) : 0;
         n_pass += (uint64_t)(first < 0 ? (int32_t)(v.L < wbase + G ? v.L - k : wbase + G - k)
                                        : passed);
@@ -1350,7 +1404,6 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
             line_hit = true;
             d_line = grp.bcast(dl, fl);
             nu_hit = grp.bcast(wn, fl);
-            inv_hit = grp.bcast(winv, fl);
           } else {
             tau_rem = grp.bcast(rem, fl);
           }
@@ -1364,7 +1417,8 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
       }
       next_line = k;
 
-      const double d_electron = (!line_hit && kappa > 0.0) ? tau_rem * recip(kappa) : INFINITY;
+      const double d_electron =
+          (!line_hit && kappa > 0.0) ? quot_checked(tau_rem, rkappa) : INFINITY;
       const bool escat = !line_hit && d_electron < d_shell;
       const bool cross = !line_hit && !escat;
       const double d = line_hit ? d_line : (escat ? d_electron : d_shell);
@@ -1384,11 +1438,11 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
       acc_J += jc;
       acc_nb += jc * nu_cmf;
 
-      const double r_new = sqrt(r * r + d * d + 2.0 * r * d * mu);
+      const double r_new = root(r * r + d * d + 2.0 * r * d * mu);
+      double mu_new = quot(rmu + d, divisor(r_new));
+      mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
       if (cross) {
         const int kind = inward ? EV_SHELL_IN : EV_SHELL_OUT;
-        double mu_new = (rmu + d) * recip(r_new);
-        mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
         r = inward ? c_rin : c_rout;
         mu = mu_new;
         if (v.records) hash = fnv_event(hash, kind, sh, -1, -1);
@@ -1396,24 +1450,21 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
         if (shell >= v.S) status = SMC_ESCAPED;
         if (shell < 0) status = SMC_REABSORBED;
       } else {
-        // mu_new * r_new = r mu + d along the straight path
-        const double D_old = 1.0 - (rmu + d) * v.inv_ct;
+        const double D_old = 1.0 - quot(mu_new * r_new, v.rct);
         const double e_cmf_ev = E * D_old;
-        double nu_cmf_out, inv_cmf_out;
+        double nu_cmf_out;
         int32_t emit = k;
         if (line_hit) {
           const double u_branch =
               grp.bcast((draw & 1) ? ub : ua, grp.uni((int)((draw >> 1) - rb)));
           draw += 1;
           nu_cmf_out = nu_hit;
-          inv_cmf_out = inv_hit;
           if (v.downbranch) {
             const int32_t up = v.line_upper[k];
             const int64_t j =
                 grp.row_select(v.em_cum, v.level_ptr[up], v.level_ptr[up + 1], u_branch);
             emit = v.em_line[j];
             nu_cmf_out = v.line_nu[emit];
-            inv_cmf_out = recip(nu_cmf_out);
           } else if (kExt && v.macroatom) {
             // internal jumps until deactivation, one draw per step from this
             // shell's rows (section 2.5)
@@ -1437,30 +1488,25 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
             }
             if (emit < 0) {
               // a macro atom that never deactivated: the packet ends here
-              double mu_new = (rmu + d) * recip(r_new);
-              mu = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
+              mu = mu_new;
               r = r_new;
               status = SMC_CAPPED;
               dead_atom = true;
               break;
             }
             nu_cmf_out = v.line_nu[emit];
-            inv_cmf_out = recip(nu_cmf_out);
           }
         } else {
           nu_cmf_out = nu * D_old;
-          inv_cmf_out = recip(nu_cmf_out);
         }
         const double mu_out =
             2.0 * grp.bcast((draw & 1) ? ub : ua, grp.uni((int)((draw >> 1) - rb))) - 1.0;
         draw += 1;
-        const double D_new = 1.0 - (mu_out * r_new) * v.inv_ct;
-        const double inv_D = recip(D_new);
+        const Divisor rD = divisor(1.0 - quot(mu_out * r_new, v.rct));
         r = r_new;
         mu = mu_out;
-        nu = nu_cmf_out * inv_D;
-        E = e_cmf_ev * inv_D;
-        inv_nu = D_new * inv_cmf_out;
+        nu = quot(nu_cmf_out, rD);
+        E = quot(e_cmf_ev, rD);
         if (line_hit) {
           next_line = emit + 1;
           n_line += 1;

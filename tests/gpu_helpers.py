@@ -44,10 +44,13 @@ def divergent(gpu_packets, oracle_packets):
 
 
 def assert_packets_match(g, o, rel=REL, allow_fraction=DIVERGE_FRACTION):
+    """Per-packet parity; returns the indices of packets whose event sequence
+    took the other branch at a rounding tie, at most allow_fraction of them
+    (none below 1/allow_fraction packets)."""
     assert g.shape == o.shape
     assert np.array_equal(g["id"], o["id"])
     bad = divergent(g, o)
-    assert bad.size <= max(1, int(allow_fraction * g.size)), f"{bad.size} divergent packets"
+    assert bad.size <= int(allow_fraction * g.size), f"{bad.size} divergent of {g.size} packets"
     ok = np.ones(g.size, dtype=bool)
     ok[bad] = False
     a, b = g[ok], o[ok]
@@ -66,6 +69,23 @@ def assert_close_or_zero(gpu, ref, rel=REL, what=""):
     zero = ref == 0.0
     assert np.all(gpu[zero] == 0.0), f"{what}: nonzero where the oracle has zero"
     np.testing.assert_allclose(gpu[~zero], ref[~zero], rtol=rel, atol=0, err_msg=what)
+
+
+def assert_estimators_match(est, spec, fin, rel=REL, jblue=True, T_R_W=True):
+    """Normalised estimators and spectrum of one GPU iteration against the
+    oracle's (section 2.7 J, nu-bar, J_blue; section 2.9 L_nu; the
+    luminosity scalars and the next T_inner of section 2.8)."""
+    assert_close_or_zero(est["J"], fin["J"], rel=rel, what="J")
+    assert_close_or_zero(est["nubar"], fin["nubar"], rel=rel, what="nubar")
+    if T_R_W:
+        np.testing.assert_allclose(est["T_R"], fin["T_R"], rtol=rel, err_msg="T_R")
+        np.testing.assert_allclose(est["W"], fin["W"], rtol=rel, err_msg="W")
+    if jblue and fin.get("jblue") is not None:
+        assert_close_or_zero(est["jblue"], fin["jblue"], rel=rel, what="jblue")
+    assert_close_or_zero(spec["L_nu"], fin["L_nu"], rel=rel, what="L_nu")
+    for k in ("L_emitted", "L_reabsorbed", "L_capped", "L_inner", "T_inner_next"):
+        ref = fin[k]
+        assert abs(spec[k] - ref) <= rel * abs(ref), (k, spec[k], ref)
 
 
 def spectrum_chi2_pvalue(a, b, n_packets):
