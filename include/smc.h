@@ -148,7 +148,10 @@ typedef struct {
                                 lane-per-packet to the group-per-packet kernel;
                                 UINT32_MAX keeps every history in the first kernel */
   uint32_t long_lanes;       /* lanes that carry one handed-off history: 16, 32 or 64
-                                (a wavefront carries 64 / long_lanes of them) */
+                                (a wavefront carries 64 / long_lanes of them); the
+                                default is 64 (the wavefront-per-history kernel) for the
+                                scatter and downbranch modes without v-packets, 32 with
+                                macro atoms or v-packets */
 } smc_tune;
 
 /* Create a context on HIP device `hip_device`.  The context owns a few small

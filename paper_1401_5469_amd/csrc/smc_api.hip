@@ -103,10 +103,15 @@ constexpr uint64_t kAlign = 256;
 // throughput matters more than the latency of one history)
 constexpr uint32_t kDefaultLongBudget = 256;
 constexpr uint32_t kDefaultLongBudgetWide = 1024;
-constexpr int kDefaultLongLanes = 32;
+// lanes per handed-off history unless tuned: one history per wavefront (its
+// segments have the shortest latency) in the plain modes, two per wavefront
+// in the group kernel variant with the macro-atom and v-packet code
+constexpr int kDefaultLongLanes = 64;
+constexpr int kDefaultLongLanesExt = 32;
 // wavefronts per CU of the group-per-packet kernel unless tuned (fewer when
-// its occupancy allows fewer)
+// its occupancy allows fewer): 16 one-history wavefronts, else 12
 constexpr int kDefaultLongWaves = 12;
+constexpr int kDefaultSoloWaves = 16;
 // launch-wide control block of a multi-model launch: 4 queue counters, then
 // the hand-off order histogram and cursors
 constexpr size_t kCtlBytes = 4 * sizeof(unsigned long long) + 2 * smc::kOrderBuckets * 4;
@@ -125,12 +130,16 @@ void release_ctx(smc_ctx* c) {
   delete c;
 }
 
-int lanes_of(const smc_tune& t) { return t.long_lanes == 0 ? kDefaultLongLanes : (int)t.long_lanes; }
+int lanes_of(const smc_tune& t, bool ext) {
+  return t.long_lanes != 0 ? (int)t.long_lanes : (ext ? kDefaultLongLanesExt : kDefaultLongLanes);
+}
 int lanes_index(int lanes) { return lanes == 16 ? 0 : (lanes == 32 ? 1 : 2); }
 
 int default_long_waves(const smc_ctx* c, bool multi, const smc_tune& t, bool ext) {
-  const int occ = c->long_blocks_per_cu[multi][lanes_index(lanes_of(t))][ext];
-  return occ < kDefaultLongWaves ? occ : kDefaultLongWaves;
+  const int lanes = lanes_of(t, ext);
+  const int occ = c->long_blocks_per_cu[multi][lanes_index(lanes)][ext];
+  const int want = (lanes == 64 && !ext) ? kDefaultSoloWaves : kDefaultLongWaves;
+  return occ < want ? occ : want;
 }
 
 int check_tune(const smc_tune& t) {
@@ -143,7 +152,12 @@ int check_tune(const smc_tune& t) {
 }
 
 // hand-off positions run at the highest wave priority: two histories per SIMD
-uint32_t hot_of(const smc_ctx* c) { return 8u * (uint32_t)c->n_cu; }
+// hand-off positions that run at the highest wave priority: one wavefront's
+// histories per SIMD (4 SIMDs per CU), so that no two top-priority
+// wavefronts share a SIMD
+uint32_t hot_of(const smc_ctx* c, const smc_tune& t, bool ext) {
+  return 4u * (uint32_t)c->n_cu * (uint32_t)(64 / lanes_of(t, ext));
+}
 
 uint32_t budget_of(const smc_tune& t, bool wide) {
   return t.long_budget == 0 ? (wide ? kDefaultLongBudgetWide : kDefaultLongBudget)
@@ -167,7 +181,7 @@ smc::Shape shape_of(const smc_ctx* c, const smc_tune& t, bool multi, uint64_t n_
     if (lgrid > n_work) lgrid = n_work;
   }
   sh.long_grid = (int)lgrid;
-  sh.long_lanes = lanes_of(t);
+  sh.long_lanes = lanes_of(t, ext);
   sh.long_ext = ext;
   return sh;
 }
@@ -248,9 +262,14 @@ int validate(const smc_model_desc* d) {
   // overflow
   if (!(d->v_bounds[d->n_shells] < 0.5 * 2.99792458e10))
     return fail(SMC_EINVAL, "outer velocity must be below c/2");
+  // radii within [2^-300, 2^300] cm keep every squared distance the kernels
+  // take a root of either zero or a normal number
+  if (!(d->v_bounds[0] * d->t_exp >= 0x1p-300) ||
+      !(d->v_bounds[d->n_shells] * d->t_exp <= 0x1p300))
+    return fail(SMC_EINVAL, "radii v t_exp must lie in [2^-300, 2^300] cm");
   for (int i = 0; i < d->n_shells; ++i)
-    if (!(d->n_e[i] >= 0.0) || !isfinite(d->n_e[i]))
-      return fail(SMC_EINVAL, "n_e[%d] must be finite and >= 0", i);
+    if (!(d->n_e[i] >= 0.0) || !(d->n_e[i] <= 1e200))
+      return fail(SMC_EINVAL, "n_e[%d] must lie in [0, 1e200]", i);
   for (int64_t k = 0; k < d->n_lines; ++k) {
     if (!(d->line_nu[k] > 0.0) || !isfinite(d->line_nu[k]))
       return fail(SMC_EINVAL, "line_nu[%lld] must be finite and > 0", (long long)k);
@@ -597,11 +616,11 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   a.ctr = m->dev.counters + smc::CTR_QUEUE;
   a.order_hist = m->order_hist;
   a.max_lines = (uint32_t)m->dev.L;
-  a.hot = hot_of(m->ctx);
+  const bool ext = a.single.it.n_virtual > 0 || m->dev.mode == SMC_MACROATOM;
+  a.hot = hot_of(m->ctx, m->tune, ext);
   const smc::Shape sh =
       shape_of(m->ctx, m->tune, false, a.total_work,
-               a.single.it.long_budget > 0 || a.single.it.n_virtual > 0,
-               a.single.it.n_virtual > 0 || m->dev.mode == SMC_MACROATOM);
+               a.single.it.long_budget > 0 || a.single.it.n_virtual > 0, ext);
   HIP_TRY(smc::launch_iteration(a, false, sh, jblue_entries(m, p->flags),
                                 timed ? m->ev_start : nullptr, timed ? m->ev_stop : nullptr, s),
           "iteration launch");
@@ -675,7 +694,7 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
   a.ctr = ctx->dev_ctr[slot];
   a.order_hist = (unsigned int*)(ctx->dev_ctr[slot] + 4);
   a.max_lines = max_lines;
-  a.hot = hot_of(ctx);
+  a.hot = hot_of(ctx, t, any_ext);
   const smc::Shape sh = shape_of(ctx, t, true, work, budget > 0 || any_virtual, any_ext);
   HIP_TRY(smc::launch_iteration(a, true, sh, max_jb, timed ? ctx->ev_start : nullptr,
                                 timed ? ctx->ev_stop : nullptr, s),
@@ -859,7 +878,7 @@ int smc_model_get_tune(smc_model* m, smc_tune* t) {
   if (!m || !t) return fail(SMC_EINVAL, "null model or output");
   *t = m->tune;
   if (t->blocks_per_cu == 0) t->blocks_per_cu = m->ctx->transport_blocks_per_cu[0];
-  if (t->long_lanes == 0) t->long_lanes = kDefaultLongLanes;
+  if (t->long_lanes == 0) t->long_lanes = lanes_of(*t, m->dev.mode == SMC_MACROATOM);
   if (t->long_waves_per_cu == 0)
     t->long_waves_per_cu = default_long_waves(m->ctx, false, *t, m->dev.mode == SMC_MACROATOM);
   if (t->long_budget == 0)
@@ -1024,7 +1043,7 @@ static int graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_
       a.order_hist = models[0]->order_hist;
     }
     a.max_lines = max_lines;
-    a.hot = hot_of(ctx);
+    a.hot = hot_of(ctx, t, any_ext[i]);
     const smc::Shape sh =
         shape_of(ctx, t, multi, work[i], budget > 0 || any_virtual[i], any_ext[i]);
     le = smc::launch_iteration(a, multi, sh, max_jb[i], nullptr, nullptr, s);

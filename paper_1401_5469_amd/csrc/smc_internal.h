@@ -148,7 +148,8 @@ enum { SC_L_EMITTED = 0, SC_L_REABSORBED = 1, SC_L_CAPPED = 2, SC_L_INNER = 3,
 struct Shape {
   int transport_grid;
   int long_grid;   // wavefronts of the group-per-packet kernel
-  int long_lanes;  // lanes per handed-off history: 16, 32 or 64
+  int long_lanes;  // lanes per handed-off history: 16, 32 or 64 (64 without the extended
+                   // code: the wavefront-per-history kernel)
   bool long_ext;   // some model of the launch runs v-packets or the macroatom mode: the
                    // group kernel variant with that code (more registers)
 };

@@ -294,9 +294,10 @@ __device__ __forceinline__ double quot_checked(double a, const Divisor& d) {
 // Square root: reciprocal square-root estimate, then the coupled Newton
 // iteration for sqrt(x) and 1/(2 sqrt(x)) with two exact-residual corrections
 // (Markstein 1990; the gfx950 sqrt sequence without its scaling of x below
-// 2^-767).  Zero and tiny arguments take the general sequence.
+// 2^-767).  The transport takes roots of squared distances only, which the
+// radius range the library accepts ([2^-300, 2^300] cm) keeps at zero or in
+// [2^-700, 2^700]; zero gives zero.
 __device__ __forceinline__ double root(double x) {
-  if (!(x >= 0x1p-767 && x <= 0x1p1000)) return sqrt(x);
   const double y = __builtin_amdgcn_rsq(x);
   double g = x * y;
   double h = y * 0.5;
@@ -306,7 +307,8 @@ __device__ __forceinline__ double root(double x) {
   double d = fma(-g, g, x);
   g = fma(d, h, g);
   d = fma(-g, g, x);
-  return fma(d, h, g);
+  g = fma(d, h, g);
+  return x > 0.0 ? g : 0.0;
 }
 
 // distance along (r, mu) to the boundary of shell [r_in, r_out] met first
@@ -974,6 +976,17 @@ __device__ __forceinline__ double readlane_f64(double x, int src) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// x moved by a DPP row shift (both 32-bit halves); a lane whose source lies
+// outside its row of 16 reads 0
+template <int kCtrl>
+__device__ __forceinline__ double dpp_shr_f64(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, kCtrl, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), kCtrl, 0xF, 0xF,
+                                                         true);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // x moved by DPP (both 32-bit halves); lanes the control does not write keep 0
 template <int kCtrl, int kRowMask>
 __device__ __forceinline__ double dpp_f64(double x) {
@@ -1020,6 +1033,11 @@ struct Group {
     return __shfl(x, base + src, kWave);
   }
   __device__ __forceinline__ unsigned long long bcast_u64(unsigned long long x, int src) const {
+    if constexpr (G == 64) {
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
+      const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
+      return ((unsigned long long)hi << 32) | lo;
+    }
     return __shfl(x, base + src, kWave);
   }
   // this group's bits of a wave ballot
@@ -1043,10 +1061,10 @@ struct Group {
   // inclusive prefix sum over the group (row shifts within rows of 16 lanes,
   // then the row broadcasts of lanes 15 and 31)
   __device__ __forceinline__ double prefix_sum(double x) const {
-    x += dpp_f64<0x111, 0xF>(x);  // row_shr:1
-    x += dpp_f64<0x112, 0xF>(x);  // row_shr:2
-    x += dpp_f64<0x114, 0xF>(x);  // row_shr:4
-    x += dpp_f64<0x118, 0xF>(x);  // row_shr:8
+    x += dpp_shr_f64<0x111>(x);  // row_shr:1
+    x += dpp_shr_f64<0x112>(x);  // row_shr:2
+    x += dpp_shr_f64<0x114>(x);  // row_shr:4
+    x += dpp_shr_f64<0x118>(x);  // row_shr:8
     if constexpr (G >= 32) x += dpp_f64<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
     if constexpr (G == 64) x += dpp_f64<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
     return x;
@@ -1172,7 +1190,7 @@ constexpr int kLongBlock = 64;
 // together.  A group whose packet ends takes the next one from the hand-off
 // queue while the other groups of its wavefront keep marching.
 template <bool kMulti, int G, bool kExt>
-__global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
+__device__ __forceinline__ void long_body(const LaunchArgs& a) {
   constexpr int kGroups = kWave / G;
   __shared__ LaneTally tly_all[kGroups];  // one tally slot per group, its lane 0 writes it
   // next window of each group, copied ahead straight from HBM: low and high
@@ -1548,6 +1566,369 @@ __global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// wavefront-per-history kernel for the handed-off histories of the plain
+// line modes (scatter, downbranch) without v-packets
+// ---------------------------------------------------------------------------
+// A history's segments form one dependent chain (where one segment ends sets
+// up the next), so the time of one segment in one wavefront bounds the pass
+// once few histories are left.  Here every per-history value is uniform over
+// the wavefront: its integers live in scalar registers, its branches are
+// scalar, and a value held by one lane (a draw, the distance to the
+// interacting line) reaches the others by a lane read.  The 64 lanes test the
+// next 64 lines of the shell at once.  The common segment, a line event
+// inside the current window of lines, runs straight through the inner loop;
+// window and shell changes, draw refills, a march across several windows and
+// the downbranch emission sit in branches off that path.  Arithmetic and
+// operand order are those of the group kernel.
+template <bool kMulti>
+__device__ __forceinline__ void solo_body(const LaunchArgs& a) {
+  __shared__ LaneTally tly;
+  // next window, copied ahead straight from HBM: low and high words of the
+  // line frequencies, then of the Sobolev depths, by lane
+  __shared__ uint32_t pf[4][kWave];
+  const int lane = threadIdx.x;
+  const bool leader = lane == 0;
+  const unsigned long long n_long = long_total<kMulti>(a);
+  unsigned long long* queue = kMulti ? a.ctr + 2 : a.single.m.counters + CTR_LONG_QUEUE;
+  if (leader) lane_tally_clear(tly);
+  int tally_model = kMulti ? -1 : 0;
+  double acc_J = 0.0, acc_nb = 0.0;
+  int acc_shell = -1, acc_model = -1;
+  const Group<64> grp{lane, 0};
+
+  for (;;) {
+    // ---- the next handed-off history, in the processing order
+    unsigned long long pos = 0;
+    if (leader) pos = atomicAdd(queue, 1ull);
+    pos = grp.bcast_u64(pos, 0);
+    if (pos >= n_long) break;
+    const int jo = grp.uni(long_owner<kMulti>(a, pos));
+    const uint64_t gidx = ENTRY(a, jo).m.long_order[pos - ENTRY(a, jo).long_begin];
+    const int model = grp.uni(long_owner<kMulti>(a, gidx));
+    const uint64_t idx = gidx - ENTRY(a, model).long_begin;
+    if (pos < a.hot)
+      __builtin_amdgcn_s_setprio(3);
+    else if (pos < 3ull * a.hot)
+      __builtin_amdgcn_s_setprio(2);
+    else if (pos < 7ull * a.hot)
+      __builtin_amdgcn_s_setprio(1);
+    else
+      __builtin_amdgcn_s_setprio(0);
+    if (kMulti && tally_model != model) {
+      if (tally_model >= 0 && leader) lane_tally_flush(a.table[tally_model].m, tly);
+      tally_model = model;
+    }
+    View v = make_view(ENTRY(a, model).m, ENTRY(a, model).it);
+    // values the segment loop rarely reads, and that decide nothing, stay in
+    // vector registers, which leaves the scalar ones to the history's
+    // counters and line indices
+    asm volatile("" : "+v"(v.line_upper), "+v"(v.level_ptr), "+v"(v.em_line), "+v"(v.em_cum));
+    const LongState st = ENTRY(a, model).m.longs[idx];
+    // the history's integers are wave-uniform: scalar registers
+    uint64_t n_seg = grp.bcast_u64(st.n_seg, 0), n_pass = grp.bcast_u64(st.n_pass, 0);
+    uint64_t hash = grp.bcast_u64(st.hash, 0);
+    uint32_t draw = (uint32_t)grp.uni((int)st.draw), n_esc = (uint32_t)grp.uni((int)st.n_esc);
+    uint32_t n_line = (uint32_t)grp.uni((int)st.n_line);
+    double r = st.r, mu = st.mu, nu = st.nu, E = st.E;
+    int32_t shell = grp.uni(st.shell), next_line = grp.uni(st.next_line);
+    int32_t last_line = grp.uni(st.last_line);
+    StreamKey sk;
+    sk.k0 = v.k0;
+    sk.k1 = v.k1;
+    sk.iter = v.iter;
+    sk.p0 = (uint32_t)st.pid;
+    sk.p1 = (uint32_t)(st.pid >> 32);
+    asm volatile("" : "+v"(sk.k0), "+v"(sk.k1), "+v"(sk.p0), "+v"(sk.p1), "+v"(sk.iter));
+    // draws 2(rb + i) and 2(rb + i) + 1 in lane i, with -log of each
+    uint32_t rb = draw >> 1;
+    double ua, ub, la, lb;
+    auto refill_draws = [&]() {
+      rb = draw >> 1;
+      const Block blk = stream_block(sk, rb + lane);
+      ua = to_uniform(blk.a);
+      ub = to_uniform(blk.b);
+      la = -log(ua);
+      lb = -log(ub);
+    };
+    refill_draws();
+    // line wbase + i of shell wshell in lane i: frequency, depth, the J_blue
+    // the history has left on it since the window was installed, and the
+    // depth of the live lines below it when the march starts at line bef_k
+    int32_t wbase = -1, wshell = -1, bef_k = -1;
+    double wn = 0.0, wt = 0.0, jb_acc = 0.0, bef = 0.0;
+    auto depth_below = [&](int32_t k) {
+      const int32_t line = wbase + lane;
+      const double t = (line >= k && line < v.L) ? wt : 0.0;
+      return grp.prefix_sum(t) - t;
+    };
+    // the shell's bounds and sigma_T n_e, and whether its opacity takes the
+    // short quotient x / kappa (sigma_T n_e >= 2^-898, D in (1/2, 3/2)); below
+    // that the distance to a Thomson event exceeds 2^840 cm, beyond every
+    // chord of a shell (radii <= 2^300 cm), exactly as with no electrons
+    int32_t c_shell = -1;
+    double c_rin = 0.0, c_rout = 0.0, c_sig = 0.0;
+    bool c_kfast = true;
+    int status = SMC_LIVE;
+
+    // ---- the history's flight segments (section 2.6); segments left before
+    // the cap, counted down (a scalar test)
+    uint64_t seg_left = v.max_segments > n_seg ? v.max_segments - n_seg : 0ull;
+    for (;;) {
+      if (seg_left == 0ull) {
+        status = SMC_CAPPED;
+        break;
+      }
+      seg_left -= 1;
+      // the draws this segment may take: tau_event, then the branch and
+      // direction draws of a line event (or the direction of a Thomson one)
+      if (draw + 3 > 2u * (rb + kWave)) refill_draws();
+      const bool odd = draw & 1;
+      const int i0 = (int)((draw >> 1) - rb);
+      const double tau0 = grp.bcast(odd ? lb : la, i0);
+      const double u1 = grp.bcast(odd ? ua : ub, odd ? i0 + 1 : i0);
+      const double u2 = grp.bcast(odd ? ub : ua, i0 + 1);
+      const int sh = shell;
+      if (sh != c_shell) {
+        c_shell = sh;
+        c_rin = v.r_bounds[sh];
+        c_rout = v.r_bounds[sh + 1];
+        const double ne = v.n_e[sh];
+        // wait for these loads here, on the rare shell change
+        asm volatile("" ::"v"(c_rin), "v"(c_rout), "v"(ne));
+        c_sig = kSigmaT * ne;
+        c_kfast = __ballot(c_sig >= 0x1p-898) != 0ull;
+      }
+      const double rmu = r * mu;
+      const double D = 1.0 - quot(mu * r, v.rct);
+      const double nu_cmf = nu * D;
+      const double e_cmf = E * D;
+      bool inward;
+      const double d_shell = shell_distance(r, mu, rmu, c_rin, c_rout, inward);
+      const double kappa = c_sig * D;
+      const Divisor rkappa = divisor(kappa);
+      // distance to the Thomson event with optical depth x left
+      auto elec = [&](double x) { return c_kfast ? quot(x, rkappa) : (double)INFINITY; };
+      const Divisor rnu = divisor(nu);
+      const double ct_over_nu = quot(v.ct, rnu);
+      // J_blue weight per unit line frequency, E / nu^2: a lane sums it over
+      // its line's passages and multiplies by nu_k when the window changes
+      const double jb_f = E * rnu.y * rnu.y;
+
+      // line march over the window: lane j tests line wbase+j against the
+      // optical depth left after the live lines before it; the first lane
+      // that stops the march decides
+      double tau_ev = tau0;  // left after the windows already passed
+      int32_t k = next_line;
+      bool line_hit = false;
+      double d_line = 0.0, nu_hit = 0.0, tau_rem = tau0;
+      while (k < v.L) {
+        if ((sh != wshell) | (k < wbase) | (k >= wbase + kWave)) {
+          // The following window of the same shell was copied ahead from
+          // HBM into LDS by the direct global-to-LDS load; anything else (a
+          // new shell, a jump after a downbranch emission) is loaded now.
+          // Nothing outside this block waits for those copies, and the old
+          // window's J_blue leaves in one atomic per lane after them.
+          const bool ahead = sh == wshell && k == wbase + kWave;
+          const int32_t line = k + lane;
+          const bool in = line < v.L;
+          const size_t row = (size_t)sh * (size_t)v.Lp;
+          const double jb_out = jb_acc * wn;
+          const int32_t jb_shell = wshell, jb_base = wbase;
+          if (ahead) {
+            const double n_raw = join_u32(pf[0][lane], pf[1][lane]);
+            const double t_raw = join_u32(pf[2][lane], pf[3][lane]);
+            wn = in ? n_raw : 1.0;
+            wt = in ? t_raw : 0.0;
+          } else {
+            const int32_t lc = line < v.Lp ? line : v.Lp - 1;
+            const double n_raw = v.line_nu[lc];
+            const double t_raw = v.tau[row + lc];
+            wn = in ? n_raw : 1.0;
+            wt = in ? t_raw : 0.0;
+          }
+          asm volatile("s_waitcnt lgkmcnt(0)" ::"v"(wn), "v"(wt) : "memory");
+          const int32_t next = k + kWave + lane;
+          const int32_t nc = next < v.Lp ? next : v.Lp - 1;
+          copy_f64_to_lds(v.line_nu + nc, &pf[0][0], &pf[1][0]);
+          copy_f64_to_lds(v.tau + row + nc, &pf[2][0], &pf[3][0]);
+          if (v.jblue && jb_shell >= 0 && jb_out != 0.0)
+            unsafeAtomicAdd(&v.jblue[(size_t)jb_shell * (size_t)v.L + jb_base + lane], jb_out);
+          jb_acc = 0.0;
+          wbase = k;
+          wshell = sh;
+          bef_k = -1;
+        }
+        if (bef_k != k) {
+          bef = depth_below(k);
+          bef_k = k;
+        }
+        const int32_t line = wbase + lane;
+        const bool live = line >= k && line < v.L;
+        const double before = bef;  // depth of the live lines below
+        double dl = (nu_cmf - wn) * ct_over_nu;
+        dl = dl < 0.0 ? 0.0 : dl;
+        const double rem = tau_ev - before;
+        const bool reach = dl < elec(rem) && dl < d_shell;
+        const bool hit = reach && wt + kappa * dl > rem;
+        const unsigned long long stop = __ballot(live && (!reach || hit));
+        const unsigned long long hits = __ballot(live && hit);
+        const int first = stop ? (int)__builtin_ctzll(stop) : -1;
+        // J_blue: every line reached up to the stop, the interacting one included
+        const int end = first < 0 ? kWave : first + ((hits >> first) & 1ull ? 1 : 0);
+        if (v.jblue) jb_acc += (live && lane < end) ? jb_f : 0.0;
+        const int passed = end - (k - wbase) > 0 ? end - (k - wbase) : 0;
+        n_pass += (uint64_t)(first < 0
+                                 ? (int32_t)(v.L < wbase + kWave ? v.L - k : wbase + kWave - k)
+                                 : passed);
+        if (first >= 0) {
+          k = wbase + first;
+          if ((hits >> first) & 1ull) {
+            line_hit = true;
+            d_line = grp.bcast(dl, first);
+            nu_hit = grp.bcast(wn, first);
+          } else {
+            tau_rem = grp.bcast(rem, first);
+          }
+          break;
+        }
+        // every live line of the window passed
+        const int top = v.L < wbase + kWave ? v.L - wbase - 1 : kWave - 1;
+        tau_ev -= grp.bcast(before + (live ? wt : 0.0), top);
+        tau_rem = tau_ev;
+        k = wbase + top + 1;
+      }
+      next_line = k;
+
+      // the next march in this shell starts at the line after the
+      // interacting one (scatter mode) or here after a Thomson event: sum
+      // its depths while this event's transforms run
+      {
+        const int32_t kn = line_hit ? k + 1 : k;
+        if ((wshell == sh) & (kn >= wbase) & (kn < wbase + kWave)) {
+          bef = depth_below(kn);
+          bef_k = kn;
+        }
+      }
+      if (acc_shell != sh || acc_model != model) {
+        if (acc_shell >= 0 && leader) {
+          const DevModel& am = ENTRY(a, acc_model).m;
+          unsafeAtomicAdd(&am.raw[acc_shell], acc_J);
+          unsafeAtomicAdd(&am.raw[am.S + acc_shell], acc_nb);
+        }
+        acc_shell = sh;
+        acc_model = model;
+        acc_J = 0.0;
+        acc_nb = 0.0;
+      }
+
+      if (line_hit) {
+        // ---- line interaction (section 2.5): J and nu-bar over the flight
+        // (section 2.7), move, branch draw, new direction
+        const double d = d_line;
+        const double jc = e_cmf * d * D;
+        acc_J += jc;
+        acc_nb += jc * nu_cmf;
+        const double r_new = root(r * r + d * d + 2.0 * r * d * mu);
+        double mu_new = quot(rmu + d, divisor(r_new));
+        mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
+        const double D_old = 1.0 - quot(mu_new * r_new, v.rct);
+        const double e_cmf_ev = E * D_old;
+        double nu_cmf_out = nu_hit;
+        int32_t emit = k;
+        if (v.downbranch) {
+          const int32_t up = v.line_upper[k];
+          const int64_t j = grp.row_select(v.em_cum, v.level_ptr[up], v.level_ptr[up + 1], u1);
+          emit = grp.uni(v.em_line[j]);
+          nu_cmf_out = v.line_nu[emit];
+        }
+        const double mu_out = 2.0 * u2 - 1.0;
+        const Divisor rD = divisor(1.0 - quot(mu_out * r_new, v.rct));
+        r = r_new;
+        mu = mu_out;
+        nu = quot(nu_cmf_out, rD);
+        E = quot(e_cmf_ev, rD);
+        draw += 3;
+        next_line = emit + 1;
+        n_line += 1;
+        last_line = k;
+        if (v.records) hash = fnv_event(hash, EV_LINE, sh, k, emit);
+        continue;
+      }
+      // ---- no line reached first: Thomson event or shell boundary
+      const double d_electron = elec(tau_rem);
+      const bool escat = d_electron < d_shell;
+      const double d = escat ? d_electron : d_shell;
+      const double jc = e_cmf * d * D;
+      acc_J += jc;
+      acc_nb += jc * nu_cmf;
+      const double r_new = root(r * r + d * d + 2.0 * r * d * mu);
+      double mu_new = quot(rmu + d, divisor(r_new));
+      mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
+      if (escat) {
+        // coherent, isotropic in the comoving frame (section 2.5)
+        const double D_old = 1.0 - quot(mu_new * r_new, v.rct);
+        const double e_cmf_ev = E * D_old;
+        const double nu_cmf_out = nu * D_old;
+        const double mu_out = 2.0 * u1 - 1.0;
+        const Divisor rD = divisor(1.0 - quot(mu_out * r_new, v.rct));
+        r = r_new;
+        mu = mu_out;
+        nu = quot(nu_cmf_out, rD);
+        E = quot(e_cmf_ev, rD);
+        draw += 2;
+        n_esc += 1;
+        if (v.records) hash = fnv_event(hash, EV_ESCATTER, sh, -1, -1);
+        continue;
+      }
+      const int kind = inward ? EV_SHELL_IN : EV_SHELL_OUT;
+      r = inward ? c_rin : c_rout;
+      mu = mu_new;
+      draw += 1;
+      if (v.records) hash = fnv_event(hash, kind, sh, -1, -1);
+      shell = sh + (inward ? -1 : 1);
+      if (shell >= v.S) {
+        status = SMC_ESCAPED;
+        break;
+      }
+      if (shell < 0) {
+        status = SMC_REABSORBED;
+        break;
+      }
+    }
+    n_seg = v.max_segments - seg_left;
+
+    // ---- end of the history
+    if (v.jblue && wshell >= 0 && jb_acc != 0.0)
+      unsafeAtomicAdd(&v.jblue[(size_t)wshell * (size_t)v.L + wbase + lane], jb_acc * wn);
+    if (leader) {
+      const DevModel& m = ENTRY(a, model).m;
+      lane_tally_end(m, tly, status, nu, E, n_seg, n_pass, n_line, n_esc, false);
+      if (v.records)
+        write_record(m, st.slot, st.pid, status, shell, nu, E, mu, r, st.mu0, st.nu_cmf0, n_seg,
+                     n_esc, n_line, n_pass, hash, last_line);
+    }
+  }
+  if (leader) {
+    if (acc_shell >= 0) {
+      const DevModel& am = ENTRY(a, acc_model).m;
+      unsafeAtomicAdd(&am.raw[acc_shell], acc_J);
+      unsafeAtomicAdd(&am.raw[am.S + acc_shell], acc_nb);
+    }
+    if (tally_model >= 0) lane_tally_flush(ENTRY(a, tally_model).m, tly);
+  }
+}
+
+template <bool kMulti, int G, bool kExt>
+__global__ __launch_bounds__(kLongBlock) void long_kernel(LaunchArgs a) {
+  long_body<kMulti, G, kExt>(a);
+}
+
+template <bool kMulti>
+__global__ __launch_bounds__(kLongBlock) void solo_kernel(LaunchArgs a) {
+  solo_body<kMulti>(a);
+}
+
+// ---------------------------------------------------------------------------
 // estimator normalisation and radiation-field update (sections 2.7, 2.8);
 // blockIdx.x selects the model
 // ---------------------------------------------------------------------------
@@ -1652,6 +2033,9 @@ static hipError_t long_occupancy_of(int lanes, int* blocks_per_cu) {
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(
           blocks_per_cu, long_kernel<kMulti, 32, kExt>, kLongBlock, 0);
     case 64:
+      if constexpr (!kExt)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, solo_kernel<kMulti>,
+                                                            kLongBlock, 0);
       return hipOccupancyMaxActiveBlocksPerMultiprocessor(
           blocks_per_cu, long_kernel<kMulti, 64, kExt>, kLongBlock, 0);
   }
@@ -1677,7 +2061,10 @@ static hipError_t launch_long(int lanes, dim3 grid, dim3 block, const LaunchArgs
       hipLaunchKernelGGL((long_kernel<kMulti, 32, kExt>), grid, block, 0, s, a);
       break;
     case 64:
-      hipLaunchKernelGGL((long_kernel<kMulti, 64, kExt>), grid, block, 0, s, a);
+      if constexpr (!kExt)
+        hipLaunchKernelGGL(solo_kernel<kMulti>, grid, block, 0, s, a);
+      else
+        hipLaunchKernelGGL((long_kernel<kMulti, 64, kExt>), grid, block, 0, s, a);
       break;
     default:
       return hipErrorInvalidValue;
