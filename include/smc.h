@@ -234,6 +234,20 @@ int smc_read_packets(smc_model* model, smc_packet_out* out, uint64_t n, void* st
 int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
                   int n_models, const smc_tune* tune, uint32_t flags, void* stream);
 
+/* smc_batch_run for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops): the launch-wide scratch (queue heads,
+ * hand-off order histogram, device model table) lives in a static array of
+ * 128 KiB on each device instead of the context's buffers, and the call
+ * makes no allocation of any kind.  At most SMC_STATIC_MAX_MODELS models;
+ * more is SMC_EINVAL.  Arguments, results and errors are those of
+ * smc_batch_run.  All calls on one device share that array and keep its last
+ * contents (each launch clears what it needs cleared), so two such calls on
+ * one device must not overlap: issue them on one stream, or wait for one
+ * before issuing the next.  Asynchronous. */
+#define SMC_STATIC_MAX_MODELS 64
+int smc_batch_run_static(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
+                         int n_models, const smc_tune* tune, uint32_t flags, void* stream);
+
 /* Duration in milliseconds of the transport kernels of the last timed batch
  * of this context.  Waits for them to end. */
 int smc_batch_read_timing(smc_ctx* ctx, double* transport_ms);

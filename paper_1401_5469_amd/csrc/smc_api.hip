@@ -34,6 +34,7 @@ struct smc_ctx {
   int next_slot;
   hipEvent_t ev_start, ev_stop;               // timing of the last batch
   bool batch_timed;
+  uint8_t* scratch;  // device address of this device's copy of `scratch`
 };
 
 struct smc_model {
@@ -115,6 +116,17 @@ constexpr int kDefaultSoloWaves = 16;
 // launch-wide control block of a multi-model launch: 4 queue counters, then
 // the hand-off order histogram and cursors
 constexpr size_t kCtlBytes = 4 * sizeof(unsigned long long) + 2 * smc::kOrderBuckets * 4;
+
+// Launch-wide scratch of smc_batch_run_static, which allocates nothing: the
+// control block (queue heads, hand-off order histogram and cursors), then the
+// device model table.  Every GPU the library runs on holds one copy until the
+// process ends; its device address is looked up once per context.
+constexpr size_t kScratchBytes = 128 * 1024;
+constexpr size_t kScratchTableOffset = (kCtlBytes + 255) / 256 * 256;
+constexpr int kScratchModels =
+    (int)((kScratchBytes - kScratchTableOffset) / sizeof(smc::BatchEntry));
+static_assert(kScratchModels >= SMC_STATIC_MAX_MODELS, "the scratch holds the largest batch");
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 
 void release_ctx(smc_ctx* c) {
   if (!c) return;
@@ -453,6 +465,19 @@ int smc_ctx_create(smc_ctx** out, int hip_device) {
       }
     }
   }
+  {
+    // the device's copy of the static scratch (host code may not use the
+    // array's name as a device address)
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) e = hipEventCreate(&c->ev_start);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev_stop);
+    if (e != hipSuccess) {
+      release_ctx(c);
+      return hip_fail(e, "scratch lookup");
+    }
+    c->scratch = static_cast<uint8_t*>(p);
+  }
   for (int i = 0; i < kBatchSlots; ++i) {
     const size_t tb = sizeof(smc::BatchEntry) * smc::kMaxBatchModels;
     hipError_t e = hipHostMalloc((void**)&c->host_table[i], tb, hipHostMallocDefault);
@@ -633,8 +658,17 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   return ok();
 }
 
-int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
-                  int n_models, const smc_tune* tune, uint32_t flags, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// One iteration of each model in one set of launches.  The launch-wide
+// control block and device model table are `dev_ctr` and `dev_table` when
+// given (the static scratch), else the context's next slot; the table is
+// staged in that slot's pinned host buffer either way.
+int batch_launch(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
+                 int n_models, const smc_tune* tune, uint32_t flags, void* stream,
+                 smc::BatchEntry* dev_table, unsigned long long* dev_ctr) {
   if (!ctx || !models || !params) return fail(SMC_EINVAL, "null context, models or parameters");
   if (n_models < 1 || n_models > smc::kMaxBatchModels)
     return fail(SMC_EINVAL, "n_models=%d outside [1, %d]", n_models, smc::kMaxBatchModels);
@@ -677,22 +711,20 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
     const uint64_t jb = jblue_entries(m, params[k].flags);
     if (jb > max_jb) max_jb = jb;
   }
+  if (!dev_table) dev_table = ctx->dev_table[slot];
+  if (!dev_ctr) dev_ctr = ctx->dev_ctr[slot];
   hipStream_t s = (hipStream_t)stream;
-  HIP_TRY(hipMemcpyAsync(ctx->dev_table[slot], tab, sizeof(smc::BatchEntry) * n_models,
+  HIP_TRY(hipMemcpyAsync(dev_table, tab, sizeof(smc::BatchEntry) * n_models,
                          hipMemcpyHostToDevice, s),
           "batch table upload");
   const bool timed = (flags & SMC_F_TIMING) != 0;
-  if (timed && !ctx->ev_start) {
-    HIP_TRY(hipEventCreate(&ctx->ev_start), "hipEventCreate");
-    HIP_TRY(hipEventCreate(&ctx->ev_stop), "hipEventCreate");
-  }
   smc::LaunchArgs a;
   memset(&a, 0, sizeof a);
-  a.table = ctx->dev_table[slot];
+  a.table = dev_table;
   a.n_models = n_models;
   a.total_work = work;
-  a.ctr = ctx->dev_ctr[slot];
-  a.order_hist = (unsigned int*)(ctx->dev_ctr[slot] + 4);
+  a.ctr = dev_ctr;
+  a.order_hist = (unsigned int*)(dev_ctr + 4);
   a.max_lines = max_lines;
   a.hot = hot_of(ctx, t, any_ext);
   const smc::Shape sh = shape_of(ctx, t, true, work, budget > 0 || any_virtual, any_ext);
@@ -713,6 +745,29 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
     m->last_virtual = params[k].n_virtual > 0;
   }
   return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
+                  int n_models, const smc_tune* tune, uint32_t flags, void* stream) {
+  return batch_launch(ctx, models, params, n_models, tune, flags, stream, nullptr, nullptr);
+}
+
+int smc_batch_run_static(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
+                         int n_models, const smc_tune* tune, uint32_t flags, void* stream) {
+  if (!ctx) return fail(SMC_EINVAL, "null context");
+  if (n_models > SMC_STATIC_MAX_MODELS)
+    return fail(SMC_EINVAL,
+                "n_models=%d exceeds the %d models the static scratch holds (use smc_batch_run)",
+                n_models, SMC_STATIC_MAX_MODELS);
+  // the scratch keeps the last call's contents: the reset kernel clears the
+  // queue heads and histogram, and the upload rewrites the table
+  return batch_launch(ctx, models, params, n_models, tune, flags, stream,
+                      reinterpret_cast<smc::BatchEntry*>(ctx->scratch + kScratchTableOffset),
+                      reinterpret_cast<unsigned long long*>(ctx->scratch));
 }
 
 int smc_batch_autotune(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,

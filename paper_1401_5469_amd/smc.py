@@ -21,6 +21,7 @@ SMC_OK, SMC_EINVAL, SMC_ENOMEM, SMC_EDEVICE, SMC_EBUSY = 0, -1, -2, -3, -4
 SCATTER, DOWNBRANCH, MACROATOM = 0, 1, 2
 LIVE, ESCAPED, REABSORBED, CAPPED = 0, 1, 2, 3
 F_JBLUE, F_PACKETS, F_TIMING = 1, 2, 4
+STATIC_MAX_MODELS = 64  # models one smc_batch_run_static call takes
 COUNTER_NAMES = ("segments", "line_passes", "line_events", "escatters", "escaped",
                  "reabsorbed", "capped", "crossings")
 
@@ -84,7 +85,8 @@ EXPORTS = ("smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_model_wor
            "smc_model_set_tune", "smc_model_get_tune", "smc_batch_run", "smc_batch_read_timing",
            "smc_batch_autotune", "smc_graph_capture", "smc_graph_launch", "smc_graph_destroy",
            "smc_read_virtual_spectrum", "smc_plasma_workspace_bytes", "smc_plasma_load",
-           "smc_plasma_update", "smc_plasma_read", "smc_plasma_free", "smc_graph_capture_plasma")
+           "smc_plasma_update", "smc_plasma_read", "smc_plasma_free", "smc_graph_capture_plasma",
+           "smc_batch_run_static")
 
 
 class SmcError(RuntimeError):
@@ -125,6 +127,8 @@ def load_library(path: str = LIB_PATH):
     L.smc_model_set_tune.argtypes = [vp, C.POINTER(smc_tune)]
     L.smc_batch_run.argtypes = [vp, C.POINTER(vp), C.POINTER(smc_iter_params), C.c_int,
                                 C.POINTER(smc_tune), C.c_uint32, vp]
+    L.smc_batch_run_static.argtypes = [vp, C.POINTER(vp), C.POINTER(smc_iter_params), C.c_int,
+                                       C.POINTER(smc_tune), C.c_uint32, vp]
     L.smc_batch_read_timing.argtypes = [vp, _dp]
     L.smc_batch_autotune.argtypes = [vp, C.POINTER(vp), C.POINTER(smc_iter_params), C.c_int,
                                      C.POINTER(smc_tune), C.c_int, C.POINTER(smc_tune), _dp, vp]
@@ -215,6 +219,22 @@ class Context:
         t = _tune(tune) if tune else None
         _check(_lib.smc_batch_run(self.handle, handles, arr, n, C.byref(t) if t else None,
                                   F_TIMING if timing else 0, _stream_ptr(stream)))
+
+    def batch_run_static(self, models, params, tune=None, timing=False, stream=None):
+        """batch_run with the launch-wide scratch in the library's static
+        device array: no allocation (at most STATIC_MAX_MODELS models)."""
+        n = len(models)
+        if len(params) != n:
+            raise ValueError("one parameter set per model")
+        arr = (smc_iter_params * n)()
+        handles = (C.c_void_p * n)()
+        for k, (m, p) in enumerate(zip(models, params)):
+            arr[k] = m._params(**p)
+            handles[k] = m.handle
+        t = _tune(tune) if tune else None
+        _check(_lib.smc_batch_run_static(self.handle, handles, arr, n,
+                                         C.byref(t) if t else None,
+                                         F_TIMING if timing else 0, _stream_ptr(stream)))
 
     def batch_autotune(self, models, params, candidates=None, stream=None):
         """Time the batch under each candidate tuning (default: the library's
