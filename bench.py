@@ -25,16 +25,29 @@ timed steps are iterations 0..K-1 starting from T_inner = 9000 K.
 
 Prints ONE JSON line.  The value is packet interactions (line events plus
 Thomson scatterings) per second over the timed iterations.  The roofline
-entry prices the transport pass (the lane-per-packet kernel and the
-group-per-packet kernel of the handed-off histories, timed together by the
-library's HIP events on the launch stream) at its algorithmic bytes (32 B
-per line resonance: nu_k and tau_S read, J_blue read-modify-write) against
-the HBM peak; `traffic` is the measured HBM bytes per transport pass from
-the committed hardware-counter summary when it was taken on the current
-kernel source (else null).  The CPU baseline times the FP64 oracle on a
-bounded packet sample of the same workload, once on one host core and once
-split over --cpu-procs oracle processes on disjoint packet-id ranges (the
-host's CPU share); it reports the latter, with the single-core figure inside.
+entry prices the transport pass (the lane-per-packet kernel, the hand-off
+ordering and the group kernel of the handed-off histories, timed together by
+the library's HIP events on the launch stream) at its algorithmic bytes --
+16 B per line passed (nu_k and tau_S read), 24 B per flight segment (shell
+radii and density), 96 B per packet (its state written and read once) --
+against the HBM peak; `traffic` is the measured HBM bytes per transport pass
+from the committed hardware-counter summary when it was taken on the current
+kernel source (else null).  Its `atomic` entry sets the pass's FP64 atomic
+adds (J_blue, J, nu-bar and spectrum tallies; counted by the same counter
+summary) per second against the device's rate for the tally pattern,
+measured in the same run.  The `batched` entry is the 64-model mix in one
+autotuned multi-model launch against 64 single-model launches (models/s).
+The CPU baseline times the FP64 oracle on a bounded packet sample of the
+same iterations: an equal share of --cpu-sample packets from every timed
+iteration, each at the iteration number and T_inner the device used, once
+on one host core and once split over --cpu-procs oracle processes on
+disjoint packet-id ranges (the host's CPU share); it reports the latter,
+with the single-core figure inside.
+
+    python bench.py --workload atomics   (the device's FP64 atomic-add rate)
+    python bench.py --profile-summary DB [DB ...]
+                                         (per-kernel counter summary of
+                                          rocprofv3 --pmc databases)
 """
 import argparse
 import json
@@ -47,9 +60,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_LINE_PASS = 32.0
+# algorithmic bytes of the transport pass
+BYTES_PER_LINE_PASS = 16.0   # nu_k and tau_S of every line passed
+BYTES_PER_SEGMENT = 24.0     # shell radii and electron density
+BYTES_PER_PACKET = 96.0      # packet state written once and read once
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1401_5469_amd", "csrc", "smc_kernels.hip")
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_scatter-20shell-300kline.json")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_scatter-20shell-300kline.json")
 
 
 def parse():
@@ -58,19 +75,23 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--packets", type=int, default=1_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
-                    help="packets of iteration 0 the oracle runs for the CPU baseline")
+    ap.add_argument("--cpu-sample", type=int, default=400_000,
+                    help="packets the oracle runs for the CPU baseline, shared equally "
+                         "among the timed iterations")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-procs", type=int, default=16,
                     help="oracle processes of the all-cores CPU baseline (the host's CPU share)")
-    ap.add_argument("--cpu-worker", type=int, nargs=2, metavar=("LO", "HI"),
-                    help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-worker", metavar="JOBS", help=argparse.SUPPRESS)
     ap.add_argument("--no-critical-path", action="store_true",
                     help="skip the untimed replay of the longest history (profiling runs)")
     ap.add_argument("--no-jblue", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-plain entry of the paper-scale line (profiling runs)")
+    ap.add_argument("--profile-summary", nargs="+", metavar="DB",
+                    help="print per-kernel summaries of rocprofv3 --pmc result databases")
     ap.add_argument("--workload", default="paper-scale",
                     choices=["paper-scale", "batched", "served", "copy", "virtual",
-                             "macroatom", "plasma"])
+                             "macroatom", "plasma", "atomics"])
     ap.add_argument("--n-virtual", type=int, default=3,
                     help="virtual packets per packet launch in the virtual mode")
     ap.add_argument("--nlte", action="store_true",
@@ -83,21 +104,80 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic():
-    """HBM bytes per transport pass from the hardware-counter summary, if it
-    was taken on the kernel source that is built now."""
+def _current_summary(path):
+    """A committed hardware-counter summary, if it was taken on the kernel
+    source that is built now (else None)."""
     import hashlib
 
     try:
-        with open(TRAFFIC_SUMMARY) as f:
+        with open(path) as f:
             summ = json.load(f)
         with open(KERNEL_SOURCE, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if summ.get("kernel_source_sha256") != sha:
-        return None
-    return summ.get("bytes_per_transport_pass")
+    return summ if summ.get("kernel_source_sha256") == sha else None
+
+
+def measured_traffic():
+    """HBM bytes per transport pass from the hardware-counter summary."""
+    summ = _current_summary(TRAFFIC_SUMMARY)
+    return summ.get("bytes_per_transport_pass") if summ else None
+
+
+def measured_atomics():
+    """FP64 atomic adds per transport pass from the counter summary."""
+    summ = _current_summary(COUNTER_SUMMARY)
+    return summ.get("atomics_per_transport_pass") if summ else None
+
+
+def atomic_peak(n_rounds=256):
+    """The device's FP64 atomic-add rate in the tally pattern, on a table
+    the size of the paper-scale J_blue array (20 x 3e5 doubles)."""
+    import torch
+
+    from paper_1401_5469_amd import smc
+
+    table = torch.zeros(20 * 300_000, dtype=torch.float64, device="cuda")
+    rate = smc.measure_atomic_rate(table, n_rounds)
+    del table
+    return rate
+
+
+def atomics(args):
+    """Print the device's FP64 atomic-add rate in the tally pattern."""
+    rates = [atomic_peak() for _ in range(3)]
+    print(json.dumps({"metric": "FP64 atomic adds per second (tally pattern)", "value": max(rates),
+                      "unit": "atomics/s", "runs": rates,
+                      "pattern": "64 consecutive doubles per wavefront at a pseudo-random place "
+                                 "of a 48 MB table, 8 workgroups of 256 per CU, 256 rounds"}),
+          flush=True)
+
+
+def profile_summary(paths):
+    """Per-kernel sums of the counters in rocprofv3 --pmc result databases,
+    with the dispatch count and mean duration (one table per database)."""
+    import sqlite3
+    from collections import defaultdict
+
+    for path in paths:
+        con = sqlite3.connect(path)
+        rows = con.execute("select dispatch_id, kernel_name, counter_name, value, duration "
+                           "from counters_collection").fetchall()
+        per = defaultdict(lambda: defaultdict(float))
+        disp = defaultdict(set)
+        dur = defaultdict(dict)
+        for d, k, c, v, t in rows:
+            name = k.split("(")[0].replace("smc::(anonymous namespace)::", "").replace("void ", "")
+            per[name][c] += v
+            disp[name].add(d)
+            dur[name][d] = t
+        print(f"# {os.path.basename(os.path.dirname(path))}")
+        for name in sorted(per, key=lambda n: -sum(dur[n].values())):
+            n = len(disp[name])
+            mean_ms = sum(dur[name].values()) / n * 1e-6
+            cs = "  ".join(f"{c}={v:.6g}" for c, v in sorted(per[name].items()))
+            print(f"{name} | dispatches {n} | mean {mean_ms:.3f} ms | {cs}")
 
 
 def copy_reference(args):
@@ -372,16 +452,24 @@ def plasma(args):
     print(json.dumps(out), flush=True)
 
 
-def _oracle_sample(w, lo, hi):
-    """The oracle on packet ids [lo, hi) of iteration 0: counters and seconds."""
+def _oracle_jobs(w, jobs):
+    """The oracle on jobs [(iteration, T_inner, lo, hi), ...]: packet ids
+    [lo, hi) of each iteration at its T_inner.  Summed counters and seconds."""
     from oracle import oracle as O
     import numpy as np
 
-    ids = np.arange(lo, hi, dtype=np.uint64)
-    t0 = time.perf_counter()
-    r = O.run(w.model, w.T_inner, w.n_packets, iteration=0, packet_ids=ids, want_jblue=True,
-              want_packets=False)
-    return r["counters"], time.perf_counter() - t0
+    tot, dt = None, 0.0
+    for it, T, lo, hi in jobs:
+        if hi <= lo:
+            continue
+        ids = np.arange(lo, hi, dtype=np.uint64)
+        t0 = time.perf_counter()
+        r = O.run(w.model, T, w.n_packets, iteration=it, packet_ids=ids, want_jblue=True,
+                  want_packets=False)
+        dt += time.perf_counter() - t0
+        c = r["counters"]
+        tot = dict(c) if tot is None else {k: tot[k] + c[k] for k in tot}
+    return tot, dt
 
 
 def cpu_worker(args):
@@ -389,29 +477,34 @@ def cpu_worker(args):
     from paper_1401_5469_amd import workloads as W
 
     w = W.config2(n_packets=args.packets)
-    c, dt = _oracle_sample(w, args.cpu_worker[0], args.cpu_worker[1])
+    c, dt = _oracle_jobs(w, json.loads(args.cpu_worker))
     print(json.dumps({"counters": c, "seconds": dt}), flush=True)
 
 
-def cpu_baseline(w, n_sample, procs):
-    """The FP64 oracle on packet ids 0..n_sample-1 of iteration 0: once in
-    this process on one core, then split into `procs` disjoint id ranges run
-    by as many oracle processes at once (wall time = the slowest)."""
+def cpu_baseline(w, n_sample, procs, schedule):
+    """The FP64 oracle on a sample of the timed iterations: `schedule` lists
+    the (iteration, T_inner) of each, and each contributes packet ids
+    0..n_sample/len(schedule)-1.  Run once in this process on one core, then
+    with every iteration's ids split into `procs` disjoint ranges run by as
+    many oracle processes at once (wall time = the slowest)."""
     import subprocess
     from oracle import build as ob
 
     if not os.path.exists(ob.LIB):
         ob.build()
-    c, dt = _oracle_sample(w, 0, n_sample)
+    per = max(1, n_sample // len(schedule))
+    jobs = [(it, T, 0, per) for it, T in schedule]
+    c, dt = _oracle_jobs(w, jobs)
     inter = c["line_events"] + c["escatters"]
     single = {"value": inter / dt, "unit": "interactions/s", "cores": 1, "seconds": dt,
-              "packets_per_s": n_sample / dt, "segments_per_s": c["segments"] / dt,
+              "packets_per_s": per * len(jobs) / dt, "segments_per_s": c["segments"] / dt,
               "line_passes_per_s": c["line_passes"] / dt}
-    edges = [n_sample * k // procs for k in range(procs + 1)]
+    edges = [per * k // procs for k in range(procs + 1)]
+    parts = [[(it, T, a, b) for it, T in schedule] for a, b in zip(edges[:-1], edges[1:])
+             if b > a]
     workers = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--packets",
-                                 str(w.n_packets), "--cpu-worker", str(a), str(b)],
-                                stdout=subprocess.PIPE, text=True)
-               for a, b in zip(edges[:-1], edges[1:]) if b > a]
+                                 str(w.n_packets), "--cpu-worker", json.dumps(p)],
+                                stdout=subprocess.PIPE, text=True) for p in parts]
     res = []
     for p in workers:
         out, _ = p.communicate()
@@ -422,23 +515,27 @@ def cpu_baseline(w, n_sample, procs):
     tot = {k: sum(r["counters"][k] for r in res) for k in res[0]["counters"]}
     inter_all = tot["line_events"] + tot["escatters"]
     assert inter_all == inter, "the split sample must hold the same interactions"
+    temps = ", ".join(f"{T:.0f}" for _, T in schedule)
     return {"value": inter_all / wall, "unit": "interactions/s", "cores": len(workers),
             "kind": "oracle",
-            "sample": f"packet ids 0..{n_sample - 1} of iteration 0 at T_inner = {w.T_inner:g} K "
-                      f"({inter} interactions, {c['segments']} segments), split over "
-                      f"{len(workers)} single-threaded FP64 C oracle processes on disjoint id "
-                      f"ranges (slowest {wall:.2f} s); the same sample in one process took "
-                      f"{dt:.2f} s",
-            "packets_per_s": n_sample / wall, "segments_per_s": tot["segments"] / wall,
+            "sample": f"packet ids 0..{per - 1} of each timed iteration "
+                      f"{schedule[0][0]}..{schedule[-1][0]} at the T_inner the device used "
+                      f"({temps} K): {inter} interactions, {c['segments']} segments, split "
+                      f"over {len(workers)} single-threaded FP64 C oracle processes on "
+                      f"disjoint id ranges (slowest {wall:.2f} s); the same sample in one "
+                      f"process took {dt:.2f} s",
+            "packets_per_s": per * len(jobs) / wall, "segments_per_s": tot["segments"] / wall,
             "line_passes_per_s": tot["line_passes"] / wall, "seconds": wall,
+            "interactions_per_packet": inter / (per * len(jobs)),
             "single_core": single}
 
 
-def batched(args):
+def batched_measure(n_models, steps, warmup, jblue, log=True):
     """64 models of uneven size (shells U{10..100}, lines log-uniform 1e4-3e5,
     packets log-uniform 1e5-1e6, otherwise as the paper-scale model; model i
     from seed i), one iteration each: one autotuned multi-model launch per
-    step against 64 sequential single-model launches with the same packets."""
+    step against the 64 single-model launches one after the other, with the
+    same packets.  Returns the measurement (models/s of both forms)."""
     import numpy as np
     import torch
 
@@ -446,13 +543,15 @@ def batched(args):
     from paper_1401_5469_amd import workloads as W
 
     t0 = time.perf_counter()
-    mix = [W.config4_model(i) for i in range(args.models)]
+    mix = [W.config4_model(i) for i in range(n_models)]
     gen_s = time.perf_counter() - t0
-    flags = 0 if args.no_jblue else smc.F_JBLUE
+    flags = smc.F_JBLUE if jblue else 0
     ctx = smc.Context(0)
     models = [smc.Model(ctx, w.model, w.n_packets, flags=flags) for w in mix]
     torch.cuda.synchronize()
-    print(f"# {len(mix)} models generated in {gen_s:.1f} s and loaded", file=sys.stderr, flush=True)
+    if log:
+        print(f"# {len(mix)} models generated in {gen_s:.1f} s and loaded", file=sys.stderr,
+              flush=True)
     params = [dict(n_packets=w.n_packets, T_inner=w.T_inner, iteration=0, flags=flags)
               for w in mix]
 
@@ -461,64 +560,87 @@ def batched(args):
         return (sum(x["line_events"] + x["escatters"] for x in c), sum(x["segments"] for x in c))
 
     # plain form: one single-model iteration after the other
-    for w, m, p in zip(mix[:2], models[:2], params[:2]):
+    for m, p in zip(models[:2], params[:2]):
         m.run_iteration(**p)  # warm-up
     torch.cuda.synchronize()
     plain_walls = []
-    for step in range(args.steps):
+    for step in range(steps):
         t0 = time.perf_counter()
         for m, p in zip(models, params):
             m.run_iteration(**p)
         torch.cuda.synchronize()
         plain_walls.append(time.perf_counter() - t0)
-        print(f"# plain step {step}: {plain_walls[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        if log:
+            print(f"# plain step {step}: {plain_walls[-1] * 1e3:.1f} ms", file=sys.stderr,
+                  flush=True)
     inter, segs = counts(models)
 
     # batched form: the autotuned multi-model launch
     t0 = time.perf_counter()
     best, best_ms = ctx.batch_autotune(models, params)
     tune_s = time.perf_counter() - t0
-    print(f"# autotune: {best} {best_ms:.1f} ms ({tune_s:.1f} s)", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
+    if log:
+        print(f"# autotune: {best} {best_ms:.1f} ms ({tune_s:.1f} s)", file=sys.stderr, flush=True)
+    for _ in range(warmup):
         ctx.batch_run(models, params, tune=best)
     torch.cuda.synchronize()
     walls, kern = [], []
-    for step in range(args.steps):
+    for step in range(steps):
         t0 = time.perf_counter()
         ctx.batch_run(models, params, tune=best, timing=True)
         torch.cuda.synchronize()
         walls.append(time.perf_counter() - t0)
         kern.append(ctx.batch_read_timing())
-        print(f"# batched step {step}: {walls[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        if log:
+            print(f"# batched step {step}: {walls[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
     b_inter, b_segs = counts(models)
     n = len(mix)
     wall = float(np.mean(walls))
     plain = float(np.mean(plain_walls))
     out = {
+        "workload": f"batched-{n}-models", "models": n, "steps": steps,
+        "packets_total": int(sum(w.n_packets for w in mix)),
+        "shells_mean": float(np.mean([w.model.n_shells for w in mix])),
+        "lines_mean": float(np.mean([w.model.n_lines for w in mix])),
+        "batched": {"models_per_s": n / wall, "interactions_per_s": b_inter / wall,
+                    "segments_per_s": b_segs / wall, "wall_ms": wall * 1e3,
+                    "transport_ms": kern, "tune": best,
+                    "autotune_s": tune_s, "autotune_note": "coordinate search, two timed runs "
+                    "per candidate, a candidate kept only when 2 % faster; not in wall_ms"},
+        "plain": {"models_per_s": n / plain, "interactions_per_s": inter / plain,
+                  "segments_per_s": segs / plain, "wall_ms": plain * 1e3},
+        "speedup_vs_plain": plain / wall,
+        "interactions_per_step": b_inter,
+    }
+    for m in models:
+        m.free()
+    ctx.close()
+    return out
+
+
+def batched(args):
+    """The batched mix as its own bench line (value: models/s batched)."""
+    r = batched_measure(args.models, args.steps, args.warmup, not args.no_jblue)
+    out = {
         "metric": "models/sec (batched)",
-        "value": n / wall,
+        "value": r["batched"]["models_per_s"],
         "unit": "models/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3,
+        "ms_per_step": r["batched"]["wall_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"batched-{n}-models", "models": n,
-                   "packets_total": int(sum(w.n_packets for w in mix)),
-                   "shells_mean": float(np.mean([w.model.n_shells for w in mix])),
-                   "lines_mean": float(np.mean([w.model.n_lines for w in mix])),
-                   "jblue": not args.no_jblue},
-        "batched": {"models_per_s": n / wall, "interactions_per_s": b_inter / wall,
-                    "segments_per_s": b_segs / wall, "wall_ms": wall * 1e3,
-                    "transport_ms": kern, "tune": best, "autotune_s": tune_s},
-        "plain": {"models_per_s": n / plain, "interactions_per_s": inter / plain,
-                  "segments_per_s": segs / plain, "wall_ms": plain * 1e3},
-        "speedup_vs_plain": plain / wall,
-        "interactions_per_step": b_inter,
+        "config": {"workload": r["workload"], "models": r["models"],
+                   "packets_total": r["packets_total"], "shells_mean": r["shells_mean"],
+                   "lines_mean": r["lines_mean"], "jblue": not args.no_jblue},
+        "batched": r["batched"],
+        "plain": r["plain"],
+        "speedup_vs_plain": r["speedup_vs_plain"],
+        "interactions_per_step": r["interactions_per_step"],
     }
     print(json.dumps(out), flush=True)
 
@@ -666,6 +788,8 @@ def critical_path(ctx, w, flags, iteration, T_inner, pass_ms):
 
 def main():
     args = parse()
+    if args.profile_summary:
+        return profile_summary(args.profile_summary)
     if args.cpu_worker:
         return cpu_worker(args)
     if args.gpus != 1:
@@ -689,6 +813,8 @@ def main():
         return macroatom(args)
     if args.workload == "plasma":
         return plasma(args)
+    if args.workload == "atomics":
+        return atomics(args)
 
     import numpy as np
     import torch
@@ -730,8 +856,12 @@ def main():
     passes = sum(c["line_passes"] for c, _, _, _ in rec)
     kern_ms = [ms for _, ms, _, _ in rec]
     mean_ms = float(np.mean(kern_ms))
-    bytes_per_launch = BYTES_PER_LINE_PASS * passes / len(rec)
+    bytes_per_launch = (BYTES_PER_LINE_PASS * passes + BYTES_PER_SEGMENT * segs) / len(rec) + \
+        BYTES_PER_PACKET * N
     achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
+    atom_peak = atomic_peak()
+    atom_per_launch = measured_atomics()
+    atom_rate = atom_per_launch / (mean_ms * 1e-3) if atom_per_launch else None
 
     out = {
         "metric": "packet-interactions/sec",
@@ -759,8 +889,16 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "traffic_unit": "HBM bytes per transport pass",
-                     "kernel": "transport pass: transport_kernel + long_kernel",
-                     "bytes_per_launch": bytes_per_launch},
+                     "kernel": "transport pass: transport_kernel, order kernels and the "
+                               "group kernel of the handed-off histories",
+                     "bytes_per_launch": bytes_per_launch,
+                     "bytes_model": "16 B per line passed + 24 B per segment + 96 B per packet",
+                     "atomic": {"achieved": atom_rate, "peak": atom_peak, "unit": "atomics/s",
+                                "frac": atom_rate / atom_peak if atom_rate else None,
+                                "atomics_per_launch": atom_per_launch,
+                                "peak_source": "bench.py --workload atomics pattern, this run",
+                                "count_source": "committed counter summary (null when the "
+                                                "kernel source has changed since)"}},
         "cpu_baseline": None,
     }
     out["pcie_inclusive"] = host_boundary(ctx, w, flags, N, inter, wall, args.steps)
@@ -770,8 +908,14 @@ def main():
                                              kern_ms[-1])
         print(f"# critical path: {json.dumps(out['critical_path'])}", file=sys.stderr,
               flush=True)
+    if not args.no_batched:
+        model.free()
+        out["batched"] = batched_measure(args.models, 3, 1, not args.no_jblue, log=True)
+        print(f"# batched: {out['batched']['batched']['models_per_s']:.2f} models/s, plain "
+              f"{out['batched']['plain']['models_per_s']:.2f}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_procs)
+        schedule = [(i, t) for i, (_, _, t, _) in enumerate(rec)]
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_procs, schedule)
     print(json.dumps(out), flush=True)
 
 

@@ -248,14 +248,28 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
 int smc_batch_run_static(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
                          int n_models, const smc_tune* tune, uint32_t flags, void* stream);
 
+/* Measurement: the device's throughput of FP64 atomic adds in the pattern the
+ * J_blue tallies use (each wavefront adds to 64 consecutive doubles of a
+ * table, at a new pseudo-random place each round).  `d_table` is caller-owned
+ * device memory of n_doubles (>= 64) doubles, which the call overwrites;
+ * 8 * n_cu workgroups of 256 lanes make n_rounds adds per lane; the rate of
+ * the second of two launches goes to *atomics_per_s.  Synchronises `stream`.
+ * Returns SMC_EINVAL for a null pointer, n_doubles < 64, n_rounds = 0 or
+ * n_cu < 1, SMC_EDEVICE on a HIP error. */
+int smc_measure_atomic_rate(double* d_table, uint64_t n_doubles, uint32_t n_rounds, int n_cu,
+                            void* stream, double* atomics_per_s);
+
 /* Duration in milliseconds of the transport kernels of the last timed batch
  * of this context.  Waits for them to end. */
 int smc_batch_read_timing(smc_ctx* ctx, double* transport_ms);
 
 /* Pick launch tuning for this batch by running it: each candidate (NULL:
- * the library's coordinate search over hand-off budget, waves per CU and
- * workgroups per CU) runs one timed iteration of the whole batch and the
- * fastest is written to *best (its time to *best_ms, may be NULL).  Every
+ * the library's coordinate search over hand-off budget, lanes per handed-off
+ * history, waves per CU and workgroups per CU) runs two timed iterations of
+ * the whole batch, the faster counting; a candidate of the search replaces
+ * the current choice only when at least 2 % faster (runs of one batch vary
+ * by a few per cent).  The choice goes to *best (its time to *best_ms, may
+ * be NULL).  Every
  * params[k].T_inner must be > 0 so that all trials see the same inputs; the
  * models' tallies hold the last trial's results afterwards.  Synchronises
  * `stream`. */

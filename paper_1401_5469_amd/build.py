@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsmc.so")
-SOURCES = ["smc_api.hip", "smc_kernels.hip", "smc_plasma.hip"]
+SOURCES = ["smc_api.hip", "smc_kernels.hip", "smc_plasma.hip", "smc_measure.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

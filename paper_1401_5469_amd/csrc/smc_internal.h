@@ -256,6 +256,12 @@ struct DevPlasma {
   const double* line_nu;   // the model's [Lp]
 };
 
+// Launcher implemented in smc_measure.hip: 8 * n_cu workgroups of 256 lanes,
+// each wavefront adding 1.0 to 64 consecutive doubles of `table` at a new
+// pseudo-random place in each of n_rounds rounds.
+hipError_t launch_atomic_rate(double* table, uint64_t n_doubles, uint32_t n_rounds, int n_cu,
+                              hipStream_t s);
+
 // Launchers implemented in smc_plasma.hip.
 hipError_t launch_plasma_lines(const DevPlasma& p, int n_nlte_lines, hipStream_t s);
 hipError_t launch_plasma_update(const DevPlasma& p, hipStream_t s);

@@ -86,7 +86,7 @@ EXPORTS = ("smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_model_wor
            "smc_batch_autotune", "smc_graph_capture", "smc_graph_launch", "smc_graph_destroy",
            "smc_read_virtual_spectrum", "smc_plasma_workspace_bytes", "smc_plasma_load",
            "smc_plasma_update", "smc_plasma_read", "smc_plasma_free", "smc_graph_capture_plasma",
-           "smc_batch_run_static")
+           "smc_batch_run_static", "smc_measure_atomic_rate")
 
 
 class SmcError(RuntimeError):
@@ -129,6 +129,7 @@ def load_library(path: str = LIB_PATH):
                                 C.POINTER(smc_tune), C.c_uint32, vp]
     L.smc_batch_run_static.argtypes = [vp, C.POINTER(vp), C.POINTER(smc_iter_params), C.c_int,
                                        C.POINTER(smc_tune), C.c_uint32, vp]
+    L.smc_measure_atomic_rate.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_int, vp, _dp]
     L.smc_batch_read_timing.argtypes = [vp, _dp]
     L.smc_batch_autotune.argtypes = [vp, C.POINTER(vp), C.POINTER(smc_iter_params), C.c_int,
                                      C.POINTER(smc_tune), C.c_int, C.POINTER(smc_tune), _dp, vp]
@@ -628,3 +629,17 @@ class Plasma:
             self.free()
         except Exception:
             pass
+
+
+def measure_atomic_rate(table, n_rounds: int = 256, stream=None) -> float:
+    """FP64 atomic adds per second in the J_blue tally pattern, on a caller's
+    float64 CUDA tensor (overwritten); see smc_measure_atomic_rate."""
+    import torch
+    lib = load_library()
+    if table.dtype != torch.float64 or not table.is_cuda or not table.is_contiguous():
+        raise ValueError("table must be a contiguous float64 CUDA tensor")
+    n_cu = torch.cuda.get_device_properties(table.device).multi_processor_count
+    out = C.c_double()
+    _check(lib.smc_measure_atomic_rate(C.c_void_p(table.data_ptr()), table.numel(), int(n_rounds),
+                                       int(n_cu), _stream_ptr(stream), C.byref(out)))
+    return float(out.value)
