@@ -32,10 +32,11 @@ the library's HIP events on the launch stream) at its algorithmic bytes --
 radii and density), 96 B per packet (its state written and read once) --
 against the HBM peak; `traffic` is the measured HBM bytes per transport pass
 from the committed hardware-counter summary when it was taken on the current
-kernel source (else null).  Its `atomic` entry sets the pass's FP64 atomic
-adds (J_blue, J, nu-bar and spectrum tallies; counted by the same counter
-summary) per second against the device's rate for the tally pattern,
-measured in the same run.  The `batched` entry is the 64-model mix in one
+kernel source (else null).  Its `atomic` entry sets the pass's atomic
+requests at the L2 (J_blue, J, nu-bar and spectrum tallies; TCC_ATOMIC from
+the committed counter summary) per second against the request rate the
+device sustains in the two tally patterns: their FP64 add rates, measured in
+the same run, times the requests per add the calibration counters read.  The `batched` entry is the 64-model mix in one
 autotuned multi-model launch against 64 single-model launches (models/s).
 The CPU baseline times the FP64 oracle on a bounded packet sample of the
 same iterations: an equal share of --cpu-sample packets from every timed
@@ -44,10 +45,20 @@ on one host core and once split over --cpu-procs oracle processes on
 disjoint packet-id ranges (the host's CPU share); it reports the latter,
 with the single-core figure inside.
 
-    python bench.py --workload atomics   (the device's FP64 atomic-add rate)
+    python bench.py --workload atomics   (the device's FP64 atomic-add rates)
+    python bench.py --workload critical  (the longest history of the last of
+                                          --steps iterations, run alone)
     python bench.py --profile-summary DB [DB ...]
                                          (per-kernel counter summary of
                                           rocprofv3 --pmc databases)
+    python bench.py --traffic-summary OUT BENCH_FETCH_DB BENCH_WRITE_DB \
+                    COPY_FETCH_DB COPY_WRITE_DB BENCH_LINE [--commands ...]
+    python bench.py --counter-summary OUT BENCH_LINE ATOMICS_DB BENCH_DB... \
+                    [--commands ...]     (the committed summaries the
+                                          roofline's traffic and atomic
+                                          entries read)
+    python bench.py --trace-summary DB [BENCH_LINE]
+                                         (kernel-trace summary per pass)
 """
 import argparse
 import json
@@ -89,9 +100,19 @@ def parse():
                     help="skip the batched-vs-plain entry of the paper-scale line (profiling runs)")
     ap.add_argument("--profile-summary", nargs="+", metavar="DB",
                     help="print per-kernel summaries of rocprofv3 --pmc result databases")
+    ap.add_argument("--traffic-summary", nargs=6, metavar="PATH",
+                    help="write the HBM traffic summary: OUT BENCH_FETCH_DB BENCH_WRITE_DB "
+                         "COPY_FETCH_DB COPY_WRITE_DB BENCH_LINE")
+    ap.add_argument("--counter-summary", nargs="+", metavar="PATH",
+                    help="write the counter summary: OUT BENCH_LINE ATOMICS_DB BENCH_DB...")
+    ap.add_argument("--trace-summary", nargs="+", metavar="PATH",
+                    help="print the kernel-trace summary: DB [BENCH_LINE]")
+    ap.add_argument("--commands", nargs="*", help="commands recorded in a summary")
+    ap.add_argument("--atomic-rounds", type=int, default=256,
+                    help="rounds per lane of the atomics workload (counter summary)")
     ap.add_argument("--workload", default="paper-scale",
                     choices=["paper-scale", "batched", "served", "copy", "virtual",
-                             "macroatom", "plasma", "atomics"])
+                             "macroatom", "plasma", "atomics", "critical"])
     ap.add_argument("--n-virtual", type=int, default=3,
                     help="virtual packets per packet launch in the virtual mode")
     ap.add_argument("--nlte", action="store_true",
@@ -126,58 +147,278 @@ def measured_traffic():
 
 
 def measured_atomics():
-    """FP64 atomic adds per transport pass from the counter summary."""
+    """The pass's L2 atomic requests from the counter summary (per pass) and
+    the requests per FP64 atomic add of each calibration pattern."""
     summ = _current_summary(COUNTER_SUMMARY)
-    return summ.get("atomics_per_transport_pass") if summ else None
+    if not summ:
+        return None
+    return {"requests_per_pass": summ["per_pass"]["TCC_ATOMIC_sum"],
+            "requests_per_add": {k: v["TCC_ATOMIC_sum_per_add"]
+                                 for k, v in summ["atomic_calibration"].items()}}
+
+
+ATOMIC_PATTERNS = ("window", "scattered")
 
 
 def atomic_peak(n_rounds=256):
-    """The device's FP64 atomic-add rate in the tally pattern, on a table
-    the size of the paper-scale J_blue array (20 x 3e5 doubles)."""
+    """The device's FP64 atomic-add rate (adds/s) in the two tally patterns
+    (a wavefront's 64 consecutive doubles; a place per lane), on a table the
+    size of the paper-scale J_blue array (20 x 3e5 doubles)."""
     import torch
 
     from paper_1401_5469_amd import smc
 
     table = torch.zeros(20 * 300_000, dtype=torch.float64, device="cuda")
-    rate = smc.measure_atomic_rate(table, n_rounds)
+    rates = {p: smc.measure_atomic_rate(table, n_rounds, scattered=(p == "scattered"))
+             for p in ATOMIC_PATTERNS}
     del table
-    return rate
+    return rates
 
 
 def atomics(args):
-    """Print the device's FP64 atomic-add rate in the tally pattern."""
-    rates = [atomic_peak() for _ in range(3)]
-    print(json.dumps({"metric": "FP64 atomic adds per second (tally pattern)", "value": max(rates),
-                      "unit": "atomics/s", "runs": rates,
-                      "pattern": "64 consecutive doubles per wavefront at a pseudo-random place "
-                                 "of a 48 MB table, 8 workgroups of 256 per CU, 256 rounds"}),
+    """Print the device's FP64 atomic-add rates in the tally patterns."""
+    runs = [atomic_peak() for _ in range(3)]
+    best = {p: max(r[p] for r in runs) for p in ATOMIC_PATTERNS}
+    print(json.dumps({"metric": "FP64 atomic adds per second (tally patterns)",
+                      "value": best["window"], "unit": "atomics/s", "by_pattern": best,
+                      "runs": runs,
+                      "pattern": "window: 64 consecutive doubles per wavefront at a "
+                                 "pseudo-random place of a 48 MB table; scattered: a "
+                                 "pseudo-random double per lane; 8 workgroups of 256 per CU, "
+                                 "256 rounds, two launches each (the second timed)"}),
           flush=True)
+
+
+def _kernel_name(k):
+    k = k.replace("void ", "", 1).replace("smc::(anonymous namespace)::", "")
+    return k.replace("smc::", "").split("(")[0]
+
+
+def _pmc_dispatches(path):
+    """Dispatches of a rocprofv3 --pmc database in order:
+    [(kernel, grid size, duration ns, {counter: value})]."""
+    import sqlite3
+
+    con = sqlite3.connect(path)
+    rows = con.execute("select dispatch_id, kernel_name, grid_size, duration, counter_name, value "
+                       "from counters_collection order by dispatch_id").fetchall()
+    out, index = [], {}
+    for d, k, g, t, c, v in rows:
+        if d not in index:
+            index[d] = len(out)
+            out.append((_kernel_name(k), int(g), float(t), {}))
+        cs = out[index[d]][3]
+        cs[c] = cs.get(c, 0.0) + float(v)
+    return out
+
+
+PASS_KERNELS = ("transport_kernel", "long_prefix_kernel", "order_count_kernel",
+                "order_scan_kernel", "order_place_kernel", "long_kernel", "solo_kernel")
+
+
+def _transport_passes(disp, warmup, steps):
+    """The dispatches of the timed transport passes of a bench run: a pass
+    opens at transport_kernel and holds the hand-off kernels after it; the
+    first `warmup` passes are skipped, the next `steps` returned."""
+    passes, cur = [], None
+    for d in disp:
+        base = d[0].split("<")[0]
+        if base == "transport_kernel":
+            cur = [d]
+            passes.append(cur)
+        elif base in PASS_KERNELS and cur is not None:
+            cur.append(d)
+        else:
+            cur = None
+    sel = passes[warmup:warmup + steps]
+    if len(sel) != steps:
+        raise SystemExit(f"found {len(passes)} transport passes, need {warmup + steps}")
+    return sel
+
+
+def _source_sha():
+    import hashlib
+
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _bench_line(path):
+    with open(path) as f:
+        lines = [l for l in f.read().splitlines() if l.startswith("{")]
+    return json.loads(lines[-1])
+
+
+def _algorithmic_bytes(line):
+    """Algorithmic bytes per transport pass of a bench line (the byte model)."""
+    return (BYTES_PER_LINE_PASS * line["line_passes_per_s"] + BYTES_PER_SEGMENT *
+            line["segments_per_s"]) * line["ms_per_step"] * 1e-3 + \
+        BYTES_PER_PACKET * line["config"]["packets_per_iteration"]
+
+
+def traffic_summary(args):
+    """HBM bytes per transport pass from FETCH_SIZE and WRITE_SIZE runs of
+    the bench and of the 1 GiB device copy, which scales each counter to
+    bytes.  Arguments: OUT BENCH_FETCH_DB BENCH_WRITE_DB COPY_FETCH_DB
+    COPY_WRITE_DB BENCH_LINE (the bench's output of one of the runs)."""
+    out, bf, bw, cf, cw, bl = args.traffic_summary
+    n = 1 << 30
+    copies = {}
+    for name, db in (("FETCH_SIZE", cf), ("WRITE_SIZE", cw)):
+        d = _pmc_dispatches(db)[-5:]  # the five timed copies end the run
+        copies[name] = (sum(x[3][name] for x in d) / len(d), sorted({x[0] for x in d}))
+    fetch_scale = n / (copies["FETCH_SIZE"][0] * 1024.0)
+    write_scale = n / (copies["WRITE_SIZE"][0] * 1024.0)
+    fp = _transport_passes(_pmc_dispatches(bf), args.warmup, args.steps)
+    wp = _transport_passes(_pmc_dispatches(bw), args.warmup, args.steps)
+    per = []
+    for f, w in zip(fp, wp):
+        fk = sum(d[3]["FETCH_SIZE"] for d in f)
+        wk = sum(d[3]["WRITE_SIZE"] for d in w)
+        per.append(1024.0 * (fetch_scale * fk + write_scale * wk))
+    line = _bench_line(bl)
+    alg = _algorithmic_bytes(line)
+    summ = {
+        "what": "HBM bytes per transport pass (transport_kernel, order kernels and the kernel "
+                "of the handed-off histories) of the paper-scale scatter model, 1e6 packets "
+                f"per iteration, mean over the {args.steps} timed iterations of a bench run "
+                "(T_inner from 9000 K, carried on the device)",
+        "commands": args.commands or [],
+        "calibration": {"copy_bytes_read_and_written": n,
+                        "FETCH_SIZE_KiB_per_copy": copies["FETCH_SIZE"][0],
+                        "WRITE_SIZE_KiB_per_copy": copies["WRITE_SIZE"][0],
+                        "copy_kernels": copies["FETCH_SIZE"][1],
+                        "fetch_scale": fetch_scale, "write_scale": write_scale},
+        "kernel_source_sha256": _source_sha(),
+        "bytes_per_transport_pass": sum(per) / len(per),
+        "bytes_per_transport_pass_by_iteration": per,
+        "algorithmic_bytes_per_transport_pass": alg,
+        "traffic_over_algorithmic": sum(per) / len(per) / alg,
+    }
+    with open(out, "w") as f:
+        json.dump(summ, f, indent=1)
+    print(json.dumps(summ, indent=1))
+
+
+def counter_summary(args):
+    """Per-pass and per-kernel hardware counters of the transport pass, from
+    --pmc runs of the bench (any number of counter sets), with the atomic
+    calibration from a --pmc run of --workload atomics.  Arguments: OUT
+    BENCH_LINE ATOMICS_DB BENCH_DB [BENCH_DB ...]."""
+    out, bl, adb, *dbs = args.counter_summary
+    line = _bench_line(bl)
+    per_pass, per_kernel, dur = {}, {}, {}
+    for db in dbs:
+        passes = _transport_passes(_pmc_dispatches(db), args.warmup, args.steps)
+        for p in passes:
+            for k, g, t, cs in p:
+                fam = k.split("<")[0]
+                dur.setdefault(db, []).append(t)
+                for c, v in cs.items():
+                    per_pass[c] = per_pass.get(c, 0.0) + v / len(passes)
+                    kk = per_kernel.setdefault(fam, {})
+                    kk[c] = kk.get(c, 0.0) + v / len(passes)
+    segs = line["segments_per_s"] * line["ms_per_step"] * 1e-3
+    # atomic calibration: grid x rounds adds per dispatch of atomic_rate_kernel
+    cal = {}
+    for k, g, t, cs in _pmc_dispatches(adb):
+        if not k.startswith("atomic_rate_kernel"):
+            continue
+        pat = "scattered" if "<true>" in k else "window"
+        adds = g * args.atomic_rounds
+        e = cal.setdefault(pat, {"dispatches": 0, "adds": 0.0, "ns": 0.0, "counters": {}})
+        e["dispatches"] += 1
+        e["adds"] += adds
+        e["ns"] += t
+        for c, v in cs.items():
+            e["counters"][c] = e["counters"].get(c, 0.0) + v
+    calib = {}
+    for pat, e in cal.items():
+        calib[pat] = {"adds_per_dispatch": e["adds"] / e["dispatches"],
+                      "dispatches": e["dispatches"],
+                      "adds_per_s_under_counters": e["adds"] / (e["ns"] * 1e-9)}
+        for c, v in e["counters"].items():
+            calib[pat][c + "_per_add"] = v / e["adds"]
+    summ = {
+        "what": "hardware counters of the transport pass of the paper-scale scatter model "
+                f"(1e6 packets per iteration), mean per pass over the {args.steps} timed "
+                "iterations of a bench run, in total and per kernel; atomic counters of the "
+                "FP64 atomic-add calibration kernel per add",
+        "commands": args.commands or [],
+        "kernel_source_sha256": _source_sha(),
+        "segments_per_pass": segs,
+        "per_pass": per_pass,
+        "per_kernel": per_kernel,
+        "per_segment": {c: v / segs for c, v in per_pass.items()},
+        "atomic_calibration": calib,
+    }
+    with open(out, "w") as f:
+        json.dump(summ, f, indent=1)
+    print(json.dumps(summ, indent=1))
+
+
+def trace_summary(args):
+    """Kernel-trace summary of a rocprofv3 --kernel-trace --stats database:
+    the top_kernels table, then per transport pass the durations of
+    transport_kernel and of the kernel of the handed-off histories and the
+    span from the first's start to the last pass kernel's end (the time the
+    library's events bracket).  Arguments: DB [BENCH_LINE]."""
+    import sqlite3
+
+    db, *rest = args.trace_summary
+    con = sqlite3.connect(db)
+    print("name | calls | total_ms | average_ms | percent")
+    for name, n, tot, avg, pct in con.execute(
+            "select name, total_calls, total_duration, average, percentage from top_kernels"):
+        # this view holds microseconds, the kernels view nanoseconds
+        print(f"{name} | {n} | {tot * 1e-3:.3f} | {avg * 1e-3:.3f} | {pct:.2f}")
+    rows = con.execute("select name, start, end from kernels order by start").fetchall()
+    print("\nper transport pass (ms): transport_kernel | hand-off kernels | handed-off "
+          "histories kernel | span")
+    cur = None
+    passes = []
+    for name, t0, t1 in rows:
+        k = _kernel_name(name).split("<")[0]
+        if k == "transport_kernel":
+            cur = {"t0": t0, "t1": t1, "transport": t1 - t0, "order": 0, "long": 0, "kernel": ""}
+            passes.append(cur)
+        elif k in PASS_KERNELS and cur is not None:
+            cur["t1"] = t1
+            if k in ("long_kernel", "solo_kernel"):
+                cur["long"] += t1 - t0
+                cur["kernel"] = _kernel_name(name)
+            else:
+                cur["order"] += t1 - t0
+        else:
+            cur = None
+    for p in passes:
+        print(f"{p['transport'] * 1e-6:.3f} | {p['order'] * 1e-6:.3f} | "
+              f"{p['long'] * 1e-6:.3f} ({p['kernel']}) | {(p['t1'] - p['t0']) * 1e-6:.3f}")
+    if rest:
+        line = _bench_line(rest[0])
+        print("\nthe same run's bench line: transport_ms (library HIP events) = " +
+              ", ".join(f"{t:.3f}" for t in line["transport_ms"]))
+        print(f"interactions/s over the timed iterations: {line['value']:.4g}")
 
 
 def profile_summary(paths):
     """Per-kernel sums of the counters in rocprofv3 --pmc result databases,
     with the dispatch count and mean duration (one table per database)."""
-    import sqlite3
     from collections import defaultdict
 
     for path in paths:
-        con = sqlite3.connect(path)
-        rows = con.execute("select dispatch_id, kernel_name, counter_name, value, duration "
-                           "from counters_collection").fetchall()
         per = defaultdict(lambda: defaultdict(float))
-        disp = defaultdict(set)
-        dur = defaultdict(dict)
-        for d, k, c, v, t in rows:
-            name = k.split("(")[0].replace("smc::(anonymous namespace)::", "").replace("void ", "")
-            per[name][c] += v
-            disp[name].add(d)
-            dur[name][d] = t
+        n = defaultdict(int)
+        dur = defaultdict(float)
+        for k, g, t, cs in _pmc_dispatches(path):
+            n[k] += 1
+            dur[k] += t
+            for c, v in cs.items():
+                per[k][c] += v
         print(f"# {os.path.basename(os.path.dirname(path))}")
-        for name in sorted(per, key=lambda n: -sum(dur[n].values())):
-            n = len(disp[name])
-            mean_ms = sum(dur[name].values()) / n * 1e-6
+        for name in sorted(per, key=lambda k: -dur[k]):
             cs = "  ".join(f"{c}={v:.6g}" for c, v in sorted(per[name].items()))
-            print(f"{name} | dispatches {n} | mean {mean_ms:.3f} ms | {cs}")
+            print(f"{name} | dispatches {n[name]} | mean {dur[name] / n[name] * 1e-6:.3f} ms | {cs}")
 
 
 def copy_reference(args):
@@ -786,10 +1027,44 @@ def critical_path(ctx, w, flags, iteration, T_inner, pass_ms):
             "frac": a / pass_ms}
 
 
+def critical(args):
+    """The latency bound alone: the iterative sequence from T_inner = 9000 K
+    for --steps iterations, then the longest history of the last one run
+    alone (critical_path; for counter runs of the lone history)."""
+    import torch
+
+    from paper_1401_5469_amd import smc
+    from paper_1401_5469_amd import workloads as W
+
+    w = W.config2(n_packets=args.packets)
+    N = w.n_packets
+    flags = 0 if args.no_jblue else smc.F_JBLUE
+    ctx = smc.Context(0)
+    model = smc.Model(ctx, w.model, N, flags=flags)
+    for i in range(args.steps):
+        model.run_iteration(N, w.T_inner if i == 0 else 0.0, iteration=i,
+                            flags=flags | smc.F_TIMING, L_requested=w.L_requested,
+                            damping=w.damping)
+    ms = model.read_timing()
+    T = model.read_spectrum()["T_inner"]
+    model.free()
+    torch.cuda.synchronize()
+    out = critical_path(ctx, w, flags, args.steps - 1, T, ms)
+    print(json.dumps({"metric": "critical-path microseconds per segment",
+                      "value": out["us_per_segment_alone"], "unit": "us/segment",
+                      "higher_is_better": False, "critical_path": out}), flush=True)
+
+
 def main():
     args = parse()
     if args.profile_summary:
         return profile_summary(args.profile_summary)
+    if args.traffic_summary:
+        return traffic_summary(args)
+    if args.counter_summary:
+        return counter_summary(args)
+    if args.trace_summary:
+        return trace_summary(args)
     if args.cpu_worker:
         return cpu_worker(args)
     if args.gpus != 1:
@@ -815,6 +1090,8 @@ def main():
         return plasma(args)
     if args.workload == "atomics":
         return atomics(args)
+    if args.workload == "critical":
+        return critical(args)
 
     import numpy as np
     import torch
@@ -859,9 +1136,14 @@ def main():
     bytes_per_launch = (BYTES_PER_LINE_PASS * passes + BYTES_PER_SEGMENT * segs) / len(rec) + \
         BYTES_PER_PACKET * N
     achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9
-    atom_peak = atomic_peak()
-    atom_per_launch = measured_atomics()
-    atom_rate = atom_per_launch / (mean_ms * 1e-3) if atom_per_launch else None
+    add_rates = atomic_peak()
+    atom = measured_atomics()
+    if atom:
+        req_peaks = {p: add_rates[p] * atom["requests_per_add"][p] for p in ATOMIC_PATTERNS}
+        atom_peak = max(req_peaks.values())
+        atom_rate = atom["requests_per_pass"] / (mean_ms * 1e-3)
+    else:
+        req_peaks, atom_peak, atom_rate = None, None, None
 
     out = {
         "metric": "packet-interactions/sec",
@@ -893,12 +1175,16 @@ def main():
                                "group kernel of the handed-off histories",
                      "bytes_per_launch": bytes_per_launch,
                      "bytes_model": "16 B per line passed + 24 B per segment + 96 B per packet",
-                     "atomic": {"achieved": atom_rate, "peak": atom_peak, "unit": "atomics/s",
+                     "atomic": {"achieved": atom_rate, "peak": atom_peak,
+                                "unit": "L2 atomic requests/s",
                                 "frac": atom_rate / atom_peak if atom_rate else None,
-                                "atomics_per_launch": atom_per_launch,
-                                "peak_source": "bench.py --workload atomics pattern, this run",
-                                "count_source": "committed counter summary (null when the "
-                                                "kernel source has changed since)"}},
+                                "requests_per_launch": atom["requests_per_pass"] if atom else None,
+                                "peak_by_pattern": req_peaks,
+                                "fp64_adds_per_s_by_pattern": add_rates,
+                                "source": "TCC_ATOMIC per pass and per calibration add from "
+                                          "the committed counter summary (null when the "
+                                          "kernel source has changed since); add rates of "
+                                          "the two tally patterns measured in this run"}},
         "cpu_baseline": None,
     }
     out["pcie_inclusive"] = host_boundary(ctx, w, flags, N, inter, wall, args.steps)

@@ -248,16 +248,18 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
 int smc_batch_run_static(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* params,
                          int n_models, const smc_tune* tune, uint32_t flags, void* stream);
 
-/* Measurement: the device's throughput of FP64 atomic adds in the pattern the
- * J_blue tallies use (each wavefront adds to 64 consecutive doubles of a
- * table, at a new pseudo-random place each round).  `d_table` is caller-owned
- * device memory of n_doubles (>= 64) doubles, which the call overwrites;
- * 8 * n_cu workgroups of 256 lanes make n_rounds adds per lane; the rate of
- * the second of two launches goes to *atomics_per_s.  Synchronises `stream`.
- * Returns SMC_EINVAL for a null pointer, n_doubles < 64, n_rounds = 0 or
- * n_cu < 1, SMC_EDEVICE on a HIP error. */
-int smc_measure_atomic_rate(double* d_table, uint64_t n_doubles, uint32_t n_rounds, int n_cu,
-                            void* stream, double* atomics_per_s);
+/* Measurement: the device's throughput of FP64 atomic adds in the patterns the
+ * estimator tallies use: scattered = 0, each wavefront adds to 64 consecutive
+ * doubles of a table (a J_blue window), at a new pseudo-random place each
+ * round; scattered != 0, every lane adds at a pseudo-random place of its own
+ * (the lane-per-packet tallies).  `d_table` is caller-owned device memory of
+ * n_doubles (>= 64) doubles, which the call overwrites; 8 * n_cu workgroups of
+ * 256 lanes make n_rounds adds per lane; the rate of the second of two
+ * launches goes to *atomics_per_s.  Synchronises `stream`.  Returns
+ * SMC_EINVAL for a null pointer, n_doubles < 64, n_rounds = 0 or n_cu < 1,
+ * SMC_EDEVICE on a HIP error. */
+int smc_measure_atomic_rate(double* d_table, uint64_t n_doubles, uint32_t n_rounds, int scattered,
+                            int n_cu, void* stream, double* atomics_per_s);
 
 /* Duration in milliseconds of the transport kernels of the last timed batch
  * of this context.  Waits for them to end. */

@@ -756,8 +756,8 @@ int smc_batch_run(smc_ctx* ctx, smc_model* const* models, const smc_iter_params*
   return batch_launch(ctx, models, params, n_models, tune, flags, stream, nullptr, nullptr);
 }
 
-int smc_measure_atomic_rate(double* d_table, uint64_t n_doubles, uint32_t n_rounds, int n_cu,
-                            void* stream, double* atomics_per_s) {
+int smc_measure_atomic_rate(double* d_table, uint64_t n_doubles, uint32_t n_rounds, int scattered,
+                            int n_cu, void* stream, double* atomics_per_s) {
   if (!d_table || !atomics_per_s) return fail(SMC_EINVAL, "null table or output");
   if (n_doubles < 64 || n_rounds == 0 || n_cu < 1)
     return fail(SMC_EINVAL, "need n_doubles >= 64, n_rounds >= 1, n_cu >= 1");
@@ -766,9 +766,9 @@ int smc_measure_atomic_rate(double* d_table, uint64_t n_doubles, uint32_t n_roun
   HIP_TRY(hipEventCreate(&a), "hipEventCreate");
   hipError_t e = hipEventCreate(&b);
   // an untimed launch brings the table into the caches, then the timed one
-  if (e == hipSuccess) e = smc::launch_atomic_rate(d_table, n_doubles, n_rounds, n_cu, s);
+  if (e == hipSuccess) e = smc::launch_atomic_rate(d_table, n_doubles, n_rounds, scattered, n_cu, s);
   if (e == hipSuccess) e = hipEventRecord(a, s);
-  if (e == hipSuccess) e = smc::launch_atomic_rate(d_table, n_doubles, n_rounds, n_cu, s);
+  if (e == hipSuccess) e = smc::launch_atomic_rate(d_table, n_doubles, n_rounds, scattered, n_cu, s);
   if (e == hipSuccess) e = hipEventRecord(b, s);
   if (e == hipSuccess) e = hipEventSynchronize(b);
   float ms = 0.0f;

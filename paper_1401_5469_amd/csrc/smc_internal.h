@@ -257,10 +257,11 @@ struct DevPlasma {
 };
 
 // Launcher implemented in smc_measure.hip: 8 * n_cu workgroups of 256 lanes,
-// each wavefront adding 1.0 to 64 consecutive doubles of `table` at a new
-// pseudo-random place in each of n_rounds rounds.
-hipError_t launch_atomic_rate(double* table, uint64_t n_doubles, uint32_t n_rounds, int n_cu,
-                              hipStream_t s);
+// each lane adding 1.0 to a double of `table` at a new pseudo-random place in
+// each of n_rounds rounds (a wavefront's 64 consecutive doubles, or with
+// `scattered` a place per lane).
+hipError_t launch_atomic_rate(double* table, uint64_t n_doubles, uint32_t n_rounds, int scattered,
+                              int n_cu, hipStream_t s);
 
 // Launchers implemented in smc_plasma.hip.
 hipError_t launch_plasma_lines(const DevPlasma& p, int n_nlte_lines, hipStream_t s);

@@ -129,7 +129,7 @@ def load_library(path: str = LIB_PATH):
                                 C.POINTER(smc_tune), C.c_uint32, vp]
     L.smc_batch_run_static.argtypes = [vp, C.POINTER(vp), C.POINTER(smc_iter_params), C.c_int,
                                        C.POINTER(smc_tune), C.c_uint32, vp]
-    L.smc_measure_atomic_rate.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_int, vp, _dp]
+    L.smc_measure_atomic_rate.argtypes = [vp, C.c_uint64, C.c_uint32, C.c_int, C.c_int, vp, _dp]
     L.smc_batch_read_timing.argtypes = [vp, _dp]
     L.smc_batch_autotune.argtypes = [vp, C.POINTER(vp), C.POINTER(smc_iter_params), C.c_int,
                                      C.POINTER(smc_tune), C.c_int, C.POINTER(smc_tune), _dp, vp]
@@ -631,8 +631,9 @@ class Plasma:
             pass
 
 
-def measure_atomic_rate(table, n_rounds: int = 256, stream=None) -> float:
-    """FP64 atomic adds per second in the J_blue tally pattern, on a caller's
+def measure_atomic_rate(table, n_rounds: int = 256, scattered: bool = False, stream=None) -> float:
+    """FP64 atomic adds per second in a tally pattern (a wavefront's 64
+    consecutive doubles, or with `scattered` a place per lane), on a caller's
     float64 CUDA tensor (overwritten); see smc_measure_atomic_rate."""
     import torch
     lib = load_library()
@@ -641,5 +642,6 @@ def measure_atomic_rate(table, n_rounds: int = 256, stream=None) -> float:
     n_cu = torch.cuda.get_device_properties(table.device).multi_processor_count
     out = C.c_double()
     _check(lib.smc_measure_atomic_rate(C.c_void_p(table.data_ptr()), table.numel(), int(n_rounds),
-                                       int(n_cu), _stream_ptr(stream), C.byref(out)))
+                                       1 if scattered else 0, int(n_cu), _stream_ptr(stream),
+                                       C.byref(out)))
     return float(out.value)
