@@ -127,7 +127,11 @@ def _model_struct(model, keep: _Keep) -> _Model:
     tau = model.tau_sobolev if L else np.zeros((S, 1))
     m.tau_sobolev = _ptr(keep.arr(tau, np.float64), _dp)
     m.line_mode = int(model.line_mode)
-    if model.line_mode in (DOWNBRANCH, MACROATOM):
+    if model.line_mode in (DOWNBRANCH, MACROATOM) and model.em_cum is None:
+        # a model whose macro-atom tables are still to be derived from the
+        # plasma state: only its geometry may be used (the initial field)
+        m.line_mode = SCATTER
+    elif model.line_mode in (DOWNBRANCH, MACROATOM):
         m.line_upper = _ptr(keep.arr(model.line_upper, np.int32), _i32p)
         m.n_levels = int(model.n_levels)
         m.level_ptr = _ptr(keep.arr(model.level_ptr, np.int64), _i64p)
@@ -145,6 +149,9 @@ def run(model, T_inner, n_packets, iteration=0, packet_ids=None, max_segments=10
     """One oracle iteration.  Returns a dict of raw (un-normalised) tallies,
     counters, per-packet records and the optional event trace; with
     n_virtual > 0 also the v-packet spectrum (section 2.9) and its counts."""
+    if model.line_mode in (DOWNBRANCH, MACROATOM) and model.em_cum is None:
+        raise ValueError("the model's macro-atom tables are not given (oracle.macroatom "
+                         "derives them from a plasma state)")
     keep = _Keep()
     m = _model_struct(model, keep)
     it = _Iter()

@@ -194,11 +194,12 @@ def synthetic_atom(rng, n_ions=30, n_levels_per_ion=40, n_lines=20_000):
                 em_line=_contig(em_line, np.int32), em_cum=_contig(em_cum, np.float64))
 
 
-def _atom_levels(rng, n_ions, n_levels_per_ion, n_lines):
-    """Levels and lines of the synthetic atom (same draws as synthetic_atom):
-    level energies in frequency units, and per line (sorted by
-    non-increasing frequency) its frequency, global lower and upper level and
-    A_ul."""
+def _levels_and_lines(rng, n_ions, n_levels_per_ion, n_lines):
+    """Levels and lines of a synthetic atom: per ion, level energies (in
+    frequency units) 0 and sorted U(0, c/500A); n_lines distinct (ion,
+    lower < upper) pairs drawn without replacement.  Returns per line (sorted
+    by non-increasing frequency) its frequency and global lower and upper
+    level, and the number of levels."""
     nl = n_levels_per_ion
     e = np.zeros((n_ions, nl))
     for i in range(n_ions):
@@ -209,102 +210,42 @@ def _atom_levels(rng, n_ions, n_levels_per_ion, n_lines):
     lower = np.array([pairs[p][1] for p in pick])
     upper = np.array([pairs[p][2] for p in pick])
     nu = e[ion, upper] - e[ion, lower]
-    a_ul = 10.0 ** rng.uniform(5.0, 9.0, n_lines)
     order = np.argsort(-nu, kind="stable")
-    nu, ion, lower, upper, a_ul = nu[order], ion[order], lower[order], upper[order], a_ul[order]
-    return (e.reshape(-1), nu, (ion * nl + lower).astype(np.int32),
-            (ion * nl + upper).astype(np.int32), a_ul, n_ions * nl)
-
-
-def planck_nu(nu, T):
-    """Planck function B_nu(T) [erg s^-1 cm^-2 Hz^-1 sr^-1]."""
-    x = H * nu / (K_B * T)
-    return 2.0 * H * nu ** 3 / C_LIGHT ** 2 / np.expm1(x)
-
-
-def macroatom_tables(level_e, nu, lower, upper, a_ul, n_levels, tau, W, T_R):
-    """Macro-atom transition probabilities per shell in the form of Lucy
-    (2002, 2003) for bound-bound radiative processes only: from level i,
-    radiative deactivation in a downward line i->l with weight
-    A_il beta (e_i - e_l), an internal downward jump to l with weight
-    A_il beta e_l, an internal upward jump along an upward line i->u with
-    weight B_iu J_b beta e_i, where beta = (1 - exp(-tau_S)) / tau_S is the
-    Sobolev escape probability of the line in the shell, J_b = W B_nu(T_R)
-    the (dilute blackbody) radiation field at the line and B_iu = A_ui c^2 /
-    (2 h nu^3) (equal statistical weights).  This is the plasma side of the
-    method: here it only prepares the transport's input tables.
-
-    Returns level_ptr [n_levels+1], em_line [n_em] (line index for a
-    deactivation, -(j+1) for an internal jump to level j) and em_cum
-    [S, n_em] (cumulative within each level's row, last entry 1)."""
-    S, L = tau.shape
-    # rows: per level its downward lines (deactivation, then internal down)
-    # and its upward lines (internal up)
-    entries = [[] for _ in range(n_levels)]
-    for k in range(L):
-        entries[upper[k]].append(("emit", k))
-    for k in range(L):
-        entries[upper[k]].append(("down", k))
-    for k in range(L):
-        entries[lower[k]].append(("up", k))
-    level_ptr = np.zeros(n_levels + 1, dtype=np.int64)
-    level_ptr[1:] = np.cumsum([len(x) for x in entries])
-    n_em = int(level_ptr[-1])
-    em_line = np.zeros(n_em, dtype=np.int32)
-    kind = np.zeros(n_em, dtype=np.int8)
-    line_of = np.zeros(n_em, dtype=np.int64)
-    row_level = np.zeros(n_em, dtype=np.int64)
-    j = 0
-    for lev in range(n_levels):
-        for what, k in entries[lev]:
-            line_of[j] = k
-            row_level[j] = lev
-            if what == "emit":
-                em_line[j] = k
-                kind[j] = 0
-            elif what == "down":
-                em_line[j] = -(int(lower[k]) + 1)
-                kind[j] = 1
-            else:
-                em_line[j] = -(int(upper[k]) + 1)
-                kind[j] = 2
-            j += 1
-    with np.errstate(divide="ignore", invalid="ignore"):
-        beta = np.where(tau > 1e-12, -np.expm1(-tau) / tau, 1.0)  # [S, L]
-    b_lu = a_ul * C_LIGHT ** 2 / (2.0 * H * nu ** 3)
-    em_cum = np.zeros((S, n_em), dtype=np.float64)
-    e_i = level_e[row_level]
-    e_lo = level_e[lower[line_of]]
-    for s in range(S):
-        jb = W[s] * planck_nu(nu, T_R[s])
-        bt = beta[s, line_of]
-        wgt = np.where(kind == 0, a_ul[line_of] * bt * (e_i - e_lo),
-                       np.where(kind == 1, a_ul[line_of] * bt * e_lo,
-                                b_lu[line_of] * jb[line_of] * bt * e_i))
-        for lev in range(n_levels):
-            a, b = level_ptr[lev], level_ptr[lev + 1]
-            if b > a:
-                c = np.cumsum(wgt[a:b])
-                em_cum[s, a:b] = c / c[-1] if c[-1] > 0 else np.linspace(1.0 / (b - a), 1.0,
-                                                                          b - a)
-                em_cum[s, b - 1] = 1.0
-    return level_ptr, em_line, em_cum
+    nu, ion, lower, upper = nu[order], ion[order], lower[order], upper[order]
+    return nu, (ion * nl + lower).astype(np.int32), (ion * nl + upper).astype(np.int32), n_ions * nl
 
 
 def macroatom_model(seed: int = 0, n_shells: int = 30, n_ions: int = 30,
-                    n_levels_per_ion: int = 40, n_lines: int = 20_000, T_R: float = 10000.0):
-    """Macroatom mode: the synthetic atom of the downbranch workload with
-    Lucy-form transition probabilities per shell (W geometric at the shell
-    centre, T_R uniform), tau log-normal as the paper-scale model."""
+                    n_levels_per_ion: int = 40, n_lines: int = 20_000):
+    """Macroatom mode with caller-given tables, for the transport: a
+    synthetic atom (as the downbranch workload's) whose level rows hold
+    deactivations in the level's downward lines, jumps to their lower levels
+    and jumps to the upper levels of its upward lines, with probabilities
+    from weights U(0.05, 1) drawn per shell and entry (random tables: the
+    method's own tables come from the plasma state, macroatom_plasma_model).
+    tau log-normal as the paper-scale model."""
     rng = np.random.default_rng(seed)
     v, t, n_e = shells(n_shells, 10000.0, 25000.0, 13.0)
-    level_e, nu, lower, upper, a_ul, n_levels = _atom_levels(rng, n_ions, n_levels_per_ion,
-                                                              n_lines)
+    nu, lower, upper, n_levels = _levels_and_lines(rng, n_ions, n_levels_per_ion, n_lines)
     tau = tau_log_normal(rng, n_shells, n_lines)
-    q = v[0] / (0.5 * (v[:-1] + v[1:]))
-    W = 0.5 * (1.0 - np.sqrt(1.0 - q * q))
-    level_ptr, em_line, em_cum = macroatom_tables(level_e, nu, lower, upper, a_ul, n_levels, tau,
-                                                  W, np.full(n_shells, T_R))
+    rows = [[] for _ in range(n_levels)]
+    for k in range(n_lines):
+        rows[upper[k]].append(k)
+    for k in range(n_lines):
+        rows[upper[k]].append(-(int(lower[k]) + 1))
+    for k in range(n_lines):
+        rows[lower[k]].append(-(int(upper[k]) + 1))
+    level_ptr = np.zeros(n_levels + 1, dtype=np.int64)
+    level_ptr[1:] = np.cumsum([len(r) for r in rows])
+    em_line = np.array([x for r in rows for x in r], dtype=np.int32)
+    w = rng.uniform(0.05, 1.0, (n_shells, em_line.shape[0]))
+    em_cum = np.zeros_like(w)
+    for lev in range(n_levels):
+        a, b = level_ptr[lev], level_ptr[lev + 1]
+        if b > a:
+            c = np.cumsum(w[:, a:b], axis=1)
+            em_cum[:, a:b] = c / c[:, -1:]
+            em_cum[:, b - 1] = 1.0
     return Model(v_bounds=v, t_exp=t, n_e=n_e, line_nu=_contig(nu, np.float64),
                  tau_sobolev=tau, line_mode=MACROATOM, line_upper=_contig(upper, np.int32),
                  n_levels=int(n_levels), level_ptr=_contig(level_ptr, np.int64),
@@ -312,11 +253,16 @@ def macroatom_model(seed: int = 0, n_shells: int = 30, n_ions: int = 30,
                  seed=seed)
 
 
-def config_macroatom(seed: int = 0, n_packets: int = 500_000) -> Workload:
-    """Macroatom mode at the size of the downbranch workload: 30 shells,
-    30 ions x 40 levels, 2e4 lines, T_i = 9000 K."""
-    return Workload("macroatom-30shell-20kline", macroatom_model(seed), T_inner=9000.0,
-                    n_packets=n_packets, n_iterations=1)
+def config_macroatom(seed: int = 0, n_packets: int = 500_000) -> tuple:
+    """Macroatom mode with tables from the plasma state, at the size of the
+    downbranch workload: 30 shells over 10000-25000 km/s at 13 d, 2e4 lines
+    of 8 elements x 5 stages x 40 levels, T_i = 9000 K.  Returns the
+    workload and its plasma description."""
+    model, spec = macroatom_plasma_model(seed, n_shells=30, n_levels_per_ion=40,
+                                         n_lines=20_000)
+    w = Workload("macroatom-30shell-20kline", model, T_inner=9000.0, n_packets=n_packets,
+                 n_iterations=1)
+    return w, spec
 
 
 def config3(seed: int = 0, n_packets: int = 500_000, n_lines: int = 20_000,
@@ -533,22 +479,38 @@ def element_densities(rho, n_elements: int):
 def plasma_model(seed: int = 0, n_shells: int = 20, n_elements: int = 8, n_stages: int = 5,
                  n_levels_per_ion: int = 60, n_lines: int = 20_000,
                  v_lo: float = 10000.0, v_hi: float = 25000.0, t_exp_days: float = 13.0,
-                 rho_inner: float = 3.0e-14, nlte_ions=(), n_levels_nlte: int = 40):
-    """Scatter-mode model whose Sobolev depths and electron densities come
-    from the plasma update: shells as config 2 (rho ~ v^-7), equal mass
-    fractions of the synthetic elements.  tau_sobolev and n_e start at zero
-    and are filled by the plasma state of the initial radiation field."""
+                 rho_inner: float = 3.0e-14, nlte_ions=(), n_levels_nlte: int = 40,
+                 line_mode: int = SCATTER):
+    """Model whose Sobolev depths and electron densities come from the
+    plasma update: shells as config 2 (rho ~ v^-7), equal mass fractions of
+    the synthetic elements.  tau_sobolev and n_e start at zero and are
+    filled by the plasma state of the initial radiation field.  Scatter mode,
+    or with line_mode = MACROATOM the macro atom of the plasma's atom with
+    no tables (the plasma update derives them)."""
     rng = np.random.default_rng(seed)
     v = np.linspace(v_lo * KM, v_hi * KM, n_shells + 1)
     v_mid = 0.5 * (v[:-1] + v[1:])
     rho = rho_inner * (v_mid / v_mid[0]) ** -7.0
     atom, nu = synthetic_plasma_atom(rng, n_elements, n_stages, n_levels_per_ion, n_lines,
                                      nlte_ions=nlte_ions, n_levels_nlte=n_levels_nlte)
+    macro = line_mode == MACROATOM
     model = Model(v_bounds=_contig(v, np.float64), t_exp=t_exp_days * DAY,
                   n_e=np.zeros(n_shells), line_nu=nu,
-                  tau_sobolev=np.zeros((n_shells, n_lines)), seed=seed)
+                  tau_sobolev=np.zeros((n_shells, n_lines)), seed=seed,
+                  line_mode=MACROATOM if macro else SCATTER,
+                  line_upper=atom.line_upper if macro else None,
+                  n_levels=atom.n_levels if macro else 0)
     return model, PlasmaSpec(atom=atom, number_density=element_densities(rho, n_elements),
                              nlte_ions=tuple(int(i) for i in nlte_ions))
+
+
+def macroatom_plasma_model(seed: int = 0, n_shells: int = 20, n_elements: int = 8,
+                           n_stages: int = 5, n_levels_per_ion: int = 60,
+                           n_lines: int = 20_000, **kw):
+    """plasma_model in macroatom mode: tables derived from the plasma state."""
+    return plasma_model(seed, n_shells=n_shells, n_elements=n_elements, n_stages=n_stages,
+                        n_levels_per_ion=n_levels_per_ion, n_lines=n_lines,
+                        line_mode=MACROATOM, **kw)
 
 
 def config_plasma(seed: int = 0, n_packets: int = 1_000_000, n_lines: int = 300_000,

@@ -1,7 +1,9 @@
-"""Macroatom line mode (section 2.5, Table 1) on the GPU against the oracle:
-packet histories, estimators and spectrum, in both transport kernels and in
-a multi-model launch; the degenerate tables (no internal jumps: downbranch;
-no deactivation: CAPPED) behave as in the oracle."""
+"""Macroatom line mode (section 2.5, Table 1) on the GPU against the oracle,
+with caller-given transition tables: packet histories, estimators and
+spectrum, in both transport kernels and in a multi-model launch; the
+degenerate tables (no internal jumps: downbranch; no deactivation: CAPPED)
+behave as in the oracle.  Tables derived from the plasma state are tested in
+test_gpu_macroatom_plasma.py."""
 import numpy as np
 import pytest
 
@@ -56,10 +58,11 @@ def test_macroatom_small_model(ctx, tune):
 
 
 def test_macroatom_30shell_20kline_sample(ctx):
-    w = W.config_macroatom()
-    ids = np.sort(np.random.default_rng(9).choice(w.n_packets, 3000, replace=False)).astype(
-        np.uint64)
-    _compare(ctx, w.model, w.n_packets, w.T_inner, ids=ids)
+    # caller-given tables at the size of the macroatom workload
+    model = W.macroatom_model(seed=0)
+    N = 500_000
+    ids = np.sort(np.random.default_rng(9).choice(N, 3000, replace=False)).astype(np.uint64)
+    _compare(ctx, model, N, 9000.0, ids=ids)
 
 
 def test_macroatom_without_internal_jumps_is_downbranch(ctx):

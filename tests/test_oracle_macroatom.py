@@ -9,9 +9,9 @@ mathematics and the paper fix:
   history for history (Table 1: downbranch is the macro atom with all
   internal probabilities zero);
 * the tables of the shell where the interaction happens are used;
-* a macro atom that never deactivates ends its packet as CAPPED;
-* the input builder's Lucy-form weights in simple cases.
-None of these tests needs a GPU.
+* a macro atom that never deactivates ends its packet as CAPPED.
+The oracle's tables from the plasma state (oracle/macroatom.py) are pinned
+in test_oracle_macroatom_tables.py.  None of these tests needs a GPU.
 """
 import numpy as np
 from scipy import stats
@@ -152,36 +152,6 @@ def test_macro_atom_that_never_deactivates_caps_its_packet():
     assert c["line_events"] == 0
     assert np.all(p["n_line"][hit] == 0)
     assert c["escaped"] + c["reabsorbed"] + c["capped"] == 4000
-
-
-def test_lucy_weights_of_the_input_builder():
-    # levels 0 < 1 < 2 of one ion; lines 2->1, 2->0, 1->0 (decreasing nu)
-    e = np.array([0.0, 3.0e14, 7.0e14])
-    nu = np.array([7.0e14, 4.0e14, 3.0e14])
-    lower = np.array([0, 1, 0], dtype=np.int32)
-    upper = np.array([2, 2, 1], dtype=np.int32)
-    a_ul = np.array([1e8, 3e8, 5e7])
-    tau = np.array([[0.0, 2.0, 50.0]])
-    level_ptr, em_line, em_cum = W.macroatom_tables(e, nu, lower, upper, a_ul, 3, tau,
-                                                    np.array([0.3]), np.array([9000.0]))
-    beta = np.array([1.0, -np.expm1(-2.0) / 2.0, -np.expm1(-50.0) / 50.0])
-    # level 2: emission 2->1 (line 1), 2->0 (line 0), internal 2->1, 2->0 (weight 0)
-    a, b = level_ptr[2], level_ptr[3]
-    p = np.diff(np.concatenate([[0.0], em_cum[0, a:b]]))
-    w = np.array([a_ul[0] * beta[0] * (e[2] - e[0]), a_ul[1] * beta[1] * (e[2] - e[1]),
-                  a_ul[0] * beta[0] * e[0], a_ul[1] * beta[1] * e[1]])
-    assert list(em_line[a:b]) == [0, 1, -1, -2]
-    np.testing.assert_allclose(p, w / w.sum(), rtol=1e-12, atol=1e-15)
-    # level 1: emission 1->0, internal 1->0 (weight 0), internal up 1->2
-    a, b = level_ptr[1], level_ptr[2]
-    assert list(em_line[a:b]) == [2, -1, -3]
-    hnu3 = 2.0 * 6.62607015e-27 * nu[1] ** 3 / C_LIGHT ** 2
-    jb = 0.3 * hnu3 / np.expm1(6.62607015e-27 * nu[1] / (1.380649e-16 * 9000.0))
-    b_lu = a_ul[1] * C_LIGHT ** 2 / (2.0 * 6.62607015e-27 * nu[1] ** 3)
-    w = np.array([a_ul[2] * beta[2] * e[1], 0.0, b_lu * jb * beta[1] * e[1]])
-    p = np.diff(np.concatenate([[0.0], em_cum[0, a:b]]))
-    np.testing.assert_allclose(p, w / w.sum(), rtol=1e-12, atol=1e-15)
-    assert np.all(em_cum[:, level_ptr[1:] - 1] == 1.0)
 
 
 def test_macro_atom_draw_schedule():
