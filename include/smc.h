@@ -90,7 +90,12 @@ typedef struct {
    * deactivates by emission in that line, em_line = -(j+1) jumps to level j
    * (which then draws from its own row), and em_cum holds one probability
    * set per shell (shell-major).  A macro atom that makes 100000 internal
-   * jumps without deactivating ends its packet as CAPPED. */
+   * jumps without deactivating ends its packet as CAPPED.
+   * Macroatom with level_ptr, em_line and em_cum all NULL (and n_em = 0):
+   * the tables are derived on the device from the plasma state (section
+   * 2.5 with 2.3): smc_plasma_load lays out the rows from the atom's lines
+   * and every smc_plasma_update recomputes em_cum (see the plasma section);
+   * iterations are refused until the first update. */
   const int32_t* line_upper; /* [L] in [0, n_levels) */
   int32_t n_levels;
   const int64_t* level_ptr;  /* [n_levels+1] row offsets into em_line / em_cum */
@@ -171,7 +176,10 @@ int smc_model_workspace_bytes(const smc_model_desc* desc, uint64_t n_packets_max
                               uint32_t flags, uint64_t* bytes);
 
 /* Validate the description, copy its arrays into the caller's device
- * workspace (`ws_bytes` bytes at `d_workspace`, 256-byte aligned) and derive
+ * workspace (`ws_bytes` bytes at `d_workspace`, 256-byte aligned, device
+ * memory of the context's device from hipMalloc: coarse-grained, since the
+ * tallies are FP64 atomic adds; host and managed memory are refused with
+ * SMC_EINVAL, and fine-grained memory must not be passed) and derive
  * the shell geometry (radii r = v t_exp and volumes) on the device
  * (section 2.1).  Synchronises `stream` before returning, so the host arrays
  * may be released afterwards.  The radiation field starts at T_R = 10^4 K and
@@ -344,8 +352,22 @@ int smc_read_timing(smc_model* model, double* transport_ms);
  * decomposition with partial pivoting, one workgroup per (ion, shell).
  * Populations below zero from rounding are stored as 0; a singular system
  * leaves that ion's populations from step 4 and is counted.
- * The model's line-interaction tables (downbranch, macroatom) are not
- * changed.  Calls on a plasma and on its model must not overlap.
+ * Macro-atom tables (a macroatom model loaded without tables): after step 5
+ * the update recomputes the model's em_cum for every shell from the new
+ * tau_S, with the macro atom of Lucy (2002, 2003) for bound-bound radiative
+ * transitions.  A line's rates are R_ul = beta (A_ul + B_ul J_b) per
+ * upper-level atom and R_lu = beta B_lu J_b per lower-level atom, beta from
+ * the new tau_S, A and B from f, J_b = W B_nu(T_R) of the update's field or,
+ * with SMC_JB_DETAILED, the model's J_blue estimator.  From level i (energy
+ * e_i above its ion's ground state) the weights are R_il (e_i - e_l) for
+ * deactivation in a line i -> l, R_il e_l for an internal jump down to l and
+ * R_iu e_i for a jump up along i -> u.  Row i (laid out by smc_plasma_load)
+ * holds the lines with upper level i as deactivations (in line order), the
+ * same lines as jumps down, then the lines with lower level i as jumps up;
+ * its cumulative sums are divided by the row's total (equal steps when the
+ * total is 0) and its last entry is 1.  Downbranch tables and caller-given
+ * macroatom tables are never changed.  Calls on a plasma and on its model
+ * must not overlap.
  * ------------------------------------------------------------------------- */
 #define SMC_ION_LTE 0        /* Saha ionization balance at T_R */
 #define SMC_ION_NEBULAR 1    /* modified nebular approximation */
@@ -401,19 +423,24 @@ typedef struct {
   const double* W;     /* host [S] dilution factors > 0, or NULL */
   int32_t nlte;        /* 1: statistical equilibrium for the description's NLTE ions;
                           0: they follow `excitation` like every other ion */
-  int32_t jblue_mode;  /* SMC_JB_DILUTE_BLACKBODY or SMC_JB_DETAILED (NLTE only; detailed
-                          needs a model loaded with SMC_F_JBLUE whose last iteration, if
-                          any, tallied J_blue) */
+  int32_t jblue_mode;  /* SMC_JB_DILUTE_BLACKBODY or SMC_JB_DETAILED: J_b of the NLTE rates
+                          and of derived macro-atom tables (detailed needs a model loaded
+                          with SMC_F_JBLUE whose last iteration, if any, tallied J_blue) */
 } smc_plasma_params;
 
 /* Device workspace of a plasma object for a model of n_shells shells and
- * n_lines lines.  Writes *bytes. */
+ * n_lines lines (including 47 bytes per line for derived macro-atom tables).
+ * Writes *bytes. */
 int smc_plasma_workspace_bytes(const smc_plasma_desc* desc, int32_t n_shells, int64_t n_lines,
                                uint64_t* bytes);
 /* Validate the description against the model, copy it into the caller's
- * device workspace (256-byte aligned, borrowed until smc_plasma_free) and
- * derive the per-line constants on the device.  The model must outlive the
- * plasma object.  Synchronises `stream`; changes nothing in the model. */
+ * device workspace (256-byte aligned device memory from hipMalloc, as for
+ * smc_model_load; borrowed until smc_plasma_free) and derive the per-line
+ * constants on the device.  The model must outlive the plasma object.  For a
+ * macroatom model loaded without tables, the atom's n_levels and line_upper
+ * must be the model's, and the call writes the model's rows (level_ptr,
+ * em_line); otherwise it changes nothing in the model.  Synchronises
+ * `stream`. */
 int smc_plasma_load(smc_model* model, const smc_plasma_desc* desc, void* d_workspace,
                     uint64_t ws_bytes, void* stream, smc_plasma** out);
 /* Enqueue steps 1-5 on `stream`, overwriting the model's tau_sobolev [S*L]
@@ -429,6 +456,14 @@ int smc_plasma_read(smc_plasma* plasma, double* n_e, double* ion_density, double
                     double* level_pop, double* tau_sobolev, uint64_t* counts, void* stream);
 /* Release the handle; never frees the caller's workspace. */
 int smc_plasma_free(smc_plasma* plasma);
+
+/* Copy a downbranch or macroatom model's tables to host buffers (any may be
+ * NULL): level_ptr [n_levels+1], em_line [n_em] and em_cum ([n_em], or
+ * [S*n_em] shell-major in macroatom mode), where n_em = 3 L for derived
+ * tables.  SMC_EINVAL for a scatter-mode model, or derived tables before
+ * the first plasma update.  Synchronises `stream`. */
+int smc_model_read_macroatom(smc_model* model, int64_t* level_ptr, int32_t* em_line,
+                             double* em_cum, void* stream);
 
 /* A captured sequence as smc_graph_capture in which every iteration of model
  * k is followed by the plasma update of plasmas[k] (NULL: none; the plasma

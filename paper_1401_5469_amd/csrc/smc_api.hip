@@ -54,6 +54,9 @@ struct smc_model {
   hipEvent_t ev_start, ev_stop;  // created on the first timed iteration
   bool timed;                    // the last iteration recorded ev_start/ev_stop
   smc_tune tune;
+  int32_t n_levels;     // macro-atom levels (0 in scatter mode)
+  bool derived_tables;  // macroatom rows laid out by a plasma object, em_cum from its updates
+  bool tables_ready;    // false until the first plasma update has derived them
 };
 
 // A plasma object bound to a model (see smc_plasma_load).
@@ -201,6 +204,10 @@ smc::Shape shape_of(const smc_ctx* c, const smc_tune& t, bool multi, uint64_t n_
 // validate one iteration's parameters against its model; fill the device view
 int make_iter(const smc_model* m, const smc_iter_params* p, uint32_t budget, smc::DevIter* it) {
   if (!p) return fail(SMC_EINVAL, "null parameters");
+  if (m->derived_tables && !m->tables_ready)
+    return fail(SMC_EINVAL,
+                "the macro-atom tables are derived from the plasma state: load a plasma object "
+                "and run smc_plasma_update before the first iteration");
   if (p->n_packets == 0) return fail(SMC_EINVAL, "n_packets must be >= 1");
   if (p->flags & ~(SMC_F_JBLUE | SMC_F_PACKETS | SMC_F_TIMING))
     return fail(SMC_EINVAL, "unknown flags");
@@ -245,9 +252,41 @@ constexpr int kMaxShells = 4096;
 
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+// A macroatom model loaded without tables takes them from a plasma object:
+// three entries per line (a deactivation and an internal jump down in the
+// upper level's row, a jump up in the lower level's row).
+bool derived_macroatom(const smc_model_desc* d) {
+  return d->line_mode == SMC_MACROATOM && !d->level_ptr && !d->em_line && !d->em_cum;
+}
+
+int64_t em_entries(const smc_model_desc* d) {
+  return derived_macroatom(d) ? 3 * d->n_lines : d->n_em;
+}
+
 uint64_t em_cum_entries(const smc_model_desc* d) {
-  return d->line_mode == SMC_MACROATOM ? (uint64_t)d->n_shells * (uint64_t)d->n_em
+  return d->line_mode == SMC_MACROATOM ? (uint64_t)d->n_shells * (uint64_t)em_entries(d)
                                        : (uint64_t)d->n_em;
+}
+
+// A workspace must be device memory of the context's device from hipMalloc
+// (coarse-grained): the tallies are FP64 atomic adds, which host and managed
+// memory do not guarantee.
+int check_workspace(const void* ptr, int device) {
+  hipPointerAttribute_t at;
+  memset(&at, 0, sizeof at);
+  const hipError_t e = hipPointerGetAttributes(&at, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SMC_EINVAL, "the workspace is not memory the HIP runtime knows (%s)",
+                hipGetErrorString(e));
+  }
+  if (at.type != hipMemoryTypeDevice || at.isManaged)
+    return fail(SMC_EINVAL, "the workspace must be device memory from hipMalloc, not host or "
+                            "managed memory");
+  if (at.device != device)
+    return fail(SMC_EINVAL, "the workspace is memory of device %d, the context's is %d",
+                at.device, device);
+  return SMC_OK;
 }
 
 int validate(const smc_model_desc* d) {
@@ -295,7 +334,15 @@ int validate(const smc_model_desc* d) {
   if (d->line_mode != SMC_SCATTER && d->line_mode != SMC_DOWNBRANCH &&
       d->line_mode != SMC_MACROATOM)
     return fail(SMC_EINVAL, "unknown line_mode %d", d->line_mode);
-  if (d->line_mode != SMC_SCATTER && d->n_lines > 0) {
+  if (derived_macroatom(d) && d->n_lines > 0) {
+    if (!d->line_upper || d->n_levels < 1)
+      return fail(SMC_EINVAL, "a macroatom model with derived tables needs line_upper and "
+                              "n_levels >= 1");
+    if (d->n_em != 0) return fail(SMC_EINVAL, "n_em must be 0 when the tables are derived");
+    for (int64_t k = 0; k < d->n_lines; ++k)
+      if (d->line_upper[k] < 0 || d->line_upper[k] >= d->n_levels)
+        return fail(SMC_EINVAL, "line_upper[%lld] out of range", (long long)k);
+  } else if (d->line_mode != SMC_SCATTER && d->n_lines > 0) {
     const bool macro = d->line_mode == SMC_MACROATOM;
     if (!d->line_upper || !d->level_ptr || !d->em_line || !d->em_cum || d->n_levels < 1)
       return fail(SMC_EINVAL, "macro-atom modes need line_upper, level_ptr, em_line, em_cum");
@@ -359,7 +406,7 @@ smc::Layout layout_of(const smc_model_desc* d, uint64_t n_packets_max, uint32_t 
   if (d->line_mode != SMC_SCATTER) {
     l.line_upper = take(L * 4);
     l.level_ptr = take(((uint64_t)d->n_levels + 1) * 8);
-    l.em_line = take((uint64_t)d->n_em * 4);
+    l.em_line = take((uint64_t)em_entries(d) * 4);
     l.em_cum = take(em_cum_entries(d) * 8);
   }
   l.raw = take((2 * S + NB) * 8);
@@ -407,7 +454,8 @@ int plasma_args(const smc_plasma* p, const smc_plasma_params* pp, bool after_ite
     return fail(SMC_EINVAL, "unknown J_b mode %d", pp->jblue_mode);
   const smc_model* m = p->model;
   const bool detailed = pp->nlte && p->n_nlte > 0 && pp->jblue_mode == SMC_JB_DETAILED;
-  if (detailed && !m->dev.jblue)
+  const bool macro_detailed = m->derived_tables && pp->jblue_mode == SMC_JB_DETAILED;
+  if ((detailed || macro_detailed) && !m->dev.jblue)
     return fail(SMC_EINVAL, "detailed J_b needs a model loaded with SMC_F_JBLUE");
   *d = p->dev;
   d->ionization = pp->ionization;
@@ -415,6 +463,8 @@ int plasma_args(const smc_plasma* p, const smc_plasma_params* pp, bool after_ite
   d->delta = pp->delta;
   d->n_nlte = pp->nlte ? p->n_nlte : 0;
   d->jb_detailed = detailed && after_iteration ? 1 : 0;  // before any iteration: W B_nu(T_R)
+  d->macro = m->derived_tables ? 1 : 0;
+  d->macro_detailed = macro_detailed && after_iteration ? 1 : 0;
   d->jblue = m->dev.jblue;
   const size_t S = (size_t)p->dev.S;
   d->T_R = m->dev.out_shell + 2 * S;
@@ -521,6 +571,7 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
     return fail(SMC_ENOMEM, "workspace of %llu bytes is smaller than the %llu needed",
                 (unsigned long long)ws_bytes, (unsigned long long)lay.total);
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  if ((rc = check_workspace(d_workspace, ctx->device))) return rc;
   hipStream_t s = (hipStream_t)stream;
   uint8_t* base = (uint8_t*)d_workspace;
   const uint64_t S = (uint64_t)d->n_shells, L = (uint64_t)d->n_lines;
@@ -538,9 +589,11 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
                              hipMemcpyHostToDevice, s),
             "upload tau_sobolev");
   }
-  if (d->line_mode != SMC_SCATTER && L > 0) {
+  const bool derived = derived_macroatom(d) && L > 0;
+  if (d->line_mode != SMC_SCATTER && L > 0)
     HIP_TRY(hipMemcpyAsync(base + lay.line_upper, d->line_upper, L * 4, hipMemcpyHostToDevice, s),
             "upload line_upper");
+  if (d->line_mode != SMC_SCATTER && L > 0 && !derived) {
     HIP_TRY(hipMemcpyAsync(base + lay.level_ptr, d->level_ptr, ((uint64_t)d->n_levels + 1) * 8,
                            hipMemcpyHostToDevice, s),
             "upload level_ptr");
@@ -567,7 +620,9 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
   dm.Lp = (int32_t)((d->n_lines + 3) / 4 * 4);
   dm.n_bins = d->n_bins;
   dm.mode = d->line_mode;
-  dm.n_em = d->line_mode != SMC_SCATTER ? d->n_em : 0;
+  dm.n_em = d->line_mode != SMC_SCATTER ? em_entries(d) : 0;
+  m->n_levels = d->line_mode != SMC_SCATTER ? d->n_levels : 0;
+  m->derived_tables = derived;
   dm.t_exp = d->t_exp;
   dm.ct = 2.99792458e10 * d->t_exp;
   dm.nu_min = d->nu_min;
@@ -1375,6 +1430,9 @@ smc::PlasmaLayout plasma_layout_of(const smc_plasma_desc* d, int32_t S, int64_t 
   l.nlte_lev_ptr = take(NN * (smc::kNlteMaxLevels + 1) * 4);
   l.nlte_ent = take(2 * n_nlte_lines * 4);
   l.line_upsilon = take(NN ? LL * 8 : 0);
+  l.macro_lines = take(LL * sizeof(smc::MacroLine));
+  l.em_via = take(3 * LL * 4);
+  l.em_kind = take(3 * LL);
   l.total = off;
   return l;
 }
@@ -1414,9 +1472,70 @@ int smc_plasma_load(smc_model* model, const smc_plasma_desc* d, void* d_workspac
     return fail(SMC_ENOMEM, "workspace of %llu bytes is smaller than the %llu needed",
                 (unsigned long long)ws_bytes, (unsigned long long)lay.total);
   HIP_TRY(hipSetDevice(model->ctx->device), "hipSetDevice");
+  if ((rc = check_workspace(d_workspace, model->ctx->device))) return rc;
   hipStream_t s = (hipStream_t)stream;
   uint8_t* base = (uint8_t*)d_workspace;
   const size_t E = (size_t)d->n_elements, NI = (size_t)d->n_ions, NL = (size_t)d->n_levels;
+
+  // A macroatom model loaded without tables: its rows follow this atom's
+  // lines.  Row i holds the lines with upper level i as deactivations (line
+  // order), the same lines as internal jumps down, then the lines with lower
+  // level i as internal jumps up; em_line is the line of a deactivation and
+  // -(j+1) for a jump to level j.
+  std::vector<int64_t> ma_ptr;
+  std::vector<int32_t> ma_line, ma_via;
+  std::vector<uint8_t> ma_kind;
+  if (model->derived_tables) {
+    if (model->n_levels != d->n_levels)
+      return fail(SMC_EINVAL, "the model has %d macro-atom levels, the atom %d", model->n_levels,
+                  d->n_levels);
+    std::vector<int32_t> up((size_t)L);
+    HIP_TRY(hipMemcpyAsync(up.data(), model->base + model->lay.line_upper, (size_t)L * 4,
+                           hipMemcpyDeviceToHost, s),
+            "read line_upper");
+    HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+    for (int64_t k = 0; k < L; ++k)
+      if (up[(size_t)k] != d->line_upper[k])
+        return fail(SMC_EINVAL, "the model's line_upper[%lld] = %d is not the atom's %d",
+                    (long long)k, up[(size_t)k], d->line_upper[k]);
+    std::vector<int64_t> n_down(NL, 0), n_up(NL, 0);
+    for (int64_t k = 0; k < L; ++k) {
+      ++n_down[(size_t)d->line_upper[k]];
+      ++n_up[(size_t)d->line_lower[k]];
+    }
+    ma_ptr.assign(NL + 1, 0);
+    for (size_t i = 0; i < NL; ++i) ma_ptr[i + 1] = ma_ptr[i] + 2 * n_down[i] + n_up[i];
+    std::vector<int64_t> c_emit(NL), c_down(NL), c_up(NL);
+    for (size_t i = 0; i < NL; ++i) {
+      c_emit[i] = ma_ptr[i];
+      c_down[i] = ma_ptr[i] + n_down[i];
+      c_up[i] = ma_ptr[i] + 2 * n_down[i];
+    }
+    ma_line.resize((size_t)(3 * L));
+    ma_via.resize((size_t)(3 * L));
+    ma_kind.resize((size_t)(3 * L));
+    for (int64_t k = 0; k < L; ++k) {
+      const int32_t lo = d->line_lower[k], hi = d->line_upper[k];
+      const size_t je = (size_t)c_emit[(size_t)hi]++, jd = (size_t)c_down[(size_t)hi]++;
+      const size_t ju = (size_t)c_up[(size_t)lo]++;
+      ma_line[je] = (int32_t)k;
+      ma_via[je] = (int32_t)k;
+      ma_kind[je] = smc::kMacroEmit;
+      ma_line[jd] = -(lo + 1);
+      ma_via[jd] = (int32_t)k;
+      ma_kind[jd] = smc::kMacroDown;
+      ma_line[ju] = -(hi + 1);
+      ma_via[ju] = (int32_t)k;
+      ma_kind[ju] = smc::kMacroUp;
+    }
+    if ((rc = h2d(model->base, model->lay.level_ptr, ma_ptr.data(), (NL + 1) * 8, s,
+                  "upload level_ptr")) ||
+        (rc = h2d(model->base, model->lay.em_line, ma_line.data(), ma_line.size() * 4, s,
+                  "upload em_line")) ||
+        (rc = h2d(base, lay.em_via, ma_via.data(), ma_via.size() * 4, s, "upload em_via")) ||
+        (rc = h2d(base, lay.em_kind, ma_kind.data(), ma_kind.size(), s, "upload em_kind")))
+      return rc;
+  }
 
   // host-side index tables: the ion of every level, and the per-line
   // record (level indices; the coefficient is set on the device)
@@ -1528,6 +1647,14 @@ int smc_plasma_load(smc_model* model, const smc_plasma_desc* d, void* d_workspac
   dp.nlte_lev_ptr = (const int32_t*)(base + lay.nlte_lev_ptr);
   dp.nlte_ent = (const int32_t*)(base + lay.nlte_ent);
   dp.line_upsilon = (const double*)(base + lay.line_upsilon);
+  dp.macro = 0;  // set per update
+  dp.macro_detailed = 0;
+  dp.macro_lines = (smc::MacroLine*)(base + lay.macro_lines);
+  dp.em_via = (const int32_t*)(base + lay.em_via);
+  dp.em_kind = (const uint8_t*)(base + lay.em_kind);
+  dp.n_em = model->dev.n_em;
+  dp.level_ptr = model->dev.level_ptr;
+  dp.em_cum = const_cast<double*>(model->dev.em_cum);
   // the host staging vectors must stay alive until the copies have run
   hipError_t e = smc::launch_plasma_lines(dp, (int)nlte_recs.size(), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1545,7 +1672,7 @@ int smc_plasma_update(smc_plasma* p, const smc_plasma_params* pp, void* stream) 
   smc::DevPlasma d;
   int rc = plasma_args(p, pp, m->ran, &d);
   if (rc) return rc;
-  if (d.jb_detailed && !(m->last_flags & SMC_F_JBLUE))
+  if ((d.jb_detailed || d.macro_detailed) && !(m->last_flags & SMC_F_JBLUE))
     return fail(SMC_EINVAL, "the model's last iteration did not tally J_blue");
   const int32_t S = p->dev.S;
   if (pp->T_R) {
@@ -1570,6 +1697,7 @@ int smc_plasma_update(smc_plasma* p, const smc_plasma_params* pp, void* stream) 
   }
   HIP_TRY(smc::launch_plasma_update(d, s), "plasma update");
   p->updated = true;
+  if (p->model->derived_tables) p->model->tables_ready = true;
   return ok();
 }
 
@@ -1592,6 +1720,26 @@ int smc_plasma_read(smc_plasma* p, double* n_e, double* ion_density, double* par
     HIP_TRY(hipMemcpy2DAsync(tau_sobolev, L * 8, d.tau, (size_t)d.Lp * 8, L * 8, S,
                              hipMemcpyDeviceToHost, s),
             "hipMemcpy2DAsync");
+  HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  return ok();
+}
+
+int smc_model_read_macroatom(smc_model* m, int64_t* level_ptr, int32_t* em_line, double* em_cum,
+                             void* stream) {
+  if (!m) return fail(SMC_EINVAL, "null model");
+  if (m->dev.mode == SMC_SCATTER || m->dev.L == 0)
+    return fail(SMC_EINVAL, "the model has no macro-atom tables");
+  if (m->derived_tables && !m->tables_ready)
+    return fail(SMC_EINVAL, "the model's tables have not been derived yet");
+  HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t n_em = (size_t)m->dev.n_em;
+  const size_t n_cum = m->dev.mode == SMC_MACROATOM ? (size_t)m->dev.S * n_em : n_em;
+  int rc;
+  if ((rc = sync_copy_out(level_ptr, m->dev.level_ptr, ((size_t)m->n_levels + 1) * 8, s)))
+    return rc;
+  if ((rc = sync_copy_out(em_line, m->dev.em_line, n_em * 4, s))) return rc;
+  if ((rc = sync_copy_out(em_cum, m->dev.em_cum, n_cum * 8, s))) return rc;
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
   return ok();
 }

@@ -192,6 +192,15 @@ struct NlteLine {
   int32_t pad[2];
 };
 
+// Per-line Einstein coefficients of the macro-atom rates, derived once at load.
+struct MacroLine {
+  double A_ul, B_ul, B_lu;  // B for J in intensity units
+  double pad;
+};
+
+// Entry kinds of a macro-atom row (see launch_plasma_update)
+constexpr uint8_t kMacroEmit = 0, kMacroDown = 1, kMacroUp = 2;
+
 struct PlasmaLayout {
   uint64_t elem_ion_ptr;   // [E+1] i32
   uint64_t ion_chi, ion_zeta;  // [n_ions]
@@ -215,6 +224,9 @@ struct PlasmaLayout {
   uint64_t nlte_ent;       // [2 * NLTE lines] i32: (line position << 16) | (other level << 1) |
                            // (1 if the level is the line's lower one), by level, in line order
   uint64_t line_upsilon;   // [L] staging of the collision strengths
+  uint64_t macro_lines;    // [L] MacroLine (macro-atom tables derived on the device)
+  uint64_t em_via;         // [3L] i32: the line of each macro-atom entry
+  uint64_t em_kind;        // [3L] u8: kMacroEmit / kMacroDown / kMacroUp
   uint64_t total;
 };
 
@@ -254,6 +266,16 @@ struct DevPlasma {
   double* n_e;             // the model's [S]
   double* tau;             // the model's [S*Lp]
   const double* line_nu;   // the model's [Lp]
+  // macro-atom tables derived from this update (macro != 0): the model's
+  // rows and per-shell cumulative probabilities
+  int32_t macro;
+  int32_t macro_detailed;  // J_b of the upward jumps from `jblue` (else W B_nu(T_R))
+  int64_t n_em;
+  const int64_t* level_ptr;  // the model's [n_levels+1]
+  const int32_t* em_via;
+  const uint8_t* em_kind;
+  MacroLine* macro_lines;
+  double* em_cum;          // the model's [S*n_em]
 };
 
 // Launcher implemented in smc_measure.hip: 8 * n_cu workgroups of 256 lanes,

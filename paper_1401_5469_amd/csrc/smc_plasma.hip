@@ -1,7 +1,8 @@
 // smc_plasma.hip -- plasma state (Kerzendorf & Sim 2014, section 2.3) and
 // Sobolev optical depths (section 2.5) on the device.
 //
-// Two launches per update (three with NLTE ions):
+// Two launches per update (one more with NLTE ions, one more for derived
+// macro-atom tables):
 //   plasma_state_kernel  one workgroup per shell: partition functions (one
 //                        wavefront per ion, lanes over its levels), the log
 //                        ionization ratios, n_e from charge conservation
@@ -16,8 +17,13 @@
 //                        on the tau_S stores.
 //   plasma_nlte_kernel   (NLTE ions only, between the two) one wavefront per
 //                        (ion, shell): rate matrix in LDS, LU solve.
+//   macroatom_table_kernel (macroatom models whose tables derive from the
+//                        plasma, after the depths) one lane per (level,
+//                        shell): the row's transition weights and their
+//                        cumulative sums.
 // plasma_lines_kernel runs once at load and folds the oscillator strength,
-// the wavelength and t_exp into one coefficient per line;
+// the wavelength and t_exp into one coefficient per line, and derives the
+// Einstein coefficients of the macro-atom rates;
 // plasma_nlte_lines_kernel derives the Einstein coefficients and collision
 // constants of the NLTE ions' lines.
 #include <hip/hip_runtime.h>
@@ -473,8 +479,70 @@ __global__ void plasma_nlte_lines_kernel(DevPlasma p, int count) {
 __global__ void plasma_lines_kernel(DevPlasma p) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= p.L) return;
-  const double coef = kLineConst * p.line_f[k] * (kC / p.line_nu[k]) * p.t_exp;
-  p.lines[k].coef_g = coef * p.level_g[p.lines[k].lower];
+  const double nu = p.line_nu[k];
+  const double coef = kLineConst * p.line_f[k] * (kC / nu) * p.t_exp;
+  const double g_l = p.level_g[p.lines[k].lower], g_u = p.level_g[p.lines[k].upper];
+  p.lines[k].coef_g = coef * g_l;
+  // Einstein coefficients of the macro-atom rates (as the NLTE lines')
+  MacroLine m;
+  m.B_lu = 4.0 * (kPi * kPi) * (kECharge * kECharge) * p.line_f[k] / (kME * kC * kH * nu);
+  m.B_ul = g_l / g_u * m.B_lu;
+  m.A_ul = 2.0 * kH * (nu * nu * nu) / (kC * kC) * m.B_ul;
+  m.pad = 0.0;
+  p.macro_lines[k] = m;
+}
+
+// Macro-atom transition tables of a shell from its new plasma state
+// (section 2.5: the macro atom of Lucy 2002, 2003 with bound-bound radiative
+// transitions).  A line's radiative rates are R_ul = beta (A_ul + B_ul J_b)
+// per upper-level atom and R_lu = beta B_lu J_b per lower-level atom, beta =
+// (1 - e^-tau) / tau of the tau_S just computed; J_b = W B_nu(T_R), or the
+// J_blue estimator in the detailed mode.  From level i (energy e_i) the
+// weights are R_il (e_i - e_l) for deactivation in a line i -> l, R_il e_l
+// for an internal jump down to l and R_iu e_i for a jump up along i -> u;
+// the cumulative sums over the row are divided by the row's total (equal
+// steps when it is 0) and the last entry is set to 1.  One lane per
+// (level, shell) row, entries in row order: the sums are sequential, so they
+// never decrease along a row.
+__global__ __launch_bounds__(kWave) void macroatom_table_kernel(DevPlasma p) {
+  const int lev = blockIdx.x * kWave + threadIdx.x;
+  const int s = blockIdx.y;
+  if (lev >= p.n_levels) return;
+  const int64_t a = p.level_ptr[lev], b = p.level_ptr[lev + 1];
+  if (b <= a) return;
+  double* cum = p.em_cum + (size_t)s * (size_t)p.n_em;
+  const double* tau = p.tau + (size_t)s * (size_t)p.Lp;
+  const double e_i = p.level_energy[lev];
+  const double T = p.T_R[s], Wd = p.W[s];
+  double run = 0.0;
+  for (int64_t j = a; j < b; ++j) {
+    const int32_t k = p.em_via[j];
+    const uint8_t kind = p.em_kind[j];
+    const double t = tau[k];
+    const double beta = t > 0.0 ? -expm1(-t) / t : 1.0;
+    double J;
+    if (p.macro_detailed) {
+      J = p.jblue[(size_t)s * (size_t)p.L + (size_t)k];
+    } else {
+      const double nu = p.line_nu[k];
+      J = Wd * (2.0 * kH * (nu * nu * nu) / (kC * kC) / expm1(kH * nu / (kKB * T)));
+    }
+    const MacroLine m = p.macro_lines[k];
+    double w;
+    if (kind == kMacroUp) {
+      w = beta * m.B_lu * J * e_i;
+    } else {
+      const double e_l = p.level_energy[p.lines[k].lower];
+      w = beta * (m.A_ul + m.B_ul * J) * (kind == kMacroEmit ? e_i - e_l : e_l);
+    }
+    run += w;
+    cum[j] = run;
+  }
+  const double total = run;
+  const double n = (double)(b - a);
+  for (int64_t j = a; j < b - 1; ++j)
+    cum[j] = total > 0.0 ? cum[j] / total : (double)(j - a + 1) / n;
+  cum[b - 1] = 1.0;
 }
 
 }  // namespace
@@ -507,6 +575,9 @@ hipError_t launch_plasma_update(const DevPlasma& p, hipStream_t s) {
                        (size_t)p.n_levels * sizeof(double), s, p);
   else
     hipLaunchKernelGGL(plasma_tau_kernel<false>, grid, dim3(kTauThreads), 0, s, p);
+  if ((e = hipGetLastError()) != hipSuccess || !p.macro) return e;
+  hipLaunchKernelGGL(macroatom_table_kernel, dim3((p.n_levels + kWave - 1) / kWave, p.S),
+                     dim3(kWave), 0, s, p);
   return hipGetLastError();
 }
 

@@ -86,7 +86,7 @@ EXPORTS = ("smc_ctx_create", "smc_ctx_destroy", "smc_last_error", "smc_model_wor
            "smc_batch_autotune", "smc_graph_capture", "smc_graph_launch", "smc_graph_destroy",
            "smc_read_virtual_spectrum", "smc_plasma_workspace_bytes", "smc_plasma_load",
            "smc_plasma_update", "smc_plasma_read", "smc_plasma_free", "smc_graph_capture_plasma",
-           "smc_batch_run_static", "smc_measure_atomic_rate")
+           "smc_batch_run_static", "smc_measure_atomic_rate", "smc_model_read_macroatom")
 
 
 class SmcError(RuntimeError):
@@ -117,6 +117,7 @@ def load_library(path: str = LIB_PATH):
     L.smc_model_load.argtypes = [vp, C.POINTER(smc_model_desc), C.c_uint64, C.c_uint32, vp,
                                  C.c_uint64, vp, C.POINTER(vp)]
     L.smc_model_free.argtypes = [vp]
+    L.smc_model_read_macroatom.argtypes = [vp, _i64p, _i32p, _dp, vp]
     L.smc_run_iteration.argtypes = [vp, C.POINTER(smc_iter_params), vp]
     L.smc_read_estimators.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, vp]
     L.smc_read_spectrum.argtypes = [vp, _dp, _dp, vp]
@@ -325,6 +326,12 @@ def _need(a, n: int, what: str, at_least: bool = False):
                          f"description needs {n}")
 
 
+def derived_tables(model) -> bool:
+    """A macroatom model without tables: a plasma object derives them."""
+    return (model.line_mode == MACROATOM and model.level_ptr is None and model.em_line is None
+            and model.em_cum is None)
+
+
 def _desc(model, keep: list) -> smc_model_desc:
     def arr(a, dt):
         a = np.ascontiguousarray(a, dtype=dt)
@@ -337,11 +344,14 @@ def _desc(model, keep: list) -> smc_model_desc:
     _need(model.tau_sobolev, S * L, "tau_sobolev")
     if L and np.ndim(model.tau_sobolev) == 2 and np.shape(model.tau_sobolev) != (S, L):
         raise ValueError(f"tau_sobolev must be [{S}, {L}], not {np.shape(model.tau_sobolev)}")
-    if model.line_mode in (DOWNBRANCH, MACROATOM):
+    derived = derived_tables(model)
+    if model.line_mode in (DOWNBRANCH, MACROATOM) and not derived:
         n_em = int(np.size(model.em_line))
         _need(model.line_upper, L, "line_upper")
         _need(model.level_ptr, int(model.n_levels) + 1, "level_ptr")
         _need(model.em_cum, S * n_em if model.line_mode == MACROATOM else n_em, "em_cum")
+    if derived:
+        _need(model.line_upper, L, "line_upper")
     d.n_shells = S
     d.v_bounds = _ptr(arr(model.v_bounds, np.float64), _dp)
     d.t_exp = float(model.t_exp)
@@ -350,7 +360,11 @@ def _desc(model, keep: list) -> smc_model_desc:
     d.line_nu = _ptr(arr(model.line_nu if L else np.zeros(1), np.float64), _dp)
     d.tau_sobolev = _ptr(arr(model.tau_sobolev if L else np.zeros(1), np.float64), _dp)
     d.line_mode = int(model.line_mode)
-    if model.line_mode in (DOWNBRANCH, MACROATOM):
+    if derived:
+        # the plasma object lays out the rows and derives the probabilities
+        d.line_upper = _ptr(arr(model.line_upper, np.int32), _i32p)
+        d.n_levels = int(model.n_levels)
+    elif model.line_mode in (DOWNBRANCH, MACROATOM):
         d.line_upper = _ptr(arr(model.line_upper, np.int32), _i32p)
         d.n_levels = int(model.n_levels)
         d.level_ptr = _ptr(arr(model.level_ptr, np.int64), _i64p)
@@ -393,6 +407,10 @@ class Model:
         self.handle = h
         self.ctx = ctx
         self.S, self.L, self.n_bins = model.n_shells, model.n_lines, model.n_bins
+        self.line_mode = int(model.line_mode)
+        self.n_levels = int(model.n_levels) if model.line_mode != SCATTER else 0
+        self.n_em = (3 * model.n_lines if derived_tables(model) else
+                     int(np.size(model.em_line)) if model.line_mode != SCATTER else 0)
         self.flags = flags
         self.n_packets_max = n_packets_max
         self._ids = None
@@ -468,6 +486,16 @@ class Model:
                                               _ptr(c, _u64p), _stream_ptr(stream)))
         return dict(L_nu=L_nu, L_total=float(tot[0]),
                     counts=dict(launched=int(c[0]), counted=int(c[1]), passes=int(c[2])))
+
+    def read_macroatom(self, stream=None):
+        """The model's downbranch or macroatom tables: level_ptr, em_line and
+        em_cum ([S, n_em] in macroatom mode)."""
+        ptr = np.zeros(self.n_levels + 1, dtype=np.int64)
+        line = np.zeros(self.n_em, dtype=np.int32)
+        cum = np.zeros((self.S, self.n_em) if self.line_mode == MACROATOM else self.n_em)
+        _check(_lib.smc_model_read_macroatom(self.handle, _ptr(ptr, _i64p), _ptr(line, _i32p),
+                                             _ptr(cum, _dp), _stream_ptr(stream)))
+        return ptr, line, cum
 
     def read_counters(self, stream=None):
         c = np.zeros(8, dtype=np.uint64)
