@@ -118,8 +118,14 @@ def parse():
     ap.add_argument("--nlte", action="store_true",
                     help="plasma mode: NLTE excitation for four ions, J_b from J_blue")
     ap.add_argument("--models", type=int, default=64, help="models in the batched mix")
-    ap.add_argument("--duration", type=float, default=10.0,
+    ap.add_argument("--duration", type=float, default=60.0,
                     help="seconds of Poisson arrivals (20 per second) in the served mode")
+    ap.add_argument("--served-modes", default="stream,step,plain",
+                    help="served mode: comma-separated paths among stream, step, plain")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="launch streams of the stream server")
+    ap.add_argument("--plain-requests", type=int, default=200,
+                    help="requests (in arrival order) the plain path serves")
     ap.add_argument("--budget-gb", type=float, default=200.0,
                     help="device-memory admission budget of the served mode")
     return ap.parse_args()
@@ -835,6 +841,19 @@ def batched_measure(n_models, steps, warmup, jblue, log=True):
                   flush=True)
     inter, segs = counts(models)
 
+    # batched form with the library's default tuning
+    ctx.batch_run(models, params)
+    torch.cuda.synchronize()
+    dwalls = []
+    for step in range(steps):
+        t0 = time.perf_counter()
+        ctx.batch_run(models, params)
+        torch.cuda.synchronize()
+        dwalls.append(time.perf_counter() - t0)
+    if log:
+        print(f"# batched, default tuning: {np.mean(dwalls) * 1e3:.1f} ms", file=sys.stderr,
+              flush=True)
+
     # batched form: the autotuned multi-model launch
     t0 = time.perf_counter()
     best, best_ms = ctx.batch_autotune(models, params)
@@ -867,6 +886,8 @@ def batched_measure(n_models, steps, warmup, jblue, log=True):
                     "transport_ms": kern, "tune": best,
                     "autotune_s": tune_s, "autotune_note": "coordinate search, two timed runs "
                     "per candidate, a candidate kept only when 2 % faster; not in wall_ms"},
+        "batched_default_tune": {"models_per_s": n / float(np.mean(dwalls)),
+                                 "wall_ms": float(np.mean(dwalls)) * 1e3},
         "plain": {"models_per_s": n / plain, "interactions_per_s": inter / plain,
                   "segments_per_s": segs / plain, "wall_ms": plain * 1e3},
         "speedup_vs_plain": plain / wall,
@@ -912,80 +933,181 @@ def _gen_request(args):
     return t, seed, n_iter, w
 
 
-def served(args):
-    """Poisson arrivals at 20 requests/s; request j is a model drawn as in the
-    batched mix from seed 1000+j with U{1..10} iterations.  The continuous-
-    batching server (admission by a device-memory budget, one multi-model
-    launch per step, state resident on the device) against the plain path
-    (one request at a time, one single-model launch per iteration), on the
-    same requests and packet counts."""
-    import multiprocessing as mp
+class _Feed:
+    """Request models built in worker processes ahead of their arrival: at
+    most `window` in flight or waiting, so that host memory holds a few GB
+    rather than the whole arrival list."""
 
+    def __init__(self, pool, arrivals, window=64):
+        self.pool, self.arrivals, self.window = pool, arrivals, window
+        self.jobs = {}
+        self.next = 0
+        for _ in range(min(window, len(arrivals))):
+            self._queue()
+
+    def _queue(self):
+        if self.next < len(self.arrivals):
+            self.jobs[self.next] = self.pool.apply_async(_gen_request, (self.arrivals[self.next],))
+            self.next += 1
+
+    def get(self, j):
+        out = self.jobs.pop(j).get()
+        self._queue()
+        return out
+
+
+def _request(serve, g):
+    t, seed, n_iter, w = g
+    return serve.Request(model=w.model, n_iterations=n_iter, n_packets=w.n_packets,
+                         T_inner=w.T_inner, L_requested=w.L_requested, damping=w.damping,
+                         arrival=t)
+
+
+def _serve_mode(mode, serve, be, pool, arrivals, budget, n_streams, log):
+    """Drive one server over the arrival list in real time, submitting each
+    request when it arrives (its model built ahead by the pool).  Returns the
+    server's statistics, its wall time and the requests."""
+    feed = _Feed(pool, arrivals)
+    srv = (serve.StreamServer(be, memory_budget=budget, n_streams=n_streams) if mode == "stream"
+           else serve.Server(be, memory_budget=budget))
+    reqs = []
+    n, j, last, k_adm = len(arrivals), 0, 0, 0
+    t0 = time.perf_counter()
+    while j < n or srv.pending or srv.active:
+        while j < n and arrivals[j][0] <= srv.now():
+            r = _request(serve, feed.get(j))
+            srv.submit(r)
+            reqs.append(r)
+            j += 1
+        moved = srv.advance() if mode == "stream" else srv.step()
+        if not moved:
+            nxt = arrivals[j][0] - srv.now() if j < n else None
+            busy = mode == "stream" and srv.busy()
+            if busy:
+                time.sleep(0.0005 if nxt is None else max(0.0, min(0.0005, nxt)))
+            elif nxt is not None:
+                time.sleep(max(0.0, nxt))
+        # admission is in arrival order: the host copies of admitted models
+        # are no longer needed
+        while k_adm < len(reqs) and reqs[k_adm].state != serve.QUEUED:
+            reqs[k_adm].model = None
+            k_adm += 1
+        done = len(reqs) - len(srv.active) - len(srv.pending)
+        if done >= last + 100:
+            last = done
+            log(f"# {mode}: served {done}/{n} at {srv.now():.1f} s, active {len(srv.active)}")
+    wall = time.perf_counter() - t0
+    for r in reqs:
+        r.model = None
+    return srv.stats(), wall, reqs
+
+
+def _compare_results(a, b):
+    """Requests served two ways: counters equal, and the largest relative
+    difference of J, nu-bar, T_R, W, L_nu, L_emitted and T_inner."""
     import numpy as np
+
+    worst, same = 0.0, 0
+    for x, y in zip(a, b):
+        rx, ry = x.result, y.result
+        same += rx["counters"] == ry["counters"]
+        for k in ("J", "nubar", "T_R", "W", "L_nu"):
+            u, v = np.asarray(rx[k]), np.asarray(ry[k])
+            den = np.maximum(np.abs(v), 1e-300)
+            worst = max(worst, float(np.max(np.abs(u - v) / den)) if u.size else 0.0)
+        for k in ("T_inner", "T_inner_next", "L_emitted"):
+            if rx[k] is not None and ry[k]:
+                worst = max(worst, abs(rx[k] - ry[k]) / abs(ry[k]))
+    return {"requests": len(a), "counters_equal": same, "max_rel_diff": worst}
+
+
+def served(args):
+    """Poisson arrivals at 20 requests/s for --duration seconds; request j is
+    a model drawn as in the batched mix from seed 1000+j with U{1..10}
+    iterations (every model kept resident on the device between its
+    iterations, admitted while its workspace fits the memory budget).  Three
+    paths over the same requests: the stream server (no global step:
+    cohorts launched concurrently on --streams streams, a new arrival waits
+    only for a free stream), the step-synchronous server (one multi-model
+    launch per step for every admitted request, waited for), and the plain
+    path (one request at a time, one single-model launch per iteration) on
+    the first --plain-requests requests, whose plain latencies do not depend
+    on later arrivals.  Reports latency, queue wait (arrival to first launch)
+    and service time (first launch to completion), models/s, and whether
+    every served result equals the plain path's (counters, and estimators to
+    rounding)."""
+    import multiprocessing as mp
 
     from paper_1401_5469_amd import serve
     from paper_1401_5469_amd import workloads as W
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     arrivals = W.config5_requests(duration_s=args.duration)
-    t0 = time.perf_counter()
-    # generate the request models before the GPU is touched
-    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
-        gen = pool.map(_gen_request, arrivals)
-    print(f"# {len(gen)} requests generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
-          flush=True)
-
-    def make():
-        return [serve.Request(model=w.model, n_iterations=n_iter, n_packets=w.n_packets,
-                              T_inner=w.T_inner, L_requested=w.L_requested, damping=w.damping,
-                              arrival=t) for t, seed, n_iter, w in gen]
-
+    modes = [m for m in args.served_modes.split(",") if m]
+    # the model builders fork before anything touches the GPU
+    pool = mp.get_context("fork").Pool(min(16, os.cpu_count() or 1))
     budget = int(args.budget_gb * 2**30)
-    be = serve.GpuBackend()
-    reqs = make()
-    srv = serve.Server(be, memory_budget=budget)
-    for r in reqs:
-        srv.submit(r)
-    t0 = time.perf_counter()
-    last = 0
-    while srv.pending or srv.active:
-        if not srv.step():
-            nxt = srv.pending[0].arrival if srv.pending else None
-            if nxt is not None:
-                time.sleep(max(0.0, nxt - srv.now()))
-        done = sum(r.state == serve.DONE for r in reqs)
-        if done >= last + 50:
-            last = done
-            print(f"# served {done}/{len(reqs)} at {srv.now():.1f} s, active {len(srv.active)}",
-                  file=sys.stderr, flush=True)
-    served_wall = time.perf_counter() - t0
-    st = srv.stats()
-    packets = sum(r.n_packets * r.n_iterations for r in reqs)
-    print(f"# served: {st}", file=sys.stderr, flush=True)
-    plain_reqs = make()
-    t0 = time.perf_counter()
-    pst = serve.serve_plain(be, plain_reqs)
-    plain_wall = time.perf_counter() - t0
-    print(f"# plain: {pst}", file=sys.stderr, flush=True)
+    be = serve.GpuBackend(flags=None, keep_jblue=False)
+    res, reqs_of = {}, {}
+    for mode in modes:
+        if mode == "plain":
+            k = min(args.plain_requests, len(arrivals))
+            feed = _Feed(pool, arrivals[:k])
+            reqs = [None] * k
+
+            def ordered():
+                for j in range(k):
+                    reqs[j] = _request(serve, feed.get(j))
+                    yield reqs[j]
+                    reqs[j].model = None
+            t0 = time.perf_counter()
+            st = serve.serve_plain(be, ordered(), ordered=True)
+            wall = time.perf_counter() - t0
+            st["requests"] = k
+        else:
+            st, wall, reqs = _serve_mode(mode, serve, be, pool, arrivals, budget, args.streams,
+                                         log)
+        packets = sum(r.n_packets * r.n_iterations for r in reqs)
+        st.update(wall_s=wall, packets_per_s=packets / wall)
+        res[mode] = st
+        reqs_of[mode] = reqs
+        log(f"# {mode}: {json.dumps(st)}")
+    pool.close()
     out = {
         "metric": "p99 synthesis latency (served)",
-        "value": st["p99_s"],
+        "value": res[modes[0]]["p99_s"] if modes[0] != "plain" else None,
         "unit": "s",
         "n_gpus": 1,
-        "steps": st["steps"],
+        "steps": res[modes[0]].get("steps"),
         "warmup": 0,
-        "ms_per_step": served_wall / max(st["steps"], 1) * 1e3,
+        "ms_per_step": None,
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"served-poisson-20hz-{args.duration:g}s", "requests": len(reqs),
-                   "iterations_total": int(sum(r.n_iterations for r in reqs)),
-                   "packets_total": int(packets), "budget_gb": args.budget_gb},
-        "served": {**st, "wall_s": served_wall, "packets_per_s": packets / served_wall},
-        "plain": {**pst, "wall_s": plain_wall, "packets_per_s": packets / plain_wall},
-        "offered_packets_per_s": packets / args.duration,
+        "config": {"workload": f"served-poisson-20hz-{args.duration:g}s", "requests": len(arrivals),
+                   "iterations_total": int(sum(n for _, _, n in arrivals)),
+                   "budget_gb": args.budget_gb, "streams": args.streams,
+                   "server": modes[0]},
+        **{m: res[m] for m in modes},
+        "result_checks": {},
     }
+    if "plain" in reqs_of:
+        k = len(reqs_of["plain"])
+        for m in modes:
+            if m != "plain":
+                byarr = sorted(reqs_of[m], key=lambda r: r.arrival)[:k]
+                out["result_checks"][f"{m}_vs_plain"] = _compare_results(byarr, reqs_of["plain"])
+                # the same first k requests as served
+                out[m]["first_k"] = serve.latency_stats(byarr)
+    if "stream" in res and "step" in res:
+        out["stream_over_step"] = {
+            "p50": res["step"]["p50_s"] / res["stream"]["p50_s"],
+            "p99": res["step"]["p99_s"] / res["stream"]["p99_s"],
+            "models_per_s": res["stream"]["models_per_s"] / res["step"]["models_per_s"]}
     print(json.dumps(out), flush=True)
 
 

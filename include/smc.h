@@ -151,16 +151,20 @@ typedef struct {
   int32_t long_waves_per_cu; /* group-per-packet kernel: wavefronts resident per CU */
   uint32_t long_budget;      /* flight segments after which a history moves from the
                                 lane-per-packet to the group-per-packet kernel;
-                                UINT32_MAX keeps every history in the first kernel */
+                                UINT32_MAX keeps every history in the first kernel;
+                                the default is 256 for one model in the scatter and
+                                downbranch modes, 4096 for a multi-model launch of
+                                them, 1024 with macro atoms */
   uint32_t long_lanes;       /* lanes that carry one handed-off history: 16, 32 or 64
                                 (a wavefront carries 64 / long_lanes of them); the
-                                default is 64 (the wavefront-per-history kernel) for the
-                                scatter and downbranch modes without v-packets, 32 with
+                                default is 64 (the wavefront-per-history kernel) for one
+                                model in the scatter and downbranch modes without
+                                v-packets, 16 for a multi-model launch of them, 32 with
                                 macro atoms or v-packets */
 } smc_tune;
 
 /* Create a context on HIP device `hip_device`.  The context owns a few small
- * device and pinned host buffers for multi-model launches (about 1.5 MB). */
+ * device and pinned host buffers for multi-model launches (about 3 MB). */
 int smc_ctx_create(smc_ctx** out, int hip_device);
 /* Free a context's buffers once the multi-model launches that use them have
  * finished (NULL: no-op).  Models, plasmas and graphs made on it are freed

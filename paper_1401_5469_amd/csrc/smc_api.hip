@@ -16,9 +16,10 @@
 #include "smc_internal.h"
 
 // Multi-model launches stage their model table in pinned host memory and
-// copy it to a device table; kBatchSlots of each rotate so that a slot is
-// reused only after the launch that read it has finished (event per slot).
-constexpr int kBatchSlots = 4;
+// copy it to a device table; a launch takes a slot whose last launch has
+// finished (event per slot), so that launches in flight on several streams
+// never make the host wait while a slot is free.
+constexpr int kBatchSlots = 8;
 
 struct smc_ctx {
   int device;
@@ -103,14 +104,19 @@ constexpr uint64_t kAlign = 256;
 // flight segments before a history moves to the group kernel unless tuned:
 // fewer for one model in a plain mode (its longest histories start sooner),
 // more with macro atoms (their group-kernel variant carries more registers
-// and runs fewer histories at once) and in multi-model launches (where
-// throughput matters more than the latency of one history)
+// and runs fewer histories at once), most in multi-model launches of the
+// plain modes (where throughput matters more than the latency of one
+// history: the coordinate search picks 4096 on the 64-model mix)
 constexpr uint32_t kDefaultLongBudget = 256;
 constexpr uint32_t kDefaultLongBudgetWide = 1024;
+constexpr uint32_t kDefaultLongBudgetMulti = 4096;
 // lanes per handed-off history unless tuned: one history per wavefront (its
-// segments have the shortest latency) in the plain modes, two per wavefront
-// in the group kernel variant with the macro-atom and v-packet code
+// segments have the shortest latency) for one model in the plain modes,
+// four per wavefront in their multi-model launches (the search's pick on
+// the 64-model mix), two per wavefront in the group kernel variant with the
+// macro-atom and v-packet code
 constexpr int kDefaultLongLanes = 64;
+constexpr int kDefaultLongLanesMulti = 16;
 constexpr int kDefaultLongLanesExt = 32;
 // wavefronts per CU of the group-per-packet kernel unless tuned (fewer when
 // its occupancy allows fewer): 16 one-history wavefronts, else 12
@@ -145,13 +151,14 @@ void release_ctx(smc_ctx* c) {
   delete c;
 }
 
-int lanes_of(const smc_tune& t, bool ext) {
-  return t.long_lanes != 0 ? (int)t.long_lanes : (ext ? kDefaultLongLanesExt : kDefaultLongLanes);
+int lanes_of(const smc_tune& t, bool ext, bool multi) {
+  if (t.long_lanes != 0) return (int)t.long_lanes;
+  return ext ? kDefaultLongLanesExt : (multi ? kDefaultLongLanesMulti : kDefaultLongLanes);
 }
 int lanes_index(int lanes) { return lanes == 16 ? 0 : (lanes == 32 ? 1 : 2); }
 
 int default_long_waves(const smc_ctx* c, bool multi, const smc_tune& t, bool ext) {
-  const int lanes = lanes_of(t, ext);
+  const int lanes = lanes_of(t, ext, multi);
   const int occ = c->long_blocks_per_cu[multi][lanes_index(lanes)][ext];
   const int want = (lanes == 64 && !ext) ? kDefaultSoloWaves : kDefaultLongWaves;
   return occ < want ? occ : want;
@@ -170,13 +177,14 @@ int check_tune(const smc_tune& t) {
 // hand-off positions that run at the highest wave priority: one wavefront's
 // histories per SIMD (4 SIMDs per CU), so that no two top-priority
 // wavefronts share a SIMD
-uint32_t hot_of(const smc_ctx* c, const smc_tune& t, bool ext) {
-  return 4u * (uint32_t)c->n_cu * (uint32_t)(64 / lanes_of(t, ext));
+uint32_t hot_of(const smc_ctx* c, const smc_tune& t, bool ext, bool multi) {
+  return 4u * (uint32_t)c->n_cu * (uint32_t)(64 / lanes_of(t, ext, multi));
 }
 
-uint32_t budget_of(const smc_tune& t, bool wide) {
-  return t.long_budget == 0 ? (wide ? kDefaultLongBudgetWide : kDefaultLongBudget)
-                            : (t.long_budget == UINT32_MAX ? 0u : t.long_budget);
+uint32_t budget_of(const smc_tune& t, bool macro, bool multi) {
+  if (t.long_budget == 0)
+    return macro ? kDefaultLongBudgetWide : (multi ? kDefaultLongBudgetMulti : kDefaultLongBudget);
+  return t.long_budget == UINT32_MAX ? 0u : t.long_budget;
 }
 
 // launch shape from the tuning (0 = occupancy default), capped by the work
@@ -196,7 +204,7 @@ smc::Shape shape_of(const smc_ctx* c, const smc_tune& t, bool multi, uint64_t n_
     if (lgrid > n_work) lgrid = n_work;
   }
   sh.long_grid = (int)lgrid;
-  sh.long_lanes = lanes_of(t, ext);
+  sh.long_lanes = lanes_of(t, ext, multi);
   sh.long_ext = ext;
   return sh;
 }
@@ -678,7 +686,8 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   if (!m || !p) return fail(SMC_EINVAL, "null model or parameters");
   smc::LaunchArgs a;
   memset(&a, 0, sizeof a);
-  int rc = make_iter(m, p, budget_of(m->tune, m->dev.mode == SMC_MACROATOM), &a.single.it);
+  int rc = make_iter(m, p, budget_of(m->tune, m->dev.mode == SMC_MACROATOM, false),
+                     &a.single.it);
   if (rc) return rc;
   HIP_TRY(hipSetDevice(m->ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
@@ -697,7 +706,7 @@ int smc_run_iteration(smc_model* m, const smc_iter_params* p, void* stream) {
   a.order_hist = m->order_hist;
   a.max_lines = (uint32_t)m->dev.L;
   const bool ext = a.single.it.n_virtual > 0 || m->dev.mode == SMC_MACROATOM;
-  a.hot = hot_of(m->ctx, m->tune, ext);
+  a.hot = hot_of(m->ctx, m->tune, ext, false);
   const smc::Shape sh =
       shape_of(m->ctx, m->tune, false, a.total_work,
                a.single.it.long_budget > 0 || a.single.it.n_virtual > 0, ext);
@@ -735,10 +744,24 @@ int batch_launch(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* 
   bool any_macro = false;
   for (int k = 0; k < n_models; ++k)
     if (models[k] && models[k]->dev.mode == SMC_MACROATOM) any_macro = true;
-  const uint32_t budget = budget_of(t, any_macro || n_models > 1);
+  const uint32_t budget = budget_of(t, any_macro, n_models > 1);
   HIP_TRY(hipSetDevice(ctx->device), "hipSetDevice");
-  // take the next slot once the launch that last used it has finished
-  const int slot = ctx->next_slot;
+  // a slot whose last launch has finished, searched from the next in turn;
+  // with every slot in flight, wait for that next one
+  int slot = ctx->next_slot;
+  for (int i = 0; i < kBatchSlots; ++i) {
+    const int c = (ctx->next_slot + i) % kBatchSlots;
+    if (!ctx->slot_used[c]) {
+      slot = c;
+      break;
+    }
+    const hipError_t q = hipEventQuery(ctx->slot_done[c]);
+    if (q == hipSuccess) {
+      slot = c;
+      break;
+    }
+    if (q != hipErrorNotReady) return hip_fail(q, "slot query");
+  }
   if (ctx->slot_used[slot]) HIP_TRY(hipEventSynchronize(ctx->slot_done[slot]), "slot wait");
   smc::BatchEntry* tab = ctx->host_table[slot];
   uint64_t work = 0, max_jb = 0;
@@ -781,7 +804,7 @@ int batch_launch(smc_ctx* ctx, smc_model* const* models, const smc_iter_params* 
   a.ctr = dev_ctr;
   a.order_hist = (unsigned int*)(dev_ctr + 4);
   a.max_lines = max_lines;
-  a.hot = hot_of(ctx, t, any_ext);
+  a.hot = hot_of(ctx, t, any_ext, true);
   const smc::Shape sh = shape_of(ctx, t, true, work, budget > 0 || any_virtual, any_ext);
   HIP_TRY(smc::launch_iteration(a, true, sh, max_jb, timed ? ctx->ev_start : nullptr,
                                 timed ? ctx->ev_stop : nullptr, s),
@@ -1026,7 +1049,7 @@ int smc_model_get_tune(smc_model* m, smc_tune* t) {
   if (!m || !t) return fail(SMC_EINVAL, "null model or output");
   *t = m->tune;
   if (t->blocks_per_cu == 0) t->blocks_per_cu = m->ctx->transport_blocks_per_cu[0];
-  if (t->long_lanes == 0) t->long_lanes = lanes_of(*t, m->dev.mode == SMC_MACROATOM);
+  if (t->long_lanes == 0) t->long_lanes = lanes_of(*t, m->dev.mode == SMC_MACROATOM, false);
   if (t->long_waves_per_cu == 0)
     t->long_waves_per_cu = default_long_waves(m->ctx, false, *t, m->dev.mode == SMC_MACROATOM);
   if (t->long_budget == 0)
@@ -1086,7 +1109,7 @@ static int graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_
   bool any_macro = false;
   for (int k = 0; k < n_models; ++k)
     if (models[k] && models[k]->dev.mode == SMC_MACROATOM) any_macro = true;
-  const uint32_t budget = budget_of(t, any_macro || n_models > 1);
+  const uint32_t budget = budget_of(t, any_macro, n_models > 1);
   for (int k = 0; k < n_models; ++k) {
     if (!models[k] || models[k]->ctx != ctx)
       return fail(SMC_EINVAL, "model %d is null or of another context", k);
@@ -1191,7 +1214,7 @@ static int graph_capture(smc_ctx* ctx, smc_model* const* models, const smc_iter_
       a.order_hist = models[0]->order_hist;
     }
     a.max_lines = max_lines;
-    a.hot = hot_of(ctx, t, any_ext[i]);
+    a.hot = hot_of(ctx, t, any_ext[i], multi);
     const smc::Shape sh =
         shape_of(ctx, t, multi, work[i], budget > 0 || any_virtual[i], any_ext[i]);
     le = smc::launch_iteration(a, multi, sh, max_jb[i], nullptr, nullptr, s);

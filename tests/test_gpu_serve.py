@@ -1,10 +1,14 @@
-"""Served requests give the same results alone and in the mix: requests of
-different sizes and iteration counts arrive while others run, join the
-multi-model launches, and each result matches the same request run alone
-(one single-model launch per iteration) to the parity tolerance."""
+"""Served requests against their own oracle chains: requests of different
+sizes and iteration counts arrive while others run and join the
+multi-model launches (the step-synchronous server, and the stream server
+with launches in flight on several streams); every result -- J, nu-bar,
+T_R, W, J_blue, L_nu, the T_inner it ran at and the next one, the counters
+-- matches the oracle run iteration by iteration with T_inner carried as
+the library carries it (section 2.8), and the same request run alone."""
 import numpy as np
 import pytest
 
+from oracle import oracle as O
 from paper_1401_5469_amd import serve
 from paper_1401_5469_amd import workloads as W
 
@@ -42,8 +46,8 @@ def test_results_are_the_same_alone_and_in_the_mix():
     clk = StepClock()
 
     class Backend(serve.GpuBackend):
-        def step(self, reqs):
-            super().step(reqs)
+        def step(self, reqs, stream=None):
+            super().step(reqs, stream)
             clk.t += 1.0
 
     be = Backend(tune=dict(long_budget=6))
@@ -76,8 +80,8 @@ def test_wait_returns_each_result():
         clk = StepClock()
 
         class Backend(serve.GpuBackend):
-            def step(self, reqs):
-                super().step(reqs)
+            def step(self, reqs, stream=None):
+                super().step(reqs, stream)
                 clk.t += 1.0
 
         srv = serve.Server(Backend(), memory_budget=200 * 2**30, clock=clk, sleep=clk.sleep)
@@ -95,3 +99,66 @@ def test_wait_returns_each_result():
         for k in ("J", "nubar", "T_R", "W"):
             np.testing.assert_allclose(rb[k], ra[k], rtol=REL, atol=0)
         assert rb["T_inner_next"] == pytest.approx(ra["T_inner_next"], rel=REL, abs=0)
+
+
+def _oracle_chain(req):
+    """The request's iterations on the oracle: T_inner and the radiation
+    field carried from one iteration to the next."""
+    T = req.T_inner
+    T_R, W_ = O.initial_radiation_field(req.model)
+    for it in range(req.n_iterations):
+        raw = O.run(req.model, T, req.n_packets, iteration=it)
+        fin = O.finalise(req.model, raw, T, L_requested=req.L_requested, T_R_prev=T_R,
+                         W_prev=W_, damping=req.damping)
+        T_R, W_ = fin["T_R"], fin["W"]
+        fin["T_inner"] = T
+        T = fin["T_inner_next"]
+    return raw, fin
+
+
+def _assert_oracle(req):
+    raw, fin = _oracle_chain(req)
+    r = req.result
+    assert r["counters"] == raw["counters"]
+    for k in ("J", "nubar", "T_R", "W"):
+        np.testing.assert_allclose(r[k], fin[k], rtol=REL, atol=0)
+    assert_close_or_zero(r["jblue"], fin["jblue"], what="jblue")
+    assert_close_or_zero(r["L_nu"], fin["L_nu"], what="L_nu")
+    assert r["T_inner"] == pytest.approx(fin["T_inner"], rel=REL, abs=0)
+    assert r["T_inner_next"] == pytest.approx(fin["T_inner_next"], rel=REL, abs=0)
+
+
+def test_each_served_request_matches_its_oracle_chain():
+    clk = StepClock()
+
+    class Backend(serve.GpuBackend):
+        def step(self, reqs, stream=None):
+            super().step(reqs, stream)
+            clk.t += 1.0
+
+    srv = serve.Server(Backend(tune=dict(long_budget=6)), memory_budget=200 * 2**30, clock=clk,
+                       sleep=clk.sleep)
+    reqs = _requests()
+    for r in reqs:
+        srv.submit(r)
+    srv.run()
+    assert srv.stats()["max_batch"] >= 3
+    for r in reqs:
+        _assert_oracle(r)
+
+
+def test_stream_server_requests_match_their_oracle_chains():
+    # real time: arrivals spread over 0.3 s, launches on three streams
+    reqs = _requests()
+    for r in reqs:
+        r.arrival *= 0.05
+    srv = serve.StreamServer(serve.GpuBackend(tune=dict(long_budget=6)),
+                             memory_budget=200 * 2**30, n_streams=3)
+    for r in reqs:
+        srv.submit(r)
+    srv.run()
+    st = srv.stats()
+    assert st["completed"] == len(reqs)
+    for r in reqs:
+        assert r.state == serve.DONE and r.iteration == r.n_iterations
+        _assert_oracle(r)

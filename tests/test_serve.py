@@ -3,6 +3,7 @@ clock: admission by memory budget in arrival order, continuous batching (a
 request that arrives while others run joins at the next step), completion
 after its iterations, cancellation and rejection."""
 import numpy as np
+import pytest
 
 from paper_1401_5469_amd import serve
 from paper_1401_5469_amd import workloads as W
@@ -141,3 +142,94 @@ def test_wait_serves_until_the_request_is_done():
     assert srv.poll(b) == serve.DONE and clock.t >= 100.0
     huge = srv.submit(_req(10**9, 1, 0.0))
     assert srv.wait(huge) is None and srv.poll(huge) == serve.REJECTED
+
+
+class FakeStreams(FakeBackend):
+    """Launch streams on the simulated clock: a launch on a stream ends
+    `cost(reqs)` seconds after it starts; streams run concurrently."""
+
+    def __init__(self, clock, cost=lambda reqs: 1.0 + 0.1 * len(reqs)):
+        super().__init__(clock)
+        self.cost = cost
+        self.launches = []  # (stream, start, end, [(rid, iteration)])
+
+    def stream(self, k):
+        return k
+
+    def launch(self, reqs, stream):
+        t = self.clock.t
+        end = t + self.cost(reqs)
+        self.launches.append((stream, t, end, [(r.rid, r.iteration) for r in reqs]))
+        self.steps.append([(r.rid, r.iteration) for r in reqs])
+        return end
+
+    def query(self, ev):
+        return self.clock.t >= ev
+
+    def result(self, req, stream=None):
+        return dict(iterations=req.iteration)
+
+
+def _stream_server(budget, n_streams=2, cost=None):
+    clk = Clock()
+    be = FakeStreams(clk) if cost is None else FakeStreams(clk, cost)
+    return (serve.StreamServer(be, memory_budget=budget, n_streams=n_streams, poll_s=0.01,
+                               clock=clk, sleep=clk.sleep), be, clk)
+
+
+def test_stream_server_launches_arrivals_without_waiting_for_a_cohort():
+    # a long launch (request a, 10 s per iteration) is running when b
+    # arrives: b goes out on the idle stream at once, and finishes first
+    srv, be, clk = _stream_server(10**9, cost=lambda reqs: 10.0 if reqs[0].rid == 0 else 1.0)
+    a = srv.submit(_req(100, 2, 0.0))
+    b = srv.submit(_req(100, 3, 0.5))
+    srv.run()
+    assert srv.poll(a) == serve.DONE and srv.poll(b) == serve.DONE
+    ra, rb = srv.requests[a], srv.requests[b]
+    assert rb.first_launch_at == pytest.approx(0.5, abs=0.02)
+    assert rb.completed_at < ra.completed_at
+    assert rb.queue_wait < 0.05
+    # the step-synchronous server makes b wait for a's first iteration
+    srv2, be2, clk2 = _server(10**9)
+    a2 = srv2.submit(_req(100, 2, 0.0))
+    b2 = srv2.submit(_req(100, 3, 0.5))
+    srv2.run()
+    assert srv2.requests[b2].queue_wait > 0.5  # until the step of a ends at 1.1 s
+
+
+def test_stream_server_keeps_each_requests_iterations_in_order():
+    srv, be, clk = _stream_server(10**9, n_streams=3,
+                                  cost=lambda reqs: 0.3 + 0.7 * (len(reqs) % 3))
+    ids = [srv.submit(_req(100, 1 + k % 4, 0.2 * k)) for k in range(15)]
+    srv.run()
+    assert all(srv.poll(i) == serve.DONE for i in ids)
+    assert all(srv.result(i)["iterations"] == srv.requests[i].n_iterations for i in ids)
+    for rid in ids:
+        runs = [(s, e, it) for _, s, e, c in be.launches for r, it in c if r == rid]
+        # iterations 0, 1, ... in order, each after the previous one ended
+        assert [it for _, _, it in runs] == list(range(srv.requests[rid].n_iterations))
+        for (s0, e0, _), (s1, _, _) in zip(runs, runs[1:]):
+            assert s1 >= e0
+    # no request is in two launches at once
+    for k, (_, s, e, c) in enumerate(be.launches):
+        for _, s2, e2, c2 in be.launches[k + 1:]:
+            if s2 < e and s < e2:
+                assert not ({r for r, _ in c} & {r for r, _ in c2})
+    assert be.live == {}
+    st = srv.stats()
+    assert st["completed"] == 15 and st["n_streams"] == 3
+    assert st["mean_launches_in_flight"] > 1.0
+    assert st["queue_wait_s"]["p99"] is not None and st["service_s"]["p50"] > 0.0
+
+
+def test_stream_server_budget_cancel_and_wait():
+    srv, be, clk = _stream_server(budget=2500)
+    ids = [srv.submit(_req(100, 2, 0.01 * k)) for k in range(6)]  # 1000 B each
+    big = srv.submit(_req(1000, 1, 0.0))
+    assert srv.poll(big) == serve.REJECTED
+    assert srv.wait(ids[0]) == dict(iterations=2)
+    assert srv.cancel(ids[5]) and srv.poll(ids[5]) == serve.CANCELLED
+    srv.run()
+    assert be.peak <= 2500
+    assert all(srv.poll(i) == serve.DONE for i in ids[:5])
+    assert be.live == {}
