@@ -124,6 +124,11 @@ def parse():
                     help="served mode: comma-separated paths among stream, step, plain")
     ap.add_argument("--streams", type=int, default=4,
                     help="launch streams of the stream server")
+    ap.add_argument("--max-active", type=int, default=128,
+                    help="requests a server keeps admitted at once (the rest queue in "
+                         "arrival order)")
+    ap.add_argument("--max-cohort", type=int, default=1024,
+                    help="requests one launch of the stream server takes at most")
     ap.add_argument("--plain-requests", type=int, default=200,
                     help="requests (in arrival order) the plain path serves")
     ap.add_argument("--budget-gb", type=float, default=200.0,
@@ -963,13 +968,15 @@ def _request(serve, g):
                          arrival=t)
 
 
-def _serve_mode(mode, serve, be, pool, arrivals, budget, n_streams, log):
+def _serve_mode(mode, serve, be, pool, arrivals, budget, n_streams, max_active, max_cohort,
+                log):
     """Drive one server over the arrival list in real time, submitting each
     request when it arrives (its model built ahead by the pool).  Returns the
     server's statistics, its wall time and the requests."""
     feed = _Feed(pool, arrivals)
-    srv = (serve.StreamServer(be, memory_budget=budget, n_streams=n_streams) if mode == "stream"
-           else serve.Server(be, memory_budget=budget))
+    srv = (serve.StreamServer(be, memory_budget=budget, n_streams=n_streams,
+                              max_active=max_active, max_cohort=max_cohort) if mode == "stream"
+           else serve.Server(be, memory_budget=budget, max_active=max_active))
     reqs = []
     n, j, last, k_adm = len(arrivals), 0, 0, 0
     t0 = time.perf_counter()
@@ -1068,7 +1075,7 @@ def served(args):
             st["requests"] = k
         else:
             st, wall, reqs = _serve_mode(mode, serve, be, pool, arrivals, budget, args.streams,
-                                         log)
+                                         args.max_active, args.max_cohort, log)
         packets = sum(r.n_packets * r.n_iterations for r in reqs)
         st.update(wall_s=wall, packets_per_s=packets / wall)
         res[mode] = st
@@ -1091,6 +1098,7 @@ def served(args):
         "config": {"workload": f"served-poisson-20hz-{args.duration:g}s", "requests": len(arrivals),
                    "iterations_total": int(sum(n for _, _, n in arrivals)),
                    "budget_gb": args.budget_gb, "streams": args.streams,
+                   "max_active": args.max_active, "max_cohort": args.max_cohort,
                    "server": modes[0]},
         **{m: res[m] for m in modes},
         "result_checks": {},

@@ -103,10 +103,11 @@ def test_batch_equals_alone(ctx, tune):
     for (mdl, N, T), b in zip(mix, together):
         # the same hand-off budget and group width alone: each history takes
         # the same kernels with the same rounding (untuned, a multi-model
-        # launch hands off after 1024 segments, one model alone after 256)
+        # launch hands off after 4096 segments to 16 lanes per history, one
+        # model alone after 256 to a wavefront per history)
         same = {k: v for k, v in (tune or {}).items() if k in ("long_budget", "long_lanes")}
-        if "long_budget" not in same:
-            same["long_budget"] = 1024
+        same.setdefault("long_budget", 4096)
+        same.setdefault("long_lanes", 16)
         a = _alone(ctx, mdl, N, T, tune=same)
         assert np.array_equal(a["packets"], b["packets"])
         for k in ("J", "nubar", "T_R", "W"):
