@@ -107,6 +107,10 @@ def parse():
                     help="write the counter summary: OUT BENCH_LINE ATOMICS_DB BENCH_DB...")
     ap.add_argument("--trace-summary", nargs="+", metavar="PATH",
                     help="print the kernel-trace summary: DB [BENCH_LINE]")
+    ap.add_argument("--profile-last", type=int, default=0,
+                    help="with --profile-summary: also list the last N dispatches one by one")
+    ap.add_argument("--profile-kernel", default="",
+                    help="with --profile-last: only dispatches whose kernel name contains this")
     ap.add_argument("--commands", nargs="*", help="commands recorded in a summary")
     ap.add_argument("--atomic-rounds", type=int, default=256,
                     help="rounds per lane of the atomics workload (counter summary)")
@@ -412,7 +416,7 @@ def trace_summary(args):
         print(f"interactions/s over the timed iterations: {line['value']:.4g}")
 
 
-def profile_summary(paths):
+def profile_summary(paths, last=0, kernel=""):
     """Per-kernel sums of the counters in rocprofv3 --pmc result databases,
     with the dispatch count and mean duration (one table per database)."""
     from collections import defaultdict
@@ -430,6 +434,12 @@ def profile_summary(paths):
         for name in sorted(per, key=lambda k: -dur[k]):
             cs = "  ".join(f"{c}={v:.6g}" for c, v in sorted(per[name].items()))
             print(f"{name} | dispatches {n[name]} | mean {dur[name] / n[name] * 1e-6:.3f} ms | {cs}")
+        if last:
+            sel = [d for d in _pmc_dispatches(path) if kernel in d[0]][-last:]
+            print(f"# the last {last} dispatches" + (f" of {kernel}" if kernel else ""))
+            for k, g, t, cs in sel:
+                c = "  ".join(f"{c}={v:.6g}" for c, v in sorted(cs.items()))
+                print(f"{k} | grid {g} | {t * 1e-6:.3f} ms | {c}")
 
 
 def copy_reference(args):
@@ -1207,7 +1217,7 @@ def critical(args):
 def main():
     args = parse()
     if args.profile_summary:
-        return profile_summary(args.profile_summary)
+        return profile_summary(args.profile_summary, args.profile_last, args.profile_kernel)
     if args.traffic_summary:
         return traffic_summary(args)
     if args.counter_summary:
