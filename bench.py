@@ -172,6 +172,45 @@ def measured_atomics():
                                  for k, v in summ["atomic_calibration"].items()}}
 
 
+def measured_valu():
+    """The pass's wave64 VALU instructions from the counter summary (per
+    pass, and the part of them in the kernel of the handed-off histories)."""
+    summ = _current_summary(COUNTER_SUMMARY)
+    if not summ:
+        return None
+    solo = summ["per_kernel"].get("solo_kernel", {}).get("SQ_INSTS_VALU")
+    return {"per_pass": summ["per_pass"]["SQ_INSTS_VALU"], "handed_off_kernel": solo,
+            "segments_per_pass": summ["segments_per_pass"]}
+
+
+def valu_entry(pass_ms):
+    """The pass's VALU issue rate against the device's: the resource the
+    handed-off histories' kernel saturates while thousands of long histories
+    run (its FP64 chains are uniform per history, so every segment costs the
+    same wave64 instructions whatever the lanes do)."""
+    v = measured_valu()
+    peak = valu_peak()
+    if not v:
+        return {"achieved": None, "peak": peak, "unit": "wave64 VALU instructions/s",
+                "frac": None, "source": "committed counter summary (null: kernel source changed)"}
+    rate = v["per_pass"] / (pass_ms * 1e-3)
+    return {"achieved": rate, "peak": peak, "unit": "wave64 VALU instructions/s",
+            "frac": rate / peak, "instructions_per_pass": v["per_pass"],
+            "instructions_per_segment": v["per_pass"] / v["segments_per_pass"],
+            "source": "SQ_INSTS_VALU per pass from the committed counter summary over this "
+                      "run's mean pass time; peak = 4 SIMDs x CUs x 2.4 GHz / 4 cycles"}
+
+
+def valu_peak():
+    """wave64 VALU instructions per second the device can issue: one per 4
+    cycles on each SIMD (a 64-lane FP64 instruction occupies a 16-lane SIMD
+    for 4 cycles), 4 SIMDs per CU."""
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    clock_hz = 2.4e9  # MI355X peak engine clock
+    return 4 * p.multi_processor_count * clock_hz / 4.0
+
+
 ATOMIC_PATTERNS = ("window", "scattered")
 
 
@@ -1352,6 +1391,7 @@ def main():
                                "group kernel of the handed-off histories",
                      "bytes_per_launch": bytes_per_launch,
                      "bytes_model": "16 B per line passed + 24 B per segment + 96 B per packet",
+                     "valu": valu_entry(mean_ms),
                      "atomic": {"achieved": atom_rate, "peak": atom_peak,
                                 "unit": "L2 atomic requests/s",
                                 "frac": atom_rate / atom_peak if atom_rate else None,
