@@ -36,8 +36,12 @@ kernel source (else null).  Its `atomic` entry sets the pass's atomic
 requests at the L2 (J_blue, J, nu-bar and spectrum tallies; TCC_ATOMIC from
 the committed counter summary) per second against the request rate the
 device sustains in the two tally patterns: their FP64 add rates, measured in
-the same run, times the requests per add the calibration counters read.  The `batched` entry is the 64-model mix in one
-autotuned multi-model launch against 64 single-model launches (models/s).
+the same run, times the requests per add the calibration counters read.  Its
+`valu` entry sets the pass's wave64 VALU instructions (SQ_INSTS_VALU from the
+same summary) per second against the issue peak, one per 4 cycles per SIMD:
+the resource the pass is bound by.  The `batched` entry is the 64-model mix
+in one autotuned multi-model launch against 64 single-model launches
+(models/s; also with the library's default tuning).
 The CPU baseline times the FP64 oracle on a bounded packet sample of the
 same iterations: an equal share of --cpu-sample packets from every timed
 iteration, each at the iteration number and T_inner the device used, once
