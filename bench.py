@@ -610,8 +610,9 @@ def macroatom(args):
             continue
         p = np.diff(np.concatenate([np.zeros((cum.shape[0], 1)), cum[:, a:b]], axis=1), axis=1)
         p[:, line[a:b] < 0] = 0.0
-        tot = p.sum(axis=1, keepdims=True)
-        c = np.where(tot > 0, np.cumsum(p, axis=1) / np.where(tot > 0, tot, 1.0), 1.0)
+        run = np.cumsum(p, axis=1)  # sequential: never above its last entry
+        tot = run[:, -1:]
+        c = np.where(tot > 0, run / np.where(tot > 0, tot, 1.0), 1.0)
         c[:, -1] = 1.0
         db_cum[:, a:b] = c
     db_model = W.Model(**{**w.model.__dict__, "tau_sobolev": np.ascontiguousarray(st["tau"]),

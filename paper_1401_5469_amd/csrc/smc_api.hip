@@ -276,6 +276,20 @@ uint64_t em_cum_entries(const smc_model_desc* d) {
                                        : (uint64_t)d->n_em;
 }
 
+// Copies between a host [rows][width] array and a device one of row pitch
+// `pitch`, one plain copy per row (one copy in all when the rows are not
+// padded): strided copies from or to pageable host memory are avoided.
+hipError_t copy_rows(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
+                     size_t rows, hipMemcpyKind kind, hipStream_t s) {
+  if (dpitch == width && spitch == width) return hipMemcpyAsync(dst, src, width * rows, kind, s);
+  for (size_t r = 0; r < rows; ++r) {
+    const hipError_t e = hipMemcpyAsync((uint8_t*)dst + r * dpitch,
+                                        (const uint8_t*)src + r * spitch, width, kind, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // A workspace must be device memory of the context's device from hipMalloc
 // (coarse-grained): the tallies are FP64 atomic adds, which host and managed
 // memory do not guarantee.
@@ -588,14 +602,20 @@ int smc_model_load(smc_ctx* ctx, const smc_model_desc* d, uint64_t n_packets_max
           "upload v_bounds");
   HIP_TRY(hipMemcpyAsync(base + lay.n_e, d->n_e, S * 8, hipMemcpyHostToDevice, s), "upload n_e");
   if (L > 0) {
+    // the rows are padded to whole 4-line loads; the copies and the clears
+    // of the padding touch disjoint bytes, so no ordering between a fill and
+    // a copy engine is relied on
     const uint64_t Lp = (L + 3) / 4 * 4;
-    HIP_TRY(hipMemsetAsync(base + lay.line_nu, 0, Lp * 8, s), "clear line_nu");
-    HIP_TRY(hipMemsetAsync(base + lay.tau, 0, S * Lp * 8, s), "clear tau_sobolev");
     HIP_TRY(hipMemcpyAsync(base + lay.line_nu, d->line_nu, L * 8, hipMemcpyHostToDevice, s),
             "upload line_nu");
-    HIP_TRY(hipMemcpy2DAsync(base + lay.tau, Lp * 8, d->tau_sobolev, L * 8, L * 8, S,
-                             hipMemcpyHostToDevice, s),
+    HIP_TRY(copy_rows(base + lay.tau, Lp * 8, d->tau_sobolev, L * 8, L * 8, S,
+                      hipMemcpyHostToDevice, s),
             "upload tau_sobolev");
+    if (Lp > L) {
+      HIP_TRY(hipMemsetAsync(base + lay.line_nu + L * 8, 0, (Lp - L) * 8, s), "pad line_nu");
+      HIP_TRY(hipMemset2DAsync(base + lay.tau + L * 8, Lp * 8, 0, (Lp - L) * 8, S, s),
+              "pad tau_sobolev");
+    }
   }
   const bool derived = derived_macroatom(d) && L > 0;
   if (d->line_mode != SMC_SCATTER && L > 0)
@@ -1740,9 +1760,9 @@ int smc_plasma_read(smc_plasma* p, double* n_e, double* ion_density, double* par
   if ((rc = sync_copy_out(level_pop, d.level_pop, S * NL * 8, s))) return rc;
   if ((rc = sync_copy_out(counts, d.clamped, 2 * 8, s))) return rc;
   if (tau_sobolev && L > 0)
-    HIP_TRY(hipMemcpy2DAsync(tau_sobolev, L * 8, d.tau, (size_t)d.Lp * 8, L * 8, S,
-                             hipMemcpyDeviceToHost, s),
-            "hipMemcpy2DAsync");
+    HIP_TRY(copy_rows(tau_sobolev, L * 8, d.tau, (size_t)d.Lp * 8, L * 8, S,
+                      hipMemcpyDeviceToHost, s),
+            "read tau_sobolev");
   HIP_TRY(hipStreamSynchronize(s), "hipStreamSynchronize");
   return ok();
 }
