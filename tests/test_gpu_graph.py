@@ -146,3 +146,39 @@ def test_graph_with_plasma_updates_matches_eager(ctx, nlte):
     with pytest.raises(smc.SmcError):  # an unknown J_b mode is refused at capture
         ctx.capture([m], [[p] for p in seq], plasmas=[pg],
                     plasma_params=[dict(upd, jblue_mode=7)])
+
+
+@pytest.mark.parametrize("jb", ["dilute", "detailed"])
+def test_graph_of_the_macroatom_loop_matches_eager(ctx, jb):
+    """A macroatom model whose transition tables are derived by every plasma
+    update: the captured loop (iteration, plasma update with new depths and
+    tables) replays the eager one, tables included."""
+    import torch
+    model, spec = W.macroatom_plasma_model(seed=33, n_shells=5, n_elements=5, n_stages=4,
+                                           n_levels_per_ion=15, n_lines=1500)
+    N = 2500
+    seq = _iters(11000.0, 3, N, 0.0)
+    upd = dict(ionization=smc.ION_NEBULAR, excitation=smc.EXC_DILUTE_LTE, delta=1.0,
+               jblue_mode=smc.JB_DETAILED if jb == "detailed" else smc.JB_DILUTE_BLACKBODY)
+    eager = smc.Model(ctx, model, N, flags=F_ALL)
+    pe = smc.Plasma(eager, spec)
+    pe.update(upd["ionization"], upd["excitation"], upd["delta"])
+    m = smc.Model(ctx, model, N, flags=F_ALL)
+    pg = smc.Plasma(m, spec)
+    pg.update(upd["ionization"], upd["excitation"], upd["delta"])
+    g = ctx.capture([m], [[p] for p in seq], plasmas=[pg], plasma_params=[upd])
+    for rep in range(2):
+        for p in seq:
+            eager.run_iteration(**p)
+            pe.update(**upd)
+        ref, ref_tab = _state(eager, N), eager.read_macroatom()
+        g.launch()
+        torch.cuda.synchronize()
+        got, got_tab = _state(m, N), m.read_macroatom()
+        assert_packets_match(got["packets"], ref["packets"], rel=1e-9, allow_fraction=0.0)
+        for k in ("J", "nubar", "T_R", "W"):
+            np.testing.assert_allclose(got["est"][k], ref["est"][k], rtol=1e-9, atol=0)
+        assert np.array_equal(got_tab[0], ref_tab[0]) and np.array_equal(got_tab[1], ref_tab[1])
+        np.testing.assert_allclose(got_tab[2], ref_tab[2], rtol=0, atol=1e-9)
+        assert m.read_counters()["line_events"] > 100
+    g.destroy()
