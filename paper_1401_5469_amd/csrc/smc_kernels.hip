@@ -998,6 +998,15 @@ __device__ __forceinline__ double dpp_f64(double x) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// x of the next lower wave lane (DPP wave_shr:1); lane 0 reads 0
+__device__ __forceinline__ double wave_shr1_f64(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x138, 0xF, 0xF, true);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), 0x138, 0xF, 0xF,
+                                                         true);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 __device__ __forceinline__ double join_u32(uint32_t lo, uint32_t hi) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
@@ -1586,6 +1595,9 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
   // next window, copied ahead straight from HBM: low and high words of the
   // line frequencies, then of the Sobolev depths, by lane
   __shared__ uint32_t pf[4][kWave];
+  // the history's draws 2 rb .. 2 rb + 127 in draw order: uniforms and their
+  // -log (read back at a wave-uniform address, one LDS broadcast each)
+  __shared__ double dr_u[2 * kWave], dr_l[2 * kWave];
   const int lane = threadIdx.x;
   const bool leader = lane == 0;
   const unsigned long long n_long = long_total<kMulti>(a);
@@ -1639,28 +1651,27 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
     sk.p0 = (uint32_t)st.pid;
     sk.p1 = (uint32_t)(st.pid >> 32);
     asm volatile("" : "+v"(sk.k0), "+v"(sk.k1), "+v"(sk.p0), "+v"(sk.p1), "+v"(sk.iter));
-    // draws 2(rb + i) and 2(rb + i) + 1 in lane i, with -log of each
+    const bool use_jb = v.jblue != nullptr;
+    // draws 2(rb + i) and 2(rb + i) + 1 from lane i's counter block
     uint32_t rb = draw >> 1;
-    double ua, ub, la, lb;
     auto refill_draws = [&]() {
       rb = draw >> 1;
       const Block blk = stream_block(sk, rb + lane);
-      ua = to_uniform(blk.a);
-      ub = to_uniform(blk.b);
-      la = -log(ua);
-      lb = -log(ub);
+      const double ua = to_uniform(blk.a), ub = to_uniform(blk.b);
+      __syncthreads();  // the last draws read have been used
+      dr_u[2 * lane] = ua;
+      dr_u[2 * lane + 1] = ub;
+      dr_l[2 * lane] = -log(ua);
+      dr_l[2 * lane + 1] = -log(ub);
+      __syncthreads();
     };
     refill_draws();
-    // line wbase + i of shell wshell in lane i: frequency, depth, the J_blue
-    // the history has left on it since the window was installed, and the
-    // depth of the live lines below it when the march starts at line bef_k
-    int32_t wbase = -1, wshell = -1, bef_k = -1;
-    double wn = 0.0, wt = 0.0, jb_acc = 0.0, bef = 0.0;
-    auto depth_below = [&](int32_t k) {
-      const int32_t line = wbase + lane;
-      const double t = (line >= k && line < v.L) ? wt : 0.0;
-      return grp.prefix_sum(t) - t;
-    };
+    // line wbase + i of shell wshell in lane i: frequency, depth, the summed
+    // depth of the window's lines before it, and the J_blue the history has
+    // left on it since the window was installed; wx_at = wx of line wx_k
+    int32_t wbase = -1, wshell = -1, wx_k = -1;
+    double wn = 0.0, wt = 0.0, wx = 0.0, jb_acc = 0.0, wx_at = 0.0;
+    unsigned long long wlive = 0ull;  // lanes of the window that hold a line
     // the shell's bounds and sigma_T n_e, and whether its opacity takes the
     // short quotient x / kappa (sigma_T n_e >= 2^-898, D in (1/2, 3/2)); below
     // that the distance to a Thomson event exceeds 2^840 cm, beyond every
@@ -1682,11 +1693,8 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
       // the draws this segment may take: tau_event, then the branch and
       // direction draws of a line event (or the direction of a Thomson one)
       if (draw + 3 > 2u * (rb + kWave)) refill_draws();
-      const bool odd = draw & 1;
-      const int i0 = (int)((draw >> 1) - rb);
-      const double tau0 = grp.bcast(odd ? lb : la, i0);
-      const double u1 = grp.bcast(odd ? ua : ub, odd ? i0 + 1 : i0);
-      const double u2 = grp.bcast(odd ? ub : ua, i0 + 1);
+      const uint32_t di = draw - 2u * rb;
+      const double tau0 = dr_l[di], u1 = dr_u[di + 1], u2 = dr_u[di + 2];
       const int sh = shell;
       if (sh != c_shell) {
         c_shell = sh;
@@ -1715,8 +1723,9 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
       const double jb_f = E * rnu.y * rnu.y;
 
       // line march over the window: lane j tests line wbase+j against the
-      // optical depth left after the live lines before it; the first lane
-      // that stops the march decides
+      // optical depth left after the live lines before it, tau - (X_j - X_k)
+      // with X the window's summed depths and k the first live line; the
+      // first lane that stops the march decides
       double tau_ev = tau0;  // left after the windows already passed
       int32_t k = next_line;
       bool line_hit = false;
@@ -1756,33 +1765,41 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
           jb_acc = 0.0;
           wbase = k;
           wshell = sh;
-          bef_k = -1;
+          // summed depth of the lanes below: the inclusive sum moved up a lane
+          wx = wave_shr1_f64(grp.prefix_sum(wt));
+          wx_k = k;
+          wx_at = 0.0;
+          const int32_t n_in = v.L - k;
+          wlive = n_in >= kWave ? ~0ull : ((1ull << n_in) - 1ull);
         }
-        if (bef_k != k) {
-          bef = depth_below(k);
-          bef_k = k;
+        if (wx_k != k) {
+          wx_at = grp.bcast(wx, k - wbase);
+          wx_k = k;
         }
-        const int32_t line = wbase + lane;
-        const bool live = line >= k && line < v.L;
-        const double before = bef;  // depth of the live lines below
-        double dl = (nu_cmf - wn) * ct_over_nu;
-        dl = dl < 0.0 ? 0.0 : dl;
-        const double rem = tau_ev - before;
-        const bool reach = dl < elec(rem) && dl < d_shell;
-        const bool hit = reach && wt + kappa * dl > rem;
-        const unsigned long long stop = __ballot(live && (!reach || hit));
-        const unsigned long long hits = __ballot(live && hit);
-        const int first = stop ? (int)__builtin_ctzll(stop) : -1;
+        // live lanes: lines k .. L - 1 of the window
+        const unsigned long long live = wlive & (~0ull << (k - wbase));
+        // (the difference of two finite frequencies is +0 when they are
+        // equal, so the clamp at 0 keeps the sign of every zero)
+        const double dl = fmax((nu_cmf - wn) * ct_over_nu, 0.0);
+        const double rem = tau_ev - (wx - wx_at);  // tau itself at line k
+        // lanes whose line lies beyond the Thomson event or the boundary, and
+        // lanes whose line would absorb if reached
+        const unsigned long long far = __ballot(dl >= elec(rem)) | __ballot(dl >= d_shell);
+        const unsigned long long deep = __ballot(wt + kappa * dl > rem);
+        const unsigned long long stop = (far | deep) & live;
+        // the first stopping lane (none: 0), and whether its line absorbs
+        const unsigned long long low = stop & (0ull - stop);
+        const unsigned long long hit_low = low & deep & ~far;
         // J_blue: every line reached up to the stop, the interacting one included
-        const int end = first < 0 ? kWave : first + ((hits >> first) & 1ull ? 1 : 0);
-        if (v.jblue) jb_acc += (live && lane < end) ? jb_f : 0.0;
-        const int passed = end - (k - wbase) > 0 ? end - (k - wbase) : 0;
-        n_pass += (uint64_t)(first < 0
-                                 ? (int32_t)(v.L < wbase + kWave ? v.L - k : wbase + kWave - k)
-                                 : passed);
-        if (first >= 0) {
+        const unsigned long long reached = live & ((low - 1ull) | hit_low);
+        if (use_jb) {
+          if (__builtin_amdgcn_inverse_ballot_w64(reached)) jb_acc += jb_f;
+        }
+        n_pass += (uint64_t)__builtin_popcountll(reached);
+        if (low) {
+          const int first = (int)__builtin_ctzll(low);
           k = wbase + first;
-          if ((hits >> first) & 1ull) {
+          if (hit_low) {
             line_hit = true;
             d_line = grp.bcast(dl, first);
             nu_hit = grp.bcast(wn, first);
@@ -1792,21 +1809,21 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
           break;
         }
         // every live line of the window passed
-        const int top = v.L < wbase + kWave ? v.L - wbase - 1 : kWave - 1;
-        tau_ev -= grp.bcast(before + (live ? wt : 0.0), top);
+        const int top = 63 - (int)__builtin_clzll(wlive);
+        tau_ev -= grp.bcast(wx + wt, top) - wx_at;
         tau_rem = tau_ev;
         k = wbase + top + 1;
       }
       next_line = k;
 
       // the next march in this shell starts at the line after the
-      // interacting one (scatter mode) or here after a Thomson event: sum
-      // its depths while this event's transforms run
+      // interacting one (scatter mode) or here after a Thomson event: fetch
+      // its summed depth while this event's transforms run
       {
         const int32_t kn = line_hit ? k + 1 : k;
         if ((wshell == sh) & (kn >= wbase) & (kn < wbase + kWave)) {
-          bef = depth_below(kn);
-          bef_k = kn;
+          wx_at = grp.bcast(wx, kn - wbase);
+          wx_k = kn;
         }
       }
       if (acc_shell != sh || acc_model != model) {
@@ -1829,8 +1846,7 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
         acc_J += jc;
         acc_nb += jc * nu_cmf;
         const double r_new = root(r * r + d * d + 2.0 * r * d * mu);
-        double mu_new = quot(rmu + d, divisor(r_new));
-        mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
+        const double mu_new = fmin(fmax(quot(rmu + d, divisor(r_new)), -1.0), 1.0);
         const double D_old = 1.0 - quot(mu_new * r_new, v.rct);
         const double e_cmf_ev = E * D_old;
         double nu_cmf_out = nu_hit;
@@ -1862,8 +1878,7 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
       acc_J += jc;
       acc_nb += jc * nu_cmf;
       const double r_new = root(r * r + d * d + 2.0 * r * d * mu);
-      double mu_new = quot(rmu + d, divisor(r_new));
-      mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
+      const double mu_new = fmin(fmax(quot(rmu + d, divisor(r_new)), -1.0), 1.0);
       if (escat) {
         // coherent, isotropic in the comoving frame (section 2.5)
         const double D_old = 1.0 - quot(mu_new * r_new, v.rct);

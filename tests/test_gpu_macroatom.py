@@ -74,7 +74,11 @@ def test_macroatom_without_internal_jumps_is_downbranch(ctx):
     for tune in (dict(long_budget=2**32 - 1), dict(long_budget=1)):
         a = gpu_run(ctx, m, 3000, 12000.0, tune=tune)
         b = gpu_run(ctx, ma, 3000, 12000.0, tune=tune)
-        assert np.array_equal(a["packets"], b["packets"])
+        # every history takes the same events; after a hand-off the two modes
+        # run in kernels that sum the lines' depths over windows of different
+        # widths, so positions and energies agree to rounding
+        assert divergent(a["packets"], b["packets"]).size == 0
+        assert_packets_match(a["packets"], b["packets"])
         assert a["counters"] == b["counters"]
 
 
