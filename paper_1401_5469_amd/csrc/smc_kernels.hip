@@ -11,6 +11,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/smc.h"
 #include "smc_internal.h"
 
@@ -313,15 +315,20 @@ __device__ __forceinline__ double root(double x) {
 
 // distance along (r, mu) to the boundary of shell [r_in, r_out] met first
 // (ray-sphere intersection; a tangent ray misses the inner sphere)
-__device__ __forceinline__ double shell_distance(double r, double mu, double rmu, double r_in,
-                                                 double r_out, bool& inward) {
+// (from the squared radii; q is +0 when r_x^2 = b, so its clamp keeps the sign)
+__device__ __forceinline__ double shell_distance_sq(double r, double mu, double rmu, double r_in2,
+                                                    double r_out2, bool& inward) {
   const double b = r * r * ((1.0 - mu) * (1.0 + mu));
-  inward = mu < 0.0 && b < r_in * r_in;
-  double q = inward ? r_in * r_in - b : r_out * r_out - b;
-  q = q < 0.0 ? 0.0 : q;
+  inward = mu < 0.0 && b < r_in2;
+  const double q = fmax((inward ? r_in2 : r_out2) - b, 0.0);
   const double sq = root(q);
   const double d = inward ? -rmu - sq : sq - rmu;
   return d < 0.0 ? 0.0 : d;
+}
+
+__device__ __forceinline__ double shell_distance(double r, double mu, double rmu, double r_in,
+                                                 double r_out, bool& inward) {
+  return shell_distance_sq(r, mu, rmu, r_in * r_in, r_out * r_out, inward);
 }
 
 
@@ -1205,6 +1212,12 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
   // next window of each group, copied ahead straight from HBM: low and high
   // words of the line frequencies, then of the Sobolev depths, by wave lane
   __shared__ uint32_t pf[4][kWave];
+  // each group's draws 2 rb .. 2 rb + 2G - 1 in draw order: uniforms and
+  // their -log, at 2 x (the group's first wave lane)
+  __shared__ double dr_u[2 * kWave], dr_l[2 * kWave];
+  // lane masks of a group's window
+  using Mask = typename std::conditional<G == 64, unsigned long long, uint32_t>::type;
+  constexpr Mask kFull = G == 64 ? (Mask)~0ull : (Mask)((1ull << G) - 1ull);
   Group<G> grp;
   grp.lane = threadIdx.x & (G - 1);
   grp.base = threadIdx.x & ~(G - 1);
@@ -1227,25 +1240,32 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
   uint32_t draw = 0, rb = 0, n_esc = 0, n_line = 0;
   double r = 0.0, mu = 0.0, nu = 0.0, E = 0.0;
   int32_t shell = 0, next_line = 0, last_line = -1;
-  // draws 2(rb + i) and 2(rb + i) + 1 in group lane i, with -log of each
-  double ua = 0.0, ub = 0.0, la = 0.0, lb = 0.0;
-  // line wbase + i of shell wshell in group lane i: frequency, depth, and
-  // the J_blue the history has left on it since the window was installed
-  // (the following window of the same shell waits in pf)
-  int32_t wbase = -1, wshell = -1;
-  double wn = 0.0, wt = 0.0, jb_acc = 0.0;
+  // line wbase + i of shell wshell in group lane i: frequency, depth, the
+  // summed depth of the window's lines before it, and the J_blue the history
+  // has left on it since the window was installed (the following window of
+  // the same shell waits in pf); wx_at = wx of line wx_k
+  int32_t wbase = -1, wshell = -1, wx_k = -1;
+  double wn = 0.0, wt = 0.0, wx = 0.0, jb_acc = 0.0, wx_at = 0.0;
+  Mask wlive = 0;  // lanes of the window that hold a line
   int32_t c_shell = -1;
   double c_rin = 0.0, c_rout = 0.0, c_ne = 0.0;
 
-  // move the group's window of 2G draws to start at the next one
+  // move the group's window of 2G draws to start at the next one (draws
+  // 2(rb + i) and 2(rb + i) + 1 from group lane i's counter block)
   auto refill_draws = [&]() {
     rb = draw >> 1;
     const Block blk = stream_block(sk, rb + grp.lane);
-    ua = to_uniform(blk.a);
-    ub = to_uniform(blk.b);
-    la = -log(ua);
-    lb = -log(ub);
+    const double ua = to_uniform(blk.a), ub = to_uniform(blk.b);
+    const int o = 2 * (int)threadIdx.x;
+    dr_u[o] = ua;
+    dr_u[o + 1] = ub;
+    dr_l[o] = -log(ua);
+    dr_l[o + 1] = -log(ub);
+    __builtin_amdgcn_wave_barrier();
   };
+  // draw d (2 rb <= d < 2 rb + 2G) of the group's history
+  auto draw_u = [&](uint32_t d) { return dr_u[2 * grp.base + (int)(d - 2u * rb)]; };
+  auto draw_l = [&](uint32_t d) { return dr_l[2 * grp.base + (int)(d - 2u * rb)]; };
 
   for (;;) {
     bool fetched = false;
@@ -1291,12 +1311,7 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
         sk.iter = v.iter;
         sk.p0 = (uint32_t)pid;
         sk.p1 = (uint32_t)(pid >> 32);
-        rb = draw >> 1;
-        const Block blk = stream_block(sk, rb + grp.lane);
-        ua = to_uniform(blk.a);
-        ub = to_uniform(blk.b);
-        la = -log(ua);
-        lb = -log(ub);
+        refill_draws();
         wbase = -1;
         wshell = -1;
         c_shell = -1;
@@ -1338,7 +1353,7 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
       }
       n_seg += 1;
       if (draw + 3 > 2u * (rb + G)) refill_draws();
-      const double tau0 = grp.bcast((draw & 1) ? lb : la, grp.uni((int)((draw >> 1) - rb)));
+      const double tau0 = draw_l(draw);
       draw += 1;
       const int sh = shell;
       if (sh != c_shell) {
@@ -1358,13 +1373,17 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
       const double d_shell = shell_distance(r, mu, rmu, c_rin, c_rout, inward);
       const double kappa = kSigmaT * c_ne * D;
       const Divisor rkappa = divisor(kappa);
-      const double ct_over_nu = quot(v.ct, divisor(nu));
-      const Divisor rnn = divisor(nu * nu);  // J_blue weight E nu_k / nu^2
-      double* jb_row = v.jblue ? v.jblue + (size_t)sh * (size_t)v.L : nullptr;
+      const Divisor rnu = divisor(nu);
+      const double ct_over_nu = quot(v.ct, rnu);
+      // J_blue weight per unit line frequency, E / nu^2: a lane sums it over
+      // its line's passages and multiplies by nu_k when the window changes
+      const double jb_f = E * rnu.y * rnu.y;
+      const bool jb_row = v.jblue != nullptr;
 
       // line march over the window: lane j tests line wbase+j against the
-      // optical depth left after the live lines before it; the first lane
-      // that stops the march decides
+      // optical depth left after the live lines before it, tau - (X_j - X_k)
+      // with X the window's summed depths and k the first live line; the
+      // first lane that stops the march decides
       double tau_ev = tau0;  // left after the windows already passed
       int32_t k = next_line;
       bool line_hit = false;
@@ -1380,6 +1399,7 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
           const int32_t line = k + grp.lane;
           const bool in = line < v.L;
           const size_t row = (size_t)sh * (size_t)v.Lp;
+          const double jb_out = jb_acc * wn;
           if (ahead) {
             const double n_raw = join_u32(pf[0][threadIdx.x], pf[1][threadIdx.x]);
             const double t_raw = join_u32(pf[2][threadIdx.x], pf[3][threadIdx.x]);
@@ -1399,35 +1419,47 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
           const int32_t nc = next < v.Lp ? next : v.Lp - 1;
           copy_f64_to_lds(v.line_nu + nc, &pf[0][0], &pf[1][0]);
           copy_f64_to_lds(v.tau + row + nc, &pf[2][0], &pf[3][0]);
-          if (v.jblue && wshell >= 0 && jb_acc != 0.0)
-            unsafeAtomicAdd(&v.jblue[(size_t)wshell * (size_t)v.L + wbase + grp.lane], jb_acc);
+          if (v.jblue && wshell >= 0 && jb_out != 0.0)
+            unsafeAtomicAdd(&v.jblue[(size_t)wshell * (size_t)v.L + wbase + grp.lane], jb_out);
           jb_acc = 0.0;
           wbase = k;
           wshell = sh;
+          // summed depth of the group's lanes below each lane
+          const double incl = grp.prefix_sum(wt);
+          const double below = wave_shr1_f64(incl);
+          wx = grp.lane == 0 ? 0.0 : below;
+          wx_k = k;
+          wx_at = 0.0;
+          const int32_t n_in = v.L - k;
+          wlive = n_in >= G ? kFull : (Mask)(((Mask)1 << n_in) - 1);
         }
-        const int32_t line = wbase + grp.lane;
-        const bool live = line >= k && line < v.L;
-        const double t = live ? wt : 0.0;
-        const double before = grp.prefix_sum(t) - t;  // depth of the live lines below
-        double dl = (nu_cmf - wn) * ct_over_nu;
-        dl = dl < 0.0 ? 0.0 : dl;
-        const double rem = tau_ev - before;
+        if (wx_k != k) {
+          wx_at = grp.bcast(wx, k - wbase);
+          wx_k = k;
+        }
+        // live lanes: lines k .. L - 1 of the window
+        const Mask live = wlive & (Mask)(kFull << (k - wbase));
+        const double dl = fmax((nu_cmf - wn) * ct_over_nu, 0.0);
+        const double rem = tau_ev - (wx - wx_at);  // tau itself at line k
         const double de = kappa > 0.0 ? quot_checked(rem, rkappa) : INFINITY;
-        const bool reach = dl < de && dl < d_shell;
-        const bool hit = reach && wt + kappa * dl > rem;
-        const unsigned long long stop = grp.bits(__ballot(live && (!reach || hit)));
-        const unsigned long long hits = grp.bits(__ballot(live && hit));
-        const int first = stop ? (int)__builtin_ctzll(stop) : -1;
+        // lanes whose line lies beyond the Thomson event or the boundary, and
+        // lanes whose line would absorb if reached
+        const Mask far = (Mask)grp.bits(__ballot(dl >= de)) | (Mask)grp.bits(__ballot(dl >= d_shell));
+        const Mask deep = (Mask)grp.bits(__ballot(wt + kappa * dl > rem));
+        const Mask stop = (far | deep) & live;
+        // the first stopping lane (none: 0), and whether its line absorbs
+        const Mask low = stop & (Mask)(0 - stop);
+        const Mask hit_low = low & deep & (Mask)~far;
         // J_blue: every line reached up to the stop, the interacting one included
-        const int end = first < 0 ? G : first + ((hits >> first) & 1ull ? 1 : 0);
-        if (jb_row && live && grp.lane < end) jb_acc += quot(E * wn, rnn);
-        const int passed = end - (k - wbase) > 0 ? end - (k - wbase) : 0;
-        n_pass += (uint64_t)(first < 0 ? (int32_t)(v.L < wbase + G ? v.L - k : wbase + G - k)
-                                       : passed);
-        if (first >= 0) {
-          const int fl = grp.uni(first);
+        const Mask reached = live & ((Mask)(low - 1) | hit_low);
+        if (jb_row && ((reached >> grp.lane) & 1)) jb_acc += jb_f;
+        n_pass += (uint64_t)(G == 64 ? __builtin_popcountll((unsigned long long)reached)
+                                     : __builtin_popcount((uint32_t)reached));
+        if (low) {
+          const int fl = grp.uni(G == 64 ? __builtin_ctzll((unsigned long long)low)
+                                         : __builtin_ctz((uint32_t)low));
           k = wbase + fl;
-          if ((hits >> fl) & 1ull) {
+          if (hit_low) {
             line_hit = true;
             d_line = grp.bcast(dl, fl);
             nu_hit = grp.bcast(wn, fl);
@@ -1437,12 +1469,23 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
           break;
         }
         // every live line of the window passed
-        const int top = grp.uni(v.L < wbase + G ? v.L - wbase - 1 : G - 1);
-        tau_ev -= grp.bcast(before + t, top);
+        const int top = grp.uni(G == 64 ? 63 - __builtin_clzll((unsigned long long)wlive)
+                                        : 31 - __builtin_clz((uint32_t)wlive));
+        tau_ev -= grp.bcast(wx + wt, top) - wx_at;
         tau_rem = tau_ev;
         k = wbase + top + 1;
       }
       next_line = k;
+      // the next march in this shell starts at the line after the
+      // interacting one (scatter mode) or here after a Thomson event: fetch
+      // its summed depth while this event's transforms run
+      {
+        const int32_t kn = line_hit ? k + 1 : k;
+        if (wshell == sh && kn >= wbase && kn < wbase + G) {
+          wx_at = grp.bcast(wx, kn - wbase);
+          wx_k = kn;
+        }
+      }
 
       const double d_electron =
           (!line_hit && kappa > 0.0) ? quot_checked(tau_rem, rkappa) : INFINITY;
@@ -1466,8 +1509,7 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
       acc_nb += jc * nu_cmf;
 
       const double r_new = root(r * r + d * d + 2.0 * r * d * mu);
-      double mu_new = quot(rmu + d, divisor(r_new));
-      mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
+      const double mu_new = fmin(fmax(quot(rmu + d, divisor(r_new)), -1.0), 1.0);
       if (cross) {
         const int kind = inward ? EV_SHELL_IN : EV_SHELL_OUT;
         r = inward ? c_rin : c_rout;
@@ -1482,8 +1524,7 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
         double nu_cmf_out;
         int32_t emit = k;
         if (line_hit) {
-          const double u_branch =
-              grp.bcast((draw & 1) ? ub : ua, grp.uni((int)((draw >> 1) - rb)));
+          const double u_branch = draw_u(draw);
           draw += 1;
           nu_cmf_out = nu_hit;
           if (v.downbranch) {
@@ -1510,7 +1551,7 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
               level = -target - 1;
               if (++steps >= kMacroMaxSteps) break;
               if (draw + 2 > 2u * (rb + G)) refill_draws();  // this step's and the direction's
-              u = grp.bcast((draw & 1) ? ub : ua, grp.uni((int)((draw >> 1) - rb)));
+              u = draw_u(draw);
               draw += 1;
             }
             if (emit < 0) {
@@ -1526,8 +1567,7 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
         } else {
           nu_cmf_out = nu * D_old;
         }
-        const double mu_out =
-            2.0 * grp.bcast((draw & 1) ? ub : ua, grp.uni((int)((draw >> 1) - rb))) - 1.0;
+        const double mu_out = 2.0 * draw_u(draw) - 1.0;
         draw += 1;
         const Divisor rD = divisor(1.0 - quot(mu_out * r_new, v.rct));
         r = r_new;
@@ -1551,7 +1591,7 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
 
     if (status != SMC_LIVE) {
       if (v.jblue && wshell >= 0 && jb_acc != 0.0)
-        unsafeAtomicAdd(&v.jblue[(size_t)wshell * (size_t)v.L + wbase + grp.lane], jb_acc);
+        unsafeAtomicAdd(&v.jblue[(size_t)wshell * (size_t)v.L + wbase + grp.lane], jb_acc * wn);
       jb_acc = 0.0;
       wshell = -1;
       if (leader) {
@@ -1677,7 +1717,7 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
     // that the distance to a Thomson event exceeds 2^840 cm, beyond every
     // chord of a shell (radii <= 2^300 cm), exactly as with no electrons
     int32_t c_shell = -1;
-    double c_rin = 0.0, c_rout = 0.0, c_sig = 0.0;
+    double c_rin = 0.0, c_rout = 0.0, c_rin2 = 0.0, c_rout2 = 0.0, c_sig = 0.0;
     bool c_kfast = true;
     int status = SMC_LIVE;
 
@@ -1703,6 +1743,8 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
         const double ne = v.n_e[sh];
         // wait for these loads here, on the rare shell change
         asm volatile("" ::"v"(c_rin), "v"(c_rout), "v"(ne));
+        c_rin2 = c_rin * c_rin;
+        c_rout2 = c_rout * c_rout;
         c_sig = kSigmaT * ne;
         c_kfast = __ballot(c_sig >= 0x1p-898) != 0ull;
       }
@@ -1711,7 +1753,7 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
       const double nu_cmf = nu * D;
       const double e_cmf = E * D;
       bool inward;
-      const double d_shell = shell_distance(r, mu, rmu, c_rin, c_rout, inward);
+      const double d_shell = shell_distance_sq(r, mu, rmu, c_rin2, c_rout2, inward);
       const double kappa = c_sig * D;
       const Divisor rkappa = divisor(kappa);
       // distance to the Thomson event with optical depth x left
