@@ -313,6 +313,20 @@ __device__ __forceinline__ double root(double x) {
   return x > 0.0 ? g : 0.0;
 }
 
+// root(x) for x > 0 (a radius after a move: at least the inner boundary's)
+__device__ __forceinline__ double root_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y;
+  double h = y * 0.5;
+  const double r = fma(-h, g, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 // distance along (r, mu) to the boundary of shell [r_in, r_out] met first
 // (ray-sphere intersection; a tangent ray misses the inner sphere)
 // (from the squared radii; q is +0 when r_x^2 = b, so its clamp keeps the sign)
@@ -548,9 +562,26 @@ void transport_kernel(LaunchArgs a) {
   // cached shell parameters
   int32_t c_shell = -1;
   double c_rin = 0.0, c_rout = 0.0, c_ne = 0.0;
-  // line window: lines wbase..wbase+3 of shell wshell of the current model
+  // line window: lines wbase..wbase+3 of shell wshell of the current model,
+  // and the J_blue the lane has tallied on them since the window was loaded
   int32_t wbase = -8, wshell = -1;
   double wn0 = 0, wn1 = 0, wn2 = 0, wn3 = 0, wt0 = 0, wt1 = 0, wt2 = 0, wt3 = 0;
+  double wj0 = 0, wj1 = 0, wj2 = 0, wj3 = 0;
+  // The window's J_blue leaves in one atomic per line when the window does,
+  // issued after the next window's loads: a wait for those loads then never
+  // includes these atomics, which complete while the lane computes.
+  auto flush_window_jblue = [&](double* jrow) {
+    if (jrow) {
+      if (wj0 != 0.0) unsafeAtomicAdd(&jrow[wbase], wj0);
+      if (wj1 != 0.0) unsafeAtomicAdd(&jrow[wbase + 1], wj1);
+      if (wj2 != 0.0) unsafeAtomicAdd(&jrow[wbase + 2], wj2);
+      if (wj3 != 0.0) unsafeAtomicAdd(&jrow[wbase + 3], wj3);
+    }
+    wj0 = wj1 = wj2 = wj3 = 0.0;
+  };
+  auto jblue_row = [&](int32_t sh) {
+    return (v.jblue && sh >= 0) ? v.jblue + (size_t)sh * (size_t)v.L : (double*)nullptr;
+  };
   // J and nu-bar of one shell of one model, held in registers
   double acc_J = 0.0, acc_nb = 0.0;
   int acc_shell = -1, acc_model = -1;
@@ -580,6 +611,7 @@ void transport_kernel(LaunchArgs a) {
               else
                 hi = mid - 1;
             }
+            flush_window_jblue(jblue_row(wshell));
             model = lo;
             model_end = work_begin[lo + 1];
             v = make_view(a.table[model].m, a.table[model].it);
@@ -705,7 +737,7 @@ void transport_kernel(LaunchArgs a) {
       bool line_hit = false;
       double d_line = 0.0, nu_hit = 0.0;
       const double* __restrict__ tau_row = v.tau + (size_t)sh * (size_t)v.Lp;
-      double* jb_row = v.jblue ? v.jblue + (size_t)sh * (size_t)v.L : nullptr;
+      const bool jb_on = v.jblue != nullptr;
       bool stop = k >= v.L;
       while (!stop) {
         const int32_t base = k & ~3;
@@ -713,6 +745,7 @@ void transport_kernel(LaunchArgs a) {
           const double2* pn = reinterpret_cast<const double2*>(v.line_nu + base);
           const double2* pt = reinterpret_cast<const double2*>(tau_row + base);
           const double2 n01 = pn[0], n23 = pn[1], t01 = pt[0], t23 = pt[1];
+          flush_window_jblue(jblue_row(wshell));
           wn0 = n01.x; wn1 = n01.y; wn2 = n23.x; wn3 = n23.y;
           wt0 = t01.x; wt1 = t01.y; wt2 = t23.x; wt3 = t23.y;
           wbase = base;
@@ -732,7 +765,13 @@ void transport_kernel(LaunchArgs a) {
                 stop = true;
               } else {
                 n_pass += 1;
-                if (jb_row) unsafeAtomicAdd(&jb_row[base + j], quot(E * nu_k, rnn));
+                if (jb_on) {
+                  const double w = quot(E * nu_k, rnn);
+                  if (j == 0) wj0 += w;
+                  if (j == 1) wj1 += w;
+                  if (j == 2) wj2 += w;
+                  if (j == 3) wj3 += w;
+                }
                 if (tau_k + kappa * dl > tau_rem) {
                   line_hit = true;
                   d_line = dl;
@@ -772,7 +811,7 @@ void transport_kernel(LaunchArgs a) {
       acc_nb += jc * nu_cmf;
 
       // move along the flight path
-      const double r_new = root(r * r + d * d + 2.0 * r * d * mu);
+      const double r_new = root_pos(r * r + d * d + 2.0 * r * d * mu);
       double mu_new = quot(rmu + d, divisor(r_new));
       mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
 
@@ -865,6 +904,7 @@ void transport_kernel(LaunchArgs a) {
     unsafeAtomicAdd(&am.raw[acc_shell], acc_J);
     unsafeAtomicAdd(&am.raw[am.S + acc_shell], acc_nb);
   }
+  flush_window_jblue(jblue_row(wshell));
   if (tally_model >= 0) lane_tally_flush(ENTRY(a, tally_model).m, tly);
 }
 
@@ -1139,7 +1179,7 @@ __device__ bool virtual_path(const Group<G>& grp, const View& v, double r, doubl
     }
     tau += kappa * d_shell;
     if (tau > kTauVirtualMax) return false;
-    const double r_new = root(r * r + d_shell * d_shell + 2.0 * r * d_shell * mu);
+    const double r_new = root_pos(r * r + d_shell * d_shell + 2.0 * r * d_shell * mu);
     double mu_new = quot(rmu + d_shell, divisor(r_new));
     mu_new = mu_new > 1.0 ? 1.0 : (mu_new < -1.0 ? -1.0 : mu_new);
     r = inward ? r_in : r_out;
@@ -1508,7 +1548,7 @@ __device__ __forceinline__ void long_body(const LaunchArgs& a) {
       acc_J += jc;
       acc_nb += jc * nu_cmf;
 
-      const double r_new = root(r * r + d * d + 2.0 * r * d * mu);
+      const double r_new = root_pos(r * r + d * d + 2.0 * r * d * mu);
       const double mu_new = fmin(fmax(quot(rmu + d, divisor(r_new)), -1.0), 1.0);
       if (cross) {
         const int kind = inward ? EV_SHELL_IN : EV_SHELL_OUT;
@@ -1826,7 +1866,8 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
         const double rem = tau_ev - (wx - wx_at);  // tau itself at line k
         // lanes whose line lies beyond the Thomson event or the boundary, and
         // lanes whose line would absorb if reached
-        const unsigned long long far = __ballot(dl >= elec(rem)) | __ballot(dl >= d_shell);
+        const unsigned long long far_e = __ballot(dl >= quot(rem, rkappa));
+        const unsigned long long far = (c_kfast ? far_e : 0ull) | __ballot(dl >= d_shell);
         const unsigned long long deep = __ballot(wt + kappa * dl > rem);
         const unsigned long long stop = (far | deep) & live;
         // the first stopping lane (none: 0), and whether its line absorbs
@@ -1887,7 +1928,7 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
         const double jc = e_cmf * d * D;
         acc_J += jc;
         acc_nb += jc * nu_cmf;
-        const double r_new = root(r * r + d * d + 2.0 * r * d * mu);
+        const double r_new = root_pos(r * r + d * d + 2.0 * r * d * mu);
         const double mu_new = fmin(fmax(quot(rmu + d, divisor(r_new)), -1.0), 1.0);
         const double D_old = 1.0 - quot(mu_new * r_new, v.rct);
         const double e_cmf_ev = E * D_old;
@@ -1919,7 +1960,7 @@ __device__ __forceinline__ void solo_body(const LaunchArgs& a) {
       const double jc = e_cmf * d * D;
       acc_J += jc;
       acc_nb += jc * nu_cmf;
-      const double r_new = root(r * r + d * d + 2.0 * r * d * mu);
+      const double r_new = root_pos(r * r + d * d + 2.0 * r * d * mu);
       const double mu_new = fmin(fmax(quot(rmu + d, divisor(r_new)), -1.0), 1.0);
       if (escat) {
         // coherent, isotropic in the comoving frame (section 2.5)
